@@ -1,0 +1,176 @@
+/*
+ * ffcz.h -- C ABI of the MI355X (gfx950) dual-domain error correction.
+ *
+ * The library corrects a base compressor's reconstruction x_hat of a field x
+ * so that the error eps = y - x satisfies both bounds of Eq. 2 of the FFCz
+ * paper (Sec. IV-A):
+ *     |eps_n| <= E                                   for every point n,
+ *     |Re delta_k| <= Delta and |Im delta_k| <= Delta for every frequency k,
+ * where delta = DFT(eps) is the unnormalised forward DFT of Eq. 1 (sign -i).
+ * It runs the alternating projection of Alg. 1 (Sec. IV-B): forward FFT,
+ * violation count (CheckConvergence), clip of Re and Im (ProjectOntoFCube),
+ * inverse FFT, clip of eps (ProjectOntoSCube), until no coefficient violates.
+ *
+ * Conventions shared by every entry point
+ *  - Every data pointer is a DEVICE pointer, 16-byte aligned, owned by the
+ *    caller.  The library allocates no device memory: scratch comes from the
+ *    caller's workspace.  Fields are C-ordered (last axis contiguous); the
+ *    real-to-complex half-spectrum runs along the last axis.
+ *  - dtype selects the storage type of x, x_hat, y and gradients: FFCZ_F32
+ *    (float) or FFCZ_F64 (double).  FFCZ_F32 runs its transforms in FP32 with
+ *    twiddle tables evaluated in FP64 and rounded once; the output clamp and
+ *    the bound verification always run in FP64.
+ *  - Shapes: 1 <= ndim <= 3; unit extents are squeezed away; every remaining
+ *    extent must be a power of two, the last one between 2 and 4096 and the
+ *    others at most 2048 (FP32) / 1024 (FP64).  Violation counts refer to the
+ *    half-spectrum of the squeezed shape.
+ *  - stream is a hipStream_t (NULL = the null stream).  Work is stream-ordered.
+ *  - Return value: an ffcz_status.  Negative values are errors (the output is
+ *    unspecified); ffcz_last_error() then describes the cause.
+ *  - Bounds are shrunk by (1 - mu) for the projections and checked unshrunk
+ *    (the m = 16 shrink of Sec. IV-B, mu = 2^-16 by default), which makes the
+ *    loop terminate.
+ */
+#ifndef FFCZ_H
+#define FFCZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { FFCZ_F32 = 0, FFCZ_F64 = 1 } ffcz_dtype;
+
+typedef enum {
+  FFCZ_OK = 0,             /* converged; FP64 re-verification passed (if run)       */
+  FFCZ_NOT_CONVERGED = 1,  /* max_iter rounds ran; y holds the last iterate (in S)   */
+  FFCZ_VERIFY_FAILED = 2,  /* converged but the FP64 re-check of the output failed   */
+  FFCZ_E_INVALID = -1,     /* bad scalar argument or null pointer                    */
+  FFCZ_E_SHAPE = -2,       /* unsupported ndim / extent                              */
+  FFCZ_E_WORKSPACE = -3,   /* workspace too small or misaligned                      */
+  FFCZ_E_NONFINITE = -4,   /* x or x_hat holds NaN or Inf                            */
+  FFCZ_E_HIP = -5          /* a HIP runtime call failed                              */
+} ffcz_status;
+
+typedef struct {
+  /* Relative shrink mu of both bounds for the projections.  0 selects the
+   * default: 2^-16 for FFCZ_F64; for FFCZ_F32 the value of
+   * ffcz_suggest_margin() (room for the FP32 rounding of the output). */
+  double margin_rel;
+  /* 1: run exactly max_iter projection blocks whatever the check says (the
+   * map x_hat -> y is then piecewise linear; used for differentiation). */
+  int32_t fixed_iterations;
+  /* 1 (default): FP64 re-verification of both bounds on the output. */
+  int32_t verify_fp64;
+  /* Optional device buffer of ffcz_mask_bytes(ndim, shape, max_iter) bytes that
+   * receives the clip keep-masks (layout documented at ffcz_mask_bytes). */
+  void* masks_out;
+  /* Optional device int64 array of max_iter + 1 entries: violation count of
+   * every check (entry k = check after k projection blocks; unused entries 0). */
+  int64_t* viol_per_round;
+  /* Rounds enqueued between two host polls of the device done-flag (0 = 4). */
+  int32_t graph_chunk;
+  /* 1: capture a chunk of rounds once in a hipGraph and replay it. */
+  int32_t use_graph;
+} ffcz_options;
+
+typedef struct {               /* host struct filled on return */
+  int32_t rounds;              /* completed projection blocks                     */
+  int32_t converged;           /* 1 if the last check found no violation          */
+  int64_t f_viol_initial;      /* violations at the first check                   */
+  int64_t f_viol_final;        /* violations at the last check                    */
+  int64_t s_clipped_total;     /* spatial clips summed over all blocks             */
+  int64_t s_guard;             /* initial errors clipped into the shrunk s-cube    */
+  int64_t nonfinite;           /* non-finite inputs found                          */
+  double max_spatial_err;      /* FP64 max |y - x| (verification)                  */
+  double max_spectral_err;     /* FP64 max(|Re|,|Im|) of DFT(y - x)               */
+  int64_t spectral_viol;       /* coefficients above Delta in the verification    */
+  double margin_used;          /* mu actually used                                */
+} ffcz_stats;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int32_t ffcz_version(void);
+
+/* Thread-local description of the last non-OK status returned on this thread. */
+const char* ffcz_last_error(void);
+
+/* Fill *opts with the defaults described in ffcz_options. */
+void ffcz_default_options(ffcz_options* opts);
+
+/* Workspace bytes ffcz_correct / ffcz_correct_backward / ffcz_suggest_margin
+ * need for this dtype, shape and round cap.  0 if the shape is unsupported.
+ * Holds two half-spectrum buffers, the twiddle tables and the loop state. */
+size_t ffcz_workspace_bytes(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max_iter);
+
+/* Bytes of the clip keep-mask record for `rounds` projection blocks.
+ * Layout (little-endian 64-bit words, bit b of a word = element 64*w + b of
+ * its row; a bit is 1 iff the projection left that component unchanged):
+ *   rows_s = N / n_last rows of ceil(n_last/64) words          ("s-mask"),
+ *   rows_f = N / n_last rows of ceil((n_last/2+1)/64) words    ("f-mask"),
+ *   [s-mask 0 (guard)] [s-mask 1] ... [s-mask rounds]
+ *   [f-mask Re 1][f-mask Im 1] ... [f-mask Re rounds][f-mask Im rounds]
+ * where the shape is the squeezed one and f rows run over the half-spectrum. */
+size_t ffcz_mask_bytes(int32_t ndim, const int64_t* shape, int32_t rounds);
+
+/* Suggested shrink mu for an FP32 output (FP64 outputs: 2^-16).  Rounding
+ * y = x + eps to FP32 perturbs every spectral component by about
+ * sigma * sqrt(N/2) with sigma^2 = mean(ulp(x)^2)/12; mu keeps eight of these
+ * inside the shrunk f-cube: mu = max(2^-16, 8 sigma sqrt(N/2) / Delta),
+ * capped at 0.5.  Reads x (device) once; blocks until *mu_out is written. */
+int32_t ffcz_suggest_margin(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x_orig,
+                            double delta_f, void* workspace, size_t workspace_bytes, void* stream,
+                            double* mu_out);
+
+/* Alg. 1 on one field.
+ *   x_orig  original data x (device, dtype, shape)
+ *   x_base  base reconstruction x_hat (device; may alias x_out, not x_orig)
+ *   x_out   corrected y (device)
+ *   eps_s   spatial bound E (>= 0, finite)
+ *   delta_f spectral bound Delta on Re and Im (>= 0, finite)
+ *   max_iter cap on projection blocks (>= 0)
+ *   opts    NULL for defaults
+ *   workspace / workspace_bytes  device scratch of ffcz_workspace_bytes() bytes
+ *   stats   NULL or a host struct filled on return
+ * The call blocks on the host once per graph_chunk rounds to read the device
+ * done-flag, and at the end for the statistics. */
+int32_t ffcz_correct(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x_orig,
+                     const void* x_base, void* x_out, double eps_s, double delta_f,
+                     int32_t max_iter, const ffcz_options* opts, void* workspace,
+                     size_t workspace_bytes, void* stream, ffcz_stats* stats);
+
+/* Vector-Jacobian product of the fixed-round map x_hat -> y (fixed_iterations
+ * = 1, `rounds` blocks) recorded by ffcz_correct into `masks`.  With the clips
+ * frozen, block k is eps -> M_s^k (F^-1 M_f^k F eps); F^-1 M_f^k F is
+ * symmetric (orthogonal cos/sin basis, Sec. IV-A), so
+ *   grad_base = M_s^0 (A_1 (M_s^1 ... A_K (M_s^K grad_out))),  A_k = F^-1 M_f^k F.
+ * The FP32 output clamp is taken as the identity.  dL/dx = grad_out - grad_base.
+ *   masks     device buffer written by ffcz_correct (same shape, rounds)
+ *   grad_out  dL/dy (device, dtype)       grad_base  dL/dx_hat (device, dtype)
+ * Asynchronous (no host synchronisation). */
+int32_t ffcz_correct_backward(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t rounds,
+                              const void* masks, const void* grad_out, void* grad_base,
+                              void* workspace, size_t workspace_bytes, void* stream);
+
+/* Per-pass device timing for benchmarking.  While enabled, every launch made
+ * by ffcz_correct / ffcz_correct_backward on this host thread is bracketed by
+ * HIP events on the call's stream; launches that returned at entry because the
+ * loop had already finished are not counted.  Pass kinds (index into ms/count):
+ *   0 init (eps0, guard clip, R2C)   1 y-forward   2 x-pass (forward, count,
+ *   clip, inverse)   3 y-inverse   4 z-pass (C2R, clip, R2C)   5 finalize
+ *   6-8 FP64 verification z / y / x   9-11 adjoint z / y / x.
+ * ffcz_profile_enable(1) also resets the sums; ffcz_profile_read waits for the
+ * recorded events, returns the sums and resets them. */
+#define FFCZ_PROFILE_KINDS 12
+typedef struct {
+  double ms[FFCZ_PROFILE_KINDS];
+  int64_t count[FFCZ_PROFILE_KINDS];
+} ffcz_profile;
+void ffcz_profile_enable(int32_t on);
+int32_t ffcz_profile_read(ffcz_profile* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FFCZ_H */

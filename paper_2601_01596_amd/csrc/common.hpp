@@ -1,0 +1,110 @@
+// Device state, kernel argument blocks and pass modes shared by the kernels
+// and the host driver.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_engine.hpp"
+
+namespace ffcz {
+
+// Loop state kept in the caller's workspace.  Written by one lane at a time
+// (the set-up kernel, or the last block of the x-pass); read at the entry of
+// every loop kernel.
+struct DevState {
+  // parameters
+  double E, Ep, Delta, Dp, inv_n;
+  int32_t max_iter, fixed, record_masks, pad0;
+  // loop control
+  int32_t done, round, converged, nonfinite_stop;
+  uint32_t ticket, pad1;
+  // counters
+  unsigned long long nonfinite, s_guard, s_clipped_total;
+  unsigned long long max_spatial_bits, max_spectral_bits, spectral_viol;
+  // margin suggestion: sum of ulp^2 (FP64), count
+  double ulp2_sum;
+  unsigned long long ulp_cnt;
+};
+
+enum ColMode : int {
+  COL_FWD = 0,     // forward C2C along the strided axis
+  COL_INV = 1,     // inverse C2C
+  COL_XPASS = 2,   // forward, count + clip (+ f-mask), inverse; decides convergence
+  COL_XBACK = 3,   // forward, multiply by recorded f-mask, inverse (adjoint)
+  COL_VERIFY = 4,  // forward (FP64), max |Re|,|Im| and violation count; no store
+  COL_FWD_NS = 5,  // forward, ignores the done flag (adjoint, verification)
+  COL_INV_NS = 6   // inverse, ignores the done flag (adjoint)
+};
+
+enum RowMode : int {
+  ROW_INIT = 0,    // eps0 = x_hat - x (FP64), guard clip, R2C
+  ROW_LOOP = 1,    // C2R, 1/N, s-clip (+ s-mask), R2C
+  ROW_FINAL = 2,   // C2R, 1/N, y = x + eps in FP64, closing clamp, store y
+  ROW_VERIFY = 3,  // d = y - x in FP64, max |d|, FP64 R2C
+  ROW_BINIT = 4,   // g * s-mask, R2C        (adjoint)
+  ROW_BLOOP = 5,   // C2R, 1/N, g * s-mask, R2C (adjoint)
+  ROW_BFINAL = 6   // C2R, 1/N, g * s-mask, store (adjoint)
+};
+
+template <typename T>
+struct ColArgs {
+  const cx<T>* src;
+  cx<T>* dst;
+  int64_t so;      // stride between outer indices (complex entries)
+  int64_t s;       // stride along the transformed axis
+  int32_t ncols;   // valid contiguous columns
+  int32_t ncb;     // column blocks per outer index
+  const cx<T>* tw; // stage twiddles of this length
+  DevState* st;
+  unsigned long long* viol;  // per-check violation counts
+  // f-masks (forward record / adjoint read)
+  uint8_t* fmask;      // forward: base of the f-mask region; adjoint: Re plane of block k
+  int64_t f_plane;     // bytes per Re (or Im) plane
+  int64_t f_row_bytes; // bytes per half-spectrum row
+  int64_t mrow_i;      // mask row = i * mrow_i + outer * mrow_o
+  int64_t mrow_o;
+};
+
+template <typename T, typename TIO>
+struct RowArgs {
+  const cx<T>* src;
+  cx<T>* dst;
+  int64_t pitch;   // complex entries per spectrum row
+  int64_t nrows;
+  const TIO* x;    // original (ROW_INIT, ROW_FINAL, ROW_VERIFY)
+  const TIO* xb;   // base reconstruction (ROW_INIT), output y (ROW_VERIFY), dL/dy (ROW_BINIT)
+  TIO* y;          // output (ROW_FINAL), dL/dx_hat (ROW_BFINAL)
+  const cx<T>* tw; // stage twiddles of length H followed by H R2C twiddles
+  DevState* st;
+  uint32_t* smask;   // forward: base of the s-mask region; adjoint: s-mask plane to apply
+  int64_t s_plane;   // uint32 words per s-mask plane
+  int32_t s_row_w32; // uint32 words per s-mask row
+  int32_t pad;
+};
+
+// FP64 bound -> working type, rounded toward zero (a tighter bound in FP32).
+template <typename T>
+__device__ __forceinline__ T to_t(double v);
+template <>
+__device__ __forceinline__ float to_t<float>(double v) { return __double2float_rz(v); }
+template <>
+__device__ __forceinline__ double to_t<double>(double v) { return v; }
+
+// Clip to [-b, b].
+template <typename T>
+__device__ __forceinline__ T clipv(T v, T b) { return v > b ? b : (v < -b ? -b : v); }
+
+// Columns per block: 128-byte rows, halved until the tile fits in 128 KiB of LDS.
+template <typename T>
+__host__ __device__ constexpr int pick_C(int L) {
+  int c = 128 / (int)sizeof(cx<T>);
+  while (c > 1 && (long)c * L * (long)sizeof(cx<T>) > 128 * 1024) c /= 2;
+  return c;
+}
+// Rows per block for the last-axis passes: about 256 lanes.
+__host__ __device__ constexpr int pick_rows(int H) {
+  const int P = H / pick_E(H);
+  return P >= 256 ? 1 : 256 / (P < 1 ? 1 : P);
+}
+
+}  // namespace ffcz

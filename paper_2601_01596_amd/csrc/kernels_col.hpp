@@ -1,0 +1,174 @@
+// Strided-axis passes.  A block owns C contiguous columns of one outer index
+// and the whole transformed axis (length L): element (c, i) is read from
+// src[outer*so + col0 + c + i*s], so every row of the tile is one 64-128 B
+// contiguous segment.  Lane (j, c) keeps elements i = j + q*P of column c.
+#pragma once
+#include "common.hpp"
+
+namespace ffcz {
+
+template <typename T, int L, int C, int MODE>
+__global__ void __launch_bounds__(C*(L / pick_E(L)))
+col_kernel(ColArgs<T> a) {
+  constexpr int E = pick_E(L);
+  constexpr int P = L / E;
+  constexpr int NT = C * P;
+  using S = Sched<L, E>;
+  constexpr int TW = S::twsize;
+  constexpr int NW = (NT + 63) / 64;
+  __shared__ cx<T> lds[S::nst > 1 ? L * C : 1];
+  __shared__ cx<T> tws[TW > 0 ? TW : 1];
+  __shared__ unsigned long long red_u[NW];
+  __shared__ double red_d[NW];
+
+  DevState* st = a.st;
+  constexpr bool uses_done = (MODE == COL_FWD || MODE == COL_INV || MODE == COL_XPASS);
+  if (uses_done) {
+    if (*(volatile int32_t*)&st->done) return;
+  }
+  const int t = threadIdx.x;
+  const int c = t % C;
+  const int j = t / C;
+  const int64_t bid = blockIdx.x;
+  const int64_t o = bid / a.ncb;
+  const int cb = (int)(bid - o * a.ncb);
+  const int col = cb * C + c;
+  const bool valid = col < a.ncols;
+  const int64_t base = o * a.so + col;
+
+  for (int i = t; i < TW; i += NT) tws[i] = a.tw[i];
+
+  cx<T> v[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int64_t idx = base + (int64_t)(j + q * P) * a.s;
+    v[q] = valid ? a.src[idx] : cx<T>{T(0), T(0)};
+  }
+
+  if constexpr (MODE == COL_FWD || MODE == COL_FWD_NS) {
+    fft<T, L, E, false, C, 1>(v, lds, tws, c, j);
+  } else if constexpr (MODE == COL_INV || MODE == COL_INV_NS) {
+    fft<T, L, E, true, C, 1>(v, lds, tws, c, j);
+  } else if constexpr (MODE == COL_XPASS) {
+    const int k = *(volatile int32_t*)&st->round;
+    const T D = to_t<T>(st->Delta);
+    const T Dp = to_t<T>(st->Dp);
+    const bool rec = st->record_masks && (k < st->max_iter);
+    fft<T, L, E, false, C, 1>(v, lds, tws, c, j);
+    unsigned long long cnt = 0;
+    const int lane = t & 63;
+    uint8_t* mre = a.fmask + (int64_t)k * 2 * a.f_plane;
+    uint8_t* mim = mre + a.f_plane;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      cx<T> z = v[q];
+      const bool bad = valid && (fabs(z.re) > D || fabs(z.im) > D);
+      cnt += bad ? 1 : 0;
+      const bool kre = fabs(z.re) <= Dp;
+      const bool kim = fabs(z.im) <= Dp;
+      z.re = clipv(z.re, Dp);
+      z.im = clipv(z.im, Dp);
+      v[q] = z;
+      if (rec) {
+        const unsigned long long bre = __ballot(valid && kre);
+        const unsigned long long bim = __ballot(valid && kim);
+        if (c == 0) {
+          const int64_t row = (int64_t)(j + q * P) * a.mrow_i + o * a.mrow_o;
+          const int64_t off = row * a.f_row_bytes + (cb * C) / 8;
+          if constexpr (C == 16) {
+            *(uint16_t*)(mre + off) = (uint16_t)((bre >> lane) & 0xFFFFull);
+            *(uint16_t*)(mim + off) = (uint16_t)((bim >> lane) & 0xFFFFull);
+          } else if constexpr (C == 8) {
+            mre[off] = (uint8_t)((bre >> lane) & 0xFFull);
+            mim[off] = (uint8_t)((bim >> lane) & 0xFFull);
+          }
+        }
+      }
+    }
+    fft<T, L, E, true, C, 1>(v, lds, tws, c, j);
+    // violations of this check: one atomic per block
+    cnt = wave_sum_u64(cnt);
+    if ((t & 63) == 0) red_u[t >> 6] = cnt;
+    __syncthreads();
+    if (t == 0) {
+      unsigned long long s = 0;
+      for (int w = 0; w < NW; ++w) s += red_u[w];
+      if (s) atomicAdd(&a.viol[k], s);
+      __threadfence();
+      const unsigned int tk = atomicAdd(&st->ticket, 1u);
+      if (tk == gridDim.x - 1) {
+        // last block of this check: every count is in
+        __threadfence();
+        const unsigned long long vk = atomicAdd(&a.viol[k], 0ull);
+        int stop = 0;
+        if (st->nonfinite) {
+          stop = 1;
+          st->nonfinite_stop = 1;
+        } else if (!st->fixed && vk == 0) {
+          stop = 1;
+          st->converged = 1;
+        } else if (k >= st->max_iter) {
+          stop = 1;
+          st->converged = (vk == 0) ? 1 : 0;
+        }
+        if (stop) st->done = 1;
+        else st->round = k + 1;
+        st->ticket = 0u;
+        __threadfence();
+      }
+    }
+  } else if constexpr (MODE == COL_XBACK) {
+    fft<T, L, E, false, C, 1>(v, lds, tws, c, j);
+    const uint8_t* mre = a.fmask;
+    const uint8_t* mim = a.fmask + a.f_plane;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int64_t row = (int64_t)(j + q * P) * a.mrow_i + o * a.mrow_o;
+      const int64_t off = row * a.f_row_bytes + col / 8;
+      const int bit = col & 7;
+      const int kr = valid ? (mre[off] >> bit) & 1 : 0;
+      const int ki = valid ? (mim[off] >> bit) & 1 : 0;
+      v[q].re = kr ? v[q].re : T(0);
+      v[q].im = ki ? v[q].im : T(0);
+    }
+    fft<T, L, E, true, C, 1>(v, lds, tws, c, j);
+  } else if constexpr (MODE == COL_VERIFY) {
+    fft<T, L, E, false, C, 1>(v, lds, tws, c, j);
+    const double D = st->Delta;
+    unsigned long long cnt = 0;
+    double mx = 0.0;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      if (valid) {
+        const double m = fmax(fabs((double)v[q].re), fabs((double)v[q].im));
+        mx = fmax(mx, m);
+        cnt += (m > D) ? 1 : 0;
+      }
+    }
+    cnt = wave_sum_u64(cnt);
+    mx = wave_max_f64(mx);
+    if ((t & 63) == 0) {
+      red_u[t >> 6] = cnt;
+      red_d[t >> 6] = mx;
+    }
+    __syncthreads();
+    if (t == 0) {
+      unsigned long long s = 0;
+      double m = 0.0;
+      for (int w = 0; w < NW; ++w) {
+        s += red_u[w];
+        m = fmax(m, red_d[w]);
+      }
+      if (s) atomicAdd(&st->spectral_viol, s);
+      atomicMax(&st->max_spectral_bits, (unsigned long long)__double_as_longlong(m));
+    }
+    return;
+  }
+
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    if (valid) a.dst[base + (int64_t)(j + q * P) * a.s] = v[q];
+  }
+}
+
+}  // namespace ffcz

@@ -1,0 +1,326 @@
+"""Python binding of ``libffcz.so`` (argument marshalling only).
+
+The functions named ``ffcz_*`` mirror the C ABI of ``include/ffcz.h`` one to
+one and take raw device pointers.  ``correct``, ``correct_backward`` and
+``FFCzCorrect`` are conveniences over them for torch tensors: torch supplies
+device memory and the current stream, every arithmetic step runs in the HIP
+library.  There is no fallback: if the library is missing, importing this
+module's functions raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libffcz.so")
+
+F32 = 0
+F64 = 1
+OK = 0
+NOT_CONVERGED = 1
+VERIFY_FAILED = 2
+E_INVALID = -1
+E_SHAPE = -2
+E_WORKSPACE = -3
+E_NONFINITE = -4
+E_HIP = -5
+
+EXPORTS = ("ffcz_version", "ffcz_last_error", "ffcz_default_options", "ffcz_workspace_bytes",
+           "ffcz_mask_bytes", "ffcz_suggest_margin", "ffcz_correct", "ffcz_correct_backward",
+           "ffcz_profile_enable", "ffcz_profile_read")
+
+PROFILE_KINDS = ("init", "y_fwd", "x_pass", "y_inv", "z_pass", "finalize", "verify_z", "verify_y", "verify_x",
+                 "adjoint_z", "adjoint_y", "adjoint_x")
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("margin_rel", ctypes.c_double),
+        ("fixed_iterations", ctypes.c_int32),
+        ("verify_fp64", ctypes.c_int32),
+        ("masks_out", ctypes.c_void_p),
+        ("viol_per_round", ctypes.c_void_p),
+        ("graph_chunk", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("rounds", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("f_viol_initial", ctypes.c_int64),
+        ("f_viol_final", ctypes.c_int64),
+        ("s_clipped_total", ctypes.c_int64),
+        ("s_guard", ctypes.c_int64),
+        ("nonfinite", ctypes.c_int64),
+        ("max_spatial_err", ctypes.c_double),
+        ("max_spectral_err", ctypes.c_double),
+        ("spectral_viol", ctypes.c_int64),
+        ("margin_used", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 12), ("count", ctypes.c_int64 * 12)]
+
+
+class FFCzError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ffcz status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load ``libffcz.so`` (built by ``paper_2601_01596_amd.build``); raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FFCzError(E_HIP, f"{LIB_PATH} is missing: run python -m paper_2601_01596_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.ffcz_version.restype = ctypes.c_int32
+        L.ffcz_last_error.restype = ctypes.c_char_p
+        L.ffcz_default_options.argtypes = [ctypes.POINTER(Options)]
+        L.ffcz_default_options.restype = None
+        L.ffcz_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, i64p, ctypes.c_int32]
+        L.ffcz_workspace_bytes.restype = ctypes.c_size_t
+        L.ffcz_mask_bytes.argtypes = [ctypes.c_int32, i64p, ctypes.c_int32]
+        L.ffcz_mask_bytes.restype = ctypes.c_size_t
+        L.ffcz_suggest_margin.argtypes = [ctypes.c_int32, ctypes.c_int32, i64p, ctypes.c_void_p, ctypes.c_double,
+                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_double)]
+        L.ffcz_suggest_margin.restype = ctypes.c_int32
+        L.ffcz_correct.argtypes = [ctypes.c_int32, ctypes.c_int32, i64p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                   ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                   ctypes.POINTER(Stats)]
+        L.ffcz_correct.restype = ctypes.c_int32
+        L.ffcz_correct_backward.argtypes = [ctypes.c_int32, ctypes.c_int32, i64p, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                            ctypes.c_void_p]
+        L.ffcz_correct_backward.restype = ctypes.c_int32
+        L.ffcz_profile_enable.argtypes = [ctypes.c_int32]
+        L.ffcz_profile_enable.restype = None
+        L.ffcz_profile_read.argtypes = [ctypes.POINTER(Profile)]
+        L.ffcz_profile_read.restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def _shape(shape: Sequence[int]):
+    arr = (ctypes.c_int64 * len(shape))(*[int(s) for s in shape])
+    return len(shape), arr
+
+
+# ---------------------------------------------------------------- raw C ABI
+
+def ffcz_version() -> int:
+    return lib().ffcz_version()
+
+
+def ffcz_last_error() -> str:
+    return lib().ffcz_last_error().decode()
+
+
+def ffcz_default_options() -> Options:
+    o = Options()
+    lib().ffcz_default_options(ctypes.byref(o))
+    return o
+
+
+def ffcz_workspace_bytes(dtype: int, shape: Sequence[int], max_iter: int) -> int:
+    nd, arr = _shape(shape)
+    return int(lib().ffcz_workspace_bytes(dtype, nd, arr, max_iter))
+
+
+def ffcz_mask_bytes(shape: Sequence[int], rounds: int) -> int:
+    nd, arr = _shape(shape)
+    return int(lib().ffcz_mask_bytes(nd, arr, rounds))
+
+
+def ffcz_suggest_margin(dtype: int, shape, x_ptr: int, delta_f: float, ws_ptr: int, ws_bytes: int,
+                        stream: int) -> float:
+    nd, arr = _shape(shape)
+    mu = ctypes.c_double(0.0)
+    st = lib().ffcz_suggest_margin(dtype, nd, arr, ctypes.c_void_p(x_ptr), float(delta_f), ctypes.c_void_p(ws_ptr),
+                                   ws_bytes, ctypes.c_void_p(stream), ctypes.byref(mu))
+    if st < 0:
+        raise FFCzError(st, ffcz_last_error())
+    return mu.value
+
+
+def ffcz_correct(dtype: int, shape, x_ptr: int, xb_ptr: int, y_ptr: int, eps_s: float, delta_f: float,
+                 max_iter: int, opts: Optional[Options], ws_ptr: int, ws_bytes: int, stream: int,
+                 stats: Optional[Stats]) -> int:
+    nd, arr = _shape(shape)
+    return int(lib().ffcz_correct(dtype, nd, arr, ctypes.c_void_p(x_ptr), ctypes.c_void_p(xb_ptr),
+                                  ctypes.c_void_p(y_ptr), float(eps_s), float(delta_f), int(max_iter),
+                                  ctypes.byref(opts) if opts is not None else None, ctypes.c_void_p(ws_ptr),
+                                  ws_bytes, ctypes.c_void_p(stream),
+                                  ctypes.byref(stats) if stats is not None else None))
+
+
+def ffcz_correct_backward(dtype: int, shape, rounds: int, masks_ptr: int, grad_out_ptr: int, grad_base_ptr: int,
+                          ws_ptr: int, ws_bytes: int, stream: int) -> int:
+    nd, arr = _shape(shape)
+    return int(lib().ffcz_correct_backward(dtype, nd, arr, int(rounds), ctypes.c_void_p(masks_ptr),
+                                           ctypes.c_void_p(grad_out_ptr), ctypes.c_void_p(grad_base_ptr),
+                                           ctypes.c_void_p(ws_ptr), ws_bytes, ctypes.c_void_p(stream)))
+
+
+def ffcz_profile_enable(on: bool) -> None:
+    lib().ffcz_profile_enable(1 if on else 0)
+
+
+def ffcz_profile_read() -> dict:
+    """Summed device ms and launch counts per pass kind since the last read."""
+    pr = Profile()
+    st = lib().ffcz_profile_read(ctypes.byref(pr))
+    if st < 0:
+        raise FFCzError(st, ffcz_last_error())
+    return {k: (pr.ms[i], int(pr.count[i])) for i, k in enumerate(PROFILE_KINDS)}
+
+
+# ---------------------------------------------------------------- torch conveniences
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise FFCzError(E_INVALID, f"unsupported dtype {t.dtype}")
+
+
+def _check_tensor(t, name):
+    if not t.is_cuda:
+        raise FFCzError(E_INVALID, f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise FFCzError(E_INVALID, f"{name} must be contiguous")
+
+
+def workspace(dtype_code: int, shape, max_iter: int, device=None):
+    torch = _torch()
+    nbytes = ffcz_workspace_bytes(dtype_code, shape, max_iter)
+    if nbytes == 0:
+        raise FFCzError(E_SHAPE, f"unsupported shape {tuple(shape)}: {ffcz_last_error()}")
+    # 256-byte alignment: torch's caching allocator returns 512-byte aligned blocks
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+@dataclasses.dataclass
+class Result:
+    y: object
+    status: int
+    stats: dict
+    masks: object = None
+    viol: object = None
+
+
+def correct(x, xb, eps_s: float, delta_f: float, max_iter: int, *, margin: float = 0.0, fixed: bool = False,
+            verify: bool = True, record_masks: bool = False, record_viol: bool = False, chunk: int = 4,
+            out=None, ws=None, check: bool = True) -> Result:
+    """Run ``ffcz_correct`` on device tensors ``x`` (original) and ``xb`` (base)."""
+    torch = _torch()
+    _check_tensor(x, "x")
+    _check_tensor(xb, "xb")
+    if x.shape != xb.shape or x.dtype != xb.dtype:
+        raise FFCzError(E_INVALID, "x and xb must have the same shape and dtype")
+    dt = _dtype_code(x)
+    shape = tuple(x.shape)
+    y = torch.empty_like(x) if out is None else out
+    if ws is None:
+        ws = workspace(dt, shape, max_iter, x.device)
+    opts = ffcz_default_options()
+    opts.margin_rel = float(margin)
+    opts.fixed_iterations = 1 if fixed else 0
+    opts.verify_fp64 = 1 if verify else 0
+    opts.graph_chunk = int(chunk)
+    masks = None
+    if record_masks:
+        masks = torch.zeros(ffcz_mask_bytes(shape, max_iter), dtype=torch.uint8, device=x.device)
+        opts.masks_out = masks.data_ptr()
+    viol = None
+    if record_viol:
+        viol = torch.zeros(max_iter + 1, dtype=torch.int64, device=x.device)
+        opts.viol_per_round = viol.data_ptr()
+    stats = Stats()
+    stream = torch.cuda.current_stream(x.device).cuda_stream
+    st = ffcz_correct(dt, shape, x.data_ptr(), xb.data_ptr(), y.data_ptr(), eps_s, delta_f, max_iter, opts,
+                      ws.data_ptr(), ws.numel(), stream, stats)
+    if check and st < 0:
+        raise FFCzError(st, ffcz_last_error())
+    return Result(y=y, status=st, stats=stats.as_dict(), masks=masks, viol=viol)
+
+
+def correct_backward(grad_y, masks, rounds: int, ws=None):
+    """``ffcz_correct_backward``: dL/dx_hat from dL/dy and the recorded masks."""
+    torch = _torch()
+    _check_tensor(grad_y, "grad_y")
+    dt = _dtype_code(grad_y)
+    shape = tuple(grad_y.shape)
+    if ws is None:
+        ws = workspace(dt, shape, rounds, grad_y.device)
+    gb = torch.empty_like(grad_y)
+    stream = torch.cuda.current_stream(grad_y.device).cuda_stream
+    st = ffcz_correct_backward(dt, shape, rounds, masks.data_ptr(), grad_y.data_ptr(), gb.data_ptr(),
+                               ws.data_ptr(), ws.numel(), stream)
+    if st < 0:
+        raise FFCzError(st, ffcz_last_error())
+    return gb
+
+
+def _autograd():
+    torch = _torch()
+
+    class FFCzCorrect(torch.autograd.Function):
+        """``y = FFCzCorrect.apply(xb, x, eps_s, delta_f, K)``: K fixed rounds, differentiable in xb.
+
+        The forward records 1-bit clip masks per round; the backward replays the
+        rounds in reverse with masks in place of clips (no stored iterates).
+        ``x`` is treated as a constant.
+        """
+
+        @staticmethod
+        def forward(ctx, xb, x, eps_s, delta_f, K, margin=0.0):
+            r = correct(x.detach(), xb.detach(), eps_s, delta_f, int(K), margin=margin, fixed=True,
+                        verify=False, record_masks=True)
+            ctx.save_for_backward(r.masks)
+            ctx.K = int(K)
+            return r.y
+
+        @staticmethod
+        def backward(ctx, gy):
+            (masks,) = ctx.saved_tensors
+            gb = correct_backward(gy.contiguous(), masks, ctx.K)
+            return gb, None, None, None, None, None
+
+    return FFCzCorrect
+
+
+class _Lazy:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _Lazy._cls is None:
+            _Lazy._cls = _autograd()
+        return getattr(_Lazy._cls, name)
+
+
+FFCzCorrect = _Lazy()

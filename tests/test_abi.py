@@ -1,0 +1,59 @@
+"""The C-ABI library loads on the CPU and exports every entry point ffcz.h declares.
+
+No compute is called here (no GPU); shape/size queries are host-only."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ffcz.h")
+LIB = os.path.join(ROOT, "paper_2601_01596_amd", "libffcz.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ffcz_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libffcz.so is not built: run python -m paper_2601_01596_amd.build")
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert "ffcz_correct" in names and "ffcz_correct_backward" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_python_binding_names_match_the_header():
+    from paper_2601_01596_amd import ffcz
+    for n in declared():
+        assert n in ffcz.EXPORTS and callable(getattr(ffcz, n)), n
+
+
+def test_size_queries_and_shape_rules():
+    from paper_2601_01596_amd import ffcz
+    assert ffcz.ffcz_version() >= 100
+    w = ffcz.ffcz_workspace_bytes(ffcz.F32, (64, 64, 64), 200)
+    # two FP32 half-spectra with 128-byte padded rows: 64*64*(33 -> 48) * 8 bytes each
+    assert w >= 2 * 64 * 64 * 48 * 8
+    assert ffcz.ffcz_workspace_bytes(ffcz.F32, (64, 63, 64), 10) == 0   # not a power of two
+    assert ffcz.ffcz_workspace_bytes(ffcz.F32, (2, 2, 2, 2), 10) == 0   # ndim 4
+    assert ffcz.ffcz_workspace_bytes(ffcz.F64, (1, 64, 1), 10) > 0       # squeezes to 1D
+    # masks: (K+1) s-planes of 64*64 rows x 1 word + K f-pairs of 64*64 rows x 1 word
+    assert ffcz.ffcz_mask_bytes((64, 64, 64), 3) == 4 * 4096 * 8 + 3 * 2 * 4096 * 8
+    assert ffcz.ffcz_mask_bytes((8, 8, 256), 1) == 2 * 64 * 4 * 8 + 2 * 64 * 3 * 8
+
+
+def test_options_defaults():
+    from paper_2601_01596_amd import ffcz
+    o = ffcz.ffcz_default_options()
+    assert o.verify_fp64 == 1 and o.fixed_iterations == 0 and o.masks_out is None

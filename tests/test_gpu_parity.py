@@ -1,0 +1,222 @@
+"""GPU parity of the HIP correction path against the FP64 CPU oracle.
+
+Every call goes through the C ABI (``paper_2601_01596_amd.ffcz`` -> libffcz.so).
+Tolerances (written here, derived in the design doc):
+  FP64: rounds and every per-check violation count equal to the oracle's;
+        max|y_gpu - y_orc| <= 1e-12 * max|y_orc|.
+  FP32: rounds equal or off by one (then the oracle is re-run for the GPU's
+        round count with fixed rounds); max|y_gpu - y_orc| <= 1e-5 * max|y_orc|;
+        per-check violation counts within 0.1% (+2).
+  Both: the FP64 re-verification of the output passes.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import ffcz as O
+from paper_2601_01596_amd import ffcz as F
+from paper_2601_01596_amd import workloads as W
+from tests.gpu_util import rel_err, run_gpu, unpack_masks
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(shape, seed, dtype, q=90.0, r=1e-2, alpha=2.0):
+    x = W.grf(shape, alpha, seed) if len(shape) > 1 or shape[0] > 4 else np.random.default_rng(seed).standard_normal(shape)
+    return W.make_problem("t", x, dtype, r, q, 200)
+
+
+def _check_fp64(p, y, res, orc):
+    assert res.status == F.OK, (res.status, F.ffcz_last_error())
+    assert res.stats["rounds"] == orc.rounds
+    assert rel_err(y, orc.y) <= 1e-12
+    assert res.stats["max_spatial_err"] <= p.E and res.stats["max_spectral_err"] <= p.Delta
+
+
+def _check_fp32(p, y, res, orc):
+    assert res.status == F.OK, (res.status, F.ffcz_last_error())
+    k = res.stats["rounds"]
+    if k != orc.rounds:
+        assert abs(k - orc.rounds) <= 1
+        orc = O.correct(p.x, p.xb, p.E, p.Delta, k, mu=res.stats["margin_used"], fixed=True)
+    assert rel_err(y, orc.y) <= 1e-5
+    ms, mf, nv, ok = O.verify(p.x, y, p.E, p.Delta)
+    assert ok and nv == 0
+
+
+def test_grf64_fp64_matches_oracle_counts_and_values():
+    # 64^3 FP64 GRF, k^-2, E = 1e-3 range, Delta at the 90th percentile, cap 200
+    p = W.config_grf_fp64(64)
+    y, res = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter, record_viol=True)
+    orc = O.correct(p.x, p.xb, p.E, p.Delta, p.max_iter)
+    _check_fp64(p, y, res, orc)
+    viol = res.viol.cpu().numpy()[: orc.rounds + 1]
+    assert list(viol) == orc.viol
+    assert res.stats["s_guard"] == orc.s_clipped[0]
+    assert res.stats["s_clipped_total"] == sum(orc.s_clipped[1:])
+    assert res.stats["f_viol_initial"] == orc.viol[0]
+
+
+SHAPES = [(16, 32, 64), (8, 8, 8), (4, 16, 128), (32, 64), (128, 16), (64, 4096), (256,), (4096,), (2, 4, 8),
+          (1, 64, 32), (64, 1, 32), (16, 16, 2), (512, 8)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_shapes_fp64(shape):
+    p = _problem(shape, 7, np.float64)
+    y, res = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter, record_viol=True)
+    orc = O.correct(p.x, p.xb, p.E, p.Delta, p.max_iter)
+    _check_fp64(p, y, res, orc)
+    assert list(res.viol.cpu().numpy()[: orc.rounds + 1]) == orc.viol
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_shapes_fp32(shape):
+    p = _problem(shape, 11, np.float32)
+    y, res = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter, record_viol=True)
+    orc = O.correct(p.x, p.xb, p.E, p.Delta, p.max_iter, mu=res.stats["margin_used"])
+    _check_fp32(p, y, res, orc)
+    v = res.viol.cpu().numpy()
+    assert abs(int(v[0]) - orc.viol[0]) <= 2 + 1e-3 * orc.viol[0]
+
+
+def test_lognormal64_fp32_and_fp64():
+    # the 512^3 lognormal recipe (k^-2.5, E = 1e-4 range, 95th percentile) at 64^3
+    for dt in (np.float32, np.float64):
+        p = W.config_lognormal(64, dt)
+        y, res = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter)
+        mu = res.stats["margin_used"]
+        orc = O.correct(p.x, p.xb, p.E, p.Delta, p.max_iter, mu=mu)
+        (_check_fp64 if dt == np.float64 else _check_fp32)(p, y, res, orc)
+
+
+def test_max_iter_zero_and_one_not_converged():
+    p = _problem((16, 16, 16), 3, np.float64, q=50.0)
+    y, res = run_gpu(p.x, p.xb, p.E, p.Delta, 0)
+    assert res.status == F.NOT_CONVERGED and res.stats["rounds"] == 0
+    orc = O.correct(p.x, p.xb, p.E, p.Delta, 0)
+    assert rel_err(y, orc.y) <= 1e-12
+    y, res = run_gpu(p.x, p.xb, p.E, p.Delta, 1)
+    orc = O.correct(p.x, p.xb, p.E, p.Delta, 1)
+    assert res.stats["rounds"] == 1 and res.status == orc.status
+    assert rel_err(y, orc.y) <= 1e-12
+
+
+def test_zero_rounds_when_already_inside_both_cubes():
+    g = np.random.default_rng(4)
+    x = g.standard_normal((8, 16, 32))
+    E = 0.01
+    xb = x + g.uniform(-0.5 * E, 0.5 * E, x.shape)
+    y, res = run_gpu(x, xb, E, x.size * E, 10)
+    assert res.status == F.OK and res.stats["rounds"] == 0 and res.stats["f_viol_initial"] == 0
+    assert rel_err(y, xb) <= 1e-13
+
+
+def test_nonfinite_input_is_reported():
+    p = _problem((16, 16, 16), 5, np.float32)
+    xb = p.xb.copy()
+    xb[3, 4, 5] = np.nan
+    _, res = run_gpu(p.x, xb, p.E, p.Delta, 20)
+    assert res.status == F.E_NONFINITE
+    assert res.stats["nonfinite"] == 1
+
+
+def test_argument_errors():
+    import torch
+    x = torch.zeros((8, 8, 8), dtype=torch.float32, device="cuda")
+    xb = torch.zeros_like(x)
+    r = F.correct(x, xb, -1.0, 1.0, 5, check=False)
+    assert r.status == F.E_INVALID
+    r = F.correct(x, xb, 1.0, float("nan"), 5, check=False)
+    assert r.status == F.E_INVALID
+    ws = torch.empty(64, dtype=torch.uint8, device="cuda")
+    r = F.correct(x, xb, 1.0, 1.0, 5, ws=ws, check=False)
+    assert r.status == F.E_WORKSPACE
+    bad = torch.zeros((8, 6, 8), dtype=torch.float32, device="cuda")
+    with pytest.raises(F.FFCzError):
+        F.correct(bad, bad.clone(), 1.0, 1.0, 5)
+
+
+def test_deterministic_bitwise():
+    p = W.config_lognormal(32, np.float32)
+    y1, r1 = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter)
+    y2, r2 = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter)
+    assert np.array_equal(y1.view(np.uint32), y2.view(np.uint32))
+    assert r1.stats == r2.stats
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_fixed_rounds_masks_match_oracle(dt):
+    """Clip keep-masks equal the oracle's; in FP32 a bit may differ only where the
+    oracle's pre-clip value lies within FP32 noise (1e-5 relative) of its bound."""
+    p = _problem((16, 16, 64), 21, dt, q=85.0, r=5e-2)
+    K = 5
+    y, res = run_gpu(p.x, p.xb, p.E, p.Delta, K, fixed=True, record_masks=True)
+    assert res.stats["rounds"] == K
+    mu = res.stats["margin_used"]
+    orc = O.correct(p.x, p.xb, p.E, p.Delta, K, mu=mu, fixed=True, record_masks=True)
+    assert rel_err(y, orc.y) <= (1e-12 if dt == np.float64 else 1e-5)
+    gm = unpack_masks(res.masks.cpu().numpy(), p.x.shape, K)
+    Ep, Dp = p.E * (1 - mu), p.Delta * (1 - mu)
+    np.testing.assert_array_equal(gm.s[0], orc.masks.s[0])  # guard clip runs in FP64
+    for k in range(1, K + 1):
+        prev = O.correct(p.x, p.xb, p.E, p.Delta, k - 1, mu=mu, fixed=True, verify_output=False).eps
+        d = O.fft(prev)                                   # pre-clip spectrum of block k
+        pre_s = O.ifft(O.project_f(d, Dp)[0], p.x.shape)  # pre-clip spatial error of block k
+        pairs = ((gm.s[k], orc.masks.s[k], pre_s, Ep), (gm.f_re[k], orc.masks.f_re[k], d.real, Dp),
+                 (gm.f_im[k], orc.masks.f_im[k], d.imag, Dp))
+        for a, b, pre, thr in pairs:
+            bad = a != b
+            if dt == np.float64:
+                assert not bad.any(), (k, int(bad.sum()))
+            else:
+                gap = np.abs(np.abs(pre[bad]) - thr)
+                assert np.all(gap <= 1e-5 * thr), (k, int(bad.sum()), float(gap.max(initial=0)) / thr)
+
+
+@pytest.mark.parametrize("dt,shape", [(np.float64, (16, 16, 64)), (np.float32, (16, 16, 64)),
+                                      (np.float64, (32, 128)), (np.float32, (8, 32, 32))])
+def test_backward_matches_oracle_adjoint(dt, shape):
+    import torch
+    p = _problem(shape, 31, dt, q=85.0, r=5e-2)
+    K = 4
+    y, res = run_gpu(p.x, p.xb, p.E, p.Delta, K, fixed=True, record_masks=True)
+    g = np.random.default_rng(32).standard_normal(shape).astype(dt)
+    gb = F.correct_backward(torch.from_numpy(g).cuda(), res.masks, K).cpu().numpy()
+    gm = unpack_masks(res.masks.cpu().numpy(), shape, K)
+    ref = O.adjoint(gm, g.astype(np.float64))          # oracle fed the GPU's own masks
+    tol = 1e-12 if dt == np.float64 else 1e-5
+    assert rel_err(gb, ref) <= tol
+    orc = O.correct(p.x, p.xb, p.E, p.Delta, K, mu=res.stats["margin_used"], fixed=True, record_masks=True)
+    ref2 = O.adjoint(orc.masks, g.astype(np.float64))  # oracle's own trajectory
+    rel_l2 = np.linalg.norm(gb - ref2) / np.linalg.norm(ref2)
+    assert rel_l2 <= (1e-12 if dt == np.float64 else 1e-4)
+
+
+def test_backward_dot_product_identity():
+    # <J u, v> = <u, J^T v> with the recorded masks: J u from the oracle's JVP, J^T v from the GPU
+    import torch
+    p = _problem((16, 32, 32), 41, np.float64, q=85.0, r=5e-2)
+    K = 3
+    _, res = run_gpu(p.x, p.xb, p.E, p.Delta, K, fixed=True, record_masks=True)
+    gm = unpack_masks(res.masks.cpu().numpy(), p.x.shape, K)
+    g = np.random.default_rng(1)
+    u = g.standard_normal(p.x.shape)
+    v = g.standard_normal(p.x.shape)
+    jtv = F.correct_backward(torch.from_numpy(v).cuda(), res.masks, K).cpu().numpy()
+    lhs = np.sum(O.forward_fixed_masks(gm, u) * v)
+    rhs = np.sum(u * jtv)
+    assert abs(lhs - rhs) <= 1e-10 * (abs(lhs) + 1.0)
+
+
+def test_autograd_function_gradient():
+    import torch
+    p = _problem((8, 16, 32), 51, np.float32, q=85.0, r=5e-2)
+    x = torch.from_numpy(p.x).cuda()
+    xb = torch.from_numpy(p.xb).cuda().requires_grad_(True)
+    w = torch.from_numpy(np.random.default_rng(52).standard_normal(p.x.shape).astype(np.float32)).cuda()
+    y = F.FFCzCorrect.apply(xb, x, p.E, p.Delta, 3)
+    (y * w).sum().backward()
+    r = F.correct(x, xb.detach(), p.E, p.Delta, 3, fixed=True, verify=False, record_masks=True)
+    ref = F.correct_backward(w, r.masks, 3)
+    assert torch.equal(xb.grad, ref)
