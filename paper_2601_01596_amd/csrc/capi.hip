@@ -134,8 +134,10 @@ struct Plan {
   // twiddle tables (complex entries): working type and double
   int64_t twz = 0, twy = 0, twx = 0, twT = 0;
   int64_t tw64z = 0, tw64y = 0, tw64x = 0, tw64 = 0;
+  // blocks of each pass (one partial slot per block)
+  int64_t nbz = 0, nbx = 0, nbvx = 0, pmax = 0;
   // workspace byte offsets
-  size_t off_state = 0, off_viol = 0, off_twT = 0, off_tw64 = 0, off_Z = 0, off_A = 0, bytes = 0;
+  size_t off_state = 0, off_viol = 0, off_part = 0, off_twT = 0, off_tw64 = 0, off_Z = 0, off_A = 0, bytes = 0;
   int32_t max_iter = 0;
   // masks
   int64_t s_row_w32 = 0, s_plane_bytes = 0, f_row_bytes = 0, f_plane_bytes = 0;
@@ -198,11 +200,22 @@ int32_t make_plan(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max
   p.tw64x = p.twx;
   p.tw64 = p.twT;
   const size_t cs = dtype == FFCZ_F32 ? 8 : 16;
+  {
+    const int64_t outer_x = nd == 3 ? p.n[1] : 1;
+    const int Cx = col_block_cols(dtype, p.Lx), Cx64 = col_block_cols(1, p.Lx);
+    p.nbz = (p.nrows + row_block_rows(p.H) - 1) / row_block_rows(p.H);
+    p.nbx = outer_x * ((p.ncols + Cx - 1) / Cx);
+    p.nbvx = outer_x * ((p.ncols + Cx64 - 1) / Cx64);
+    p.pmax = std::max(p.nbz, std::max(p.nbx, p.nbvx));
+  }
   size_t off = 0;
   p.off_state = off;
   off = align_up(off + sizeof(DevState), 256);
   p.off_viol = off;
   off = align_up(off + sizeof(unsigned long long) * ((size_t)max_iter + 2), 256);
+  // partial slots: x-pass counts | z-pass counts | verify-z max | verify-x count, max
+  p.off_part = off;
+  off = align_up(off + sizeof(unsigned long long) * 5 * (size_t)p.pmax, 256);
   p.off_twT = off;
   off = align_up(off + cs * (size_t)p.twT, 256);
   p.off_tw64 = off;
@@ -324,6 +337,89 @@ __global__ void ulp_kernel(const T* x, int64_t n, DevState* st) {
   }
 }
 
+// Per-round control: sum the x-pass partials into v_k, fold the spatial-clip
+// partials of the z-pass that produced the checked iterate into the totals,
+// and decide on the device whether the loop stops (Alg. 1: stop when no
+// coefficient violates; also at the round cap, or on non-finite input).
+__global__ void __launch_bounds__(1024) ctl_kernel(DevState* st, unsigned long long* viol,
+                                                   const unsigned long long* xpart, int64_t nbx,
+                                                   const unsigned long long* zpart, int64_t nbz) {
+  __shared__ unsigned long long rx[16], rz[16];
+  if (*(volatile int32_t*)&st->done) return;
+  const int t = threadIdx.x;
+  unsigned long long sx = 0, sz = 0;
+  for (int64_t i = t; i < nbx; i += blockDim.x) sx += xpart[i];
+  for (int64_t i = t; i < nbz; i += blockDim.x) sz += zpart[i];
+  sx = wave_sum_u64(sx);
+  sz = wave_sum_u64(sz);
+  if ((t & 63) == 0) {
+    rx[t >> 6] = sx;
+    rz[t >> 6] = sz;
+  }
+  __syncthreads();
+  if (t == 0) {
+    unsigned long long vx = 0, vz = 0;
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) {
+      vx += rx[w];
+      vz += rz[w];
+    }
+    const int k = st->round;
+    viol[k] = vx;
+    if (k == 0) st->s_guard = vz;
+    else st->s_clipped_total += vz;
+    int stop = 0;
+    if (st->nonfinite) {
+      stop = 1;
+      st->nonfinite_stop = 1;
+    } else if (!st->fixed && vx == 0) {
+      stop = 1;
+      st->converged = 1;
+    } else if (k >= st->max_iter) {
+      stop = 1;
+      st->converged = (vx == 0) ? 1 : 0;
+    }
+    if (stop) st->done = 1;
+    else st->round = k + 1;
+  }
+}
+
+// Reduce the verification partials: max |y - x|, max(|Re|,|Im|) and the count above Delta.
+__global__ void __launch_bounds__(1024) stats_kernel(DevState* st, const unsigned long long* vz, int64_t nbz,
+                                                     const unsigned long long* vxc, const unsigned long long* vxm,
+                                                     int64_t nbx) {
+  __shared__ unsigned long long ra[16], rb[16], rc[16];
+  const int t = threadIdx.x;
+  unsigned long long a = 0, b = 0, c = 0;  // max bits of non-negative doubles order as integers
+  for (int64_t i = t; i < nbz; i += blockDim.x) a = a > vz[i] ? a : vz[i];
+  for (int64_t i = t; i < nbx; i += blockDim.x) {
+    c += vxc[i];
+    b = b > vxm[i] ? b : vxm[i];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long oa = __shfl_xor(a, off, 64), ob = __shfl_xor(b, off, 64);
+    a = a > oa ? a : oa;
+    b = b > ob ? b : ob;
+    c += __shfl_xor(c, off, 64);
+  }
+  if ((t & 63) == 0) {
+    ra[t >> 6] = a;
+    rb[t >> 6] = b;
+    rc[t >> 6] = c;
+  }
+  __syncthreads();
+  if (t == 0) {
+    unsigned long long A = 0, B = 0, Cc = 0;
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) {
+      A = A > ra[w] ? A : ra[w];
+      B = B > rb[w] ? B : rb[w];
+      Cc += rc[w];
+    }
+    st->max_spatial_bits = A;
+    st->max_spectral_bits = B;
+    st->spectral_viol = Cc;
+  }
+}
+
 // ---------------------------------------------------------------------------
 
 struct Ctx {
@@ -335,7 +431,16 @@ struct Ctx {
   void* tw64() const { return ws + p->off_tw64; }
   void* Z() const { return ws + p->off_Z; }
   void* A() const { return ws + p->off_A; }
+  unsigned long long* part(int i) const { return (unsigned long long*)(ws + p->off_part) + (size_t)i * p->pmax; }
+  // region indices
+  static constexpr int PX = 0, PZ = 1, PVZ = 2, PVX = 3;  // PVX spans two regions (count, max)
 };
+
+hipError_t launch_ctl(const Ctx& c, unsigned long long* viol) {
+  hipLaunchKernelGGL(ctl_kernel, dim3(1), dim3(1024), 0, c.s, c.st(), viol, c.part(Ctx::PX), c.p->nbx,
+                     c.part(Ctx::PZ), c.p->nbz);
+  return hipGetLastError();
+}
 
 hipError_t write_twiddles(const Ctx& c) {
   const Plan& p = *c.p;
@@ -376,7 +481,7 @@ ColGeom geom_x(const Plan& p, int64_t pitch) {
 
 template <typename T>
 hipError_t run_col(int dt, int mode, const ColGeom& g, const Plan& p, const void* src, void* dst,
-                   const void* tw, DevState* st, unsigned long long* viol, uint8_t* fmask,
+                   const void* tw, DevState* st, unsigned long long* part, uint8_t* fmask,
                    hipStream_t s) {
   ColArgs<T> a;
   memset(&a, 0, sizeof(a));
@@ -389,7 +494,8 @@ hipError_t run_col(int dt, int mode, const ColGeom& g, const Plan& p, const void
   a.ncb = (int32_t)((p.ncols + C - 1) / C);
   a.tw = (const cx<T>*)tw;
   a.st = st;
-  a.viol = viol;
+  a.part = part;
+  a.part_stride = p.pmax;
   a.fmask = fmask;
   a.f_plane = p.f_plane_bytes;
   a.f_row_bytes = p.f_row_bytes;
@@ -402,7 +508,7 @@ hipError_t run_col(int dt, int mode, const ColGeom& g, const Plan& p, const void
 template <typename T, typename TIO>
 hipError_t run_row(int tdt, int iodt, int mode, const Plan& p, int64_t pitch, const void* src, void* dst,
                    const void* x, const void* xb, void* y, const void* tw, DevState* st,
-                   uint32_t* smask, hipStream_t s) {
+                   unsigned long long* part, uint32_t* smask, hipStream_t s) {
   RowArgs<T, TIO> a;
   memset(&a, 0, sizeof(a));
   a.src = (const cx<T>*)src;
@@ -414,6 +520,7 @@ hipError_t run_row(int tdt, int iodt, int mode, const Plan& p, int64_t pitch, co
   a.y = (TIO*)y;
   a.tw = (const cx<T>*)tw;
   a.st = st;
+  a.part = part;
   a.smask = smask;
   a.s_plane = p.s_plane_bytes / 4;
   a.s_row_w32 = (int32_t)p.s_row_w32;
@@ -428,11 +535,12 @@ hipError_t row_T(int mode, const Ctx& c, const void* src, void* dst, const void*
                  uint32_t* smask) {
   const Plan& p = *c.p;
   const void* tw = (const char*)c.twT() + sizeof(cx<T>) * p.twz;
-  return run_row<T, T>(p.dt, p.dt, mode, p, p.pitch, src, dst, x, xb, y, tw, c.st(), smask, c.s);
+  return run_row<T, T>(p.dt, p.dt, mode, p, p.pitch, src, dst, x, xb, y, tw, c.st(), c.part(Ctx::PZ), smask, c.s);
 }
 
 template <typename T>
 hipError_t enqueue_round(const Ctx& c, int r, unsigned long long* viol, uint8_t* fmask, uint32_t* smask) {
+  unsigned long long* px = c.part(Ctx::PX);
   const Plan& p = *c.p;
   const char* twb = (const char*)c.twT();
   const void* twy = twb + sizeof(cx<T>) * p.twy;
@@ -440,21 +548,25 @@ hipError_t enqueue_round(const Ctx& c, int r, unsigned long long* viol, uint8_t*
   hipError_t e;
   if (p.nd == 3) {
     e = timed(PK_YFWD, r, c.s, [&] {
-      return run_col<T>(p.dt, COL_FWD, geom_y(p, p.pitch), p, c.Z(), c.A(), twy, c.st(), viol, fmask, c.s);
+      return run_col<T>(p.dt, COL_FWD, geom_y(p, p.pitch), p, c.Z(), c.A(), twy, c.st(), px, fmask, c.s);
     });
     if (e != hipSuccess) return e;
     e = timed(PK_XPASS, r, c.s, [&] {
-      return run_col<T>(p.dt, COL_XPASS, geom_x(p, p.pitch), p, c.A(), c.A(), twx, c.st(), viol, fmask, c.s);
+      return run_col<T>(p.dt, COL_XPASS, geom_x(p, p.pitch), p, c.A(), c.A(), twx, c.st(), px, fmask, c.s);
     });
     if (e != hipSuccess) return e;
+    e = launch_ctl(c, viol);
+    if (e != hipSuccess) return e;
     e = timed(PK_YINV, r, c.s, [&] {
-      return run_col<T>(p.dt, COL_INV, geom_y(p, p.pitch), p, c.A(), c.A(), twy, c.st(), viol, fmask, c.s);
+      return run_col<T>(p.dt, COL_INV, geom_y(p, p.pitch), p, c.A(), c.A(), twy, c.st(), px, fmask, c.s);
     });
     if (e != hipSuccess) return e;
   } else {
     e = timed(PK_XPASS, r, c.s, [&] {
-      return run_col<T>(p.dt, COL_XPASS, geom_x(p, p.pitch), p, c.Z(), c.A(), twx, c.st(), viol, fmask, c.s);
+      return run_col<T>(p.dt, COL_XPASS, geom_x(p, p.pitch), p, c.Z(), c.A(), twx, c.st(), px, fmask, c.s);
     });
+    if (e != hipSuccess) return e;
+    e = launch_ctl(c, viol);
     if (e != hipSuccess) return e;
   }
   return timed(PK_ZPASS, r, c.s, [&] { return row_T<T>(ROW_LOOP, c, c.A(), c.Z(), nullptr, nullptr, nullptr, smask); });
@@ -467,20 +579,24 @@ hipError_t enqueue_verify(const Ctx& c, const void* x, const void* y) {
   void* W = c.Z();  // FP64 spectrum over Z..A
   hipError_t e = timed(PK_VZ, -1, c.s, [&] {
     return run_row<double, T>(1, p.dt, ROW_VERIFY, p, p.pitch64, nullptr, W, x, y, nullptr, tb + 16 * p.tw64z,
-                              c.st(), nullptr, c.s);
+                              c.st(), c.part(Ctx::PVZ), nullptr, c.s);
   });
   if (e != hipSuccess) return e;
   if (p.nd == 3) {
     e = timed(PK_VY, -1, c.s, [&] {
-      return run_col<double>(1, COL_FWD_NS, geom_y(p, p.pitch64), p, W, W, tb + 16 * p.tw64y, c.st(), nullptr,
-                             nullptr, c.s);
+      return run_col<double>(1, COL_FWD_NS, geom_y(p, p.pitch64), p, W, W, tb + 16 * p.tw64y, c.st(),
+                             c.part(Ctx::PVX), nullptr, c.s);
     });
     if (e != hipSuccess) return e;
   }
-  return timed(PK_VX, -1, c.s, [&] {
-    return run_col<double>(1, COL_VERIFY, geom_x(p, p.pitch64), p, W, W, tb + 16 * p.tw64x, c.st(), nullptr,
-                           nullptr, c.s);
+  e = timed(PK_VX, -1, c.s, [&] {
+    return run_col<double>(1, COL_VERIFY, geom_x(p, p.pitch64), p, W, W, tb + 16 * p.tw64x, c.st(),
+                           c.part(Ctx::PVX), nullptr, c.s);
   });
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(1024), 0, c.s, c.st(), c.part(Ctx::PVZ), p.nbz, c.part(Ctx::PVX),
+                     c.part(Ctx::PVX + 1), p.nbvx);
+  return hipGetLastError();
 }
 
 // pinned host mirror of the device state (one per thread)

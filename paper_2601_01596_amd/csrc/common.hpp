@@ -9,7 +9,7 @@
 namespace ffcz {
 
 // Loop state kept in the caller's workspace.  Written by one lane at a time
-// (the set-up kernel, or the last block of the x-pass); read at the entry of
+// (the set-up kernel or the per-round control kernel); read at the entry of
 // every loop kernel.
 struct DevState {
   // parameters
@@ -56,7 +56,8 @@ struct ColArgs {
   int32_t ncb;     // column blocks per outer index
   const cx<T>* tw; // stage twiddles of this length
   DevState* st;
-  unsigned long long* viol;  // per-check violation counts
+  unsigned long long* part;  // one partial result per block (count; verification: + max at part_stride)
+  int64_t part_stride;
   // f-masks (forward record / adjoint read)
   uint8_t* fmask;      // forward: base of the f-mask region; adjoint: Re plane of block k
   int64_t f_plane;     // bytes per Re (or Im) plane
@@ -76,6 +77,7 @@ struct RowArgs {
   TIO* y;          // output (ROW_FINAL), dL/dx_hat (ROW_BFINAL)
   const cx<T>* tw; // stage twiddles of length H followed by H R2C twiddles
   DevState* st;
+  unsigned long long* part;  // one partial result per block (clip count or max bits)
   uint32_t* smask;   // forward: base of the s-mask region; adjoint: s-mask plane to apply
   int64_t s_plane;   // uint32 words per s-mask plane
   int32_t s_row_w32; // uint32 words per s-mask row

@@ -23,6 +23,7 @@ col_kernel(ColArgs<T> a) {
 
   DevState* st = a.st;
   constexpr bool uses_done = (MODE == COL_FWD || MODE == COL_INV || MODE == COL_XPASS);
+  (void)red_d;
   if (uses_done) {
     if (*(volatile int32_t*)&st->done) return;
   }
@@ -86,36 +87,14 @@ col_kernel(ColArgs<T> a) {
       }
     }
     fft<T, L, E, true, C, 1>(v, lds, tws, c, j);
-    // violations of this check: one atomic per block
+    // violations of this check: one partial per block, summed by the control kernel
     cnt = wave_sum_u64(cnt);
     if ((t & 63) == 0) red_u[t >> 6] = cnt;
     __syncthreads();
     if (t == 0) {
       unsigned long long s = 0;
       for (int w = 0; w < NW; ++w) s += red_u[w];
-      if (s) atomicAdd(&a.viol[k], s);
-      __threadfence();
-      const unsigned int tk = atomicAdd(&st->ticket, 1u);
-      if (tk == gridDim.x - 1) {
-        // last block of this check: every count is in
-        __threadfence();
-        const unsigned long long vk = atomicAdd(&a.viol[k], 0ull);
-        int stop = 0;
-        if (st->nonfinite) {
-          stop = 1;
-          st->nonfinite_stop = 1;
-        } else if (!st->fixed && vk == 0) {
-          stop = 1;
-          st->converged = 1;
-        } else if (k >= st->max_iter) {
-          stop = 1;
-          st->converged = (vk == 0) ? 1 : 0;
-        }
-        if (stop) st->done = 1;
-        else st->round = k + 1;
-        st->ticket = 0u;
-        __threadfence();
-      }
+      a.part[bid] = s;
     }
   } else if constexpr (MODE == COL_XBACK) {
     fft<T, L, E, false, C, 1>(v, lds, tws, c, j);
@@ -159,8 +138,8 @@ col_kernel(ColArgs<T> a) {
         s += red_u[w];
         m = fmax(m, red_d[w]);
       }
-      if (s) atomicAdd(&st->spectral_viol, s);
-      atomicMax(&st->max_spectral_bits, (unsigned long long)__double_as_longlong(m));
+      a.part[bid] = s;
+      a.part[a.part_stride + bid] = (unsigned long long)__double_as_longlong(m);
     }
     return;
   }

@@ -258,13 +258,9 @@ row_kernel(RowArgs<T, TIO> a) {
         s += red_u[w];
         m = fmax(m, red_d[w]);
       }
-      if constexpr (MODE == ROW_INIT) {
-        if (s) atomicAdd(&st->s_guard, s);
-      } else if constexpr (MODE == ROW_LOOP) {
-        if (s) atomicAdd(&st->s_clipped_total, s);
-      } else {
-        atomicMax(&st->max_spatial_bits, (unsigned long long)__double_as_longlong(m));
-      }
+      // one partial per block, reduced by the control / statistics kernels
+      if constexpr (MODE == ROW_VERIFY) a.part[blockIdx.x] = (unsigned long long)__double_as_longlong(m);
+      else a.part[blockIdx.x] = s;
     }
     if constexpr (rec_s) {
       if (rec) {
