@@ -140,6 +140,35 @@ int32_t ffcz_correct(int32_t dtype, int32_t ndim, const int64_t* shape, const vo
                      int32_t max_iter, const ffcz_options* opts, void* workspace,
                      size_t workspace_bytes, void* stream, ffcz_stats* stats);
 
+/* One member of a batch: shape (ndim 1..3, unit extents squeezed), device
+ * pointers as in ffcz_correct, and its own bounds. */
+typedef struct {
+  int32_t ndim;
+  int32_t pad;
+  int64_t shape[3];
+  const void* x_orig;
+  const void* x_base;
+  void* x_out;
+  double eps_s;
+  double delta_f;
+} ffcz_instance;
+
+/* Workspace bytes for ffcz_correct_batched over these instances (0 if one is unsupported). */
+size_t ffcz_batched_workspace_bytes(int32_t dtype, int32_t count, const ffcz_instance* inst, int32_t max_iter);
+
+/* Alg. 1 on many fields of uneven size in one call (the paper treats 1D, 2D
+ * and 3D data alike, Sec. IV-C).  Members of the same 2D shape share every
+ * launch (their spectra are stacked; each keeps its own bounds, counts and
+ * done-flag); 1D members of any length 2..2^19 run one block per signal, the
+ * whole loop inside one launch, with a length-L DFT by four-step FFTs and, for
+ * lengths that are not powers of two, Bluestein's chirp-z convolution; 3D
+ * members run one after another.  Options as in ffcz_correct except that masks
+ * and per-round counts are not recorded.  stats: NULL or a host array[count].
+ * Returns the worst member status (negative if any member failed). */
+int32_t ffcz_correct_batched(int32_t dtype, int32_t count, const ffcz_instance* inst, int32_t max_iter,
+                             const ffcz_options* opts, void* workspace, size_t workspace_bytes, void* stream,
+                             ffcz_stats* stats);
+
 /* Vector-Jacobian product of the fixed-round map x_hat -> y (fixed_iterations
  * = 1, `rounds` blocks) recorded by ffcz_correct into `masks`.  With the clips
  * frozen, block k is eps -> M_s^k (F^-1 M_f^k F eps); F^-1 M_f^k F is

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libffcz.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["capi.hip", "launch_col_f32.hip", "launch_col_f64.hip", "launch_row_f32.hip", "launch_row_f64.hip"]
+SOURCES = ["capi.hip", "launch_col_f32.hip", "launch_col_f64.hip", "launch_row_f32.hip", "launch_row_f64.hip",
+           "launch_sig_f32.hip", "launch_sig_f64.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -4,27 +4,31 @@
 // half-spectrum rows of H+1 = n2/2+1 entries:
 //   y-fwd   Z -> A   C2C along axis 1
 //   x-pass  A -> A   C2C along axis 0, count violations, clip Re/Im, inverse C2C
+//   ctl     one block per instance: sum the counts, decide on the device
 //   y-inv   A -> A   inverse C2C along axis 1
 //   z-pass  A -> Z   C2R along axis 2, 1/N, clip eps, R2C
-// (2D: x-pass Z -> A and z-pass A -> Z; 1D: the x-pass has length 1.)
-// Z therefore always holds the spectrum of the last iterate eps_k while the
-// check of round k runs, so when that check passes the output is the C2R of Z.
-// The last block of every x-pass decides, on the device, whether the loop
-// stops; every loop kernel returns at entry once the done-flag is set, so the
-// host enqueues rounds in chunks and polls the flag once per chunk.
+// (2D: x-pass Z -> A, ctl, z-pass A -> Z; 1D fields: the x-pass has length 1.)
+// Z therefore always holds the last-axis R2C of the iterate whose check is
+// running, so when that check passes the output is the C2R of Z.  Every loop
+// kernel returns at entry once its instance's done-flag is set, so the host
+// enqueues rounds in chunks and polls the flags once per chunk.
+//
+// A plan covers B instances of one shape (B = 1 for ffcz_correct): their
+// spectra are stacked, so one launch of each pass serves all of them, while
+// every instance keeps its own bounds, counts and done-flag.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <mutex>
+#include <map>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
 #include "../../include/ffcz.h"
 #include "common.hpp"
+#include "kernels_sig.hpp"
 #include "launch.hpp"
 
 namespace ffcz {
@@ -33,9 +37,27 @@ hipError_t launch_col_f64(int mode, int L, const void* args, int64_t nb, hipStre
 hipError_t launch_row_f32(int mode, int H, const void* args, int64_t nb, hipStream_t s);
 hipError_t launch_row_f64(int mode, int H, const void* args, int64_t nb, hipStream_t s);
 hipError_t launch_row_verify_f32io(int H, const void* args, int64_t nb, hipStream_t s);
+hipError_t launch_sig_f32(int mode, int lgMc, const void* args, int nb, hipStream_t s);
+hipError_t launch_sig_f64(int mode, int lgMc, const void* args, int nb, hipStream_t s);
+
+// tdt: compute type; iodt: data type of the batch
+hipError_t launch_sig(int tdt, int iodt, int mode, int lgMc, const void* args, int nblocks, hipStream_t s) {
+  if (iodt == 0 && (mode == SIG_RUN || mode == SIG_VERIFY)) return launch_sig_f32(mode, lgMc, args, nblocks, s);
+  (void)tdt;
+  return launch_sig_f64(mode, lgMc, args, nblocks, s);
+}
+
+// Rows per row tile of the per-signal kernel (mirror of SigGeom).
+int sig_rows_per_tile(int tdt, int lgMc) {
+  const int MA = 1 << ((lgMc + 1) / 2), MB = (1 << lgMc) / MA;
+  const int PA = MA / pick_E(MA), PB = MB / pick_E(MB);
+  const int NT = imin3(512, MA * PB, MB * PA);
+  (void)tdt;
+  return NT / PA;
+}
 
 int col_block_cols(int dtype, int L) { return dtype == 0 ? pick_C<float>(L) : pick_C<double>(L); }
-int row_block_rows(int H) { return pick_rows(H); }
+int row_block_rows(int dtype, int H) { return dtype == 0 ? pick_rows<float>(H) : pick_rows<double>(H); }
 
 hipError_t launch_col(int dtype, int mode, int L, const void* args, int64_t nb, hipStream_t s) {
   return dtype == 0 ? launch_col_f32(mode, L, args, nb, s) : launch_col_f64(mode, L, args, nb, s);
@@ -119,46 +141,57 @@ bool is_pow2(int64_t v) { return v >= 1 && (v & (v - 1)) == 0; }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// squeeze unit extents
+int squeeze(int32_t ndim, const int64_t* shape, int64_t* sq) {
+  int nd = 0;
+  for (int i = 0; i < ndim; ++i)
+    if (shape[i] > 1) sq[nd++] = shape[i];
+  return nd;
+}
+
 struct Plan {
   int dt = 0;        // 0 f32, 1 f64
   int nd = 0;        // squeezed ndim
+  int64_t B = 1;     // instances of this shape
   int64_t n[3] = {1, 1, 1};
-  int64_t N = 1;
+  int64_t N = 1;     // points per instance
   int H = 0;         // n_last / 2
   int64_t ncols = 0; // H + 1
   int64_t pitch = 0; // complex entries per spectrum row (working type)
   int64_t pitch64 = 0;
-  int64_t nrows = 0; // N / n_last
+  int64_t nrows = 0; // spectrum rows per instance
   int Lx = 1, Ly = 0;
   int Ez = 1, Ey = 1, Ex = 1;
-  // twiddle tables (complex entries): working type and double
   int64_t twz = 0, twy = 0, twx = 0, twT = 0;
-  int64_t tw64z = 0, tw64y = 0, tw64x = 0, tw64 = 0;
-  // blocks of each pass (one partial slot per block)
-  int64_t nbz = 0, nbx = 0, nbvx = 0, pmax = 0;
-  // workspace byte offsets
-  size_t off_state = 0, off_viol = 0, off_part = 0, off_twT = 0, off_tw64 = 0, off_Z = 0, off_A = 0, bytes = 0;
+  // blocks of each pass per instance (one partial slot per block)
+  int64_t zbpi = 0, vzbpi = 0, xbpi = 0, vxbpi = 0;
+  int64_t pmax = 0;
+  size_t off_state = 0, off_viol = 0, off_init = 0, off_part = 0, off_twT = 0, off_tw64 = 0, off_Z = 0,
+         off_A = 0, bytes = 0;
   int32_t max_iter = 0;
-  // masks
   int64_t s_row_w32 = 0, s_plane_bytes = 0, f_row_bytes = 0, f_plane_bytes = 0;
 };
 
-int pick_E_host(int L) { return pick_E(L); }
+struct StateInit {
+  double E, Ep, Delta, Dp, inv_n;
+  int32_t max_iter, fixed, record_masks, pad;
+  const void* px;
+  const void* pxb;
+  void* py;
+};
 
-// Squeeze unit extents and check the supported shape set.
-int32_t make_plan(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max_iter, Plan& p) {
+int32_t make_plan(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max_iter, int64_t B, Plan& p) {
   if (dtype != FFCZ_F32 && dtype != FFCZ_F64) return fail(FFCZ_E_INVALID, "dtype must be FFCZ_F32 or FFCZ_F64");
   if (ndim < 1 || ndim > 3 || shape == nullptr) return fail(FFCZ_E_SHAPE, "ndim must be 1..3");
   if (max_iter < 0) return fail(FFCZ_E_INVALID, "max_iter must be >= 0");
   p = Plan();
   p.dt = dtype;
   p.max_iter = max_iter;
-  int64_t sq[3];
-  int nd = 0;
-  for (int i = 0; i < ndim; ++i) {
+  p.B = B;
+  for (int i = 0; i < ndim; ++i)
     if (shape[i] < 1) return fail(FFCZ_E_SHAPE, "every extent must be >= 1");
-    if (shape[i] > 1) sq[nd++] = shape[i];
-  }
+  int64_t sq[3];
+  const int nd = squeeze(ndim, shape, sq);
   if (nd == 0) return fail(FFCZ_E_SHAPE, "a single-point field is not supported (last extent must be >= 2)");
   const int64_t maxo = dtype == FFCZ_F32 ? 2048 : 1024;
   for (int i = 0; i < nd; ++i) {
@@ -167,6 +200,7 @@ int32_t make_plan(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max
   }
   const int64_t nl = sq[nd - 1];
   if (nl < 2 || nl > kMaxLast) return fail(FFCZ_E_SHAPE, "last extent must be in [2, 4096]");
+  if (nd == 3 && B != 1) return fail(FFCZ_E_SHAPE, "3D instances are corrected one at a time");
   p.nd = nd;
   for (int i = 0; i < nd; ++i) p.n[i] = sq[i];
   p.N = 1;
@@ -177,59 +211,49 @@ int32_t make_plan(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max
   p.pitch = align_up(p.ncols, cT);
   p.pitch64 = align_up(p.ncols, 8);
   p.nrows = p.N / nl;
-  if (nd == 1) {
-    p.Lx = 1;
-    p.Ly = 0;
-  } else if (nd == 2) {
-    p.Lx = (int)sq[0];
-    p.Ly = 0;
-  } else {
-    p.Lx = (int)sq[0];
-    p.Ly = (int)sq[1];
-  }
-  p.Ez = pick_E_host(p.H);
-  p.Ex = pick_E_host(p.Lx);
-  p.Ey = p.Ly ? pick_E_host(p.Ly) : 1;
-  // twiddle layout: z (stages + H R2C twiddles), y stages, x stages
+  p.Lx = nd >= 2 ? (int)sq[0] : 1;
+  p.Ly = nd == 3 ? (int)sq[1] : 0;
+  p.Ez = pick_E_row(p.H);
+  p.Ex = pick_E(p.Lx);
+  p.Ey = p.Ly ? pick_E(p.Ly) : 1;
   p.twz = 0;
   p.twy = p.twz + host_twsize(p.H, p.Ez) + p.H;
   p.twx = p.twy + (p.Ly ? host_twsize(p.Ly, p.Ey) : 0);
   p.twT = p.twx + host_twsize(p.Lx, p.Ex) + 1;
-  p.tw64z = p.twz;
-  p.tw64y = p.twy;
-  p.tw64x = p.twx;
-  p.tw64 = p.twT;
   const size_t cs = dtype == FFCZ_F32 ? 8 : 16;
   {
     const int64_t outer_x = nd == 3 ? p.n[1] : 1;
     const int Cx = col_block_cols(dtype, p.Lx), Cx64 = col_block_cols(1, p.Lx);
-    p.nbz = (p.nrows + row_block_rows(p.H) - 1) / row_block_rows(p.H);
-    p.nbx = outer_x * ((p.ncols + Cx - 1) / Cx);
-    p.nbvx = outer_x * ((p.ncols + Cx64 - 1) / Cx64);
-    p.pmax = std::max(p.nbz, std::max(p.nbx, p.nbvx));
+    const int Rz = row_block_rows(dtype, p.H), Rz64 = row_block_rows(1, p.H);
+    p.zbpi = (p.nrows + Rz - 1) / Rz;
+    p.vzbpi = (p.nrows + Rz64 - 1) / Rz64;
+    p.xbpi = outer_x * ((p.ncols + Cx - 1) / Cx);
+    p.vxbpi = outer_x * ((p.ncols + Cx64 - 1) / Cx64);
+    p.pmax = B * std::max(std::max(p.zbpi, p.vzbpi), std::max(p.xbpi, p.vxbpi));
   }
   size_t off = 0;
   p.off_state = off;
-  off = align_up(off + sizeof(DevState), 256);
+  off = align_up(off + sizeof(DevState) * (size_t)B, 256);
   p.off_viol = off;
-  off = align_up(off + sizeof(unsigned long long) * ((size_t)max_iter + 2), 256);
+  off = align_up(off + sizeof(unsigned long long) * ((size_t)max_iter + 2) * (size_t)B, 256);
+  p.off_init = off;
+  off = align_up(off + (B > 1 ? sizeof(StateInit) * (size_t)B : 0), 256);
   // partial slots: x-pass counts | z-pass counts | verify-z max | verify-x count, max
   p.off_part = off;
   off = align_up(off + sizeof(unsigned long long) * 5 * (size_t)p.pmax, 256);
   p.off_twT = off;
   off = align_up(off + cs * (size_t)p.twT, 256);
   p.off_tw64 = off;
-  off = align_up(off + 16 * (size_t)p.tw64, 256);
+  off = align_up(off + 16 * (size_t)p.twT, 256);
   p.off_Z = off;
-  const size_t spec = cs * (size_t)p.nrows * (size_t)p.pitch;
+  const size_t spec = cs * (size_t)B * (size_t)p.nrows * (size_t)p.pitch;
   off = align_up(off + spec, 256);
   p.off_A = off;
   off = align_up(off + spec, 256);
   // the FP64 verification reuses Z..A (contiguous) as an FP64 spectrum
-  const size_t spec64 = 16 * (size_t)p.nrows * (size_t)p.pitch64;
+  const size_t spec64 = 16 * (size_t)B * (size_t)p.nrows * (size_t)p.pitch64;
   if (p.off_Z + spec64 > off) off = align_up(p.off_Z + spec64, 256);
   p.bytes = off;
-  // masks
   const int64_t sw64 = (nl + 63) / 64;
   const int64_t fw64 = (p.ncols + 63) / 64;
   p.s_row_w32 = 2 * sw64;
@@ -240,7 +264,7 @@ int32_t make_plan(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max
 }
 
 // ---------------------------------------------------------------------------
-// set-up kernels
+// set-up, control and statistics kernels
 
 struct TwJob {
   int64_t off;  // complex entries from the table base
@@ -252,6 +276,8 @@ struct TwJobs {
   int dbl;  // 1: double table
 };
 
+// Stage twiddles exp(-2 pi i m r / (Ns R)) and R2C twiddles exp(-2 pi i k / 2L),
+// evaluated in FP64 with an exactly reduced argument and rounded once.
 __global__ void twiddle_kernel(void* base, TwJobs jobs) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t acc = 0;
@@ -295,14 +321,11 @@ __global__ void twiddle_kernel(void* base, TwJobs jobs) {
   }
 }
 
-struct StateInit {
-  double E, Ep, Delta, Dp, inv_n;
-  int32_t max_iter, fixed, record_masks;
-};
-
-__global__ void state_init_kernel(DevState* st, unsigned long long* viol, int32_t nviol, StateInit p) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0) {
+__global__ void state_init_kernel(DevState* st, int64_t B, const StateInit* arr, StateInit one,
+                                  unsigned long long* viol, int64_t nviol) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < B) {
+    const StateInit p = arr ? arr[t] : one;
     DevState s;
     memset(&s, 0, sizeof(s));
     s.E = p.E;
@@ -313,9 +336,12 @@ __global__ void state_init_kernel(DevState* st, unsigned long long* viol, int32_
     s.max_iter = p.max_iter;
     s.fixed = p.fixed;
     s.record_masks = p.record_masks;
-    *st = s;
+    s.px = p.px;
+    s.pxb = p.pxb;
+    s.py = p.py;
+    st[t] = s;
   }
-  for (int i = t; i < nviol; i += gridDim.x * blockDim.x) viol[i] = 0ull;
+  for (int64_t i = t; i < nviol; i += (int64_t)gridDim.x * blockDim.x) viol[i] = 0ull;
 }
 
 template <typename T>
@@ -337,19 +363,22 @@ __global__ void ulp_kernel(const T* x, int64_t n, DevState* st) {
   }
 }
 
-// Per-round control: sum the x-pass partials into v_k, fold the spatial-clip
-// partials of the z-pass that produced the checked iterate into the totals,
-// and decide on the device whether the loop stops (Alg. 1: stop when no
-// coefficient violates; also at the round cap, or on non-finite input).
-__global__ void __launch_bounds__(1024) ctl_kernel(DevState* st, unsigned long long* viol,
-                                                   const unsigned long long* xpart, int64_t nbx,
-                                                   const unsigned long long* zpart, int64_t nbz) {
+// Per-round control, one block per instance: sum the x-pass partials into
+// v_k, fold the spatial-clip partials of the z-pass that produced the checked
+// iterate into the totals, and decide on the device whether the loop stops
+// (Alg. 1: stop when no coefficient violates; also at the round cap, or on
+// non-finite input).
+__global__ void __launch_bounds__(1024) ctl_kernel(DevState* st0, unsigned long long* viol0, int64_t vstride,
+                                                   const unsigned long long* xpart, int64_t xbpi,
+                                                   const unsigned long long* zpart, int64_t zbpi) {
   __shared__ unsigned long long rx[16], rz[16];
+  const int64_t b = blockIdx.x;
+  DevState* st = st0 + b;
   if (*(volatile int32_t*)&st->done) return;
   const int t = threadIdx.x;
   unsigned long long sx = 0, sz = 0;
-  for (int64_t i = t; i < nbx; i += blockDim.x) sx += xpart[i];
-  for (int64_t i = t; i < nbz; i += blockDim.x) sz += zpart[i];
+  for (int64_t i = t; i < xbpi; i += blockDim.x) sx += xpart[b * xbpi + i];
+  for (int64_t i = t; i < zbpi; i += blockDim.x) sz += zpart[b * zbpi + i];
   sx = wave_sum_u64(sx);
   sz = wave_sum_u64(sz);
   if ((t & 63) == 0) {
@@ -364,7 +393,7 @@ __global__ void __launch_bounds__(1024) ctl_kernel(DevState* st, unsigned long l
       vz += rz[w];
     }
     const int k = st->round;
-    viol[k] = vx;
+    viol0[b * vstride + k] = vx;
     if (k == 0) st->s_guard = vz;
     else st->s_clipped_total += vz;
     int stop = 0;
@@ -383,17 +412,19 @@ __global__ void __launch_bounds__(1024) ctl_kernel(DevState* st, unsigned long l
   }
 }
 
-// Reduce the verification partials: max |y - x|, max(|Re|,|Im|) and the count above Delta.
-__global__ void __launch_bounds__(1024) stats_kernel(DevState* st, const unsigned long long* vz, int64_t nbz,
+// Reduce the verification partials of each instance: max |y - x|,
+// max(|Re|,|Im|) and the count above Delta.
+__global__ void __launch_bounds__(1024) stats_kernel(DevState* st0, const unsigned long long* vz, int64_t vzbpi,
                                                      const unsigned long long* vxc, const unsigned long long* vxm,
-                                                     int64_t nbx) {
+                                                     int64_t vxbpi) {
   __shared__ unsigned long long ra[16], rb[16], rc[16];
+  const int64_t inst = blockIdx.x;
   const int t = threadIdx.x;
   unsigned long long a = 0, b = 0, c = 0;  // max bits of non-negative doubles order as integers
-  for (int64_t i = t; i < nbz; i += blockDim.x) a = a > vz[i] ? a : vz[i];
-  for (int64_t i = t; i < nbx; i += blockDim.x) {
-    c += vxc[i];
-    b = b > vxm[i] ? b : vxm[i];
+  for (int64_t i = t; i < vzbpi; i += blockDim.x) a = a > vz[inst * vzbpi + i] ? a : vz[inst * vzbpi + i];
+  for (int64_t i = t; i < vxbpi; i += blockDim.x) {
+    c += vxc[inst * vxbpi + i];
+    b = b > vxm[inst * vxbpi + i] ? b : vxm[inst * vxbpi + i];
   }
   for (int off = 32; off > 0; off >>= 1) {
     const unsigned long long oa = __shfl_xor(a, off, 64), ob = __shfl_xor(b, off, 64);
@@ -408,15 +439,15 @@ __global__ void __launch_bounds__(1024) stats_kernel(DevState* st, const unsigne
   }
   __syncthreads();
   if (t == 0) {
-    unsigned long long A = 0, B = 0, Cc = 0;
+    unsigned long long A = 0, Bm = 0, Cc = 0;
     for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) {
       A = A > ra[w] ? A : ra[w];
-      B = B > rb[w] ? B : rb[w];
+      Bm = Bm > rb[w] ? Bm : rb[w];
       Cc += rc[w];
     }
-    st->max_spatial_bits = A;
-    st->max_spectral_bits = B;
-    st->spectral_viol = Cc;
+    st0[inst].max_spatial_bits = A;
+    st0[inst].max_spectral_bits = Bm;
+    st0[inst].spectral_viol = Cc;
   }
 }
 
@@ -427,18 +458,18 @@ struct Ctx {
   char* ws;
   hipStream_t s;
   DevState* st() const { return (DevState*)(ws + p->off_state); }
+  unsigned long long* viol() const { return (unsigned long long*)(ws + p->off_viol); }
   void* twT() const { return ws + p->off_twT; }
   void* tw64() const { return ws + p->off_tw64; }
   void* Z() const { return ws + p->off_Z; }
   void* A() const { return ws + p->off_A; }
   unsigned long long* part(int i) const { return (unsigned long long*)(ws + p->off_part) + (size_t)i * p->pmax; }
-  // region indices
   static constexpr int PX = 0, PZ = 1, PVZ = 2, PVX = 3;  // PVX spans two regions (count, max)
 };
 
-hipError_t launch_ctl(const Ctx& c, unsigned long long* viol) {
-  hipLaunchKernelGGL(ctl_kernel, dim3(1), dim3(1024), 0, c.s, c.st(), viol, c.part(Ctx::PX), c.p->nbx,
-                     c.part(Ctx::PZ), c.p->nbz);
+hipError_t launch_ctl(const Ctx& c, unsigned long long* viol, int64_t vstride) {
+  hipLaunchKernelGGL(ctl_kernel, dim3((unsigned)c.p->B), dim3(1024), 0, c.s, c.st(), viol, vstride, c.part(Ctx::PX),
+                     c.p->xbpi, c.part(Ctx::PZ), c.p->zbpi);
   return hipGetLastError();
 }
 
@@ -455,8 +486,7 @@ hipError_t write_twiddles(const Ctx& c) {
     if (p.Ly) jobs.j[n++] = TwJob{p.twy, p.Ly, p.Ey, 0};
     jobs.j[n++] = TwJob{p.twx, p.Lx, p.Ex, 0};
     jobs.n = n;
-    const int64_t tot = p.twT;
-    const int nb = (int)((tot + 255) / 256);
+    const int nb = (int)((p.twT + 255) / 256);
     hipLaunchKernelGGL(twiddle_kernel, dim3(nb), dim3(256), 0, c.s, tab ? c.tw64() : c.twT(), jobs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -469,14 +499,16 @@ struct ColGeom {
   int L;
   int64_t outer, so, s;
   int64_t mrow_i, mrow_o;
+  int64_t outer_per_inst;
 };
 
-ColGeom geom_y(const Plan& p, int64_t pitch) {
-  return ColGeom{p.Ly, p.n[0], p.n[1] * pitch, pitch, 0, 0};
+ColGeom geom_y(const Plan& p, int64_t pitch) {  // 3D only (B = 1)
+  return ColGeom{p.Ly, p.n[0], p.n[1] * pitch, pitch, 0, 0, p.n[0]};
 }
 ColGeom geom_x(const Plan& p, int64_t pitch) {
-  if (p.nd == 3) return ColGeom{p.Lx, p.n[1], pitch, p.n[1] * pitch, p.n[1], 1};
-  return ColGeom{p.Lx, 1, 0, pitch, 1, 0};
+  if (p.nd == 3) return ColGeom{p.Lx, p.n[1], pitch, p.n[1] * pitch, p.n[1], 1, p.n[1]};
+  // 2D (and 1D, Lx = 1): one outer index per instance
+  return ColGeom{p.Lx, p.B, p.nrows * pitch, pitch, 1, 0, 1};
 }
 
 template <typename T>
@@ -492,6 +524,7 @@ hipError_t run_col(int dt, int mode, const ColGeom& g, const Plan& p, const void
   a.s = g.s;
   a.ncols = (int32_t)p.ncols;
   a.ncb = (int32_t)((p.ncols + C - 1) / C);
+  a.outer_per_inst = g.outer_per_inst;
   a.tw = (const cx<T>*)tw;
   a.st = st;
   a.part = part;
@@ -507,41 +540,38 @@ hipError_t run_col(int dt, int mode, const ColGeom& g, const Plan& p, const void
 
 template <typename T, typename TIO>
 hipError_t run_row(int tdt, int iodt, int mode, const Plan& p, int64_t pitch, const void* src, void* dst,
-                   const void* x, const void* xb, void* y, const void* tw, DevState* st,
-                   unsigned long long* part, uint32_t* smask, hipStream_t s) {
+                   const void* tw, DevState* st, unsigned long long* part, uint32_t* smask, hipStream_t s) {
   RowArgs<T, TIO> a;
   memset(&a, 0, sizeof(a));
   a.src = (const cx<T>*)src;
   a.dst = (cx<T>*)dst;
   a.pitch = pitch;
-  a.nrows = p.nrows;
-  a.x = (const TIO*)x;
-  a.xb = (const TIO*)xb;
-  a.y = (TIO*)y;
+  a.rows_per_inst = p.nrows;
+  const int R = row_block_rows(tdt, p.H);
+  a.bpi = (p.nrows + R - 1) / R;
   a.tw = (const cx<T>*)tw;
   a.st = st;
   a.part = part;
   a.smask = smask;
   a.s_plane = p.s_plane_bytes / 4;
   a.s_row_w32 = (int32_t)p.s_row_w32;
-  const int R = row_block_rows(p.H);
-  const int64_t nb = (p.nrows + R - 1) / R;
+  const int64_t nb = a.bpi * p.B;
   if (mode == ROW_VERIFY && tdt == 1 && iodt == 0) return launch_row_verify_f32io(p.H, &a, nb, s);
   return tdt == 0 ? launch_row_f32(mode, p.H, &a, nb, s) : launch_row_f64(mode, p.H, &a, nb, s);
 }
 
 template <typename T>
-hipError_t row_T(int mode, const Ctx& c, const void* src, void* dst, const void* x, const void* xb, void* y,
-                 uint32_t* smask) {
+hipError_t row_T(int mode, const Ctx& c, const void* src, void* dst, uint32_t* smask) {
   const Plan& p = *c.p;
   const void* tw = (const char*)c.twT() + sizeof(cx<T>) * p.twz;
-  return run_row<T, T>(p.dt, p.dt, mode, p, p.pitch, src, dst, x, xb, y, tw, c.st(), c.part(Ctx::PZ), smask, c.s);
+  return run_row<T, T>(p.dt, p.dt, mode, p, p.pitch, src, dst, tw, c.st(), c.part(Ctx::PZ), smask, c.s);
 }
 
 template <typename T>
-hipError_t enqueue_round(const Ctx& c, int r, unsigned long long* viol, uint8_t* fmask, uint32_t* smask) {
-  unsigned long long* px = c.part(Ctx::PX);
+hipError_t enqueue_round(const Ctx& c, int r, unsigned long long* viol, int64_t vstride, uint8_t* fmask,
+                         uint32_t* smask) {
   const Plan& p = *c.p;
+  unsigned long long* px = c.part(Ctx::PX);
   const char* twb = (const char*)c.twT();
   const void* twy = twb + sizeof(cx<T>) * p.twy;
   const void* twx = twb + sizeof(cx<T>) * p.twx;
@@ -555,7 +585,7 @@ hipError_t enqueue_round(const Ctx& c, int r, unsigned long long* viol, uint8_t*
       return run_col<T>(p.dt, COL_XPASS, geom_x(p, p.pitch), p, c.A(), c.A(), twx, c.st(), px, fmask, c.s);
     });
     if (e != hipSuccess) return e;
-    e = launch_ctl(c, viol);
+    e = launch_ctl(c, viol, vstride);
     if (e != hipSuccess) return e;
     e = timed(PK_YINV, r, c.s, [&] {
       return run_col<T>(p.dt, COL_INV, geom_y(p, p.pitch), p, c.A(), c.A(), twy, c.st(), px, fmask, c.s);
@@ -566,157 +596,198 @@ hipError_t enqueue_round(const Ctx& c, int r, unsigned long long* viol, uint8_t*
       return run_col<T>(p.dt, COL_XPASS, geom_x(p, p.pitch), p, c.Z(), c.A(), twx, c.st(), px, fmask, c.s);
     });
     if (e != hipSuccess) return e;
-    e = launch_ctl(c, viol);
+    e = launch_ctl(c, viol, vstride);
     if (e != hipSuccess) return e;
   }
-  return timed(PK_ZPASS, r, c.s, [&] { return row_T<T>(ROW_LOOP, c, c.A(), c.Z(), nullptr, nullptr, nullptr, smask); });
+  return timed(PK_ZPASS, r, c.s, [&] { return row_T<T>(ROW_LOOP, c, c.A(), c.Z(), smask); });
 }
 
 template <typename T>
-hipError_t enqueue_verify(const Ctx& c, const void* x, const void* y) {
+hipError_t enqueue_verify(const Ctx& c) {
   const Plan& p = *c.p;
   const char* tb = (const char*)c.tw64();
   void* W = c.Z();  // FP64 spectrum over Z..A
   hipError_t e = timed(PK_VZ, -1, c.s, [&] {
-    return run_row<double, T>(1, p.dt, ROW_VERIFY, p, p.pitch64, nullptr, W, x, y, nullptr, tb + 16 * p.tw64z,
-                              c.st(), c.part(Ctx::PVZ), nullptr, c.s);
+    return run_row<double, T>(1, p.dt, ROW_VERIFY, p, p.pitch64, nullptr, W, tb + 16 * p.twz, c.st(),
+                              c.part(Ctx::PVZ), nullptr, c.s);
   });
   if (e != hipSuccess) return e;
   if (p.nd == 3) {
     e = timed(PK_VY, -1, c.s, [&] {
-      return run_col<double>(1, COL_FWD_NS, geom_y(p, p.pitch64), p, W, W, tb + 16 * p.tw64y, c.st(),
+      return run_col<double>(1, COL_FWD_NS, geom_y(p, p.pitch64), p, W, W, tb + 16 * p.twy, c.st(),
                              c.part(Ctx::PVX), nullptr, c.s);
     });
     if (e != hipSuccess) return e;
   }
   e = timed(PK_VX, -1, c.s, [&] {
-    return run_col<double>(1, COL_VERIFY, geom_x(p, p.pitch64), p, W, W, tb + 16 * p.tw64x, c.st(),
+    return run_col<double>(1, COL_VERIFY, geom_x(p, p.pitch64), p, W, W, tb + 16 * p.twx, c.st(),
                            c.part(Ctx::PVX), nullptr, c.s);
   });
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(1024), 0, c.s, c.st(), c.part(Ctx::PVZ), p.nbz, c.part(Ctx::PVX),
-                     c.part(Ctx::PVX + 1), p.nbvx);
+  hipLaunchKernelGGL(stats_kernel, dim3((unsigned)p.B), dim3(1024), 0, c.s, c.st(), c.part(Ctx::PVZ), p.vzbpi,
+                     c.part(Ctx::PVX), c.part(Ctx::PVX + 1), p.vxbpi);
   return hipGetLastError();
 }
 
-// pinned host mirror of the device state (one per thread)
-struct HostMirror {
-  DevState* st = nullptr;
-  unsigned long long* v = nullptr;
-  ~HostMirror() {
-    if (st) (void)hipHostFree(st);
-    if (v) (void)hipHostFree(v);
+// pinned host staging (one per thread), grown on demand
+struct HostBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  ~HostBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  hipError_t reserve(size_t bytes) {
+    if (bytes <= n) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+    hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+    if (e == hipSuccess) n = bytes;
+    return e;
   }
 };
-thread_local HostMirror g_mirror;
+thread_local HostBuf g_host_state, g_host_init, g_host_misc;
 
-hipError_t mirror() {
-  if (!g_mirror.st) {
-    hipError_t e = hipHostMalloc((void**)&g_mirror.st, sizeof(DevState), hipHostMallocDefault);
-    if (e != hipSuccess) return e;
-    e = hipHostMalloc((void**)&g_mirror.v, 2 * sizeof(unsigned long long), hipHostMallocDefault);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+double bits_to_double(unsigned long long b) {
+  double d;
+  memcpy(&d, &b, 8);
+  return d;
 }
 
-double default_mu(int dt) { return dt == FFCZ_F64 ? std::ldexp(1.0, -16) : 0.0; }
-
-template <typename T>
-int32_t correct_impl(const Plan& p, const void* x, const void* xb, void* y, double E, double D, int32_t max_iter,
-                     const ffcz_options& o, void* ws, hipStream_t s, ffcz_stats* stats) {
-  Ctx c{&p, (char*)ws, s};
-  unsigned long long* viol = o.viol_per_round ? (unsigned long long*)o.viol_per_round
-                                              : (unsigned long long*)((char*)ws + p.off_viol);
-  double mu = o.margin_rel;
-  if (!(mu > 0.0)) {
-    if (p.dt == FFCZ_F64) {
-      mu = default_mu(p.dt);
-    } else {
-      int32_t st = ffcz_suggest_margin(p.dt, p.nd, p.n, x, D, ws, p.bytes, s, &mu);
-      if (st != FFCZ_OK) return st;
-    }
+// Suggested FP32 margin for one field of N points (reads x once on the device).
+int32_t margin_for(int dt, int64_t N, const void* x, double D, DevState* scratch, hipStream_t s, double* mu) {
+  if (dt == FFCZ_F64) {
+    *mu = std::ldexp(1.0, -16);
+    return FFCZ_OK;
   }
-  if (!(mu < 1.0)) return fail(FFCZ_E_INVALID, "margin_rel must be in [0, 1)");
-  const bool rec = o.masks_out != nullptr;
+  StateInit si;
+  memset(&si, 0, sizeof(si));
+  hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, s, scratch, (int64_t)1, (const StateInit*)nullptr, si,
+                     (unsigned long long*)nullptr, (int64_t)0);
+  HIPCHK(hipGetLastError());
+  const int nb = (int)std::min<int64_t>(4096, (N + 255) / 256);
+  hipLaunchKernelGGL(ulp_kernel<float>, dim3(nb), dim3(256), 0, s, (const float*)x, N, scratch);
+  HIPCHK(hipGetLastError());
+  HIPCHK(g_host_misc.reserve(sizeof(DevState)));
+  HIPCHK(hipMemcpyAsync(g_host_misc.p, scratch, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double sigma = std::sqrt(((DevState*)g_host_misc.p)->ulp2_sum / (double)N / 12.0);
+  double m = D > 0 ? 8.0 * sigma * std::sqrt((double)N / 2.0) / D : 0.5;
+  *mu = std::min(0.5, std::max(std::ldexp(1.0, -16), m));
+  return FFCZ_OK;
+}
+
+// One correction over the B instances of a plan.  inst[b] supplies pointers and bounds.
+template <typename T>
+int32_t correct_group(const Plan& p, const ffcz_instance* inst, const double* mus, int32_t max_iter,
+                      const ffcz_options& o, char* ws, hipStream_t s, ffcz_stats* stats, int32_t* status) {
+  Ctx c{&p, ws, s};
+  const int64_t vstride = max_iter + 2;
+  const bool user_viol = o.viol_per_round && p.B == 1;
+  unsigned long long* viol = user_viol ? (unsigned long long*)o.viol_per_round : c.viol();
+  const int64_t vstr = user_viol ? 0 : vstride;
+  const bool rec = o.masks_out != nullptr && p.B == 1;
   uint32_t* smask = rec ? (uint32_t*)o.masks_out : nullptr;
   uint8_t* fmask = rec ? (uint8_t*)o.masks_out + (size_t)(max_iter + 1) * p.s_plane_bytes : nullptr;
 
-  StateInit si;
-  si.E = E;
-  si.Ep = E * (1.0 - mu);
-  si.Delta = D;
-  si.Dp = D * (1.0 - mu);
-  si.inv_n = 1.0 / (double)p.N;
-  si.max_iter = max_iter;
-  si.fixed = o.fixed_iterations ? 1 : 0;
-  si.record_masks = rec ? 1 : 0;
-  hipLaunchKernelGGL(state_init_kernel, dim3(std::max(1, (max_iter + 2 + 255) / 256)), dim3(256), 0, s, c.st(),
-                     viol, max_iter + 1, si);
+  auto fill = [&](int64_t b) {
+    StateInit si;
+    memset(&si, 0, sizeof(si));
+    si.E = inst[b].eps_s;
+    si.Ep = inst[b].eps_s * (1.0 - mus[b]);
+    si.Delta = inst[b].delta_f;
+    si.Dp = inst[b].delta_f * (1.0 - mus[b]);
+    si.inv_n = 1.0 / (double)p.N;
+    si.max_iter = max_iter;
+    si.fixed = o.fixed_iterations ? 1 : 0;
+    si.record_masks = rec ? 1 : 0;
+    si.px = inst[b].x_orig;
+    si.pxb = inst[b].x_base;
+    si.py = inst[b].x_out;
+    return si;
+  };
+  const StateInit* arr = nullptr;
+  StateInit one = fill(0);
+  if (p.B > 1) {
+    HIPCHK(g_host_init.reserve(sizeof(StateInit) * p.B));
+    StateInit* h = (StateInit*)g_host_init.p;
+    for (int64_t b = 0; b < p.B; ++b) h[b] = fill(b);
+    arr = (const StateInit*)(ws + p.off_init);
+    HIPCHK(hipMemcpyAsync((void*)arr, h, sizeof(StateInit) * p.B, hipMemcpyHostToDevice, s));
+  }
+  const int64_t nviol = user_viol ? (int64_t)max_iter + 1 : vstride * p.B;
+  const int64_t nthr = std::max<int64_t>(p.B, nviol);
+  hipLaunchKernelGGL(state_init_kernel, dim3((unsigned)std::max<int64_t>(1, (nthr + 255) / 256)), dim3(256), 0, s,
+                     c.st(), p.B, arr, one, viol, nviol);
   HIPCHK(hipGetLastError());
   HIPCHK(write_twiddles(c));
-  HIPCHK(timed(PK_INIT, -1, s, [&] { return row_T<T>(ROW_INIT, c, nullptr, c.Z(), x, xb, nullptr, smask); }));
+  HIPCHK(timed(PK_INIT, -1, s, [&] { return row_T<T>(ROW_INIT, c, nullptr, c.Z(), smask); }));
 
   const int chunk = o.graph_chunk > 0 ? o.graph_chunk : 4;
-  HIPCHK(mirror());
+  HIPCHK(g_host_state.reserve(sizeof(DevState) * p.B));
+  DevState* hs = (DevState*)g_host_state.p;
   int enq = 0;
   const bool sync_needed = !(o.fixed_iterations && stats == nullptr);
   if (o.fixed_iterations) {
     // exactly max_iter blocks plus the final check: no polling needed
-    for (int r = 0; r <= max_iter; ++r) HIPCHK(enqueue_round<T>(c, r, viol, fmask, smask));
+    for (int r = 0; r <= max_iter; ++r) HIPCHK(enqueue_round<T>(c, r, viol, vstr, fmask, smask));
   } else {
     for (;;) {
-      for (int r = 0; r < chunk; ++r) HIPCHK(enqueue_round<T>(c, enq + r, viol, fmask, smask));
+      for (int r = 0; r < chunk; ++r) HIPCHK(enqueue_round<T>(c, enq + r, viol, vstr, fmask, smask));
       enq += chunk;
-      HIPCHK(hipMemcpyAsync(g_mirror.st, c.st(), sizeof(DevState), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hs, c.st(), sizeof(DevState) * p.B, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      if (g_mirror.st->done) break;
+      bool all = true;
+      for (int64_t b = 0; b < p.B; ++b) all = all && hs[b].done;
+      if (all) break;
       if (enq > max_iter + 2 * chunk + 2)
         return fail(FFCZ_E_HIP, "loop did not report completion (device state inconsistent)");
     }
   }
-  HIPCHK(timed(PK_FINAL, -1, s, [&] { return row_T<T>(ROW_FINAL, c, c.Z(), nullptr, x, nullptr, y, nullptr); }));
-  if (o.verify_fp64) HIPCHK(enqueue_verify<T>(c, x, y));
+  HIPCHK(timed(PK_FINAL, -1, s, [&] { return row_T<T>(ROW_FINAL, c, c.Z(), nullptr, nullptr); }));
+  if (o.verify_fp64) HIPCHK(enqueue_verify<T>(c));
   if (!sync_needed) {
     prof_settle(max_iter);
+    for (int64_t b = 0; b < p.B; ++b) status[b] = FFCZ_OK;
     return FFCZ_OK;
   }
-  HIPCHK(hipMemcpyAsync(g_mirror.st, c.st(), sizeof(DevState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hs, c.st(), sizeof(DevState) * p.B, hipMemcpyDeviceToHost, s));
+  HIPCHK(g_host_misc.reserve(sizeof(unsigned long long) * 2 * p.B));
+  unsigned long long* hv = (unsigned long long*)g_host_misc.p;
   HIPCHK(hipStreamSynchronize(s));
-  const DevState h = *g_mirror.st;
-  prof_settle(h.round);
-  HIPCHK(hipMemcpyAsync(&g_mirror.v[0], viol, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&g_mirror.v[1], viol + h.round, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  if (stats) {
-    memset(stats, 0, sizeof(*stats));
-    stats->rounds = h.round;
-    stats->converged = h.converged;
-    stats->f_viol_initial = (int64_t)g_mirror.v[0];
-    stats->f_viol_final = (int64_t)g_mirror.v[1];
-    stats->s_clipped_total = (int64_t)h.s_clipped_total;
-    stats->s_guard = (int64_t)h.s_guard;
-    stats->nonfinite = (int64_t)h.nonfinite;
-    double ms, mf;
-    unsigned long long b1 = h.max_spatial_bits, b2 = h.max_spectral_bits;
-    memcpy(&ms, &b1, 8);
-    memcpy(&mf, &b2, 8);
-    stats->max_spatial_err = o.verify_fp64 ? ms : NAN;
-    stats->max_spectral_err = o.verify_fp64 ? mf : NAN;
-    stats->spectral_viol = (int64_t)h.spectral_viol;
-    stats->margin_used = mu;
+  int maxr = 0;
+  for (int64_t b = 0; b < p.B; ++b) {
+    const int64_t vb = b * vstr;
+    HIPCHK(hipMemcpyAsync(&hv[2 * b], viol + vb, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hv[2 * b + 1], viol + vb + hs[b].round, sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, s));
+    maxr = std::max(maxr, hs[b].round);
   }
-  if (h.nonfinite) return fail(FFCZ_E_NONFINITE, "x or x_hat holds NaN or Inf");
-  if (!h.converged && !o.fixed_iterations) return FFCZ_NOT_CONVERGED;
-  if (o.verify_fp64) {
-    double ms, mf;
-    unsigned long long b1 = h.max_spatial_bits, b2 = h.max_spectral_bits;
-    memcpy(&ms, &b1, 8);
-    memcpy(&mf, &b2, 8);
-    if (!(ms <= E) || !(mf <= D)) {
-      g_err = "FP64 re-verification failed";
-      return FFCZ_VERIFY_FAILED;
+  HIPCHK(hipStreamSynchronize(s));
+  prof_settle(maxr);
+  for (int64_t b = 0; b < p.B; ++b) {
+    const DevState& h = hs[b];
+    const double ms = bits_to_double(h.max_spatial_bits), mf = bits_to_double(h.max_spectral_bits);
+    if (stats) {
+      ffcz_stats& st = stats[b];
+      memset(&st, 0, sizeof(st));
+      st.rounds = h.round;
+      st.converged = h.converged;
+      st.f_viol_initial = (int64_t)hv[2 * b];
+      st.f_viol_final = (int64_t)hv[2 * b + 1];
+      st.s_clipped_total = (int64_t)h.s_clipped_total;
+      st.s_guard = (int64_t)h.s_guard;
+      st.nonfinite = (int64_t)h.nonfinite;
+      st.max_spatial_err = o.verify_fp64 ? ms : NAN;
+      st.max_spectral_err = o.verify_fp64 ? mf : NAN;
+      st.spectral_viol = (int64_t)h.spectral_viol;
+      st.margin_used = mus[b];
     }
+    int32_t r = FFCZ_OK;
+    if (h.nonfinite) r = FFCZ_E_NONFINITE;
+    else if (!h.converged && !o.fixed_iterations) r = FFCZ_NOT_CONVERGED;
+    else if (o.verify_fp64 && (!(ms <= inst[b].eps_s) || !(mf <= inst[b].delta_f))) r = FFCZ_VERIFY_FAILED;
+    status[b] = r;
   }
   return FFCZ_OK;
 }
@@ -729,24 +800,27 @@ int32_t backward_impl(const Plan& p, int32_t rounds, const void* masks, const vo
   memset(&si, 0, sizeof(si));
   si.inv_n = 1.0 / (double)p.N;
   si.max_iter = rounds;
-  hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, s, c.st(), (unsigned long long*)((char*)ws + p.off_viol),
-                     1, si);
+  si.pxb = gy;
+  si.py = gb;
+  hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, s, c.st(), (int64_t)1, (const StateInit*)nullptr, si,
+                     c.viol(), (int64_t)1);
   HIPCHK(hipGetLastError());
   HIPCHK(write_twiddles(c));
   const char* mb = (const char*)masks;
   auto splane = [&](int k) { return (uint32_t*)(mb + (size_t)k * p.s_plane_bytes); };
-  auto fplane = [&](int k) { return (uint8_t*)(mb + (size_t)(rounds + 1) * p.s_plane_bytes + (size_t)(k - 1) * 2 * p.f_plane_bytes); };
+  auto fplane = [&](int k) {
+    return (uint8_t*)(mb + (size_t)(rounds + 1) * p.s_plane_bytes + (size_t)(k - 1) * 2 * p.f_plane_bytes);
+  };
   const char* twb = (const char*)c.twT();
   const void* twy = twb + sizeof(cx<T>) * p.twy;
   const void* twx = twb + sizeof(cx<T>) * p.twx;
   if (rounds == 0) {
-    // y = x + M_s^0 (x_hat - x): the gradient is the guard mask times dL/dy
-    HIPCHK(row_T<T>(ROW_BINIT, c, nullptr, c.Z(), nullptr, gy, nullptr, splane(0)));
-    HIPCHK(row_T<T>(ROW_BFINAL, c, c.Z(), nullptr, nullptr, nullptr, gb, splane(0)));
-    // ROW_BFINAL applies the mask a second time; masks are idempotent
+    // y = x + M_s^0 (x_hat - x): the gradient is the guard mask times dL/dy (applied twice; masks are idempotent)
+    HIPCHK(row_T<T>(ROW_BINIT, c, nullptr, c.Z(), splane(0)));
+    HIPCHK(row_T<T>(ROW_BFINAL, c, c.Z(), nullptr, splane(0)));
     return FFCZ_OK;
   }
-  HIPCHK(timed(PK_BZ, -1, s, [&] { return row_T<T>(ROW_BINIT, c, nullptr, c.Z(), nullptr, gy, nullptr, splane(rounds)); }));
+  HIPCHK(timed(PK_BZ, -1, s, [&] { return row_T<T>(ROW_BINIT, c, nullptr, c.Z(), splane(rounds)); }));
   for (int k = rounds; k >= 1; --k) {
     if (p.nd == 3)
       HIPCHK(timed(PK_BY, -1, s, [&] {
@@ -759,12 +833,348 @@ int32_t backward_impl(const Plan& p, int32_t rounds, const void* masks, const vo
       HIPCHK(timed(PK_BY, -1, s, [&] {
         return run_col<T>(p.dt, COL_INV_NS, geom_y(p, p.pitch), p, c.Z(), c.Z(), twy, c.st(), nullptr, nullptr, s);
       }));
-    if (k > 1)
-      HIPCHK(timed(PK_BZ, -1, s, [&] { return row_T<T>(ROW_BLOOP, c, c.Z(), c.Z(), nullptr, nullptr, nullptr, splane(k - 1)); }));
-    else
-      HIPCHK(timed(PK_BZ, -1, s, [&] { return row_T<T>(ROW_BFINAL, c, c.Z(), nullptr, nullptr, nullptr, gb, splane(0)); }));
+    if (k > 1) HIPCHK(timed(PK_BZ, -1, s, [&] { return row_T<T>(ROW_BLOOP, c, c.Z(), c.Z(), splane(k - 1)); }));
+    else HIPCHK(timed(PK_BZ, -1, s, [&] { return row_T<T>(ROW_BFINAL, c, c.Z(), nullptr, splane(0)); }));
   }
   return FFCZ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// 1D batch members: one block per signal (kernels_sig.hpp)
+
+int ceil_lg(int64_t v) {
+  int r = 0;
+  while ((int64_t(1) << r) < v) ++r;
+  return r;
+}
+
+struct SigPlan {
+  int dt = 0;
+  int64_t L = 0;
+  int blue = 0;
+  int lgMc = 0;
+  size_t conv64 = 0, btab = 0, btab64 = 0, chirp = 0, chirp64 = 0, eps = 0, bytes = 0;  // offsets in the signal block
+};
+
+SigPlan sig_plan(int dt, int64_t L) {
+  SigPlan s;
+  s.dt = dt;
+  s.L = L;
+  s.blue = (is_pow2(L) && L >= 4) ? 0 : 1;  // direct four-step needs Mc = L >= 4
+  s.lgMc = s.blue ? ceil_lg(2 * L - 1) : ceil_lg(L);
+  if (s.lgMc < 2) s.lgMc = 2;
+  const size_t Mc = (size_t)1 << s.lgMc;
+  size_t off = 0;
+  s.conv64 = off;
+  off = align_up(off + 16 * Mc, 256);
+  if (s.blue) {
+    s.btab64 = off;
+    off = align_up(off + 16 * Mc, 256);
+    s.chirp64 = off;
+    off = align_up(off + 16 * (size_t)L, 256);
+    if (dt == FFCZ_F32) {
+      s.btab = off;
+      off = align_up(off + 8 * Mc, 256);
+      s.chirp = off;
+      off = align_up(off + 8 * (size_t)L, 256);
+    } else {
+      s.btab = s.btab64;
+      s.chirp = s.chirp64;
+    }
+  }
+  s.eps = off;
+  off = align_up(off + (dt == FFCZ_F32 ? 4 : 8) * (size_t)L, 256);
+  s.bytes = off;
+  return s;
+}
+
+// four-step tables of one convolution length: working type and FP64, both layouts
+struct McTabs {
+  size_t tw4, tw4r, twa, twb, tw4_64, tw4r_64, twa_64, twb_64, bytes;
+};
+
+int sig_ma(int lgMc) { return 1 << ((lgMc + 1) / 2); }
+
+McTabs mc_tabs(int dt, int lgMc) {
+  const int MA = sig_ma(lgMc), MB = (1 << lgMc) / MA;
+  const size_t Mc = (size_t)1 << lgMc;
+  const size_t cs = dt == FFCZ_F32 ? 8 : 16;
+  McTabs t;
+  size_t off = 0;
+  t.tw4 = off;
+  off = align_up(off + cs * Mc, 256);
+  t.tw4r = off;
+  off = align_up(off + cs * Mc, 256);
+  t.twa = off;
+  off = align_up(off + cs * (host_twsize(MA, pick_E(MA)) + 1), 256);
+  t.twb = off;
+  off = align_up(off + cs * (host_twsize(MB, pick_E(MB)) + 1), 256);
+  t.tw4_64 = off;
+  off = align_up(off + 16 * Mc, 256);
+  t.tw4r_64 = off;
+  off = align_up(off + 16 * Mc, 256);
+  t.twa_64 = off;
+  off = align_up(off + 16 * (host_twsize(MA, pick_E(MA)) + 1), 256);
+  t.twb_64 = off;
+  off = align_up(off + 16 * (host_twsize(MB, pick_E(MB)) + 1), 256);
+  t.bytes = off;
+  return t;
+}
+
+// W_Mc^{n1 k2} in the column layout [k2][n1] and in the row-pass layout of the sig kernel
+__global__ void tw4_kernel(void* col, void* row, int dbl, int lgMc, int MA, int RR) {
+  const int64_t Mc = (int64_t)1 << lgMc;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Mc) return;
+  const int64_t k2 = i / MA, n1 = i % MA;
+  const int64_t r = (n1 * k2) & (Mc - 1);
+  double sn, cs;
+  sincospi(-2.0 * (double)r / (double)Mc, &sn, &cs);
+  const int64_t rp = ((k2 / RR) * MA + n1) * RR + (k2 % RR);
+  if (dbl) {
+    ((cx<double>*)col)[i] = cx<double>{cs, sn};
+    ((cx<double>*)row)[rp] = cx<double>{cs, sn};
+  } else {
+    ((cx<float>*)col)[i] = cx<float>{__double2float_rn(cs), __double2float_rn(sn)};
+    ((cx<float>*)row)[rp] = cx<float>{__double2float_rn(cs), __double2float_rn(sn)};
+  }
+}
+
+hipError_t write_mc_tabs(int dt, int lgMc, char* base, const McTabs& t, hipStream_t s) {
+  const int MA = sig_ma(lgMc), MB = (1 << lgMc) / MA;
+  const int64_t Mc = (int64_t)1 << lgMc;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int dbl = (pass == 1 || dt == FFCZ_F64) ? 1 : 0;
+    char* col = base + (pass ? t.tw4_64 : t.tw4);
+    char* row = base + (pass ? t.tw4r_64 : t.tw4r);
+    hipLaunchKernelGGL(tw4_kernel, dim3((unsigned)((Mc + 255) / 256)), dim3(256), 0, s, col, row, dbl, lgMc, MA,
+                       sig_rows_per_tile(dbl, lgMc));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    TwJobs jobs;
+    memset(&jobs, 0, sizeof(jobs));
+    jobs.dbl = dbl;
+    jobs.n = 1;
+    jobs.j[0] = TwJob{0, MA, pick_E(MA), 0};
+    hipLaunchKernelGGL(twiddle_kernel, dim3(64), dim3(256), 0, s, base + (pass ? t.twa_64 : t.twa), jobs);
+    jobs.j[0] = TwJob{0, MB, pick_E(MB), 0};
+    hipLaunchKernelGGL(twiddle_kernel, dim3(64), dim3(256), 0, s, base + (pass ? t.twb_64 : t.twb), jobs);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Layout of the batched workspace
+struct BatchPlan {
+  int dt = 0;
+  std::vector<int> sig_ids;                 // 1D members
+  std::vector<SigPlan> sigs;
+  std::map<int, std::vector<int>> by_mc;    // lgMc -> positions in sig_ids
+  std::map<int, size_t> mc_off;             // lgMc -> table offset
+  std::map<int, McTabs> mc_tab;
+  std::vector<size_t> sig_off;
+  size_t off_desc = 0, off_sstats = 0, off_order = 0, off_scratch = 0;
+  // multi-dimensional groups
+  std::vector<std::vector<int>> groups;
+  std::vector<Plan> gplans;
+  std::vector<size_t> goff;
+  size_t bytes = 0;
+};
+
+int32_t batch_plan(int32_t dt, int32_t count, const ffcz_instance* inst, int32_t max_iter, BatchPlan& bp) {
+  bp = BatchPlan();
+  bp.dt = dt;
+  if (dt != FFCZ_F32 && dt != FFCZ_F64) return fail(FFCZ_E_INVALID, "dtype must be FFCZ_F32 or FFCZ_F64");
+  if (count < 0 || (count > 0 && !inst)) return fail(FFCZ_E_INVALID, "bad instance array");
+  std::map<std::vector<int64_t>, int> gkey;
+  for (int i = 0; i < count; ++i) {
+    const ffcz_instance& in = inst[i];
+    if (in.ndim < 1 || in.ndim > 3) return fail(FFCZ_E_SHAPE, "instance ndim must be 1..3");
+    int64_t sq[3];
+    for (int d = 0; d < in.ndim; ++d)
+      if (in.shape[d] < 1) return fail(FFCZ_E_SHAPE, "every extent must be >= 1");
+    const int nd = squeeze(in.ndim, in.shape, sq);
+    if (nd <= 1) {
+      const int64_t L = nd == 0 ? 1 : sq[0];
+      if (L < 2 || L > (int64_t)1 << 19) return fail(FFCZ_E_SHAPE, "1D lengths must be in [2, 2^19]");
+      bp.sig_ids.push_back(i);
+      continue;
+    }
+    std::vector<int64_t> key(sq, sq + nd);
+    if (nd == 3) key.push_back(i);  // 3D instances run one at a time
+    auto it = gkey.find(key);
+    if (it == gkey.end()) {
+      gkey[key] = (int)bp.groups.size();
+      bp.groups.push_back({i});
+    } else {
+      bp.groups[it->second].push_back(i);
+    }
+  }
+  size_t off = 0;
+  for (auto& g : bp.groups) {
+    Plan p;
+    const ffcz_instance& in = inst[g[0]];
+    int32_t r = make_plan(dt, in.ndim, in.shape, max_iter, (int64_t)g.size(), p);
+    if (r != FFCZ_OK) return r;
+    bp.gplans.push_back(p);
+    bp.goff.push_back(off);
+    off = align_up(off + p.bytes, 256);
+  }
+  const int ns = (int)bp.sig_ids.size();
+  for (int k = 0; k < ns; ++k) {
+    int64_t sq[3];
+    const ffcz_instance& in = inst[bp.sig_ids[k]];
+    const int nd = squeeze(in.ndim, in.shape, sq);
+    SigPlan sp = sig_plan(dt, nd == 0 ? 1 : sq[0]);
+    bp.sigs.push_back(sp);
+    bp.by_mc[sp.lgMc].push_back(k);
+    bp.sig_off.push_back(off);
+    off = align_up(off + sp.bytes, 256);
+  }
+  for (auto& kv : bp.by_mc) {
+    McTabs t = mc_tabs(dt, kv.first);
+    bp.mc_tab[kv.first] = t;
+    bp.mc_off[kv.first] = off;
+    off = align_up(off + t.bytes, 256);
+  }
+  bp.off_desc = off;
+  off = align_up(off + sizeof(SigDesc) * (size_t)std::max(ns, 1), 256);
+  bp.off_sstats = off;
+  off = align_up(off + sizeof(SigStats) * (size_t)std::max(ns, 1), 256);
+  bp.off_order = off;
+  off = align_up(off + sizeof(int32_t) * (size_t)std::max(ns, 1), 256);
+  bp.off_scratch = off;  // one DevState for the margin reductions
+  off = align_up(off + sizeof(DevState), 256);
+  bp.bytes = off;
+  return FFCZ_OK;
+}
+
+template <typename T>
+hipError_t sig_launch(int dt, int mode, int lgMc, const BatchPlan& bp, char* ws, const int32_t* order,
+                      int nblocks, int32_t max_iter, int32_t fixed, hipStream_t s) {
+  const McTabs& t = bp.mc_tab.at(lgMc);
+  char* tb = ws + bp.mc_off.at(lgMc);
+  const bool d64 = (mode != SIG_RUN) || dt == FFCZ_F64;  // set-up and verification compute in FP64
+  SigArgs<T> a;
+  memset(&a, 0, sizeof(a));
+  a.sig = (const SigDesc*)(ws + bp.off_desc);
+  a.stats = (SigStats*)(ws + bp.off_sstats);
+  a.order = order;
+  a.nsig = nblocks;
+  a.max_iter = max_iter;
+  a.fixed = fixed;
+  a.tab.tw4 = (const cx<T>*)(tb + (d64 ? t.tw4_64 : t.tw4));
+  a.tab.tw4r = (const cx<T>*)(tb + (d64 ? t.tw4r_64 : t.tw4r));
+  a.tab.twa = (const cx<T>*)(tb + (d64 ? t.twa_64 : t.twa));
+  a.tab.twb = (const cx<T>*)(tb + (d64 ? t.twb_64 : t.twb));
+  return launch_sig(d64 ? 1 : 0, dt, mode, lgMc, &a, nblocks, s);
+}
+
+int32_t run_sigs(const BatchPlan& bp, const ffcz_instance* inst, const double* mus, int32_t max_iter,
+                 const ffcz_options& o, char* ws, hipStream_t s) {
+  const int ns = (int)bp.sig_ids.size();
+  if (ns == 0) return FFCZ_OK;
+  HIPCHK(g_host_init.reserve(sizeof(SigDesc) * ns + sizeof(int32_t) * ns));
+  SigDesc* hd = (SigDesc*)g_host_init.p;
+  int32_t* ho = (int32_t*)(hd + ns);
+  for (int k = 0; k < ns; ++k) {
+    const ffcz_instance& in = inst[bp.sig_ids[k]];
+    const SigPlan& sp = bp.sigs[k];
+    char* b = ws + bp.sig_off[k];
+    SigDesc d;
+    memset(&d, 0, sizeof(d));
+    d.x = in.x_orig;
+    d.xb = in.x_base;
+    d.y = in.x_out;
+    d.L = sp.L;
+    d.blue = sp.blue;
+    d.E = in.eps_s;
+    d.Delta = in.delta_f;
+    d.Ep = in.eps_s * (1.0 - mus[bp.sig_ids[k]]);
+    d.Dp = in.delta_f * (1.0 - mus[bp.sig_ids[k]]);
+    d.conv = b + sp.conv64;
+    d.conv64 = b + sp.conv64;
+    if (sp.blue) {
+      d.btab = b + sp.btab;
+      d.btab64 = b + sp.btab64;
+      d.chirp = b + sp.chirp;
+      d.chirp64 = b + sp.chirp64;
+    }
+    d.eps = b + sp.eps;
+    hd[k] = d;
+  }
+  // block order per convolution length: larger signals first
+  int pos = 0;
+  std::map<int, int> first;
+  for (auto& kv : bp.by_mc) {
+    std::vector<int> ids = kv.second;
+    std::sort(ids.begin(), ids.end(), [&](int a, int b) { return bp.sigs[a].L > bp.sigs[b].L; });
+    first[kv.first] = pos;
+    for (int id : ids) ho[pos++] = id;
+  }
+  HIPCHK(hipMemcpyAsync(ws + bp.off_desc, hd, sizeof(SigDesc) * ns, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ws + bp.off_order, ho, sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
+  for (auto& kv : bp.by_mc)
+    HIPCHK(write_mc_tabs(bp.dt, kv.first, ws + bp.mc_off.at(kv.first), bp.mc_tab.at(kv.first), s));
+  const int32_t* order = (const int32_t*)(ws + bp.off_order);
+  for (auto& kv : bp.by_mc) {
+    const int lg = kv.first;
+    const int nb = (int)kv.second.size();
+    const int32_t* ord = order + first[lg];
+    HIPCHK(sig_launch<double>(bp.dt, SIG_SETUP, lg, bp, ws, ord, nb, max_iter, 0, s));
+    if (bp.dt == FFCZ_F32)
+      HIPCHK(sig_launch<float>(bp.dt, SIG_RUN, lg, bp, ws, ord, nb, max_iter, o.fixed_iterations, s));
+    else
+      HIPCHK(sig_launch<double>(bp.dt, SIG_RUN, lg, bp, ws, ord, nb, max_iter, o.fixed_iterations, s));
+    if (o.verify_fp64) HIPCHK(sig_launch<double>(bp.dt, SIG_VERIFY, lg, bp, ws, ord, nb, max_iter, 0, s));
+  }
+  return FFCZ_OK;
+}
+
+int32_t collect_sigs(const BatchPlan& bp, const ffcz_instance* inst, const double* mus, const ffcz_options& o,
+                     char* ws, hipStream_t s, ffcz_stats* stats, int32_t* status) {
+  const int ns = (int)bp.sig_ids.size();
+  if (ns == 0) return FFCZ_OK;
+  HIPCHK(g_host_misc.reserve(sizeof(SigStats) * ns));
+  SigStats* h = (SigStats*)g_host_misc.p;
+  HIPCHK(hipMemcpyAsync(h, ws + bp.off_sstats, sizeof(SigStats) * ns, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int k = 0; k < ns; ++k) {
+    const int id = bp.sig_ids[k];
+    const SigStats& g = h[k];
+    if (stats) {
+      ffcz_stats& st = stats[id];
+      memset(&st, 0, sizeof(st));
+      st.rounds = g.rounds;
+      st.converged = g.converged;
+      st.f_viol_initial = (int64_t)g.viol0;
+      st.f_viol_final = (int64_t)g.violf;
+      st.s_clipped_total = (int64_t)g.s_clipped;
+      st.s_guard = (int64_t)g.s_guard;
+      st.nonfinite = (int64_t)g.nonfinite;
+      st.max_spatial_err = o.verify_fp64 ? g.max_spatial : NAN;
+      st.max_spectral_err = o.verify_fp64 ? g.max_spectral : NAN;
+      st.spectral_viol = (int64_t)g.spectral_viol;
+      st.margin_used = mus[id];
+    }
+    int32_t r = FFCZ_OK;
+    if (g.nonfinite_stop) r = FFCZ_E_NONFINITE;
+    else if (!g.converged && !o.fixed_iterations) r = FFCZ_NOT_CONVERGED;
+    else if (o.verify_fp64 && (!(g.max_spatial <= inst[id].eps_s) || !(g.max_spectral <= inst[id].delta_f)))
+      r = FFCZ_VERIFY_FAILED;
+    status[id] = r;
+  }
+  return FFCZ_OK;
+}
+
+int32_t worst(const std::vector<int32_t>& st) {
+  int32_t w = FFCZ_OK;
+  for (int32_t v : st) {
+    if (v < 0) return v;
+    w = std::max(w, v);
+  }
+  return w;
 }
 
 }  // namespace
@@ -772,6 +1182,8 @@ int32_t backward_impl(const Plan& p, int32_t rounds, const void* masks, const vo
 extern "C" {
 
 int32_t ffcz_version(void) { return 100; }
+
+const char* ffcz_last_error(void) { return g_err.c_str(); }
 
 void ffcz_profile_enable(int32_t on) {
   g_prof.on = on != 0;
@@ -807,8 +1219,6 @@ int32_t ffcz_profile_read(ffcz_profile* out) {
   return FFCZ_OK;
 }
 
-const char* ffcz_last_error(void) { return g_err.c_str(); }
-
 void ffcz_default_options(ffcz_options* o) {
   if (!o) return;
   memset(o, 0, sizeof(*o));
@@ -819,7 +1229,7 @@ void ffcz_default_options(ffcz_options* o) {
 size_t ffcz_workspace_bytes(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max_iter) {
   Plan p;
   std::string keep = g_err;
-  if (make_plan(dtype, ndim, shape, max_iter < 0 ? 0 : max_iter, p) != FFCZ_OK) return 0;
+  if (make_plan(dtype, ndim, shape, max_iter < 0 ? 0 : max_iter, 1, p) != FFCZ_OK) return 0;
   g_err = keep;
   return p.bytes;
 }
@@ -827,7 +1237,7 @@ size_t ffcz_workspace_bytes(int32_t dtype, int32_t ndim, const int64_t* shape, i
 size_t ffcz_mask_bytes(int32_t ndim, const int64_t* shape, int32_t rounds) {
   Plan p;
   std::string keep = g_err;
-  if (rounds < 0 || make_plan(FFCZ_F32, ndim, shape, rounds, p) != FFCZ_OK) return 0;
+  if (rounds < 0 || make_plan(FFCZ_F32, ndim, shape, rounds, 1, p) != FFCZ_OK) return 0;
   g_err = keep;
   return (size_t)(rounds + 1) * p.s_plane_bytes + (size_t)rounds * 2 * p.f_plane_bytes;
 }
@@ -835,39 +1245,20 @@ size_t ffcz_mask_bytes(int32_t ndim, const int64_t* shape, int32_t rounds) {
 int32_t ffcz_suggest_margin(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x, double delta_f,
                             void* ws, size_t ws_bytes, void* stream, double* mu_out) {
   Plan p;
-  int32_t r = make_plan(dtype, ndim, shape, 0, p);
+  int32_t r = make_plan(dtype, ndim, shape, 0, 1, p);
   if (r != FFCZ_OK) return r;
   if (!x || !mu_out) return fail(FFCZ_E_INVALID, "null pointer");
   if (!std::isfinite(delta_f) || delta_f < 0) return fail(FFCZ_E_INVALID, "delta_f must be finite and >= 0");
-  if (dtype == FFCZ_F64) {
-    *mu_out = std::ldexp(1.0, -16);
-    return FFCZ_OK;
-  }
-  if (!ws || ws_bytes < p.off_state + sizeof(DevState)) return fail(FFCZ_E_WORKSPACE, "workspace too small");
-  hipStream_t s = (hipStream_t)stream;
-  DevState* st = (DevState*)((char*)ws + p.off_state);
-  StateInit si;
-  memset(&si, 0, sizeof(si));
-  hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, s, st, (unsigned long long*)nullptr, 0, si);
-  HIPCHK(hipGetLastError());
-  const int nb = (int)std::min<int64_t>(4096, (p.N + 255) / 256);
-  hipLaunchKernelGGL(ulp_kernel<float>, dim3(nb), dim3(256), 0, s, (const float*)x, p.N, st);
-  HIPCHK(hipGetLastError());
-  HIPCHK(mirror());
-  HIPCHK(hipMemcpyAsync(g_mirror.st, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  const double sigma = std::sqrt(g_mirror.st->ulp2_sum / (double)p.N / 12.0);
-  double mu = delta_f > 0 ? 8.0 * sigma * std::sqrt((double)p.N / 2.0) / delta_f : 0.5;
-  mu = std::min(0.5, std::max(std::ldexp(1.0, -16), mu));
-  *mu_out = mu;
-  return FFCZ_OK;
+  if (dtype == FFCZ_F32 && (!ws || ws_bytes < p.off_state + sizeof(DevState)))
+    return fail(FFCZ_E_WORKSPACE, "workspace too small");
+  return margin_for(dtype, p.N, x, delta_f, (DevState*)((char*)ws + p.off_state), (hipStream_t)stream, mu_out);
 }
 
 int32_t ffcz_correct(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x, const void* xb, void* y,
                      double eps_s, double delta_f, int32_t max_iter, const ffcz_options* opts, void* ws,
                      size_t ws_bytes, void* stream, ffcz_stats* stats) {
   Plan p;
-  int32_t r = make_plan(dtype, ndim, shape, max_iter, p);
+  int32_t r = make_plan(dtype, ndim, shape, max_iter, 1, p);
   if (r != FFCZ_OK) return r;
   if (!x || !xb || !y) return fail(FFCZ_E_INVALID, "null data pointer");
   if (x == xb || x == y) return fail(FFCZ_E_INVALID, "x_orig must not alias x_base or x_out");
@@ -879,17 +1270,108 @@ int32_t ffcz_correct(int32_t dtype, int32_t ndim, const int64_t* shape, const vo
   ffcz_options o;
   if (opts) o = *opts;
   else ffcz_default_options(&o);
-  if (o.fixed_iterations && o.masks_out && p.dt == FFCZ_F64 && col_block_cols(1, p.Lx) < 8)
+  if (o.masks_out && p.dt == FFCZ_F64 && col_block_cols(1, p.Lx) < 8)
     return fail(FFCZ_E_SHAPE, "mask recording needs at least 8 columns per block");
   hipStream_t s = (hipStream_t)stream;
-  if (dtype == FFCZ_F32) return correct_impl<float>(p, x, xb, y, eps_s, delta_f, max_iter, o, ws, s, stats);
-  return correct_impl<double>(p, x, xb, y, eps_s, delta_f, max_iter, o, ws, s, stats);
+  double mu = o.margin_rel;
+  if (!(mu > 0.0)) {
+    int32_t st = margin_for(dtype, p.N, x, delta_f, (DevState*)((char*)ws + p.off_state), s, &mu);
+    if (st != FFCZ_OK) return st;
+  }
+  if (!(mu < 1.0)) return fail(FFCZ_E_INVALID, "margin_rel must be in [0, 1)");
+  ffcz_instance in;
+  memset(&in, 0, sizeof(in));
+  in.ndim = ndim;
+  for (int i = 0; i < ndim; ++i) in.shape[i] = shape[i];
+  in.x_orig = x;
+  in.x_base = xb;
+  in.x_out = y;
+  in.eps_s = eps_s;
+  in.delta_f = delta_f;
+  int32_t status = FFCZ_OK;
+  r = dtype == FFCZ_F32 ? correct_group<float>(p, &in, &mu, max_iter, o, (char*)ws, s, stats, &status)
+                        : correct_group<double>(p, &in, &mu, max_iter, o, (char*)ws, s, stats, &status);
+  if (r != FFCZ_OK) return r;
+  if (status == FFCZ_E_NONFINITE) return fail(FFCZ_E_NONFINITE, "x or x_hat holds NaN or Inf");
+  if (status == FFCZ_VERIFY_FAILED) g_err = "FP64 re-verification failed";
+  return status;
+}
+
+size_t ffcz_batched_workspace_bytes(int32_t dtype, int32_t count, const ffcz_instance* inst, int32_t max_iter) {
+  BatchPlan bp;
+  std::string keep = g_err;
+  if (max_iter < 0 || batch_plan(dtype, count, inst, max_iter, bp) != FFCZ_OK) return 0;
+  g_err = keep;
+  return bp.bytes;
+}
+
+int32_t ffcz_correct_batched(int32_t dtype, int32_t count, const ffcz_instance* inst, int32_t max_iter,
+                             const ffcz_options* opts, void* ws, size_t ws_bytes, void* stream, ffcz_stats* stats) {
+  if (max_iter < 0) return fail(FFCZ_E_INVALID, "max_iter must be >= 0");
+  BatchPlan bp;
+  int32_t r = batch_plan(dtype, count, inst, max_iter, bp);
+  if (r != FFCZ_OK) return r;
+  if (!ws || ws_bytes < bp.bytes || ((uintptr_t)ws & 255))
+    return fail(FFCZ_E_WORKSPACE, "workspace smaller than ffcz_batched_workspace_bytes() or misaligned");
+  ffcz_options o;
+  if (opts) o = *opts;
+  else ffcz_default_options(&o);
+  o.masks_out = nullptr;
+  o.viol_per_round = nullptr;
+  for (int i = 0; i < count; ++i) {
+    const ffcz_instance& in = inst[i];
+    if (!in.x_orig || !in.x_base || !in.x_out) return fail(FFCZ_E_INVALID, "null data pointer");
+    if (in.x_orig == in.x_base || in.x_orig == in.x_out) return fail(FFCZ_E_INVALID, "x_orig must not alias");
+    if (!std::isfinite(in.eps_s) || in.eps_s < 0 || !std::isfinite(in.delta_f) || in.delta_f < 0)
+      return fail(FFCZ_E_INVALID, "bounds must be finite and >= 0");
+    if (((uintptr_t)in.x_orig & 15) || ((uintptr_t)in.x_base & 15) || ((uintptr_t)in.x_out & 15))
+      return fail(FFCZ_E_WORKSPACE, "data must be 16-byte aligned");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  // margins: per instance (FP32: suggested from x; FP64: 2^-16)
+  std::vector<double> mus(count, o.margin_rel);
+  for (int i = 0; i < count; ++i) {
+    if (o.margin_rel > 0.0) continue;
+    int64_t sq[3];
+    const int nd = squeeze(inst[i].ndim, inst[i].shape, sq);
+    int64_t N = 1;
+    for (int d = 0; d < nd; ++d) N *= sq[d];
+    r = margin_for(dtype, N, inst[i].x_orig, inst[i].delta_f, (DevState*)(w + bp.off_scratch), s, &mus[i]);
+    if (r != FFCZ_OK) return r;
+  }
+  std::vector<int32_t> status(count, FFCZ_OK);
+  // 1D members: one launch per convolution length; the grouped members follow on the stream
+  r = run_sigs(bp, inst, mus.data(), max_iter, o, w, s);
+  if (r != FFCZ_OK) return r;
+  for (size_t g = 0; g < bp.groups.size(); ++g) {
+    const Plan& p = bp.gplans[g];
+    std::vector<ffcz_instance> gi;
+    std::vector<double> gm;
+    for (int id : bp.groups[g]) {
+      gi.push_back(inst[id]);
+      gm.push_back(mus[id]);
+    }
+    std::vector<int32_t> gs(gi.size(), FFCZ_OK);
+    std::vector<ffcz_stats> gst(gi.size());
+    r = dtype == FFCZ_F32
+            ? correct_group<float>(p, gi.data(), gm.data(), max_iter, o, w + bp.goff[g], s, gst.data(), gs.data())
+            : correct_group<double>(p, gi.data(), gm.data(), max_iter, o, w + bp.goff[g], s, gst.data(), gs.data());
+    if (r != FFCZ_OK) return r;
+    for (size_t k = 0; k < gi.size(); ++k) {
+      status[bp.groups[g][k]] = gs[k];
+      if (stats) stats[bp.groups[g][k]] = gst[k];
+    }
+  }
+  r = collect_sigs(bp, inst, mus.data(), o, w, s, stats, status.data());
+  if (r != FFCZ_OK) return r;
+  return worst(status);
 }
 
 int32_t ffcz_correct_backward(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t rounds, const void* masks,
                               const void* gy, void* gb, void* ws, size_t ws_bytes, void* stream) {
   Plan p;
-  int32_t r = make_plan(dtype, ndim, shape, rounds, p);
+  int32_t r = make_plan(dtype, ndim, shape, rounds, 1, p);
   if (r != FFCZ_OK) return r;
   if (!masks || !gy || !gb) return fail(FFCZ_E_INVALID, "null pointer");
   if (!ws || ws_bytes < p.bytes) return fail(FFCZ_E_WORKSPACE, "workspace smaller than ffcz_workspace_bytes()");

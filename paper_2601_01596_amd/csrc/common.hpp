@@ -24,6 +24,10 @@ struct DevState {
   // margin suggestion: sum of ulp^2 (FP64), count
   double ulp2_sum;
   unsigned long long ulp_cnt;
+  // the instance's data (device pointers): x, x_hat (or dL/dy), y (or dL/dx_hat)
+  const void* px;
+  const void* pxb;
+  void* py;
 };
 
 enum ColMode : int {
@@ -54,8 +58,9 @@ struct ColArgs {
   int64_t s;       // stride along the transformed axis
   int32_t ncols;   // valid contiguous columns
   int32_t ncb;     // column blocks per outer index
+  int64_t outer_per_inst;  // outer indices per instance (instance = outer / outer_per_inst)
   const cx<T>* tw; // stage twiddles of this length
-  DevState* st;
+  DevState* st;    // per-instance loop state
   unsigned long long* part;  // one partial result per block (count; verification: + max at part_stride)
   int64_t part_stride;
   // f-masks (forward record / adjoint read)
@@ -70,13 +75,11 @@ template <typename T, typename TIO>
 struct RowArgs {
   const cx<T>* src;
   cx<T>* dst;
-  int64_t pitch;   // complex entries per spectrum row
-  int64_t nrows;
-  const TIO* x;    // original (ROW_INIT, ROW_FINAL, ROW_VERIFY)
-  const TIO* xb;   // base reconstruction (ROW_INIT), output y (ROW_VERIFY), dL/dy (ROW_BINIT)
-  TIO* y;          // output (ROW_FINAL), dL/dx_hat (ROW_BFINAL)
-  const cx<T>* tw; // stage twiddles of length H followed by H R2C twiddles
-  DevState* st;
+  int64_t pitch;          // complex entries per spectrum row
+  int64_t rows_per_inst;  // rows of one instance (spectrum rows are contiguous across instances)
+  int64_t bpi;            // blocks per instance
+  const cx<T>* tw;        // stage twiddles of length H followed by H R2C twiddles
+  DevState* st;           // per-instance loop state (also holds the instance's data pointers)
   unsigned long long* part;  // one partial result per block (clip count or max bits)
   uint32_t* smask;   // forward: base of the s-mask region; adjoint: s-mask plane to apply
   int64_t s_plane;   // uint32 words per s-mask plane
@@ -103,10 +106,17 @@ __host__ __device__ constexpr int pick_C(int L) {
   while (c > 1 && (long)c * L * (long)sizeof(cx<T>) > 128 * 1024) c /= 2;
   return c;
 }
-// Rows per block for the last-axis passes: about 256 lanes.
+// Elements per lane of the last-axis transforms (radix-16 stages from H = 64 on).
+__host__ __device__ constexpr int pick_E_row(int H) { return H >= 64 ? 16 : pick_E(H); }
+
+// Rows per block for the last-axis passes: up to 64 (one row per lane of a
+// wave at a time), at most 1024 lanes and about 72 KiB of LDS.
+template <typename T>
 __host__ __device__ constexpr int pick_rows(int H) {
-  const int P = H / pick_E(H);
-  return P >= 256 ? 1 : 256 / (P < 1 ? 1 : P);
+  const int P = H / pick_E_row(H) > 0 ? H / pick_E_row(H) : 1;
+  int r = 64;
+  while (r > 1 && (r * P > 1024 || (long)r * (H + 1) * (long)sizeof(cx<T>) > 72 * 1024)) r /= 2;
+  return r;
 }
 
 }  // namespace ffcz

@@ -21,7 +21,9 @@ col_kernel(ColArgs<T> a) {
   __shared__ unsigned long long red_u[NW];
   __shared__ double red_d[NW];
 
-  DevState* st = a.st;
+  const int64_t bid = blockIdx.x;
+  const int64_t o = bid / a.ncb;
+  DevState* st = a.st + o / a.outer_per_inst;
   constexpr bool uses_done = (MODE == COL_FWD || MODE == COL_INV || MODE == COL_XPASS);
   (void)red_d;
   if (uses_done) {
@@ -30,8 +32,6 @@ col_kernel(ColArgs<T> a) {
   const int t = threadIdx.x;
   const int c = t % C;
   const int j = t / C;
-  const int64_t bid = blockIdx.x;
-  const int64_t o = bid / a.ncb;
   const int cb = (int)(bid - o * a.ncb);
   const int col = cb * C + c;
   const bool valid = col < a.ncols;

@@ -4,9 +4,17 @@
 //   C2R:  Z'[k] = (X[k] + X[H-k]*) + i W^-k (X[k] - X[H-k]*),  r = IDFT_H(Z') / n
 //   R2C:  X[k] = (Z[k] + Z[H-k]*)/2 - i W^k (Z[k] - Z[H-k]*)/2,  X[H] = Re Z0 - Im Z0
 // with W = exp(-2 pi i / n).  The imaginary parts of X[0] and X[H] are taken
-// as zero, as a real inverse transform does.  The spatial projection runs on
-// the lane's registers between the two transforms, so the spatial error never
-// leaves the chip.
+// as zero, as a real inverse transform does.
+//
+// Three phases per block:
+//   load     lanes walk the row tile in memory order (coalesced) into LDS;
+//   compute  lane (row rl, j) with rows fastest: a wave touches up to 64 rows
+//            at one index, and the odd LDS row pitch H+1 puts those rows on
+//            distinct banks, so every Stockham exchange is conflict-free;
+//            the spatial projection runs on registers between the two
+//            transforms, so the spatial error never leaves the chip;
+//   store    lanes walk the tile in memory order again, unpacking the R2C
+//            output (or forming y = x + eps) on the way out.
 #pragma once
 #include "common.hpp"
 
@@ -42,106 +50,153 @@ __device__ __forceinline__ TIO closing_clamp(TIO y, TIO x, double E) {
 }
 
 template <typename T, typename TIO, int H, int ROWS, int MODE>
-__global__ void __launch_bounds__(ROWS*(H / pick_E(H)))
+__global__ void __launch_bounds__(ROWS*(H / pick_E_row(H)), 4)
 row_kernel(RowArgs<T, TIO> a) {
-  constexpr int E = pick_E(H);
+  constexpr int E = pick_E_row(H);
   constexpr int P = H / E;
   constexpr int NT = ROWS * P;
-  constexpr int LP = H + 1;
+  constexpr int LP = H + 1;            // LDS row pitch (odd for H >= 2)
+  constexpr int NC = H + 1;            // spectrum entries per row
   using S = Sched<H, E>;
   constexpr int TW = S::twsize;
   constexpr int NW = (NT + 63) / 64;
   constexpr int SW = 2 * (H >= 32 ? H / 32 : 1);  // uint32 words per s-mask row (64-bit padded)
   using V2 = typename Vec2<TIO>::type;
+  constexpr bool spec_in = (MODE == ROW_LOOP || MODE == ROW_FINAL || MODE == ROW_BLOOP || MODE == ROW_BFINAL);
+  constexpr bool spec_out = (MODE == ROW_INIT || MODE == ROW_LOOP || MODE == ROW_VERIFY || MODE == ROW_BINIT ||
+                             MODE == ROW_BLOOP);
+  constexpr bool rec_s = (MODE == ROW_INIT || MODE == ROW_LOOP);
+  constexpr bool use_s = (MODE == ROW_BINIT || MODE == ROW_BLOOP || MODE == ROW_BFINAL);
 
   __shared__ cx<T> lds[ROWS * LP];
   __shared__ cx<T> tws[TW + H];
   __shared__ unsigned long long red_u[NW];
   __shared__ double red_d[NW];
-  __shared__ uint32_t sbits[ROWS * SW];
+  __shared__ uint32_t sbits[(rec_s || use_s) ? ROWS * SW : 1];
 
-  DevState* st = a.st;
-  constexpr bool uses_done = (MODE == ROW_LOOP);
-  if (uses_done) {
+  // block -> (instance, first row); blocks never straddle two instances
+  const int64_t inst = (int64_t)blockIdx.x / a.bpi;
+  const int64_t lrow0 = ((int64_t)blockIdx.x - inst * a.bpi) * ROWS;  // row within the instance
+  const int64_t row0 = inst * a.rows_per_inst + lrow0;                 // row of the spectrum buffers
+  DevState* st = a.st + inst;
+  if constexpr (MODE == ROW_LOOP) {
     if (*(volatile int32_t*)&st->done) return;
   }
   const int t = threadIdx.x;
-  const int rl = t / P;
-  const int j = t - rl * P;
-  const int64_t row0 = (int64_t)blockIdx.x * ROWS;
-  const int64_t g = row0 + rl;
-  const bool valid = g < a.nrows;
+  const int rl = t % ROWS;  // compute mapping: rows fastest
+  const int j = t / ROWS;
+  const int nrow = (int)((a.rows_per_inst - lrow0) < ROWS ? (a.rows_per_inst - lrow0) : ROWS);
   cx<T>* lrow = lds + rl * LP;
   const cx<T>* rtw = tws + TW;
 
   for (int i = t; i < TW + H; i += NT) tws[i] = a.tw[i];
-  constexpr bool rec_s = (MODE == ROW_INIT || MODE == ROW_LOOP);
+
   int kround = 0;
   bool rec = false;
   if constexpr (rec_s) {
     if (MODE == ROW_LOOP) kround = *(volatile int32_t*)&st->round;
     rec = st->record_masks != 0;
-    if (rec) {
+    if (rec)
       for (int i = t; i < ROWS * SW; i += NT) sbits[i] = 0u;
-      __syncthreads();
+  }
+  if constexpr (use_s) {
+    // the rows' mask words, coalesced
+    for (int i = t; i < ROWS * SW; i += NT) {
+      const int r = i / SW, w = i - r * SW;
+      sbits[i] = (r < nrow && w < a.s_row_w32) ? a.smask[(row0 + r) * a.s_row_w32 + w] : 0u;
     }
   }
+  if constexpr (rec_s || use_s) __syncthreads();  // mask words ready before any lane touches them
 
-  cx<T> v[E];
   unsigned long long cnt = 0;
   double mx = 0.0;
+  // INIT: (x, x_hat); VERIFY: (x, y); BINIT: dL/dy in pxb; FINAL: x, writes y; BFINAL writes py
+  const V2* x2 = reinterpret_cast<const V2*>(st->px);
+  const V2* b2 = reinterpret_cast<const V2*>(MODE == ROW_VERIFY ? (const void*)st->py : st->pxb);
 
-  if constexpr (MODE == ROW_INIT || MODE == ROW_VERIFY || MODE == ROW_BINIT) {
-    // real input rows -> packed complex registers
-    const V2* x2 = reinterpret_cast<const V2*>(a.x);
-    const V2* b2 = reinterpret_cast<const V2*>(a.xb);
-    const double Ep = st->Ep;
+  // ------------------------------------------------------------------ load
+  // Unrolled in batches of BL so each lane keeps BL global loads in flight.
+  constexpr int BL = 8;
+  if constexpr (spec_in) {
+    constexpr int NL = (ROWS * NC + NT - 1) / NT;
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-      const int k = j + q * P;
-      double e0 = 0.0, e1 = 0.0;
-      if (valid) {
-        if constexpr (MODE == ROW_BINIT) {
-          const V2 gv = b2[g * H + k];
-          e0 = (double)gv.x;
-          e1 = (double)gv.y;
-          const uint32_t w = a.smask[g * a.s_row_w32 + (2 * k) / 32];
-          const int sh = (2 * k) & 31;
-          e0 = ((w >> sh) & 1u) ? e0 : 0.0;
-          e1 = ((w >> (sh + 1)) & 1u) ? e1 : 0.0;
-        } else {
-          const V2 xv = x2[g * H + k];
-          const V2 bv = b2[g * H + k];
-          e0 = (double)bv.x - (double)xv.x;
-          e1 = (double)bv.y - (double)xv.y;
-          if constexpr (MODE == ROW_INIT) {
-            const bool f0 = isfinite(e0), f1 = isfinite(e1);
-            if (!f0 || !f1) {
-              atomicAdd(&st->nonfinite, (unsigned long long)((!f0) + (!f1)));
-              e0 = f0 ? e0 : 0.0;
-              e1 = f1 ? e1 : 0.0;
-            }
-            const bool k0 = fabs(e0) <= Ep, k1 = fabs(e1) <= Ep;
-            cnt += (!k0) + (!k1);
-            e0 = clipv(e0, Ep);
-            e1 = clipv(e1, Ep);
-            if (rec) atomicOr(&sbits[rl * SW + (2 * k) / 32], ((uint32_t)k0 | ((uint32_t)k1 << 1)) << ((2 * k) & 31));
-          } else {
-            mx = fmax(mx, fmax(fabs(e0), fabs(e1)));
-          }
+    for (int b0 = 0; b0 < NL; b0 += BL) {
+      cx<T> tmp[BL];
+#pragma unroll
+      for (int u = 0; u < BL; ++u) {
+        const int f = t + (b0 + u) * NT;
+        const int r = f / NC, k = f - r * NC;
+        tmp[u] = (b0 + u < NL && f < ROWS * NC && r < nrow) ? a.src[(row0 + r) * a.pitch + k] : cx<T>{T(0), T(0)};
+      }
+#pragma unroll
+      for (int u = 0; u < BL; ++u) {
+        const int f = t + (b0 + u) * NT;
+        if (b0 + u < NL && f < ROWS * NC) {
+          const int r = f / NC, k = f - r * NC;
+          lds[r * LP + k] = tmp[u];
         }
       }
-      v[q] = cx<T>{(T)e0, (T)e1};  // eps0 is rounded once to the working type
     }
   } else {
-    // spectrum row -> LDS -> packed C2R input
+    // real rows -> packed pairs; INIT also forms eps0 = x_hat - x in FP64 and clips it
+    const double Ep = st->Ep;
+    constexpr int NL = (ROWS * H + NT - 1) / NT;
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-      const int k = j + q * P;
-      lrow[k] = valid ? a.src[g * a.pitch + k] : cx<T>{T(0), T(0)};
+    for (int b0 = 0; b0 < NL; b0 += BL) {
+      V2 xa[BL], xbv[BL];
+#pragma unroll
+      for (int u = 0; u < BL; ++u) {
+        const int f = t + (b0 + u) * NT;
+        const int r = f / H, m = f - r * H;
+        const bool ok = b0 + u < NL && f < ROWS * H && r < nrow;
+        const int64_t gi = (lrow0 + r) * H + m;
+        if constexpr (MODE != ROW_BINIT) {
+          if (ok) xa[u] = x2[gi];
+        }
+        if (ok) xbv[u] = b2[gi];
+      }
+#pragma unroll
+      for (int u = 0; u < BL; ++u) {
+        const int f = t + (b0 + u) * NT;
+        if (!(b0 + u < NL && f < ROWS * H)) continue;
+        const int r = f / H, m = f - r * H;
+        double e0 = 0.0, e1 = 0.0;
+        if (r < nrow) {
+          if constexpr (MODE == ROW_BINIT) {
+            const uint32_t w = sbits[r * SW + (2 * m) / 32];
+            const int sh = (2 * m) & 31;
+            e0 = ((w >> sh) & 1u) ? (double)xbv[u].x : 0.0;
+            e1 = ((w >> (sh + 1)) & 1u) ? (double)xbv[u].y : 0.0;
+          } else {
+            e0 = (double)xbv[u].x - (double)xa[u].x;
+            e1 = (double)xbv[u].y - (double)xa[u].y;
+            if constexpr (MODE == ROW_INIT) {
+              const bool f0 = isfinite(e0), f1 = isfinite(e1);
+              if (!f0 || !f1) {
+                atomicAdd(&st->nonfinite, (unsigned long long)((!f0) + (!f1)));
+                e0 = f0 ? e0 : 0.0;
+                e1 = f1 ? e1 : 0.0;
+              }
+              const bool k0 = fabs(e0) <= Ep, k1 = fabs(e1) <= Ep;
+              cnt += (!k0) + (!k1);
+              e0 = clipv(e0, Ep);
+              e1 = clipv(e1, Ep);
+              if (rec)
+                atomicOr(&sbits[r * SW + (2 * m) / 32], ((uint32_t)k0 | ((uint32_t)k1 << 1)) << ((2 * m) & 31));
+            } else {
+              mx = fmax(mx, fmax(fabs(e0), fabs(e1)));
+            }
+          }
+        }
+        lds[r * LP + m] = cx<T>{(T)e0, (T)e1};  // rounded once to the working type
+      }
     }
-    if (j == 0) lrow[H] = valid ? a.src[g * a.pitch + H] : cx<T>{T(0), T(0)};
-    __syncthreads();
+  }
+  __syncthreads();
+
+  // ------------------------------------------------------------------ compute
+  cx<T> v[E];
+  if constexpr (spec_in) {
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const int k = j + q * P;
@@ -160,53 +215,20 @@ row_kernel(RowArgs<T, TIO> a) {
     if constexpr (MODE == ROW_FINAL) {
       // the source holds only the last-axis R2C of eps, so the C2R scale is 1/n_last
       const T scz = T(1) / T(2 * H);
-      const V2* x2 = reinterpret_cast<const V2*>(a.x);
-      V2* y2 = reinterpret_cast<V2*>(a.y);
-      const double Eb = st->E;
 #pragma unroll
-      for (int q = 0; q < E; ++q) {
-        const int k = j + q * P;
-        if (valid) {
-          const V2 xv = x2[g * H + k];
-          const double e0 = (double)(v[q].re * scz), e1 = (double)(v[q].im * scz);
-          TIO y0 = round_io<TIO>((double)xv.x + e0);
-          TIO y1 = round_io<TIO>((double)xv.y + e1);
-          y0 = closing_clamp<TIO>(y0, xv.x, Eb);
-          y1 = closing_clamp<TIO>(y1, xv.y, Eb);
-          V2 out;
-          out.x = y0;
-          out.y = y1;
-          y2[g * H + k] = out;
-        }
-      }
-      return;
+      for (int q = 0; q < E; ++q) v[q] = scal(v[q], scz);
     } else if constexpr (MODE == ROW_BLOOP || MODE == ROW_BFINAL) {
 #pragma unroll
       for (int q = 0; q < E; ++q) {
         const int k = j + q * P;
-        uint32_t w = 0;
-        if (valid) w = a.smask[g * a.s_row_w32 + (2 * k) / 32];
+        const uint32_t w = sbits[rl * SW + (2 * k) / 32];
         const int sh = (2 * k) & 31;
-        const T e0 = ((w >> sh) & 1u) ? v[q].re * sc : T(0);
-        const T e1 = ((w >> (sh + 1)) & 1u) ? v[q].im * sc : T(0);
-        v[q] = cx<T>{e0, e1};
-      }
-      if constexpr (MODE == ROW_BFINAL) {
-        V2* y2 = reinterpret_cast<V2*>(a.y);
-#pragma unroll
-        for (int q = 0; q < E; ++q) {
-          const int k = j + q * P;
-          if (valid) {
-            V2 out;
-            out.x = (TIO)v[q].re;
-            out.y = (TIO)v[q].im;
-            y2[g * H + k] = out;
-          }
-        }
-        return;
+        v[q].re = ((w >> sh) & 1u) ? v[q].re * sc : T(0);
+        v[q].im = ((w >> (sh + 1)) & 1u) ? v[q].im * sc : T(0);
       }
     } else {  // ROW_LOOP: ProjectOntoSCube
       const T Ep = to_t<T>(st->Ep);
+      const bool valid = rl < nrow;
 #pragma unroll
       for (int q = 0; q < E; ++q) {
         const int k = j + q * P;
@@ -220,29 +242,77 @@ row_kernel(RowArgs<T, TIO> a) {
           atomicOr(&sbits[rl * SW + (2 * k) / 32], ((uint32_t)k0 | ((uint32_t)k1 << 1)) << ((2 * k) & 31));
       }
     }
+  } else {
+#pragma unroll
+    for (int q = 0; q < E; ++q) v[q] = lrow[j + q * P];
   }
-
-  // ---- forward R2C of the packed registers
-  fft<T, H, E, false, 1, LP>(v, lds, tws, rl, j);
+  if constexpr (spec_out) fft<T, H, E, false, 1, LP>(v, lds, tws, rl, j);
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < E; ++q) lrow[j + q * P] = v[q];
   __syncthreads();
-  if (valid) {
+
+  // ------------------------------------------------------------------ store
+  if constexpr (spec_out) {
+    constexpr int NS = (ROWS * NC + NT - 1) / NT;
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-      const int k = j + q * P;
-      const cx<T> Zk = v[q];
-      const cx<T> Zm = lrow[(H - k) & (H - 1)];
-      const cx<T> ev = scal(Zk + conjg(Zm), T(0.5));
-      const cx<T> d = Zk - conjg(Zm);
-      const cx<T> od = cx<T>{d.im * T(0.5), -d.re * T(0.5)};  // d / (2i)
-      a.dst[g * a.pitch + k] = ev + cmul(rtw[k], od);
+    for (int it = 0; it < NS; ++it) {
+      const int f = t + it * NT;
+      const int r = f / NC, k = f - r * NC;
+      if (f < ROWS * NC && r < nrow) {
+        const cx<T>* zr = lds + r * LP;
+        cx<T> X;
+        if (k == H) {
+          const cx<T> z0 = zr[0];
+          X = cx<T>{z0.re - z0.im, T(0)};
+        } else {
+          const cx<T> Zk = zr[k];
+          const cx<T> Zm = zr[(H - k) & (H - 1)];
+          const cx<T> ev = scal(Zk + conjg(Zm), T(0.5));
+          const cx<T> d = Zk - conjg(Zm);
+          const cx<T> od = cx<T>{d.im * T(0.5), -d.re * T(0.5)};  // d / (2i)
+          X = ev + cmul(rtw[k], od);
+        }
+        a.dst[(row0 + r) * a.pitch + k] = X;
+      }
     }
-    if (j == 0) a.dst[g * a.pitch + H] = cx<T>{v[0].re - v[0].im, T(0)};
+  } else {
+    // ROW_FINAL: y = x + eps formed in FP64, rounded once, clamped;  ROW_BFINAL: store g
+    V2* y2 = reinterpret_cast<V2*>(st->py);
+    const double Eb = st->E;
+    constexpr int NS = (ROWS * H + NT - 1) / NT;
+#pragma unroll
+    for (int b0 = 0; b0 < NS; b0 += BL) {
+      V2 xa[BL];
+      if constexpr (MODE == ROW_FINAL) {
+#pragma unroll
+        for (int u = 0; u < BL; ++u) {
+          const int f = t + (b0 + u) * NT;
+          const int r = f / H, m = f - r * H;
+          if (b0 + u < NS && f < ROWS * H && r < nrow) xa[u] = x2[(lrow0 + r) * H + m];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < BL; ++u) {
+        const int f = t + (b0 + u) * NT;
+        const int r = f / H, m = f - r * H;
+        if (b0 + u < NS && f < ROWS * H && r < nrow) {
+          const cx<T> e = lds[r * LP + m];
+          V2 out;
+          if constexpr (MODE == ROW_FINAL) {
+            out.x = closing_clamp<TIO>(round_io<TIO>((double)xa[u].x + (double)e.re), xa[u].x, Eb);
+            out.y = closing_clamp<TIO>(round_io<TIO>((double)xa[u].y + (double)e.im), xa[u].y, Eb);
+          } else {
+            out.x = (TIO)e.re;
+            out.y = (TIO)e.im;
+          }
+          y2[(lrow0 + r) * H + m] = out;
+        }
+      }
+    }
   }
 
-  // ---- counters and masks
+  // ------------------------------------------------------------------ partials and masks
   if constexpr (MODE == ROW_INIT || MODE == ROW_LOOP || MODE == ROW_VERIFY) {
     cnt = wave_sum_u64(cnt);
     mx = wave_max_f64(mx);
@@ -268,7 +338,7 @@ row_kernel(RowArgs<T, TIO> a) {
         for (int i = t; i < ROWS * SW; i += NT) {
           const int r = i / SW;
           const int w = i - r * SW;
-          if (row0 + r < a.nrows && w < a.s_row_w32) plane[(row0 + r) * a.s_row_w32 + w] = sbits[i];
+          if (r < nrow && w < a.s_row_w32) plane[(row0 + r) * a.s_row_w32 + w] = sbits[i];
         }
       }
     }

@@ -9,8 +9,8 @@ static hipError_t go(int H, const RowArgs<T, TIO>& a, int64_t nb, hipStream_t s)
   switch (H) {
 #define FFCZ_CASE(HH)                                                                  \
   case HH: {                                                                           \
-    constexpr int R = pick_rows(HH);                                                   \
-    constexpr int NT = R * (HH / pick_E(HH));                                          \
+    constexpr int R = pick_rows<T>(HH);                                                   \
+    constexpr int NT = R * (HH / pick_E_row(HH));                                          \
     hipLaunchKernelGGL((row_kernel<T, TIO, HH, R, MODE>), dim3((unsigned)nb), dim3(NT), 0, s, a); \
     return hipGetLastError();                                                          \
   }

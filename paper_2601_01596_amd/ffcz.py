@@ -31,7 +31,7 @@ E_HIP = -5
 
 EXPORTS = ("ffcz_version", "ffcz_last_error", "ffcz_default_options", "ffcz_workspace_bytes",
            "ffcz_mask_bytes", "ffcz_suggest_margin", "ffcz_correct", "ffcz_correct_backward",
-           "ffcz_profile_enable", "ffcz_profile_read")
+           "ffcz_batched_workspace_bytes", "ffcz_correct_batched", "ffcz_profile_enable", "ffcz_profile_read")
 
 PROFILE_KINDS = ("init", "y_fwd", "x_pass", "y_inv", "z_pass", "finalize", "verify_z", "verify_y", "verify_x",
                  "adjoint_z", "adjoint_y", "adjoint_x")
@@ -66,6 +66,19 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+        ("shape", ctypes.c_int64 * 3),
+        ("x_orig", ctypes.c_void_p),
+        ("x_base", ctypes.c_void_p),
+        ("x_out", ctypes.c_void_p),
+        ("eps_s", ctypes.c_double),
+        ("delta_f", ctypes.c_double),
+    ]
 
 
 class Profile(ctypes.Structure):
@@ -110,6 +123,13 @@ def lib() -> ctypes.CDLL:
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                             ctypes.c_void_p]
         L.ffcz_correct_backward.restype = ctypes.c_int32
+        L.ffcz_batched_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Instance),
+                                                   ctypes.c_int32]
+        L.ffcz_batched_workspace_bytes.restype = ctypes.c_size_t
+        L.ffcz_correct_batched.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Instance), ctypes.c_int32,
+                                           ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                           ctypes.POINTER(Stats)]
+        L.ffcz_correct_batched.restype = ctypes.c_int32
         L.ffcz_profile_enable.argtypes = [ctypes.c_int32]
         L.ffcz_profile_enable.restype = None
         L.ffcz_profile_read.argtypes = [ctypes.POINTER(Profile)]
@@ -177,6 +197,19 @@ def ffcz_correct_backward(dtype: int, shape, rounds: int, masks_ptr: int, grad_o
     return int(lib().ffcz_correct_backward(dtype, nd, arr, int(rounds), ctypes.c_void_p(masks_ptr),
                                            ctypes.c_void_p(grad_out_ptr), ctypes.c_void_p(grad_base_ptr),
                                            ctypes.c_void_p(ws_ptr), ws_bytes, ctypes.c_void_p(stream)))
+
+
+def ffcz_batched_workspace_bytes(dtype: int, instances, max_iter: int) -> int:
+    arr = (Instance * len(instances))(*instances)
+    return int(lib().ffcz_batched_workspace_bytes(dtype, len(instances), arr, max_iter))
+
+
+def ffcz_correct_batched(dtype: int, instances, max_iter: int, opts: Optional[Options], ws_ptr: int, ws_bytes: int,
+                         stream: int, stats) -> int:
+    arr = (Instance * len(instances))(*instances)
+    return int(lib().ffcz_correct_batched(dtype, len(instances), arr, int(max_iter),
+                                          ctypes.byref(opts) if opts is not None else None, ctypes.c_void_p(ws_ptr),
+                                          ws_bytes, ctypes.c_void_p(stream), stats))
 
 
 def ffcz_profile_enable(on: bool) -> None:
@@ -267,6 +300,48 @@ def correct(x, xb, eps_s: float, delta_f: float, max_iter: int, *, margin: float
     if check and st < 0:
         raise FFCzError(st, ffcz_last_error())
     return Result(y=y, status=st, stats=stats.as_dict(), masks=masks, viol=viol)
+
+
+def correct_batched(members, max_iter: int, *, margin: float = 0.0, fixed: bool = False, verify: bool = True,
+                    chunk: int = 4, ws=None, check: bool = True):
+    """``ffcz_correct_batched`` over ``members = [(x, xb, eps_s, delta_f), ...]`` (device tensors).
+
+    Returns ``(outputs, status, per-member stats dicts)``.
+    """
+    torch = _torch()
+    if not members:
+        return [], OK, []
+    dt = _dtype_code(members[0][0])
+    outs, insts = [], []
+    for (x, xb, E, D) in members:
+        _check_tensor(x, "x")
+        _check_tensor(xb, "xb")
+        if x.shape != xb.shape or x.dtype != xb.dtype or _dtype_code(x) != dt:
+            raise FFCzError(E_INVALID, "members must pair tensors of one dtype")
+        if x.dim() < 1 or x.dim() > 3:
+            raise FFCzError(E_SHAPE, "members must have 1 to 3 dimensions")
+        y = torch.empty_like(x)
+        outs.append(y)
+        sh = list(x.shape) + [1] * (3 - x.dim())
+        insts.append(Instance(x.dim(), 0, (ctypes.c_int64 * 3)(*sh), x.data_ptr(), xb.data_ptr(), y.data_ptr(),
+                              float(E), float(D)))
+    dev = members[0][0].device
+    if ws is None:
+        nbytes = ffcz_batched_workspace_bytes(dt, insts, max_iter)
+        if nbytes == 0:
+            raise FFCzError(E_SHAPE, ffcz_last_error())
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    opts = ffcz_default_options()
+    opts.margin_rel = float(margin)
+    opts.fixed_iterations = 1 if fixed else 0
+    opts.verify_fp64 = 1 if verify else 0
+    opts.graph_chunk = int(chunk)
+    stats = (Stats * len(insts))()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    st = ffcz_correct_batched(dt, insts, max_iter, opts, ws.data_ptr(), ws.numel(), stream, stats)
+    if check and st < 0:
+        raise FFCzError(st, ffcz_last_error())
+    return outs, st, [s.as_dict() for s in stats]
 
 
 def correct_backward(grad_y, masks, rounds: int, ws=None):

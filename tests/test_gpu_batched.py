@@ -1,0 +1,134 @@
+"""Batched correction (ffcz_correct_batched) against the oracle, instance by instance.
+
+1D members of any length run one block per signal (four-step FFT; Bluestein for
+lengths that are not powers of two); same-shape 2D members share every launch.
+Tolerances as in test_gpu_parity: FP64 1e-12 with equal rounds, FP32 1e-5 (rounds
+within one), FP64 re-verification of both bounds for every member.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ffcz as O
+from paper_2601_01596_amd import ffcz as F
+from paper_2601_01596_amd import workloads as W
+from tests.gpu_util import rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _member(shape, seed, dt, q=90.0, r=1e-2):
+    if len(shape) == 1:
+        x = W.eeg_signal(seed, shape[0])
+    else:
+        x = W.grf(shape, 2.0, seed)
+    return W.make_problem("m", x, dt, r, q, 200)
+
+
+def _run(problems, max_iter=200, **kw):
+    import torch
+    mem = [(torch.from_numpy(p.x).cuda(), torch.from_numpy(p.xb).cuda(), p.E, p.Delta) for p in problems]
+    outs, st, stats = F.correct_batched(mem, max_iter, check=False, **kw)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in outs], st, stats
+
+
+def _check(p, y, s, dt, max_iter=200):
+    assert s["max_spatial_err"] <= p.E and s["max_spectral_err"] <= p.Delta, s
+    mu = s["margin_used"]
+    orc = O.correct(p.x, p.xb, p.E, p.Delta, max_iter, mu=mu)
+    k = s["rounds"]
+    if dt == np.float64:
+        assert k == orc.rounds, (k, orc.rounds)
+        assert rel_err(y, orc.y) <= 1e-12
+        assert s["f_viol_initial"] == orc.viol[0]
+    else:
+        if k != orc.rounds:
+            assert abs(k - orc.rounds) <= 1
+            orc = O.correct(p.x, p.xb, p.E, p.Delta, k, mu=mu, fixed=True)
+        assert rel_err(y, orc.y) <= 1e-5
+    ms, mf, nv, ok = O.verify(p.x, y, p.E, p.Delta)
+    assert ok and nv == 0
+    assert s["max_spatial_err"] == pytest.approx(ms, rel=1e-12)
+    assert s["max_spectral_err"] == pytest.approx(mf, rel=1e-8)
+
+
+LENGTHS = [2, 3, 7, 8, 64, 100, 1000, 1024, 4096, 4097, 31000, 65536, 100003]
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_1d_members_any_length(dt):
+    probs = [_member((L,), 100 + i, dt) for i, L in enumerate(LENGTHS)]
+    ys, st, stats = _run(probs)
+    assert st == F.OK, (st, F.ffcz_last_error(), stats)
+    for p, y, s, L in zip(probs, ys, stats, LENGTHS):
+        say(f"[batched] L={L} rounds={s['rounds']}")
+        _check(p, y, s, dt)
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_2d_group_mixed_with_1d(dt):
+    probs = [_member((64, 128), 200 + i, dt) for i in range(5)]
+    probs += [_member((5000,), 300, dt), _member((32, 64), 301, dt), _member((16, 16, 16), 302, dt)]
+    ys, st, stats = _run(probs)
+    assert st == F.OK, (st, F.ffcz_last_error(), stats)
+    for p, y, s in zip(probs, ys, stats):
+        _check(p, y, s, dt)
+
+
+def test_batched_matches_single_calls_bitwise():
+    import torch
+    probs = [_member((64, 128), 400 + i, np.float32) for i in range(3)]
+    ys, st, stats = _run(probs)
+    for p, y in zip(probs, ys):
+        r = F.correct(torch.from_numpy(p.x).cuda(), torch.from_numpy(p.xb).cuda(), p.E, p.Delta, 200)
+        assert np.array_equal(r.y.cpu().numpy().view(np.uint32), y.view(np.uint32))
+
+
+def test_batched_statuses():
+    # a member capped at 0 rounds reports NOT_CONVERGED; a NaN member reports NONFINITE
+    import torch
+    a = _member((4096,), 500, np.float32, q=50.0)
+    b = _member((64, 64), 501, np.float32, q=50.0)
+    ys, st, stats = _run([a, b], max_iter=0)
+    assert st == F.NOT_CONVERGED and all(s["rounds"] == 0 for s in stats)
+    bad = a.xb.copy()
+    bad[17] = np.nan
+    mem = [(torch.from_numpy(a.x).cuda(), torch.from_numpy(bad).cuda(), a.E, a.Delta)]
+    _, st, stats = F.correct_batched(mem, 10, check=False)
+    assert st == F.E_NONFINITE and stats[0]["nonfinite"] == 1
+
+
+@pytest.mark.timeout(900)
+def test_full_batch_eeg_and_diffraction():
+    """512 EEG-like signals (lengths log-uniform in [2^12, 2^18]) and 64 diffraction-like
+    2048^2 fields in one batched call; every member re-verified in FP64 by the library and by
+    torch, a sample against the oracle."""
+    import torch
+    O.set_workers(max(1, min(16, O.default_workers())))
+    say("[full] generating 512 EEG signals and 64 diffraction fields")
+    eeg = [W.config_eeg(i) for i in range(512)]
+    hedm = [W.config_diffraction(j) for j in range(64)]
+    probs = eeg + hedm
+    mem = [(torch.from_numpy(p.x).cuda(), torch.from_numpy(p.xb).cuda(), p.E, p.Delta) for p in probs]
+    say("[full] batched correction")
+    outs, st, stats = F.correct_batched(mem, 200, check=False)
+    torch.cuda.synchronize()
+    assert st == F.OK, (st, F.ffcz_last_error())
+    for (x, _, E, D), y, s in zip(mem, outs, stats):
+        assert s["max_spatial_err"] <= E and s["max_spectral_err"] <= D
+        d = y.double() - x.double()
+        Dk = torch.fft.rfftn(d)
+        assert float(d.abs().max()) <= E
+        assert float(torch.maximum(Dk.real.abs().max(), Dk.imag.abs().max())) <= D
+    rounds = [s["rounds"] for s in stats]
+    say(f"[full] rounds: eeg max {max(rounds[:512])} mean {np.mean(rounds[:512]):.1f}; "
+        f"hedm max {max(rounds[512:])} mean {np.mean(rounds[512:]):.1f}")
+    for i in list(range(0, 512, 97)) + [512, 575]:
+        _check(probs[i], outs[i].cpu().numpy(), stats[i], np.float32)
