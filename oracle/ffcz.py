@@ -131,6 +131,21 @@ def suggest_margin(x: np.ndarray, Delta: float) -> float:
     return float(min(0.5, max(DEFAULT_MU, mu)))
 
 
+def spectral_thresholds(Delta: float, mu: float, out_dtype) -> tuple:
+    """``(Delta_c, Delta_p)``: the bound the check compares with and the bound the
+    f-projection clips to.
+
+    FP64 output: the check uses Delta itself and the projection the shrunk
+    ``Delta (1 - mu)`` (Sec. IV-B).  FP32 output: rounding ``y`` moves every
+    component by up to the margin's 8 standard deviations (``mu Delta``), and a
+    coefficient the check accepted in ``(Delta_p, Delta]`` is never clipped, so the
+    check itself runs ``mu Delta`` below Delta and the projection another
+    ``mu Delta`` below the check.
+    """
+    rho = 0.0 if np.dtype(out_dtype) == np.float64 else float(mu)
+    return Delta * (1.0 - rho), Delta * (1.0 - rho - mu)
+
+
 def closing_clamp(y32: np.ndarray, x: np.ndarray, E: float) -> np.ndarray:
     """Move each FP32 output one ulp at a time toward ``x`` until
     ``|(double)y - (double)x| <= E`` holds in FP64."""
@@ -219,7 +234,7 @@ def correct(x, xb, E: float, Delta: float, max_iter: int, *, mu: Optional[float]
     shape = x.shape
     x64 = x.astype(np.float64)
     Ep = E * (1.0 - mu)
-    Dp = Delta * (1.0 - mu)
+    Dc, Dp = spectral_thresholds(Delta, mu, out_dtype)
 
     # Alg. 1, first statement: the spatial error of the base reconstruction.
     eps = xb.astype(np.float64) - x64
@@ -233,7 +248,7 @@ def correct(x, xb, E: float, Delta: float, max_iter: int, *, mu: Optional[float]
     converged = False
     while True:
         delta = fft(eps)                          # FFT
-        v = count_violations(delta, Delta)        # CheckConvergence
+        v = count_violations(delta, Dc)           # CheckConvergence
         viol.append(v)
         if v == 0 and not fixed:
             converged = True

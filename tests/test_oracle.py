@@ -257,6 +257,23 @@ def test_fp32_output_meets_both_bounds_in_fp64():
     assert ok and nv == 0
 
 
+def test_spectral_thresholds_per_output_precision():
+    mu = 3e-5
+    assert ffcz.spectral_thresholds(2.0, mu, np.float64) == (2.0, 2.0 * (1.0 - mu))
+    dc, dp = ffcz.spectral_thresholds(2.0, mu, np.float32)
+    assert dc == pytest.approx(2.0 * (1.0 - mu), rel=1e-15) and dp == pytest.approx(2.0 * (1.0 - 2.0 * mu), rel=1e-15)
+
+
+def test_fp32_outputs_keep_delta_after_rounding():
+    # EEG-like signals whose accepted coefficients sit just below Delta: checking the FP32
+    # iterate against Delta itself lets the output rounding lift some of them above it
+    for i in (2, 19, 97, 101):
+        p = W.config_eeg(i)
+        r = ffcz.correct(p.x, p.xb, p.E, p.Delta, 200)
+        ms, mf, nv, ok = ffcz.verify(p.x, r.y, p.E, p.Delta)
+        assert r.status == ffcz.OK and ok and nv == 0, (i, mf / p.Delta - 1.0)
+
+
 def test_suggest_margin_formula_on_constant_field():
     # all points share one ulp u: sigma = u / sqrt(12)
     x = np.full((16, 16), 3.0, np.float32)
