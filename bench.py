@@ -35,6 +35,44 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Sources that define the x-pass kernel; the committed counter summary applies only while they
+# are unchanged.
+XPASS_SOURCES = ("paper_2601_01596_amd/csrc/kernels_col.hpp", "paper_2601_01596_amd/csrc/fft_engine.hpp",
+                 "paper_2601_01596_amd/csrc/common.hpp", "paper_2601_01596_amd/csrc/launch_col_f32.hip")
+TRAFFIC_FILE = "profiles/xpass_lognormal512_fp32_traffic.md"
+
+
+def sources_digest(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of the x-pass from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (copy-calibrated), or None if that summary is missing, for another kernel, or older
+    than the kernel sources."""
+    try:
+        with open(os.path.join(ROOT, TRAFFIC_FILE)) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    kv = {}
+    for ln in lines:
+        if ":" in ln and not ln.startswith(("#", "|", " ")):
+            k, v = ln.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel") != kernel or kv.get("kernel_sources_sha256") != sources_digest(XPASS_SOURCES):
+        return None
+    try:
+        return int(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def pass_bytes(kind, N, M, s, c):
     """Algorithmic HBM bytes of one launch of a pass kind (s: real bytes, c: complex bytes)."""
     if kind in ("y_fwd", "x_pass", "y_inv", "z_pass", "adjoint_y", "adjoint_x"):
@@ -79,6 +117,44 @@ def run_correct(F, torch, prob, steps, warmup, profile):
     return (t1 - t0) / steps, res, prof
 
 
+def steady_rounds(F, torch, prob, K, reps):
+    """Per-round time from fixed-round calls: (t(K rounds) - t(0 rounds)) / K, verification off."""
+    x = torch.from_numpy(prob.x).cuda()
+    xb = torch.from_numpy(prob.xb).cuda()
+    dt = F.F32 if prob.x.dtype.itemsize == 4 else F.F64
+    ws = F.workspace(dt, prob.x.shape, K, x.device)
+    y = torch.empty_like(x)
+    mu = F.correct(x, xb, prob.E, prob.Delta, 0, fixed=True, verify=False, ws=ws, out=y).stats["margin_used"]
+
+    def timed(k):
+        F.correct(x, xb, prob.E, prob.Delta, k, margin=mu, fixed=True, verify=False, ws=ws, out=y)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            F.correct(x, xb, prob.E, prob.Delta, k, margin=mu, fixed=True, verify=False, ws=ws, out=y)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    t0, tk = timed(0), timed(K)
+    del ws
+    return (tk - t0) / K, t0
+
+
+def copy_ceiling(F, torch, nbytes, reps):
+    """Rate of the library's streaming copy kernel (bytes read + written per second)."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    F.copy_(dst, src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        F.copy_(dst, src)
+    b.record()
+    torch.cuda.synchronize()
+    return 2 * nbytes / (a.elapsed_time(b) / reps * 1e-3) / 1e9
+
+
 def cpu_baseline(prob, rounds_gpu):
     """Oracle on the host cores; rounds capped at 3, time scaled by checks run."""
     from oracle import ffcz as O
@@ -93,9 +169,30 @@ def cpu_baseline(prob, rounds_gpu):
     t_est = t * scale
     gbs = prob.x.nbytes / t_est / 1e9
     return {"value": gbs, "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "seconds_per_check": t / (r.rounds + 1), "host": host_description(),
             "sample": (f"full {'x'.join(map(str, prob.x.shape))} FP32 input, oracle run for {r.rounds} of "
                        f"{rounds_gpu} rounds ({t:.1f} s incl. FP64 verification), time scaled by checks "
                        f"({rounds_gpu + 1}/{r.rounds + 1})")}
+
+
+def host_description():
+    """CPU model and memory of the host the oracle ran on."""
+    model, mem = "unknown CPU", "unknown memory"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as fh:
+            for ln in fh:
+                if ln.startswith("MemTotal"):
+                    mem = f"{int(ln.split()[1]) / 2 ** 20:.0f} GiB"
+                    break
+    except OSError:
+        pass
+    return f"{model}, {mem}, {len(os.sched_getaffinity(0))} cores visible"
+
 
 
 def fwd_bwd(F, torch, W, n, K, steps):
@@ -121,6 +218,36 @@ def fwd_bwd(F, torch, W, n, K, steps):
     return (time.perf_counter() - t0) / steps * 1e3
 
 
+def batch_leg(F, torch, W, steps):
+    """512 EEG-like 1D signals (lengths log-uniform in [2^12, 2^18]) and 64 diffraction-like
+    2048^2 fields, FP32, corrected in one ffcz_correct_batched call per step."""
+    probs = [W.config_eeg(i) for i in range(512)] + [W.config_diffraction(j) for j in range(64)]
+    mem = [(torch.from_numpy(p.x).cuda(), torch.from_numpy(p.xb).cuda(), p.E, p.Delta) for p in probs]
+    nbytes = sum(p.x.nbytes for p in probs)
+
+    def timed(members):
+        res = F.correct_batched(members, 200)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = F.correct_batched(members, 200)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, res
+
+    t, (outs, st, stats) = timed(mem)
+    t1d, _ = timed(mem[:512])
+    t2d, _ = timed(mem[512:])
+    r1 = [s["rounds"] for s in stats[:512]]
+    r2 = [s["rounds"] for s in stats[512:]]
+    return {"batch_ms": t * 1e3, "batch_GBps": nbytes / t / 1e9, "batch_status": st, "batch_bytes": nbytes,
+            "batch_1d_only_ms": t1d * 1e3, "batch_2d_only_ms": t2d * 1e3,
+            "batch_rounds_1d_mean": float(sum(r1)) / len(r1), "batch_rounds_1d_max": max(r1),
+            "batch_rounds_2d_mean": float(sum(r2)) / len(r2), "batch_rounds_2d_max": max(r2),
+            "batch_config": "512 EEG-like FP32 signals (L log-uniform in [2^12, 2^18], seeds 40000+i) + "
+                            "64 diffraction-like FP32 2048^2 fields (seeds 50000+j); E = 1e-3 range, "
+                            "Delta = 90th pct, cap 200"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +257,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-steady", action="store_true")
     ap.add_argument("--grad-n", type=int, default=256)
     ap.add_argument("--grad-rounds", type=int, default=50)
     args = ap.parse_args()
@@ -144,6 +273,10 @@ def main():
     from paper_2601_01596_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    # tile decisions of this process, written to a scratch file and reported under extra.tuning
+    import tempfile
+    tune_path = os.path.join(tempfile.mkdtemp(prefix="ffcz_bench_"), "plans.json")
+    F.ffcz_set_tuning(1, tune_path)
     n = args.n
     log(f"[bench] generating {n}^3 lognormal field (seed 2)")
     t0 = time.perf_counter()
@@ -173,13 +306,29 @@ def main():
                   "GBps": pass_bytes(k, N, M, s, c) / (v[0] / v[1] * 1e-3) / 1e9}
               for k, v in prof.items() if v[1] > 0}
 
-    extra = {"rounds_fp32": r32.stats["rounds"], "fp32_ms": t32 * 1e3,
+    try:
+        with open(tune_path) as fh:
+            tuning = {k: v for k, v in json.load(fh)["entries"].items()}
+    except (OSError, ValueError, KeyError):
+        tuning = {}
+    extra = {"tuning": tuning, "rounds_fp32": r32.stats["rounds"], "fp32_ms": t32 * 1e3,
              "max_spatial_err_over_E": r32.stats["max_spatial_err"] / p32.E,
              "max_spectral_err_over_Delta": r32.stats["max_spectral_err"] / p32.Delta,
              "margin_fp32": r32.stats["margin_used"],
              "round_kernel_ms": per_round_ms,
              "round_model_GBps": 8 * M * c / (per_round_ms * 1e-3) / 1e9,
              "passes": passes}
+    log("[bench] copy ceiling (1 GiB streaming copy)")
+    cp = copy_ceiling(F, torch, 1 << 30, 10)
+    extra["copy_kernel_GBps"] = cp
+    if not args.no_steady:
+        log("[bench] steady-state rounds (50 fixed rounds vs 0)")
+        t_round, t_fixed0 = steady_rounds(F, torch, p32, 50, 3)
+        gbs = 8 * M * c / (t_round * 1e-3) / 1e9
+        extra.update({"steady_round_ms": t_round, "steady_rounds_per_s": 1e3 / t_round,
+                      "steady_round_model_GBps": gbs, "steady_round_frac_of_peak": gbs / HBM_PEAK_GBS,
+                      "steady_round_frac_of_copy": gbs / cp, "call_ms_0_rounds_no_verify": t_fixed0})
+        log(f"[bench] round {t_round:.3f} ms ({gbs:.0f} GB/s model), copy {cp:.0f} GB/s")
     if p64 is not None:
         log("[bench] FP64 timed steps")
         t64, r64, _ = run_correct(F, torch, p64, args.steps, args.warmup, profile=False)
@@ -191,6 +340,11 @@ def main():
         extra["fwd_bwd_ms"] = fwd_bwd(F, torch, W, args.grad_n, args.grad_rounds, max(1, args.steps // 2))
         extra["fwd_bwd_config"] = f"{args.grad_n}^3 FP32 GRF k^-2, {args.grad_rounds} fixed rounds + adjoint"
         log(f"[bench] fwd+bwd {extra['fwd_bwd_ms']:.3f} ms")
+
+    if not args.no_batch:
+        log("[bench] batched leg: 512 EEG signals + 64 x 2048^2 fields")
+        extra.update(batch_leg(F, torch, W, max(1, args.steps // 2)))
+        log(f"[bench] batch {extra['batch_ms']:.2f} ms")
 
     cpu = None
     if not args.no_cpu:
@@ -214,7 +368,8 @@ def main():
                                f"E=1e-4 x range, Delta=95th pct of initial |Re|,|Im|, cap 500 rounds, FP64 "
                                f"clamp + verification", "shape": [n, n, n], "max_iter": 500},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("x_pass") if dom == "x_pass" else None, "kernel": dom,
                      "bytes_per_launch": bpl, "avg_ms": ms_avg},
         "cpu_baseline": cpu,
         "extra": extra,

@@ -57,7 +57,11 @@ typedef enum {
 typedef struct {
   /* Relative shrink mu of both bounds for the projections.  0 selects the
    * default: 2^-16 for FFCZ_F64; for FFCZ_F32 the value of
-   * ffcz_suggest_margin() (room for the FP32 rounding of the output). */
+   * ffcz_suggest_margin() (room for the FP32 rounding of the output).
+   * FP64: the check counts |Re|,|Im| > Delta and the projections clip to
+   * E (1 - mu) and Delta (1 - mu).  FP32: the check counts |Re|,|Im| >
+   * Delta (1 - mu) and the f-projection clips to Delta (1 - 2 mu), so that
+   * rounding y to FP32 cannot lift an accepted coefficient above Delta. */
   double margin_rel;
   /* 1: run exactly max_iter projection blocks whatever the check says (the
    * map x_hat -> y is then piecewise linear; used for differentiation). */
@@ -72,8 +76,17 @@ typedef struct {
   int64_t* viol_per_round;
   /* Rounds enqueued between two host polls of the device done-flag (0 = 4). */
   int32_t graph_chunk;
-  /* 1: capture a chunk of rounds once in a hipGraph and replay it. */
+  /* 1 (default): the chunk of rounds between two polls is captured once in a
+   * hipGraph (cached per shape, workspace and output pointers) and replayed on
+   * the caller's stream; 0: plain launches.  Ignored while profiling. */
   int32_t use_graph;
+  /* Batched 1D members whose power-of-two work length Mc (Mc = L for a
+   * power-of-two L >= 4, else the Bluestein length >= 2L - 1) is at least
+   * 2^tiled_1d_lg run as tiled passes, many blocks per signal, with the rounds
+   * driven by the host; shorter ones run one block per signal for the whole
+   * correction.  0 selects the default 15; values below 12 count as 12; above 20
+   * keeps every 1D member on one block.  Both give bit-identical results. */
+  int32_t tiled_1d_lg;
 } ffcz_options;
 
 typedef struct {               /* host struct filled on return */
@@ -88,6 +101,8 @@ typedef struct {               /* host struct filled on return */
   double max_spectral_err;     /* FP64 max(|Re|,|Im|) of DFT(y - x)               */
   int64_t spectral_viol;       /* coefficients above Delta in the verification    */
   double margin_used;          /* mu actually used                                */
+  int32_t status;              /* this instance's own ffcz_status                 */
+  int32_t reserved;            /* 0                                               */
 } ffcz_stats;
 
 /* Library version (major*10000 + minor*100 + patch). */
@@ -198,6 +213,37 @@ typedef struct {
 } ffcz_profile;
 void ffcz_profile_enable(int32_t on);
 int32_t ffcz_profile_read(ffcz_profile* out);
+
+/* Plan tuning of the loop passes.  Each pass (y-forward/inverse, x-pass,
+ * last-axis pass) can run with a few tilings (columns or rows per block) that
+ * give bit-identical results and differ only in speed; the last-axis passes
+ * also have a radix-8 stage plan (the default is radix 16), which rounds
+ * differently.
+ *   mode 0  always the default plans;
+ *   mode 1  (default) on the first use of a pass geometry on a device
+ *           architecture, time every variant once on the call's own workspace
+ *           (a few launches, before the correction starts; skipped while the
+ *           stream is being captured or masks are recorded) and keep the
+ *           fastest for the rest of the process;
+ *   mode 2  always the narrower tilings (for testing);
+ *   mode 3  always the radix-8 last-axis plan (for testing).
+ * cache_path: JSON file of decisions, read now and rewritten after each new
+ * decision; NULL keeps the current path, "" stops persisting.  The initial
+ * mode and path come from FFCZ_AUTOTUNE (0 selects mode 0) and
+ * FFCZ_PLAN_CACHE.  Returns FFCZ_E_INVALID for an unknown mode. */
+int32_t ffcz_set_tuning(int32_t mode, const char* cache_path);
+/* Forget every decision held in memory (the cache file is left as it is). */
+void ffcz_clear_tuning(void);
+
+/* Device-to-device streaming copy of `bytes` bytes with the same access
+ * pattern as the passes (16-byte vector loads and stores, grid of a few
+ * blocks per compute unit).  A measurement helper: its rate is the HBM ceiling
+ * the passes are compared with, and its read/write byte counters calibrate
+ * those of the passes.  src and dst are device pointers, 16-byte aligned, not
+ * overlapping; the caller owns both.  Asynchronous on `stream`.  Returns
+ * FFCZ_E_INVALID for null or misaligned pointers, FFCZ_E_HIP if the launch
+ * fails. */
+int32_t ffcz_copy(void* dst, const void* src, size_t bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
+#include <thread>
 #include <map>
 #include <string>
 #include <vector>
@@ -30,21 +33,37 @@
 #include "common.hpp"
 #include "kernels_sig.hpp"
 #include "launch.hpp"
+#include "sig_dispatch.hpp"
 
 namespace ffcz {
-hipError_t launch_col_f32(int mode, int L, const void* args, int64_t nb, hipStream_t s);
-hipError_t launch_col_f64(int mode, int L, const void* args, int64_t nb, hipStream_t s);
-hipError_t launch_row_f32(int mode, int H, const void* args, int64_t nb, hipStream_t s);
-hipError_t launch_row_f64(int mode, int H, const void* args, int64_t nb, hipStream_t s);
+hipError_t launch_col_f32(int mode, int L, int v, const void* args, int64_t nb, hipStream_t s);
+hipError_t launch_col_f64(int mode, int L, int v, const void* args, int64_t nb, hipStream_t s);
+hipError_t launch_row_f32(int mode, int H, int v, const void* args, int64_t nb, hipStream_t s);
+hipError_t launch_row_f64(int mode, int H, int v, const void* args, int64_t nb, hipStream_t s);
 hipError_t launch_row_verify_f32io(int H, const void* args, int64_t nb, hipStream_t s);
 hipError_t launch_sig_f32(int mode, int lgMc, const void* args, int nb, hipStream_t s);
 hipError_t launch_sig_f64(int mode, int lgMc, const void* args, int nb, hipStream_t s);
+hipError_t launch_sigt_f64(int mode, int iodt, int lgMc, const void* args, int nb, hipStream_t s);
 
-// tdt: compute type; iodt: data type of the batch
-hipError_t launch_sig(int tdt, int iodt, int mode, int lgMc, const void* args, int nblocks, hipStream_t s) {
-  if (iodt == 0 && (mode == SIG_RUN || mode == SIG_VERIFY)) return launch_sig_f32(mode, lgMc, args, nblocks, s);
-  (void)tdt;
-  return launch_sig_f64(mode, lgMc, args, nblocks, s);
+// Which instantiation family runs a mode: the loop in the data type, set-up and
+// verification in FP64 (SigArgs<double>).
+bool sig_mode_fp64(int mode, int iodt) {
+  const bool loop = mode == SIG_RUN || mode == SIGT_EPS0 || mode == SIGT_CIN || mode == SIGT_RMUL ||
+                    mode == SIGT_RCHECK || mode == SIGT_CCHECK || mode == SIGT_CSPAT || mode == SIGT_Y;
+  return !loop || iodt == 1;
+}
+
+// iodt: data type of the batch; nsig: signals of the length class (the launch covers their tiles)
+hipError_t launch_sig(int iodt, int mode, int lgMc, const void* args, int nsig, hipStream_t s) {
+  const bool verify_t = mode == SIGT_VCOL || mode == SIGT_VROW || mode == SIGT_VCOL2;
+  const bool setup = mode == SIG_SETUP || mode == SIGT_CHIRP || mode == SIGT_BCOL || mode == SIGT_BROW;
+  if (iodt == 0) {
+    if (verify_t) return launch_sigt_f64(mode, 0, lgMc, args, nsig, s);
+    if (setup) return launch_sig_f64(mode, lgMc, args, nsig, s);
+    return launch_sig_f32(mode, lgMc, args, nsig, s);
+  }
+  if (sig_tiled(mode) && !setup) return launch_sigt_f64(mode, 1, lgMc, args, nsig, s);
+  return launch_sig_f64(mode, lgMc, args, nsig, s);
 }
 
 // Rows per row tile of the per-signal kernel (mirror of SigGeom).
@@ -56,11 +75,11 @@ int sig_rows_per_tile(int tdt, int lgMc) {
   return NT / PA;
 }
 
-int col_block_cols(int dtype, int L) { return dtype == 0 ? pick_C<float>(L) : pick_C<double>(L); }
-int row_block_rows(int dtype, int H) { return dtype == 0 ? pick_rows<float>(H) : pick_rows<double>(H); }
+int col_block_cols(int dtype, int L, int v) { return dtype == 0 ? tile_cols<float>(L, v) : tile_cols<double>(L, v); }
+int row_block_rows(int dtype, int H, int v) { return dtype == 0 ? tile_rows<float>(H, v) : tile_rows<double>(H, v); }
 
-hipError_t launch_col(int dtype, int mode, int L, const void* args, int64_t nb, hipStream_t s) {
-  return dtype == 0 ? launch_col_f32(mode, L, args, nb, s) : launch_col_f64(mode, L, args, nb, s);
+hipError_t launch_col(int dtype, int mode, int L, int v, const void* args, int64_t nb, hipStream_t s) {
+  return dtype == 0 ? launch_col_f32(mode, L, v, args, nb, s) : launch_col_f64(mode, L, v, args, nb, s);
 }
 }  // namespace ffcz
 
@@ -159,26 +178,64 @@ struct Plan {
   int64_t ncols = 0; // H + 1
   int64_t pitch = 0; // complex entries per spectrum row (working type)
   int64_t pitch64 = 0;
+  // complex entries per x-plane (3D: n1 rows plus one 128-byte line, so that the x-direction
+  // passes do not stride by a round multiple of the memory interleave; else a whole instance)
+  int64_t plane = 0, plane64 = 0;
+  int lg_rpp = 0;    // log2 of the spectrum rows per plane
   int64_t nrows = 0; // spectrum rows per instance
   int Lx = 1, Ly = 0;
   int Ez = 1, Ey = 1, Ex = 1;
-  int64_t twz = 0, twy = 0, twx = 0, twT = 0;
+  int64_t twz = 0, twy = 0, twx = 0, twz8 = 0, twT = 0;  // twz8: last-axis tables of the radix-8 plan
+  int Ez8 = 1;
+  // tile variants of the loop passes (y-forward/inverse, x-pass, last-axis init/loop/final)
+  int vy = 0, vx = 0, vz = 0;
   // blocks of each pass per instance (one partial slot per block)
   int64_t zbpi = 0, vzbpi = 0, xbpi = 0, vxbpi = 0;
   int64_t pmax = 0;
   size_t off_state = 0, off_viol = 0, off_init = 0, off_part = 0, off_twT = 0, off_tw64 = 0, off_Z = 0,
-         off_A = 0, bytes = 0;
+         off_A = 0, off_W = 0, bytes = 0;
   int32_t max_iter = 0;
   int64_t s_row_w32 = 0, s_plane_bytes = 0, f_row_bytes = 0, f_plane_bytes = 0;
 };
 
 struct StateInit {
-  double E, Ep, Delta, Dp, inv_n;
+  double E, Ep, Delta, Dc, Dp, inv_n;
   int32_t max_iter, fixed, record_masks, pad;
   const void* px;
   const void* pxb;
   void* py;
 };
+
+// Check threshold and projection bound of the f-cube.  An FP64 output is
+// checked against Delta and projected onto Delta (1 - mu) (Sec. IV-B).  An FP32
+// output moves every spectral component by up to mu Delta when it is rounded,
+// and a coefficient accepted just below the check is never clipped, so the
+// check runs mu Delta below Delta and the projection mu Delta below the check.
+void spectral_thresholds(int dt, double delta, double mu, double* dc, double* dp) {
+  const double rho = dt == FFCZ_F64 ? 0.0 : mu;
+  *dc = delta * (1.0 - rho);
+  *dp = delta * (1.0 - rho - mu);
+}
+
+int ceil_lg(int64_t v) {
+  int r = 0;
+  while ((int64_t(1) << r) < v) ++r;
+  return r;
+}
+
+// Choose the loop passes' tile variants and the per-instance block counts that follow.
+void set_variants(Plan& p, int vy, int vx, int vz) {
+  p.vy = vy;
+  p.vx = vx;
+  p.vz = vz;
+  const int64_t outer_x = p.nd == 3 ? p.n[1] : 1;
+  const int Cx = col_block_cols(p.dt, p.Lx, vx), Cx64 = col_block_cols(1, p.Lx, 0);
+  const int Rz = row_block_rows(p.dt, p.H, vz), Rz64 = row_block_rows(1, p.H, 0);
+  p.zbpi = (p.nrows + Rz - 1) / Rz;
+  p.vzbpi = (p.nrows + Rz64 - 1) / Rz64;
+  p.xbpi = outer_x * ((p.ncols + Cx - 1) / Cx);
+  p.vxbpi = outer_x * ((p.ncols + Cx64 - 1) / Cx64);
+}
 
 int32_t make_plan(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max_iter, int64_t B, Plan& p) {
   if (dtype != FFCZ_F32 && dtype != FFCZ_F64) return fail(FFCZ_E_INVALID, "dtype must be FFCZ_F32 or FFCZ_F64");
@@ -219,17 +276,19 @@ int32_t make_plan(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max
   p.twz = 0;
   p.twy = p.twz + host_twsize(p.H, p.Ez) + p.H;
   p.twx = p.twy + (p.Ly ? host_twsize(p.Ly, p.Ey) : 0);
-  p.twT = p.twx + host_twsize(p.Lx, p.Ex) + 1;
+  p.Ez8 = row_E(p.H, 2);
+  p.twz8 = p.twx + host_twsize(p.Lx, p.Ex) + 1;
+  p.twT = p.twz8 + host_twsize(p.H, p.Ez8) + p.H;
   const size_t cs = dtype == FFCZ_F32 ? 8 : 16;
+  set_variants(p, 0, 0, 0);
   {
+    // partial slots for the narrowest tiles any variant uses
     const int64_t outer_x = nd == 3 ? p.n[1] : 1;
-    const int Cx = col_block_cols(dtype, p.Lx), Cx64 = col_block_cols(1, p.Lx);
-    const int Rz = row_block_rows(dtype, p.H), Rz64 = row_block_rows(1, p.H);
-    p.zbpi = (p.nrows + Rz - 1) / Rz;
-    p.vzbpi = (p.nrows + Rz64 - 1) / Rz64;
-    p.xbpi = outer_x * ((p.ncols + Cx - 1) / Cx);
-    p.vxbpi = outer_x * ((p.ncols + Cx64 - 1) / Cx64);
-    p.pmax = B * std::max(std::max(p.zbpi, p.vzbpi), std::max(p.xbpi, p.vxbpi));
+    const int Cmin = col_block_cols(dtype, p.Lx, kColVariants - 1);
+    int Rmin = row_block_rows(dtype, p.H, 0);
+    for (int v = 1; v < kRowVariants; ++v) Rmin = std::min(Rmin, row_block_rows(dtype, p.H, v));
+    const int64_t zmax = (p.nrows + Rmin - 1) / Rmin, xmax = outer_x * ((p.ncols + Cmin - 1) / Cmin);
+    p.pmax = B * std::max(std::max(zmax, p.vzbpi), std::max(xmax, p.vxbpi));
   }
   size_t off = 0;
   p.off_state = off;
@@ -246,13 +305,19 @@ int32_t make_plan(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max
   p.off_tw64 = off;
   off = align_up(off + 16 * (size_t)p.twT, 256);
   p.off_Z = off;
-  const size_t spec = cs * (size_t)B * (size_t)p.nrows * (size_t)p.pitch;
+  const int64_t rpp = nd == 3 ? p.n[1] : p.nrows;
+  p.lg_rpp = ceil_lg(rpp);
+  p.plane = rpp * p.pitch + (nd == 3 ? cT : 0);
+  p.plane64 = rpp * p.pitch64 + (nd == 3 ? 8 : 0);
+  const size_t nplanes = (size_t)B * (size_t)(p.nrows / rpp);
+  const size_t spec = cs * nplanes * (size_t)p.plane;
   off = align_up(off + spec, 256);
   p.off_A = off;
   off = align_up(off + spec, 256);
-  // the FP64 verification reuses Z..A (contiguous) as an FP64 spectrum
-  const size_t spec64 = 16 * (size_t)B * (size_t)p.nrows * (size_t)p.pitch64;
-  if (p.off_Z + spec64 > off) off = align_up(p.off_Z + spec64, 256);
+  // the FP64 verification spectrum reuses Z..A (contiguous) once y is written
+  p.off_W = p.off_Z;
+  const size_t spec64 = 16 * nplanes * (size_t)p.plane64;
+  if (p.off_W + spec64 > off) off = align_up(p.off_W + spec64, 256);
   p.bytes = off;
   const int64_t sw64 = (nl + 63) / 64;
   const int64_t fw64 = (p.ncols + 63) / 64;
@@ -271,7 +336,7 @@ struct TwJob {
   int L, E, rtw;
 };
 struct TwJobs {
-  TwJob j[3];
+  TwJob j[4];
   int n;
   int dbl;  // 1: double table
 };
@@ -331,6 +396,7 @@ __global__ void state_init_kernel(DevState* st, int64_t B, const StateInit* arr,
     s.E = p.E;
     s.Ep = p.Ep;
     s.Delta = p.Delta;
+    s.Dc = p.Dc;
     s.Dp = p.Dp;
     s.inv_n = p.inv_n;
     s.max_iter = p.max_iter;
@@ -361,6 +427,28 @@ __global__ void ulp_kernel(const T* x, int64_t n, DevState* st) {
     for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) b += red[w];
     atomicAdd(&st->ulp2_sum, b);
   }
+}
+
+// Sums of ulp(x)^2 of many FP32 fields in one launch: blockIdx.y picks the
+// field, the blocks along x stride over it.
+struct MarginJob {
+  const float* x;
+  int64_t n;
+};
+
+__global__ void __launch_bounds__(256) ulp_batch_kernel(const MarginJob* jobs, double* sums) {
+  __shared__ double red[4];
+  const MarginJob jb = jobs[blockIdx.y];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < jb.n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float a = fabsf(jb.x[i]);
+    const double u = (double)nextafterf(a, INFINITY) - (double)a;
+    s += u * u;
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(&sums[blockIdx.y], red[0] + red[1] + red[2] + red[3]);
 }
 
 // Per-round control, one block per instance: sum the x-pass partials into
@@ -463,6 +551,7 @@ struct Ctx {
   void* tw64() const { return ws + p->off_tw64; }
   void* Z() const { return ws + p->off_Z; }
   void* A() const { return ws + p->off_A; }
+  void* W() const { return ws + p->off_W; }
   unsigned long long* part(int i) const { return (unsigned long long*)(ws + p->off_part) + (size_t)i * p->pmax; }
   static constexpr int PX = 0, PZ = 1, PVZ = 2, PVX = 3;  // PVX spans two regions (count, max)
 };
@@ -483,6 +572,7 @@ hipError_t write_twiddles(const Ctx& c) {
     jobs.dbl = dbl;
     int n = 0;
     jobs.j[n++] = TwJob{p.twz, p.H, p.Ez, 1};
+    jobs.j[n++] = TwJob{p.twz8, p.H, p.Ez8, 1};
     if (p.Ly) jobs.j[n++] = TwJob{p.twy, p.Ly, p.Ey, 0};
     jobs.j[n++] = TwJob{p.twx, p.Lx, p.Ex, 0};
     jobs.n = n;
@@ -502,22 +592,23 @@ struct ColGeom {
   int64_t outer_per_inst;
 };
 
-ColGeom geom_y(const Plan& p, int64_t pitch) {  // 3D only (B = 1)
-  return ColGeom{p.Ly, p.n[0], p.n[1] * pitch, pitch, 0, 0, p.n[0]};
+// pitch / plane: complex entries per spectrum row / per x-plane of the buffer addressed
+ColGeom geom_y(const Plan& p, int64_t pitch, int64_t plane) {  // 3D only (B = 1)
+  return ColGeom{p.Ly, p.n[0], plane, pitch, 0, 0, p.n[0]};
 }
-ColGeom geom_x(const Plan& p, int64_t pitch) {
-  if (p.nd == 3) return ColGeom{p.Lx, p.n[1], pitch, p.n[1] * pitch, p.n[1], 1, p.n[1]};
-  // 2D (and 1D, Lx = 1): one outer index per instance
-  return ColGeom{p.Lx, p.B, p.nrows * pitch, pitch, 1, 0, 1};
+ColGeom geom_x(const Plan& p, int64_t pitch, int64_t plane) {
+  if (p.nd == 3) return ColGeom{p.Lx, p.n[1], pitch, plane, p.n[1], 1, p.n[1]};
+  // 2D (and 1D, Lx = 1): one outer index per instance (a whole instance is one plane)
+  return ColGeom{p.Lx, p.B, plane, pitch, 1, 0, 1};
 }
 
 template <typename T>
-hipError_t run_col(int dt, int mode, const ColGeom& g, const Plan& p, const void* src, void* dst,
+hipError_t run_col(int dt, int mode, int v, const ColGeom& g, const Plan& p, const void* src, void* dst,
                    const void* tw, DevState* st, unsigned long long* part, uint8_t* fmask,
                    hipStream_t s) {
   ColArgs<T> a;
   memset(&a, 0, sizeof(a));
-  const int C = col_block_cols(dt, g.L);
+  const int C = col_block_cols(dt, g.L, v);
   a.src = (const cx<T>*)src;
   a.dst = (cx<T>*)dst;
   a.so = g.so;
@@ -535,19 +626,20 @@ hipError_t run_col(int dt, int mode, const ColGeom& g, const Plan& p, const void
   a.mrow_i = g.mrow_i;
   a.mrow_o = g.mrow_o;
   const int64_t nb = g.outer * a.ncb;
-  return launch_col(dt, mode, g.L, &a, nb, s);
+  return launch_col(dt, mode, g.L, v, &a, nb, s);
 }
 
 template <typename T, typename TIO>
-hipError_t run_row(int tdt, int iodt, int mode, const Plan& p, int64_t pitch, const void* src, void* dst,
-                   const void* tw, DevState* st, unsigned long long* part, uint32_t* smask, hipStream_t s) {
+hipError_t run_row(int tdt, int iodt, int mode, int v, const Plan& p, int64_t pitch, int64_t plane, const void* src,
+                   void* dst, const void* tw, DevState* st, unsigned long long* part, uint32_t* smask,
+                   hipStream_t s) {
   RowArgs<T, TIO> a;
   memset(&a, 0, sizeof(a));
   a.src = (const cx<T>*)src;
   a.dst = (cx<T>*)dst;
   a.pitch = pitch;
   a.rows_per_inst = p.nrows;
-  const int R = row_block_rows(tdt, p.H);
+  const int R = row_block_rows(tdt, p.H, v);
   a.bpi = (p.nrows + R - 1) / R;
   a.tw = (const cx<T>*)tw;
   a.st = st;
@@ -556,15 +648,18 @@ hipError_t run_row(int tdt, int iodt, int mode, const Plan& p, int64_t pitch, co
   a.s_plane = p.s_plane_bytes / 4;
   a.s_row_w32 = (int32_t)p.s_row_w32;
   const int64_t nb = a.bpi * p.B;
+  a.plane = plane;
+  a.lg_rpp = p.lg_rpp;
   if (mode == ROW_VERIFY && tdt == 1 && iodt == 0) return launch_row_verify_f32io(p.H, &a, nb, s);
-  return tdt == 0 ? launch_row_f32(mode, p.H, &a, nb, s) : launch_row_f64(mode, p.H, &a, nb, s);
+  return tdt == 0 ? launch_row_f32(mode, p.H, v, &a, nb, s) : launch_row_f64(mode, p.H, v, &a, nb, s);
 }
 
 template <typename T>
 hipError_t row_T(int mode, const Ctx& c, const void* src, void* dst, uint32_t* smask) {
   const Plan& p = *c.p;
-  const void* tw = (const char*)c.twT() + sizeof(cx<T>) * p.twz;
-  return run_row<T, T>(p.dt, p.dt, mode, p, p.pitch, src, dst, tw, c.st(), c.part(Ctx::PZ), smask, c.s);
+  const int v = (mode == ROW_INIT || mode == ROW_LOOP) ? p.vz : 0;
+  const void* tw = (const char*)c.twT() + sizeof(cx<T>) * (v == 2 ? p.twz8 : p.twz);
+  return run_row<T, T>(p.dt, p.dt, mode, v, p, p.pitch, p.plane, src, dst, tw, c.st(), c.part(Ctx::PZ), smask, c.s);
 }
 
 template <typename T>
@@ -578,22 +673,22 @@ hipError_t enqueue_round(const Ctx& c, int r, unsigned long long* viol, int64_t 
   hipError_t e;
   if (p.nd == 3) {
     e = timed(PK_YFWD, r, c.s, [&] {
-      return run_col<T>(p.dt, COL_FWD, geom_y(p, p.pitch), p, c.Z(), c.A(), twy, c.st(), px, fmask, c.s);
+      return run_col<T>(p.dt, COL_FWD, p.vy, geom_y(p, p.pitch, p.plane), p, c.Z(), c.A(), twy, c.st(), px, fmask, c.s);
     });
     if (e != hipSuccess) return e;
     e = timed(PK_XPASS, r, c.s, [&] {
-      return run_col<T>(p.dt, COL_XPASS, geom_x(p, p.pitch), p, c.A(), c.A(), twx, c.st(), px, fmask, c.s);
+      return run_col<T>(p.dt, COL_XPASS, p.vx, geom_x(p, p.pitch, p.plane), p, c.A(), c.A(), twx, c.st(), px, fmask, c.s);
     });
     if (e != hipSuccess) return e;
     e = launch_ctl(c, viol, vstride);
     if (e != hipSuccess) return e;
     e = timed(PK_YINV, r, c.s, [&] {
-      return run_col<T>(p.dt, COL_INV, geom_y(p, p.pitch), p, c.A(), c.A(), twy, c.st(), px, fmask, c.s);
+      return run_col<T>(p.dt, COL_INV, p.vy, geom_y(p, p.pitch, p.plane), p, c.A(), c.A(), twy, c.st(), px, fmask, c.s);
     });
     if (e != hipSuccess) return e;
   } else {
     e = timed(PK_XPASS, r, c.s, [&] {
-      return run_col<T>(p.dt, COL_XPASS, geom_x(p, p.pitch), p, c.Z(), c.A(), twx, c.st(), px, fmask, c.s);
+      return run_col<T>(p.dt, COL_XPASS, p.vx, geom_x(p, p.pitch, p.plane), p, c.Z(), c.A(), twx, c.st(), px, fmask, c.s);
     });
     if (e != hipSuccess) return e;
     e = launch_ctl(c, viol, vstride);
@@ -602,25 +697,27 @@ hipError_t enqueue_round(const Ctx& c, int r, unsigned long long* viol, int64_t 
   return timed(PK_ZPASS, r, c.s, [&] { return row_T<T>(ROW_LOOP, c, c.A(), c.Z(), smask); });
 }
 
+// FP64 verification: last-axis R2C of y - x (max |y - x|), then the y and x
+// transforms of that spectrum with the max-reduce in the x-pass.
 template <typename T>
 hipError_t enqueue_verify(const Ctx& c) {
   const Plan& p = *c.p;
   const char* tb = (const char*)c.tw64();
-  void* W = c.Z();  // FP64 spectrum over Z..A
+  void* W = c.W();
   hipError_t e = timed(PK_VZ, -1, c.s, [&] {
-    return run_row<double, T>(1, p.dt, ROW_VERIFY, p, p.pitch64, nullptr, W, tb + 16 * p.twz, c.st(),
+    return run_row<double, T>(1, p.dt, ROW_VERIFY, 0, p, p.pitch64, p.plane64, nullptr, W, tb + 16 * p.twz, c.st(),
                               c.part(Ctx::PVZ), nullptr, c.s);
   });
   if (e != hipSuccess) return e;
   if (p.nd == 3) {
     e = timed(PK_VY, -1, c.s, [&] {
-      return run_col<double>(1, COL_FWD_NS, geom_y(p, p.pitch64), p, W, W, tb + 16 * p.twy, c.st(),
+      return run_col<double>(1, COL_FWD_NS, 0, geom_y(p, p.pitch64, p.plane64), p, W, W, tb + 16 * p.twy, c.st(),
                              c.part(Ctx::PVX), nullptr, c.s);
     });
     if (e != hipSuccess) return e;
   }
   e = timed(PK_VX, -1, c.s, [&] {
-    return run_col<double>(1, COL_VERIFY, geom_x(p, p.pitch64), p, W, W, tb + 16 * p.twx, c.st(),
+    return run_col<double>(1, COL_VERIFY, 0, geom_x(p, p.pitch64, p.plane64), p, W, W, tb + 16 * p.twx, c.st(),
                            c.part(Ctx::PVX), nullptr, c.s);
   });
   if (e != hipSuccess) return e;
@@ -646,7 +743,60 @@ struct HostBuf {
     return e;
   }
 };
-thread_local HostBuf g_host_state, g_host_init, g_host_misc;
+thread_local HostBuf g_host_state, g_host_init, g_host_misc, g_host_sig;
+
+// Private streams (default priority): one to capture graphs on, one for the
+// 1D members of a batch, which run beside the grouped members.
+struct Streams {
+  hipStream_t cap = nullptr, side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  ~Streams() {
+    if (cap) (void)hipStreamDestroy(cap);
+    if (side) (void)hipStreamDestroy(side);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+  }
+  hipError_t ready() {
+    hipError_t e = hipSuccess;
+    if (!cap) e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess && !side) e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+    if (e == hipSuccess && !fork) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e == hipSuccess && !join) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    return e;
+  }
+};
+thread_local Streams g_streams;
+
+// Instantiated graphs of a chunk of rounds, keyed by everything the launches capture.
+struct GraphKey {
+  std::vector<int64_t> k;
+  bool operator<(const GraphKey& o) const { return k < o.k; }
+};
+struct GraphCache {
+  std::map<GraphKey, hipGraphExec_t> m;
+  std::vector<GraphKey> order;
+  ~GraphCache() {
+    for (auto& kv : m) (void)hipGraphExecDestroy(kv.second);
+  }
+  hipGraphExec_t find(const GraphKey& key) {
+    auto it = m.find(key);
+    return it == m.end() ? nullptr : it->second;
+  }
+  void put(const GraphKey& key, hipGraphExec_t g) {
+    if (m.size() >= 16) {
+      auto old = order.front();
+      order.erase(order.begin());
+      auto it = m.find(old);
+      if (it != m.end()) {
+        (void)hipGraphExecDestroy(it->second);
+        m.erase(it);
+      }
+    }
+    m[key] = g;
+    order.push_back(key);
+  }
+};
+thread_local GraphCache g_graphs;
 
 double bits_to_double(unsigned long long b) {
   double d;
@@ -655,6 +805,24 @@ double bits_to_double(unsigned long long b) {
 }
 
 // Suggested FP32 margin for one field of N points (reads x once on the device).
+// mu = max(2^-16, 8 sigma sqrt(N/2) / Delta) with sigma^2 = mean(ulp(x)^2) / 12:
+// the rounding of y to FP32 moves each Re/Im component by sigma sqrt(N/2) rms.
+double margin_from_ulp2(double ulp2_sum, int64_t N, double D) {
+  const double sigma = std::sqrt(ulp2_sum / (double)N / 12.0);
+  const double m = D > 0 ? 8.0 * sigma * std::sqrt((double)N / 2.0) / D : 0.5;
+  return std::min(0.5, std::max(std::ldexp(1.0, -16), m));
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+__global__ void zero_f64_kernel(double* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
 int32_t margin_for(int dt, int64_t N, const void* x, double D, DevState* scratch, hipStream_t s, double* mu) {
   if (dt == FFCZ_F64) {
     *mu = std::ldexp(1.0, -16);
@@ -671,16 +839,211 @@ int32_t margin_for(int dt, int64_t N, const void* x, double D, DevState* scratch
   HIPCHK(g_host_misc.reserve(sizeof(DevState)));
   HIPCHK(hipMemcpyAsync(g_host_misc.p, scratch, sizeof(DevState), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  const double sigma = std::sqrt(((DevState*)g_host_misc.p)->ulp2_sum / (double)N / 12.0);
-  double m = D > 0 ? 8.0 * sigma * std::sqrt((double)N / 2.0) / D : 0.5;
-  *mu = std::min(0.5, std::max(std::ldexp(1.0, -16), m));
+  *mu = margin_from_ulp2(((DevState*)g_host_misc.p)->ulp2_sum, N, D);
+  return FFCZ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Plan tuner.  Each loop pass of a plan (y-forward/inverse, x-pass, last-axis
+// pass) has a few variants: tilings that compute bit-identical results and
+// differ only in how many columns / rows one block owns, and for the last-axis
+// passes a radix-8 stage plan.  On the first use of a pass geometry on a device
+// architecture, every variant is timed on the plan's own workspace (in place on
+// the scratch spectrum, before the correction starts) and the fastest is kept;
+// a variant other than the default must win by 2 % (rows) or 10 % (columns).
+// The table is process-wide and, when a cache path is set, read from and
+// written back to a JSON file.
+
+struct TuneEntry {
+  int choice = 0;
+  std::vector<float> ms;
+};
+
+struct Tuner {
+  std::mutex m;
+  int mode = -1;  // -1: not read yet; 0: default plans; 1: tune on a miss; 2: narrower tiles; 3: radix-8 rows
+  bool loaded = false;
+  std::string path;
+  std::map<std::string, TuneEntry> tab;
+
+  void init_locked() {
+    if (mode >= 0) return;
+    const char* e = getenv("FFCZ_AUTOTUNE");
+    mode = (e && e[0] == '0') ? 0 : 1;
+    const char* c = getenv("FFCZ_PLAN_CACHE");
+    if (c && *c) path = c;
+  }
+  // Entries are one per line: "key": {"choice": N, "ms": [..]}.  Lines that do
+  // not parse are ignored, so a damaged file only costs a re-tune.
+  void load_locked() {
+    if (loaded) return;
+    loaded = true;
+    if (path.empty()) return;
+    FILE* f = fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[1024];
+    while (fgets(line, sizeof(line), f)) {
+      const char* q0 = strchr(line, '"');
+      if (!q0) continue;
+      const char* q1 = strchr(q0 + 1, '"');
+      if (!q1) continue;
+      const char* ch = strstr(q1, "\"choice\":");
+      if (!ch) continue;
+      int v = -1;
+      if (sscanf(ch + 9, "%d", &v) != 1 || v < 0 || v >= std::max(kColVariants, kRowVariants)) continue;
+      TuneEntry te;
+      te.choice = v;
+      tab[std::string(q0 + 1, q1)] = te;
+    }
+    fclose(f);
+  }
+  void save_locked() {
+    if (path.empty()) return;
+    const std::string tmp = path + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    fprintf(f, "{\n \"format\": \"ffcz tile plans 1\",\n \"entries\": {\n");
+    size_t i = 0;
+    for (const auto& kv : tab) {
+      fprintf(f, "  \"%s\": {\"choice\": %d, \"ms\": [", kv.first.c_str(), kv.second.choice);
+      for (size_t k = 0; k < kv.second.ms.size(); ++k) fprintf(f, "%s%.5f", k ? ", " : "", kv.second.ms[k]);
+      fprintf(f, "]}%s\n", ++i < tab.size() ? "," : "");
+    }
+    fprintf(f, " }\n}\n");
+    const bool ok = fclose(f) == 0;
+    if (ok) rename(tmp.c_str(), path.c_str());
+  }
+};
+Tuner g_tuner;
+
+std::string device_arch() {
+  thread_local std::map<int, std::string> names;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+  auto it = names.find(dev);
+  if (it != names.end()) return it->second;
+  hipDeviceProp_t prop;
+  std::string n = "unknown";
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) n = prop.gcnArchName;
+  names[dev] = n;
+  return n;
+}
+
+// The variant kept for `key`; on a miss, time `launch(v)` for every variant
+// (only if may_time, else the default tiles).
+template <typename F>
+int32_t tune_pass(const std::string& key, hipStream_t s, bool may_time, float keep, int nvar, F&& launch, int* out) {
+  *out = 0;
+  {
+    std::lock_guard<std::mutex> g(g_tuner.m);
+    g_tuner.init_locked();
+    g_tuner.load_locked();
+    if (g_tuner.mode == 0) return FFCZ_OK;
+    if (g_tuner.mode == 2) {  // the narrower tiles
+      *out = 1;
+      return FFCZ_OK;
+    }
+    if (g_tuner.mode == 3) {  // the radix-8 last-axis plan
+      *out = nvar > 2 ? 2 : 0;
+      return FFCZ_OK;
+    }
+    auto it = g_tuner.tab.find(key);
+    if (it != g_tuner.tab.end() && it->second.choice < nvar) {
+      *out = it->second.choice;
+      return FFCZ_OK;
+    }
+  }
+  if (!may_time) return FFCZ_OK;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  TuneEntry te;
+  hipError_t err = hipSuccess;
+  for (int v = 0; v < nvar && err == hipSuccess; ++v) {
+    err = launch(v);  // warm-up
+    if (err != hipSuccess) break;
+    float best = 1e30f;
+    for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
+      err = hipEventRecord(e0, s);
+      if (err == hipSuccess) err = launch(v);
+      if (err == hipSuccess) err = hipEventRecord(e1, s);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      best = std::min(best, ms);
+    }
+    te.ms.push_back(best);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPCHK(err);
+  te.choice = 0;
+  for (int v = 1; v < nvar; ++v)
+    if (te.ms[v] < keep * te.ms[0] && te.ms[v] < te.ms[te.choice]) te.choice = v;
+  std::lock_guard<std::mutex> g(g_tuner.m);
+  g_tuner.tab[key] = te;
+  g_tuner.save_locked();
+  *out = te.choice;
+  return FFCZ_OK;
+}
+
+// A narrower column tile reads 64-byte halves of lines whose other halves belong to
+// another block (fetched again, from the last-level cache at best), so it must win clearly.
+constexpr float kColKeep = 0.90f;
+
+// Pick the loop passes' tile variants for plan p (state and twiddles already
+// written; the scratch spectrum A is overwritten).  Nothing is timed while the
+// stream is being captured or masks are recorded (the loop kernels would write
+// mask planes); mask recording also keeps the default x-pass tiles, whose
+// width the 1-bit mask words assume.
+template <typename T>
+int32_t tune_plan(Plan& p, char* ws, hipStream_t s, bool rec) {
+  const std::string pre = device_arch() + (p.dt == FFCZ_F32 ? " f32" : " f64");
+  char buf[256];
+  int vy = 0, vx = 0, vz = 0;
+  Ctx c{&p, ws, s};
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIPCHK(hipStreamIsCapturing(s, &cs));
+  const bool may_time = !rec && cs == hipStreamCaptureStatusNone;
+  const char* twb = (const char*)c.twT();
+  if (p.nd == 3 && p.Ly >= 64) {
+    snprintf(buf, sizeof(buf), "%s y L=%d cols=%lld outer=%lld", pre.c_str(), p.Ly, (long long)p.ncols,
+             (long long)p.n[0]);
+    int32_t r = tune_pass(buf, s, may_time, kColKeep, kColVariants, [&](int v) {
+      return run_col<T>(p.dt, COL_FWD, v, geom_y(p, p.pitch, p.plane), p, c.A(), c.A(), twb + sizeof(cx<T>) * p.twy,
+                        c.st(), c.part(Ctx::PX), nullptr, s);
+    }, &vy);
+    if (r != FFCZ_OK) return r;
+  }
+  if (p.nd >= 2 && p.Lx >= 64 && !rec) {
+    snprintf(buf, sizeof(buf), "%s x L=%d cols=%lld outer=%lld B=%lld", pre.c_str(), p.Lx, (long long)p.ncols,
+             (long long)(p.nd == 3 ? p.n[1] : 1), (long long)p.B);
+    int32_t r = tune_pass(buf, s, may_time, kColKeep, kColVariants, [&](int v) {
+      Plan q = p;
+      set_variants(q, q.vy, v, q.vz);
+      return run_col<T>(p.dt, COL_XPASS, v, geom_x(q, q.pitch, q.plane), q, c.A(), c.A(), twb + sizeof(cx<T>) * p.twx,
+                        c.st(), c.part(Ctx::PX), nullptr, s);
+    }, &vx);
+    if (r != FFCZ_OK) return r;
+  }
+  if (p.H >= 64) {
+    snprintf(buf, sizeof(buf), "%s z H=%d rows=%lld", pre.c_str(), p.H, (long long)(p.nrows * p.B));
+    int32_t r = tune_pass(buf, s, may_time, 0.98f, kRowVariants, [&](int v) {
+      return run_row<T, T>(p.dt, p.dt, ROW_LOOP, v, p, p.pitch, p.plane, c.A(), c.A(),
+                           twb + sizeof(cx<T>) * (v == 2 ? p.twz8 : p.twz), c.st(),
+                           c.part(Ctx::PZ), nullptr, s);
+    }, &vz);
+    if (r != FFCZ_OK) return r;
+  }
+  set_variants(p, vy, vx, vz);
   return FFCZ_OK;
 }
 
 // One correction over the B instances of a plan.  inst[b] supplies pointers and bounds.
 template <typename T>
-int32_t correct_group(const Plan& p, const ffcz_instance* inst, const double* mus, int32_t max_iter,
+int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* mus, int32_t max_iter,
                       const ffcz_options& o, char* ws, hipStream_t s, ffcz_stats* stats, int32_t* status) {
+  Plan p = p0;
   Ctx c{&p, ws, s};
   const int64_t vstride = max_iter + 2;
   const bool user_viol = o.viol_per_round && p.B == 1;
@@ -696,7 +1059,7 @@ int32_t correct_group(const Plan& p, const ffcz_instance* inst, const double* mu
     si.E = inst[b].eps_s;
     si.Ep = inst[b].eps_s * (1.0 - mus[b]);
     si.Delta = inst[b].delta_f;
-    si.Dp = inst[b].delta_f * (1.0 - mus[b]);
+    spectral_thresholds(p.dt, inst[b].delta_f, mus[b], &si.Dc, &si.Dp);
     si.inv_n = 1.0 / (double)p.N;
     si.max_iter = max_iter;
     si.fixed = o.fixed_iterations ? 1 : 0;
@@ -721,6 +1084,10 @@ int32_t correct_group(const Plan& p, const ffcz_instance* inst, const double* mu
                      c.st(), p.B, arr, one, viol, nviol);
   HIPCHK(hipGetLastError());
   HIPCHK(write_twiddles(c));
+  {
+    const int32_t tr = tune_plan<T>(p, ws, s, rec);
+    if (tr != FFCZ_OK) return tr;
+  }
   HIPCHK(timed(PK_INIT, -1, s, [&] { return row_T<T>(ROW_INIT, c, nullptr, c.Z(), smask); }));
 
   const int chunk = o.graph_chunk > 0 ? o.graph_chunk : 4;
@@ -732,8 +1099,35 @@ int32_t correct_group(const Plan& p, const ffcz_instance* inst, const double* mu
     // exactly max_iter blocks plus the final check: no polling needed
     for (int r = 0; r <= max_iter; ++r) HIPCHK(enqueue_round<T>(c, r, viol, vstr, fmask, smask));
   } else {
+    // a chunk of rounds, captured once in a hipGraph (unless per-launch timing is on)
+    hipGraphExec_t gexec = nullptr;
+    if (o.use_graph && !g_prof.on) {
+      GraphKey key{{(int64_t)p.dt, p.nd, p.B, p.n[0], p.n[1], p.n[2], (int64_t)(uintptr_t)ws, (int64_t)(uintptr_t)viol,
+                    vstr, (int64_t)(uintptr_t)fmask, (int64_t)(uintptr_t)smask, chunk, max_iter, p.vy, p.vx, p.vz}};
+      gexec = g_graphs.find(key);
+      if (!gexec) {
+        HIPCHK(g_streams.ready());
+        Ctx cc{&p, ws, g_streams.cap};
+        HIPCHK(hipStreamBeginCapture(g_streams.cap, hipStreamCaptureModeThreadLocal));
+        hipError_t ce = hipSuccess;
+        for (int r = 0; r < chunk && ce == hipSuccess; ++r) ce = enqueue_round<T>(cc, r, viol, vstr, fmask, smask);
+        hipGraph_t graph = nullptr;
+        hipError_t ee = hipStreamEndCapture(g_streams.cap, &graph);
+        if (ce != hipSuccess) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return fail(FFCZ_E_HIP, std::string("capture: ") + hipGetErrorString(ce));
+        }
+        HIPCHK(ee);
+        hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(ie);
+        g_graphs.put(key, gexec);
+      }
+    }
     for (;;) {
-      for (int r = 0; r < chunk; ++r) HIPCHK(enqueue_round<T>(c, enq + r, viol, vstr, fmask, smask));
+      if (gexec) HIPCHK(hipGraphLaunch(gexec, s));
+      else
+        for (int r = 0; r < chunk; ++r) HIPCHK(enqueue_round<T>(c, enq + r, viol, vstr, fmask, smask));
       enq += chunk;
       HIPCHK(hipMemcpyAsync(hs, c.st(), sizeof(DevState) * p.B, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -824,14 +1218,14 @@ int32_t backward_impl(const Plan& p, int32_t rounds, const void* masks, const vo
   for (int k = rounds; k >= 1; --k) {
     if (p.nd == 3)
       HIPCHK(timed(PK_BY, -1, s, [&] {
-        return run_col<T>(p.dt, COL_FWD_NS, geom_y(p, p.pitch), p, c.Z(), c.Z(), twy, c.st(), nullptr, nullptr, s);
+        return run_col<T>(p.dt, COL_FWD_NS, 0, geom_y(p, p.pitch, p.plane), p, c.Z(), c.Z(), twy, c.st(), nullptr, nullptr, s);
       }));
     HIPCHK(timed(PK_BX, -1, s, [&] {
-      return run_col<T>(p.dt, COL_XBACK, geom_x(p, p.pitch), p, c.Z(), c.Z(), twx, c.st(), nullptr, fplane(k), s);
+      return run_col<T>(p.dt, COL_XBACK, 0, geom_x(p, p.pitch, p.plane), p, c.Z(), c.Z(), twx, c.st(), nullptr, fplane(k), s);
     }));
     if (p.nd == 3)
       HIPCHK(timed(PK_BY, -1, s, [&] {
-        return run_col<T>(p.dt, COL_INV_NS, geom_y(p, p.pitch), p, c.Z(), c.Z(), twy, c.st(), nullptr, nullptr, s);
+        return run_col<T>(p.dt, COL_INV_NS, 0, geom_y(p, p.pitch, p.plane), p, c.Z(), c.Z(), twy, c.st(), nullptr, nullptr, s);
       }));
     if (k > 1) HIPCHK(timed(PK_BZ, -1, s, [&] { return row_T<T>(ROW_BLOOP, c, c.Z(), c.Z(), splane(k - 1)); }));
     else HIPCHK(timed(PK_BZ, -1, s, [&] { return row_T<T>(ROW_BFINAL, c, c.Z(), nullptr, splane(0)); }));
@@ -842,11 +1236,6 @@ int32_t backward_impl(const Plan& p, int32_t rounds, const void* masks, const vo
 // ---------------------------------------------------------------------------
 // 1D batch members: one block per signal (kernels_sig.hpp)
 
-int ceil_lg(int64_t v) {
-  int r = 0;
-  while ((int64_t(1) << r) < v) ++r;
-  return r;
-}
 
 struct SigPlan {
   int dt = 0;
@@ -966,6 +1355,12 @@ hipError_t write_mc_tabs(int dt, int lgMc, char* base, const McTabs& t, hipStrea
 }
 
 // Layout of the batched workspace
+// Length classes from 2^this (work length Mc) up run as tiled passes, many blocks per
+// signal; shorter ones run one block per signal.
+int sig_tiled_from_lg(const ffcz_options& o) {
+  return o.tiled_1d_lg > 0 ? std::max(kSigTiledMinLg, (int)o.tiled_1d_lg) : 15;
+}
+
 struct BatchPlan {
   int dt = 0;
   std::vector<int> sig_ids;                 // 1D members
@@ -974,7 +1369,10 @@ struct BatchPlan {
   std::map<int, size_t> mc_off;             // lgMc -> table offset
   std::map<int, McTabs> mc_tab;
   std::vector<size_t> sig_off;
-  size_t off_desc = 0, off_sstats = 0, off_order = 0, off_scratch = 0;
+  size_t off_desc = 0, off_sstats = 0, off_order = 0, off_scratch = 0, off_mjobs = 0, off_msum = 0;
+  // length classes run as tiled passes: partial slots [kind][signal][tile] per class
+  std::map<int, size_t> tpart_off;
+  std::map<int, int> tpart_tiles;
   // multi-dimensional groups
   std::vector<std::vector<int>> groups;
   std::vector<Plan> gplans;
@@ -1038,6 +1436,15 @@ int32_t batch_plan(int32_t dt, int32_t count, const ffcz_instance* inst, int32_t
     bp.mc_off[kv.first] = off;
     off = align_up(off + t.bytes, 256);
   }
+  for (auto& kv : bp.by_mc) {
+    if (kv.first < kSigTiledMinLg) continue;  // partial slots for every class that may run tiled
+    int nct = 0, nrt = 0;
+    sig_tiles(kv.first, &nct, &nrt);
+    const int pt = std::max(nct, nrt);
+    bp.tpart_off[kv.first] = off;
+    bp.tpart_tiles[kv.first] = pt;
+    off = align_up(off + sizeof(unsigned long long) * SP_KINDS * kv.second.size() * (size_t)pt, 256);
+  }
   bp.off_desc = off;
   off = align_up(off + sizeof(SigDesc) * (size_t)std::max(ns, 1), 256);
   bp.off_sstats = off;
@@ -1046,37 +1453,155 @@ int32_t batch_plan(int32_t dt, int32_t count, const ffcz_instance* inst, int32_t
   off = align_up(off + sizeof(int32_t) * (size_t)std::max(ns, 1), 256);
   bp.off_scratch = off;  // one DevState for the margin reductions
   off = align_up(off + sizeof(DevState), 256);
+  bp.off_mjobs = off;  // margin jobs (x pointer, length) and their ulp^2 sums
+  off = align_up(off + sizeof(MarginJob) * (size_t)std::max(count, 1), 256);
+  bp.off_msum = off;
+  off = align_up(off + sizeof(double) * (size_t)std::max(count, 1), 256);
   bp.bytes = off;
   return FFCZ_OK;
 }
 
+// Tiled loop control, one block per signal slot of a length class: sum the
+// check's partial counts (and the spatial-clip counts of the pass that made the
+// checked iterate), record them, and decide whether the signal's loop ends.
+__global__ void __launch_bounds__(256) sig_ctl_kernel(const SigDesc* sig, SigStats* stats, const int32_t* order,
+                                                       const unsigned long long* part, int32_t nsig, int32_t ptiles,
+                                                       int32_t nct, int32_t nrt, int32_t max_iter, int32_t fixed) {
+  __shared__ unsigned long long red[3][4];
+  const int slot = blockIdx.x;
+  if (slot >= nsig) return;
+  const int sid = order[slot];
+  SigStats* so = stats + sid;
+  if (*(volatile int32_t*)&so->done) return;
+  const int nck = sig[sid].blue ? nct : nrt;  // tiles of the pass that counted violations
+  const int k = so->rounds;
+  auto at = [&](int kind, int tl) { return part[((int64_t)kind * nsig + slot) * ptiles + tl]; };
+  unsigned long long v = 0, z = 0, nf = 0;
+  for (int i = threadIdx.x; i < nck; i += blockDim.x) v += at(SP_VIOL, i);
+  for (int i = threadIdx.x; i < nct; i += blockDim.x) {
+    z += at(SP_SCLIP, i);
+    if (k == 0) nf += at(SP_NONFIN, i);
+  }
+  v = wave_sum_u64(v);
+  z = wave_sum_u64(z);
+  nf = wave_sum_u64(nf);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = v;
+    red[1][threadIdx.x >> 6] = z;
+    red[2][threadIdx.x >> 6] = nf;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long V = 0, Z = 0, NF = 0;
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) {
+      V += red[0][w];
+      Z += red[1][w];
+      NF += red[2][w];
+    }
+    if (k == 0) {
+      so->s_guard = Z;
+      so->viol0 = V;
+    } else {
+      so->s_clipped += Z;
+    }
+    so->violf = V;
+    int stop = 0;
+    if (k == 0 && NF) {
+      so->nonfinite = NF;
+      so->nonfinite_stop = 1;
+      so->converged = 0;
+      stop = 1;
+    } else if (!fixed && V == 0) {
+      so->converged = 1;
+      stop = 1;
+    } else if (k >= max_iter) {
+      so->converged = (V == 0) ? 1 : 0;
+      stop = 1;
+    }
+    if (stop) so->done = 1;
+    else so->rounds = k + 1;
+  }
+}
+
+// Tiled verification totals, one block per signal slot.
+__global__ void __launch_bounds__(256) sig_vstats_kernel(const SigDesc* sig, SigStats* stats, const int32_t* order,
+                                                          const unsigned long long* part, int32_t nsig, int32_t ptiles,
+                                                          int32_t nct, int32_t nrt) {
+  __shared__ unsigned long long red[3][4];
+  const int slot = blockIdx.x;
+  if (slot >= nsig) return;
+  const int sid = order[slot];
+  SigStats* so = stats + sid;
+  const int nv = sig[sid].blue ? nct : nrt;
+  auto at = [&](int kind, int tl) { return part[((int64_t)kind * nsig + slot) * ptiles + tl]; };
+  unsigned long long mf = 0, ms = 0, c = 0;  // maxima of non-negative doubles compare as their bits
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+    const unsigned long long b = at(SP_VMAXF, i);
+    mf = mf > b ? mf : b;
+    c += at(SP_VCNT, i);
+  }
+  for (int i = threadIdx.x; i < nct; i += blockDim.x) {
+    const unsigned long long b = at(SP_VMAXS, i);
+    ms = ms > b ? ms : b;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o1 = __shfl_xor(mf, off, 64), o2 = __shfl_xor(ms, off, 64);
+    mf = mf > o1 ? mf : o1;
+    ms = ms > o2 ? ms : o2;
+    c += __shfl_xor(c, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = mf;
+    red[1][threadIdx.x >> 6] = ms;
+    red[2][threadIdx.x >> 6] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long F = 0, S = 0, C = 0;
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) {
+      F = F > red[0][w] ? F : red[0][w];
+      S = S > red[1][w] ? S : red[1][w];
+      C += red[2][w];
+    }
+    so->max_spectral = __longlong_as_double((long long)F);
+    so->max_spatial = __longlong_as_double((long long)S);
+    so->spectral_viol = C;
+  }
+}
+
 template <typename T>
 hipError_t sig_launch(int dt, int mode, int lgMc, const BatchPlan& bp, char* ws, const int32_t* order,
-                      int nblocks, int32_t max_iter, int32_t fixed, hipStream_t s) {
+                      int nsig, int32_t max_iter, int32_t fixed, hipStream_t s) {
   const McTabs& t = bp.mc_tab.at(lgMc);
   char* tb = ws + bp.mc_off.at(lgMc);
-  const bool d64 = (mode != SIG_RUN) || dt == FFCZ_F64;  // set-up and verification compute in FP64
+  const bool d64 = sig_mode_fp64(mode, dt);
   SigArgs<T> a;
   memset(&a, 0, sizeof(a));
   a.sig = (const SigDesc*)(ws + bp.off_desc);
   a.stats = (SigStats*)(ws + bp.off_sstats);
   a.order = order;
-  a.nsig = nblocks;
+  a.nsig = nsig;
   a.max_iter = max_iter;
   a.fixed = fixed;
   a.tab.tw4 = (const cx<T>*)(tb + (d64 ? t.tw4_64 : t.tw4));
   a.tab.tw4r = (const cx<T>*)(tb + (d64 ? t.tw4r_64 : t.tw4r));
   a.tab.twa = (const cx<T>*)(tb + (d64 ? t.twa_64 : t.twa));
   a.tab.twb = (const cx<T>*)(tb + (d64 ? t.twb_64 : t.twb));
-  return launch_sig(d64 ? 1 : 0, dt, mode, lgMc, &a, nblocks, s);
+  auto it = bp.tpart_off.find(lgMc);
+  if (it != bp.tpart_off.end()) {
+    a.part = (unsigned long long*)(ws + it->second);
+    a.ptiles = bp.tpart_tiles.at(lgMc);
+  }
+  return launch_sig(dt, mode, lgMc, &a, nsig, s);
 }
 
 int32_t run_sigs(const BatchPlan& bp, const ffcz_instance* inst, const double* mus, int32_t max_iter,
                  const ffcz_options& o, char* ws, hipStream_t s) {
   const int ns = (int)bp.sig_ids.size();
   if (ns == 0) return FFCZ_OK;
-  HIPCHK(g_host_init.reserve(sizeof(SigDesc) * ns + sizeof(int32_t) * ns));
-  SigDesc* hd = (SigDesc*)g_host_init.p;
+  // own staging buffer: the grouped members reuse g_host_init while these copies may be in flight
+  HIPCHK(g_host_sig.reserve(sizeof(SigDesc) * ns + sizeof(int32_t) * ns));
+  SigDesc* hd = (SigDesc*)g_host_sig.p;
   int32_t* ho = (int32_t*)(hd + ns);
   for (int k = 0; k < ns; ++k) {
     const ffcz_instance& in = inst[bp.sig_ids[k]];
@@ -1092,7 +1617,7 @@ int32_t run_sigs(const BatchPlan& bp, const ffcz_instance* inst, const double* m
     d.E = in.eps_s;
     d.Delta = in.delta_f;
     d.Ep = in.eps_s * (1.0 - mus[bp.sig_ids[k]]);
-    d.Dp = in.delta_f * (1.0 - mus[bp.sig_ids[k]]);
+    spectral_thresholds(bp.dt, in.delta_f, mus[bp.sig_ids[k]], &d.Dc, &d.Dp);
     d.conv = b + sp.conv64;
     d.conv64 = b + sp.conv64;
     if (sp.blue) {
@@ -1118,16 +1643,89 @@ int32_t run_sigs(const BatchPlan& bp, const ffcz_instance* inst, const double* m
   for (auto& kv : bp.by_mc)
     HIPCHK(write_mc_tabs(bp.dt, kv.first, ws + bp.mc_off.at(kv.first), bp.mc_tab.at(kv.first), s));
   const int32_t* order = (const int32_t*)(ws + bp.off_order);
+  hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)((ns * sizeof(SigStats) / 8 + 255) / 256)), dim3(256), 0, s,
+                     (unsigned long long*)(ws + bp.off_sstats), (int64_t)(ns * sizeof(SigStats) / 8));
+  HIPCHK(hipGetLastError());
+  const int fixed = o.fixed_iterations ? 1 : 0;
+  // a launch of one mode over every signal of class lg, in the mode's arithmetic
+  auto go = [&](int mode, int lg) -> hipError_t {
+    const int nb = (int)bp.by_mc.at(lg).size();
+    const int32_t* ord = order + first[lg];
+    if (sig_mode_fp64(mode, bp.dt)) return sig_launch<double>(bp.dt, mode, lg, bp, ws, ord, nb, max_iter, fixed, s);
+    return sig_launch<float>(bp.dt, mode, lg, bp, ws, ord, nb, max_iter, fixed, s);
+  };
+  std::vector<int> tiled;
+  std::map<int, std::pair<bool, bool>> kinds;  // class -> (has Bluestein lengths, has power-of-two lengths)
   for (auto& kv : bp.by_mc) {
     const int lg = kv.first;
-    const int nb = (int)kv.second.size();
-    const int32_t* ord = order + first[lg];
-    HIPCHK(sig_launch<double>(bp.dt, SIG_SETUP, lg, bp, ws, ord, nb, max_iter, 0, s));
-    if (bp.dt == FFCZ_F32)
-      HIPCHK(sig_launch<float>(bp.dt, SIG_RUN, lg, bp, ws, ord, nb, max_iter, o.fixed_iterations, s));
-    else
-      HIPCHK(sig_launch<double>(bp.dt, SIG_RUN, lg, bp, ws, ord, nb, max_iter, o.fixed_iterations, s));
-    if (o.verify_fp64) HIPCHK(sig_launch<double>(bp.dt, SIG_VERIFY, lg, bp, ws, ord, nb, max_iter, 0, s));
+    if (lg >= sig_tiled_from_lg(o)) {
+      tiled.push_back(lg);
+      bool b = false, p2 = false;
+      for (int k : kv.second) (bp.sigs[k].blue ? b : p2) = true;
+      kinds[lg] = {b, p2};
+      continue;
+    }
+    HIPCHK(go(SIG_SETUP, lg));
+    HIPCHK(go(SIG_RUN, lg));
+    if (o.verify_fp64) HIPCHK(go(SIG_VERIFY, lg));
+  }
+  if (tiled.empty()) return FFCZ_OK;
+
+  // tiled classes: set-up, eps0 and the first forward column pass
+  for (int lg : tiled) {
+    if (kinds[lg].first) {
+      HIPCHK(go(SIGT_CHIRP, lg));
+      HIPCHK(go(SIGT_BCOL, lg));
+      HIPCHK(go(SIGT_BROW, lg));
+    }
+    HIPCHK(go(SIGT_EPS0, lg));
+    HIPCHK(go(SIGT_CIN, lg));
+  }
+  // rounds in chunks; every round pass returns at entry once its signal's loop has ended
+  const int chunk = o.graph_chunk > 0 ? o.graph_chunk : 4;
+  HIPCHK(g_host_state.reserve(sizeof(SigStats) * ns));
+  SigStats* hs = (SigStats*)g_host_state.p;
+  for (int enq = 0;; enq += chunk) {
+    for (int r = 0; r < chunk; ++r) {
+      for (int lg : tiled) {
+        const bool b = kinds[lg].first, p2 = kinds[lg].second;
+        if (b) HIPCHK(go(SIGT_RMUL, lg));
+        if (p2) HIPCHK(go(SIGT_RCHECK, lg));
+        if (b) HIPCHK(go(SIGT_CCHECK, lg));
+        int nct = 0, nrt = 0;
+        sig_tiles(lg, &nct, &nrt);
+        const int nb = (int)bp.by_mc.at(lg).size();
+        hipLaunchKernelGGL(sig_ctl_kernel, dim3((unsigned)nb), dim3(256), 0, s, (const SigDesc*)(ws + bp.off_desc),
+                           (SigStats*)(ws + bp.off_sstats), order + first[lg],
+                           (const unsigned long long*)(ws + bp.tpart_off.at(lg)), (int32_t)nb,
+                           (int32_t)bp.tpart_tiles.at(lg), (int32_t)nct, (int32_t)nrt, max_iter, (int32_t)fixed);
+        HIPCHK(hipGetLastError());
+        if (b) HIPCHK(go(SIGT_RMUL, lg));
+        HIPCHK(go(SIGT_CSPAT, lg));
+      }
+    }
+    HIPCHK(hipMemcpyAsync(hs, ws + bp.off_sstats, sizeof(SigStats) * ns, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    bool all = true;
+    for (int lg : tiled)
+      for (int k : bp.by_mc.at(lg)) all = all && hs[k].done;
+    if (all) break;
+    if (enq > max_iter + 2 * chunk + 2) return fail(FFCZ_E_HIP, "tiled signals did not report completion");
+  }
+  for (int lg : tiled) {
+    HIPCHK(go(SIGT_Y, lg));
+    if (!o.verify_fp64) continue;
+    HIPCHK(go(SIGT_VCOL, lg));
+    HIPCHK(go(SIGT_VROW, lg));
+    if (kinds[lg].first) HIPCHK(go(SIGT_VCOL2, lg));
+    int nct = 0, nrt = 0;
+    sig_tiles(lg, &nct, &nrt);
+    const int nb = (int)bp.by_mc.at(lg).size();
+    hipLaunchKernelGGL(sig_vstats_kernel, dim3((unsigned)nb), dim3(256), 0, s, (const SigDesc*)(ws + bp.off_desc),
+                       (SigStats*)(ws + bp.off_sstats), order + first[lg],
+                       (const unsigned long long*)(ws + bp.tpart_off.at(lg)), (int32_t)nb,
+                       (int32_t)bp.tpart_tiles.at(lg), (int32_t)nct, (int32_t)nrt);
+    HIPCHK(hipGetLastError());
   }
   return FFCZ_OK;
 }
@@ -1168,6 +1766,30 @@ int32_t collect_sigs(const BatchPlan& bp, const ffcz_instance* inst, const doubl
   return FFCZ_OK;
 }
 
+// Streaming copy: one 16-byte vector per lane, one block per 4 KiB (measured on
+// MI355X as the fastest of the simple forms: more work per lane or a grid-stride
+// loop keeps fewer requests in flight).
+__global__ void __launch_bounds__(256) copy_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src,
+                                                   int64_t n16) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n16) dst[i] = src[i];
+}
+
+__global__ void copy_tail_kernel(unsigned char* __restrict__ dst, const unsigned char* __restrict__ src, int n) {
+  if ((int)threadIdx.x < n) dst[threadIdx.x] = src[threadIdx.x];
+}
+
+// The thread that drives the 1D members of a mixed batch; joined on every exit path.
+struct SigWorker {
+  std::thread th;
+  int32_t rc = FFCZ_OK;
+  std::string err;
+  void join() {
+    if (th.joinable()) th.join();
+  }
+  ~SigWorker() { join(); }
+};
+
 int32_t worst(const std::vector<int32_t>& st) {
   int32_t w = FFCZ_OK;
   for (int32_t v : st) {
@@ -1184,6 +1806,48 @@ extern "C" {
 int32_t ffcz_version(void) { return 100; }
 
 const char* ffcz_last_error(void) { return g_err.c_str(); }
+
+int32_t ffcz_set_tuning(int32_t mode, const char* cache_path) {
+  if (mode < 0 || mode > 3) return fail(FFCZ_E_INVALID, "tuning mode must be 0, 1, 2 or 3");
+  std::lock_guard<std::mutex> g(g_tuner.m);
+  g_tuner.init_locked();
+  g_tuner.mode = mode;
+  if (cache_path) {
+    g_tuner.path = cache_path;
+    g_tuner.loaded = false;
+    g_tuner.load_locked();
+  }
+  return FFCZ_OK;
+}
+
+void ffcz_clear_tuning(void) {
+  std::lock_guard<std::mutex> g(g_tuner.m);
+  g_tuner.tab.clear();
+  g_tuner.loaded = true;
+}
+
+int32_t ffcz_copy(void* dst, const void* src, size_t bytes, void* stream) {
+  if (bytes == 0) return FFCZ_OK;
+  if (!dst || !src) return fail(FFCZ_E_INVALID, "null pointer");
+  if (((uintptr_t)dst & 15) || ((uintptr_t)src & 15)) return fail(FFCZ_E_INVALID, "pointers must be 16-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 > 0) {
+    for (int64_t v0 = 0; v0 < n16; v0 += (int64_t)1 << 36) {  // grid x holds 2^31 - 1 blocks
+      const int64_t nv = std::min<int64_t>((int64_t)1 << 36, n16 - v0);
+      hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, (uint4*)dst + v0,
+                         (const uint4*)src + v0, nv);
+      HIPCHK(hipGetLastError());
+    }
+  }
+  const int tail = (int)(bytes - (size_t)n16 * 16);
+  if (tail > 0) {
+    hipLaunchKernelGGL(copy_tail_kernel, dim3(1), dim3(16), 0, s, (unsigned char*)dst + n16 * 16,
+                       (const unsigned char*)src + n16 * 16, tail);
+    HIPCHK(hipGetLastError());
+  }
+  return FFCZ_OK;
+}
 
 void ffcz_profile_enable(int32_t on) {
   g_prof.on = on != 0;
@@ -1224,6 +1888,8 @@ void ffcz_default_options(ffcz_options* o) {
   memset(o, 0, sizeof(*o));
   o->verify_fp64 = 1;
   o->graph_chunk = 4;
+  o->use_graph = 1;
+  o->tiled_1d_lg = 15;
 }
 
 size_t ffcz_workspace_bytes(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max_iter) {
@@ -1270,7 +1936,7 @@ int32_t ffcz_correct(int32_t dtype, int32_t ndim, const int64_t* shape, const vo
   ffcz_options o;
   if (opts) o = *opts;
   else ffcz_default_options(&o);
-  if (o.masks_out && p.dt == FFCZ_F64 && col_block_cols(1, p.Lx) < 8)
+  if (o.masks_out && p.dt == FFCZ_F64 && col_block_cols(1, p.Lx, 0) < 8)
     return fail(FFCZ_E_SHAPE, "mask recording needs at least 8 columns per block");
   hipStream_t s = (hipStream_t)stream;
   double mu = o.margin_rel;
@@ -1292,6 +1958,7 @@ int32_t ffcz_correct(int32_t dtype, int32_t ndim, const int64_t* shape, const vo
   r = dtype == FFCZ_F32 ? correct_group<float>(p, &in, &mu, max_iter, o, (char*)ws, s, stats, &status)
                         : correct_group<double>(p, &in, &mu, max_iter, o, (char*)ws, s, stats, &status);
   if (r != FFCZ_OK) return r;
+  if (stats) stats->status = status;
   if (status == FFCZ_E_NONFINITE) return fail(FFCZ_E_NONFINITE, "x or x_hat holds NaN or Inf");
   if (status == FFCZ_VERIFY_FAILED) g_err = "FP64 re-verification failed";
   return status;
@@ -1329,21 +1996,69 @@ int32_t ffcz_correct_batched(int32_t dtype, int32_t count, const ffcz_instance* 
   }
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
-  // margins: per instance (FP32: suggested from x; FP64: 2^-16)
+  // margins: per instance (FP32: suggested from x, all members in one launch; FP64: 2^-16)
   std::vector<double> mus(count, o.margin_rel);
-  for (int i = 0; i < count; ++i) {
-    if (o.margin_rel > 0.0) continue;
-    int64_t sq[3];
-    const int nd = squeeze(inst[i].ndim, inst[i].shape, sq);
-    int64_t N = 1;
-    for (int d = 0; d < nd; ++d) N *= sq[d];
-    r = margin_for(dtype, N, inst[i].x_orig, inst[i].delta_f, (DevState*)(w + bp.off_scratch), s, &mus[i]);
-    if (r != FFCZ_OK) return r;
+  if (!(o.margin_rel > 0.0) && count > 0) {
+    std::vector<int64_t> Ns(count);
+    for (int i = 0; i < count; ++i) {
+      int64_t sq[3];
+      const int nd = squeeze(inst[i].ndim, inst[i].shape, sq);
+      int64_t N = 1;
+      for (int d = 0; d < nd; ++d) N *= sq[d];
+      Ns[i] = N;
+    }
+    if (dtype == FFCZ_F64) {
+      for (int i = 0; i < count; ++i) mus[i] = std::ldexp(1.0, -16);
+    } else {
+      HIPCHK(g_host_misc.reserve(sizeof(MarginJob) * count + sizeof(double) * count));
+      MarginJob* hj = (MarginJob*)g_host_misc.p;
+      double* hs = (double*)(hj + count);
+      int64_t nmax = 1;
+      for (int i = 0; i < count; ++i) {
+        hj[i] = MarginJob{(const float*)inst[i].x_orig, Ns[i]};
+        nmax = std::max(nmax, Ns[i]);
+      }
+      MarginJob* dj = (MarginJob*)(w + bp.off_mjobs);
+      double* dsum = (double*)(w + bp.off_msum);
+      HIPCHK(hipMemcpyAsync(dj, hj, sizeof(MarginJob) * count, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(zero_f64_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, dsum, (int64_t)count);
+      HIPCHK(hipGetLastError());
+      const unsigned bx = (unsigned)std::min<int64_t>(64, (nmax + 255) / 256);
+      for (int c0 = 0; c0 < count; c0 += 65535) {  // grid y holds at most 65535 fields
+        const int nc = std::min(65535, count - c0);
+        hipLaunchKernelGGL(ulp_batch_kernel, dim3(bx, (unsigned)nc), dim3(256), 0, s, (const MarginJob*)dj + c0,
+                           dsum + c0);
+        HIPCHK(hipGetLastError());
+      }
+      HIPCHK(hipMemcpyAsync(hs, dsum, sizeof(double) * count, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int i = 0; i < count; ++i) mus[i] = margin_from_ulp2(hs[i], Ns[i], inst[i].delta_f);
+    }
   }
   std::vector<int32_t> status(count, FFCZ_OK);
-  // 1D members: one launch per convolution length; the grouped members follow on the stream
-  r = run_sigs(bp, inst, mus.data(), max_iter, o, w, s);
-  if (r != FFCZ_OK) return r;
+  // 1D members on a side stream forked from the caller's, driven by a worker thread (the tiled
+  // classes poll their done-flags), so they run beside the grouped members' rounds
+  hipStream_t s1 = s;
+  SigWorker worker;
+  if (!bp.sig_ids.empty() && !bp.groups.empty()) {
+    HIPCHK(g_streams.ready());
+    s1 = g_streams.side;
+    HIPCHK(hipEventRecord(g_streams.fork, s));
+    HIPCHK(hipStreamWaitEvent(s1, g_streams.fork, 0));
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    worker.th = std::thread([&, dev, s1] {
+      if (hipSetDevice(dev) != hipSuccess) {
+        worker.rc = fail(FFCZ_E_HIP, "hipSetDevice failed on the 1D worker");
+      } else {
+        worker.rc = run_sigs(bp, inst, mus.data(), max_iter, o, w, s1);
+      }
+      if (worker.rc != FFCZ_OK) worker.err = g_err;
+    });
+  } else {
+    r = run_sigs(bp, inst, mus.data(), max_iter, o, w, s1);
+    if (r != FFCZ_OK) return r;
+  }
   for (size_t g = 0; g < bp.groups.size(); ++g) {
     const Plan& p = bp.gplans[g];
     std::vector<ffcz_instance> gi;
@@ -1363,9 +2078,19 @@ int32_t ffcz_correct_batched(int32_t dtype, int32_t count, const ffcz_instance* 
       if (stats) stats[bp.groups[g][k]] = gst[k];
     }
   }
+  if (s1 != s) {
+    worker.join();
+    if (worker.rc != FFCZ_OK) return fail(worker.rc, worker.err);
+    HIPCHK(hipEventRecord(g_streams.join, s1));
+    HIPCHK(hipStreamWaitEvent(s, g_streams.join, 0));
+  }
   r = collect_sigs(bp, inst, mus.data(), o, w, s, stats, status.data());
   if (r != FFCZ_OK) return r;
-  return worst(status);
+  if (stats)
+    for (int i = 0; i < count; ++i) stats[i].status = status[i];
+  const int32_t wst = worst(status);
+  if (wst == FFCZ_VERIFY_FAILED) g_err = "FP64 re-verification failed for at least one instance";
+  return wst;
 }
 
 int32_t ffcz_correct_backward(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t rounds, const void* masks,

@@ -12,8 +12,8 @@ namespace ffcz {
 // (the set-up kernel or the per-round control kernel); read at the entry of
 // every loop kernel.
 struct DevState {
-  // parameters
-  double E, Ep, Delta, Dp, inv_n;
+  // parameters: bounds, the shrunk s-bound, the check threshold and the shrunk f-bound
+  double E, Ep, Delta, Dc, Dp, inv_n;
   int32_t max_iter, fixed, record_masks, pad0;
   // loop control
   int32_t done, round, converged, nonfinite_stop;
@@ -43,7 +43,7 @@ enum ColMode : int {
 enum RowMode : int {
   ROW_INIT = 0,    // eps0 = x_hat - x (FP64), guard clip, R2C
   ROW_LOOP = 1,    // C2R, 1/N, s-clip (+ s-mask), R2C
-  ROW_FINAL = 2,   // C2R, 1/N, y = x + eps in FP64, closing clamp, store y
+  ROW_FINAL = 2,   // C2R, 1/n_last, y = x + eps in FP64, closing clamp, store y
   ROW_VERIFY = 3,  // d = y - x in FP64, max |d|, FP64 R2C
   ROW_BINIT = 4,   // g * s-mask, R2C        (adjoint)
   ROW_BLOOP = 5,   // C2R, 1/N, g * s-mask, R2C (adjoint)
@@ -85,6 +85,9 @@ struct RowArgs {
   int64_t s_plane;   // uint32 words per s-mask plane
   int32_t s_row_w32; // uint32 words per s-mask row
   int32_t pad;
+  int64_t plane;     // complex entries per plane of rows (src / dst spectra)
+  int32_t lg_rpp;    // log2 of the rows per plane
+  int32_t pad2;
 };
 
 // FP64 bound -> working type, rounded toward zero (a tighter bound in FP32).
@@ -117,6 +120,31 @@ __host__ __device__ constexpr int pick_rows(int H) {
   int r = 64;
   while (r > 1 && (r * P > 1024 || (long)r * (H + 1) * (long)sizeof(cx<T>) > 72 * 1024)) r /= 2;
   return r;
+}
+
+// Plans the tuner chooses between.  Column passes: variant 1 halves the tile
+// width.  Last-axis passes: variant 1 halves the rows per block; variant 2
+// uses radix-8 stages (8 elements per lane, twice the lanes per row) where the
+// default is radix 16.  Variants 0 and 1 compute identical bits; variant 2
+// rounds differently.
+constexpr int kColVariants = 2;
+constexpr int kRowVariants = 3;
+template <typename T>
+__host__ __device__ constexpr int tile_cols(int L, int v) {
+  return (pick_C<T>(L) >> v) < 1 ? 1 : (pick_C<T>(L) >> v);
+}
+// Elements per lane of a last-axis plan.
+__host__ __device__ constexpr int row_E(int H, int v) { return (v == 2 && pick_E_row(H) == 16) ? 8 : pick_E_row(H); }
+template <typename T>
+__host__ __device__ constexpr int rows_for_E(int H, int E) {
+  const int P = H / E > 0 ? H / E : 1;
+  int r = 64;
+  while (r > 1 && (r * P > 1024 || (long)r * (H + 1) * (long)sizeof(cx<T>) > 72 * 1024)) r /= 2;
+  return r;
+}
+template <typename T>
+__host__ __device__ constexpr int tile_rows(int H, int v) {
+  return v == 2 ? rows_for_E<T>(H, row_E(H, 2)) : ((pick_rows<T>(H) >> v) < 1 ? 1 : (pick_rows<T>(H) >> v));
 }
 
 }  // namespace ffcz

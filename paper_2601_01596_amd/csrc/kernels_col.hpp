@@ -52,7 +52,7 @@ col_kernel(ColArgs<T> a) {
     fft<T, L, E, true, C, 1>(v, lds, tws, c, j);
   } else if constexpr (MODE == COL_XPASS) {
     const int k = *(volatile int32_t*)&st->round;
-    const T D = to_t<T>(st->Delta);
+    const T D = to_t<T>(st->Dc);
     const T Dp = to_t<T>(st->Dp);
     const bool rec = st->record_masks && (k < st->max_iter);
     fft<T, L, E, false, C, 1>(v, lds, tws, c, j);

@@ -49,10 +49,9 @@ __device__ __forceinline__ TIO closing_clamp(TIO y, TIO x, double E) {
   return (fabs((double)y - (double)x) <= E) ? y : x;
 }
 
-template <typename T, typename TIO, int H, int ROWS, int MODE>
-__global__ void __launch_bounds__(ROWS*(H / pick_E_row(H)), 4)
+template <typename T, typename TIO, int H, int ROWS, int MODE, int E>
+__global__ void __launch_bounds__(ROWS*(H / E), 4)
 row_kernel(RowArgs<T, TIO> a) {
-  constexpr int E = pick_E_row(H);
   constexpr int P = H / E;
   constexpr int NT = ROWS * P;
   constexpr int LP = H + 1;            // LDS row pitch (odd for H >= 2)
@@ -82,6 +81,10 @@ row_kernel(RowArgs<T, TIO> a) {
   if constexpr (MODE == ROW_LOOP) {
     if (*(volatile int32_t*)&st->done) return;
   }
+  // first entry of spectrum row R (rows are grouped in planes of 2^lg_rpp rows)
+  auto rowaddr = [&](int64_t R) -> int64_t {
+    return (R >> a.lg_rpp) * a.plane + (R & ((int64_t(1) << a.lg_rpp) - 1)) * a.pitch;
+  };
   const int t = threadIdx.x;
   const int rl = t % ROWS;  // compute mapping: rows fastest
   const int j = t / ROWS;
@@ -126,7 +129,7 @@ row_kernel(RowArgs<T, TIO> a) {
       for (int u = 0; u < BL; ++u) {
         const int f = t + (b0 + u) * NT;
         const int r = f / NC, k = f - r * NC;
-        tmp[u] = (b0 + u < NL && f < ROWS * NC && r < nrow) ? a.src[(row0 + r) * a.pitch + k] : cx<T>{T(0), T(0)};
+        tmp[u] = (b0 + u < NL && f < ROWS * NC && r < nrow) ? a.src[rowaddr(row0 + r) + k] : cx<T>{T(0), T(0)};
       }
 #pragma unroll
       for (int u = 0; u < BL; ++u) {
@@ -273,7 +276,7 @@ row_kernel(RowArgs<T, TIO> a) {
           const cx<T> od = cx<T>{d.im * T(0.5), -d.re * T(0.5)};  // d / (2i)
           X = ev + cmul(rtw[k], od);
         }
-        a.dst[(row0 + r) * a.pitch + k] = X;
+        a.dst[rowaddr(row0 + r) + k] = X;
       }
     }
   } else {

@@ -21,6 +21,11 @@
 // [column: finish the inverse DFT, 1/L, real part, spatial clip, start the
 // next forward DFT]; a power-of-two L needs only [row: forward, count, clip,
 // inverse] [column: inverse, clip, forward].
+//
+// Long signals run the same passes tiled: each SIGT_* launch does one pass,
+// one block per (signal, column tile) or (signal, row tile), and writes one
+// partial count per block; sig_ctl_kernel sums them per signal and sets the
+// signal's done-flag, which every round pass checks at entry.
 #pragma once
 #include <type_traits>
 
@@ -36,7 +41,7 @@ struct SigDesc {
   int64_t L;
   int32_t blue;       // 1: Bluestein, 0: L == Mc
   int32_t pad;
-  double E, Delta, Ep, Dp;
+  double E, Delta, Ep, Dc, Dp;  // bounds, shrunk s-bound, check threshold, shrunk f-bound
   void* conv;         // Mc complex of the working type (aliases conv64)
   void* conv64;       // Mc complex FP64 (set-up and verification)
   void* btab;         // Mc complex, working type, row-pass layout (Bluestein)
@@ -47,7 +52,7 @@ struct SigDesc {
 };
 
 struct SigStats {
-  int32_t rounds, converged, nonfinite_stop, pad;
+  int32_t rounds, converged, nonfinite_stop, done;
   unsigned long long viol0, violf, s_clipped, s_guard, nonfinite, spectral_viol;
   double max_spatial, max_spectral;
 };
@@ -68,7 +73,13 @@ struct SigArgs {
   int32_t nsig;
   int32_t max_iter, fixed, pad;
   SigTabs<T> tab;
+  // tiled passes: partial slots [kind][signal slot][tile], kind = SigPart
+  unsigned long long* part;
+  int32_t ptiles;  // tiles per signal slot in part
+  int32_t pad2;
 };
+
+enum SigPart : int { SP_VIOL = 0, SP_SCLIP = 1, SP_NONFIN = 2, SP_VMAXF = 3, SP_VCNT = 4, SP_VMAXS = 5, SP_KINDS = 6 };
 
 __host__ __device__ constexpr int imin3(int a, int b, int c) { return a < b ? (a < c ? a : c) : (b < c ? b : c); }
 __host__ __device__ constexpr int imax2(int a, int b) { return a > b ? a : b; }
@@ -84,13 +95,40 @@ struct SigGeom {
   static constexpr int RR = NT / PA;  // rows per row tile
   static constexpr int LPA = MA + 1;  // LDS pitch of a row (odd)
   static constexpr int LDS = imax2(CC * MB, RR * LPA);
+  static constexpr int NCT = MA / CC;  // column tiles (also the element chunks of the tiled passes)
+  static constexpr int NRT = MB / RR;  // row tiles
   // row-pass table layout: entry (k2, k1) at ((k2 / RR) * MA + k1) * RR + k2 % RR
   __host__ __device__ static constexpr int64_t rpos(int k2, int k1) {
     return ((int64_t)(k2 / RR) * MA + k1) * RR + (k2 % RR);
   }
 };
 
-enum SigMode : int { SIG_SETUP = 0, SIG_RUN = 1, SIG_VERIFY = 2 };
+enum SigMode : int {
+  // one block per signal, the whole job in one launch
+  SIG_SETUP = 0,    // chirp and the spectrum of its conjugate (Bluestein), FP64
+  SIG_RUN = 1,      // eps0, every round, y
+  SIG_VERIFY = 2,   // FP64 DFT of y - x: maxima and violation count
+  // tiled: one pass per launch, one block per (signal, tile)
+  SIGT_CHIRP = 3,   // chirp tables, element chunks                          [Bluestein]
+  SIGT_BCOL = 4,    // column pass of the conjugate chirp                      [Bluestein]
+  SIGT_BROW = 5,    // row pass, store its spectrum / Mc                       [Bluestein]
+  SIGT_EPS0 = 6,    // eps0 = x_hat - x (FP64), guard clip; guard and non-finite partials
+  SIGT_CIN = 7,     // column pass starting the forward DFT of eps (x chirp)
+  SIGT_RMUL = 8,    // row pass: forward, x spectrum of b, inverse            [Bluestein]
+  SIGT_RCHECK = 9,  // row pass: forward DFT completes, count, clip, inverse  [power of two]
+  SIGT_CCHECK = 10, // column pass: X = w c, count, clip, start the inverse DFT [Bluestein]
+  SIGT_CSPAT = 11,  // column pass: finish the inverse DFT, s-clip, next forward start
+  SIGT_Y = 12,      // y = x + eps (FP64, clamp); max |y - x| partial
+  SIGT_VCOL = 13,   // verification: column pass of d = y - x (FP64)
+  SIGT_VROW = 14,   // verification: row pass (Bluestein: x spectrum of b; else maxima partials)
+  SIGT_VCOL2 = 15   // verification: final column pass, maxima partials         [Bluestein]
+};
+
+__host__ __device__ constexpr bool sig_tiled(int m) { return m >= SIGT_CHIRP; }
+// tiled passes laid out over row tiles; all others over column tiles / element chunks
+__host__ __device__ constexpr bool sig_row_tiled(int m) {
+  return m == SIGT_BROW || m == SIGT_RMUL || m == SIGT_RCHECK || m == SIGT_VROW;
+}
 
 // Block-wide sum / max, result broadcast to every lane.
 template <int NT>
@@ -129,16 +167,44 @@ sig_kernel(SigArgs<T> a) {
   __shared__ unsigned long long red_u[NT / 64 + 1];
   __shared__ double red_d[NT / 64 + 1];
 
-  if ((int)blockIdx.x >= a.nsig) return;
-  const int sid = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
+  constexpr bool tiled = sig_tiled(MODE);
+  constexpr int NTL = sig_row_tiled(MODE) ? G::NRT : G::NCT;  // tiles per signal in this launch
+  const int slot = tiled ? (int)blockIdx.x / NTL : (int)blockIdx.x;
+  const int tile = tiled ? (int)blockIdx.x - slot * NTL : 0;
+  if (slot >= a.nsig) return;
+  const int sid = a.order ? a.order[slot] : slot;
   const SigDesc sd = a.sig[sid];
   SigStats* so = a.stats + sid;
   const int64_t L = sd.L;
   const bool blue = sd.blue != 0;
   const int t = threadIdx.x;
-  cx<T>* conv = (cx<T>*)(MODE == SIG_RUN ? sd.conv : sd.conv64);
-  const cx<T>* chirp = (const cx<T>*)(MODE == SIG_RUN ? sd.chirp : sd.chirp64);
-  const cx<T>* btab = (const cx<T>*)(MODE == SIG_RUN ? sd.btab : sd.btab64);
+  // the loop (SIG_RUN and the round passes) works in T = the data type; set-up and
+  // verification in FP64 on the FP64 buffers
+  constexpr bool loopT = (MODE == SIG_RUN || MODE == SIGT_EPS0 || MODE == SIGT_CIN || MODE == SIGT_RMUL ||
+                          MODE == SIGT_RCHECK || MODE == SIGT_CCHECK || MODE == SIGT_CSPAT || MODE == SIGT_Y);
+  cx<T>* conv = (cx<T>*)(loopT ? sd.conv : sd.conv64);
+  const cx<T>* chirp = (const cx<T>*)(loopT ? sd.chirp : sd.chirp64);
+  const cx<T>* btab = (const cx<T>*)(loopT ? sd.btab : sd.btab64);
+  // tiled partial slot of this block
+  auto pslot = [&](int kind) -> unsigned long long& {
+    return a.part[((int64_t)kind * a.nsig + slot) * a.ptiles + tile];
+  };
+  // the tiled round passes stop once the signal's loop has ended
+  if constexpr (MODE == SIGT_RMUL || MODE == SIGT_RCHECK || MODE == SIGT_CCHECK || MODE == SIGT_CSPAT) {
+    if (*(volatile int32_t*)&so->done) return;
+  }
+  // passes that exist only for one kind of length
+  if constexpr (MODE == SIGT_CHIRP || MODE == SIGT_BCOL || MODE == SIGT_BROW || MODE == SIGT_RMUL ||
+                MODE == SIGT_CCHECK || MODE == SIGT_VCOL2) {
+    if (!blue) return;
+  }
+  if constexpr (MODE == SIGT_RCHECK) {
+    if (blue) return;
+  }
+  // element chunk of the tiled element-wise passes
+  constexpr int64_t CH = (int64_t)Mc / G::NCT;
+  const int64_t n_lo = tiled ? (int64_t)tile * CH : 0;
+  const int64_t n_hi = tiled ? (n_lo + CH < L ? n_lo + CH : L) : L;
   T* eps = (T*)sd.eps;
   const TIO* xs = (const TIO*)sd.x;
   const TIO* xbs = (const TIO*)sd.xb;
@@ -148,11 +214,14 @@ sig_kernel(SigArgs<T> a) {
   // ---- column pass: for every column n1, inverse MB-FFT (if INV1), element op at the
   // natural index n = n1 + MA*i (or at k2 = i), forward MB-FFT (if FWD2), times the
   // four-step twiddle, store.  in(n1, i) supplies the input when there is no INV1.
+  // tiles [tlo, thi) of the pass (all of them in the one-block modes)
+  const int ctlo = tiled ? tile : 0, cthi = tiled ? tile + 1 : G::NCT;
+  const int rtlo = tiled ? tile : 0, rthi = tiled ? tile + 1 : G::NRT;
   auto col_pass = [&](auto INV1c, auto FWD2c, auto in, auto op) {
     constexpr bool INV1 = decltype(INV1c)::value;
     constexpr bool FWD2 = decltype(FWD2c)::value;
     const int c = t % CC, j = t / CC;
-    for (int c0 = 0; c0 < MA; c0 += CC) {
+    for (int c0 = ctlo * CC; c0 < cthi * CC; c0 += CC) {
       const int n1 = c0 + c;
       cx<T> v[EB];
       if constexpr (INV1) {
@@ -183,7 +252,7 @@ sig_kernel(SigArgs<T> a) {
     constexpr bool INV = decltype(INVc)::value;
     const int rl = t % RR, j = t / RR;
     cx<T>* lrow = lds + rl * LPA;
-    for (int r0 = 0; r0 < MB; r0 += RR) {
+    for (int r0 = rtlo * RR; r0 < rthi * RR; r0 += RR) {
       constexpr int NL = (RR * MA + NT - 1) / NT;
 #pragma unroll
       for (int b0 = 0; b0 < NL; b0 += BL) {
@@ -232,31 +301,47 @@ sig_kernel(SigArgs<T> a) {
   using FF = std::integral_constant<bool, false>;
   const cx<T> zero{T(0), T(0)};
 
-  if constexpr (MODE == SIG_SETUP) {
+  // block-wide partial of a tiled pass
+  auto put_sum = [&](int kind, unsigned long long v) {
+    v = block_sum<NT>(v, red_u);
+    if (t == 0) pslot(kind) = v;
+  };
+  auto put_max = [&](int kind, double v) {
+    v = block_max<NT>(v, red_d);
+    if (t == 0) pslot(kind) = (unsigned long long)__double_as_longlong(v);
+  };
+
+  if constexpr (MODE == SIG_SETUP || MODE == SIGT_CHIRP || MODE == SIGT_BCOL || MODE == SIGT_BROW) {
     // chirp w[n] = exp(-i pi (n^2 mod 2L) / L) in FP64, and the spectrum of b = conj(w) wrapped
     if (!blue) return;
     // FP32 copies only when the working tables are separate (FP32 batches)
     cx<float>* ch32 = (sd.chirp != sd.chirp64) ? (cx<float>*)sd.chirp : nullptr;
     cx<double>* ch64 = (cx<double>*)sd.chirp64;
-    for (int64_t n = t; n < L; n += NT) {
-      const int64_t r = (int64_t)(((unsigned long long)n * (unsigned long long)n) % (unsigned long long)(2 * L));
-      double s, c;
-      sincospi(-(double)r / (double)L, &s, &c);
-      ch64[n] = cx<double>{c, s};
-      if (ch32) ch32[n] = cx<float>{__double2float_rn(c), __double2float_rn(s)};
+    if constexpr (MODE == SIG_SETUP || MODE == SIGT_CHIRP) {
+      for (int64_t n = n_lo + t; n < n_hi; n += NT) {
+        const int64_t r = (int64_t)(((unsigned long long)n * (unsigned long long)n) % (unsigned long long)(2 * L));
+        double s, c;
+        sincospi(-(double)r / (double)L, &s, &c);
+        ch64[n] = cx<double>{c, s};
+        if (ch32) ch32[n] = cx<float>{__double2float_rn(c), __double2float_rn(s)};
+      }
+      if constexpr (MODE == SIGT_CHIRP) return;
+      __syncthreads();
     }
-    __syncthreads();
-    auto bin = [&](int n1, int i) -> cx<T> {
-      const int64_t n = n1 + (int64_t)MA * i;
-      int64_t m = -1;
-      if (n < L) m = n;
-      else if (n > Mc - L) m = Mc - n;
-      if (m < 0) return zero;
-      const cx<double> w = ch64[m];
-      return cx<T>{(T)w.re, (T)(-w.im)};
-    };
-    auto ident = [&](int, int, cx<T> v) { return v; };
-    col_pass(FF{}, TT{}, bin, ident);
+    if constexpr (MODE == SIG_SETUP || MODE == SIGT_BCOL) {
+      auto bin = [&](int n1, int i) -> cx<T> {
+        const int64_t n = n1 + (int64_t)MA * i;
+        int64_t m = -1;
+        if (n < L) m = n;
+        else if (n > Mc - L) m = Mc - n;
+        if (m < 0) return zero;
+        const cx<double> w = ch64[m];
+        return cx<T>{(T)w.re, (T)(-w.im)};
+      };
+      auto ident = [&](int, int, cx<T> v) { return v; };
+      col_pass(FF{}, TT{}, bin, ident);
+      if constexpr (MODE == SIGT_BCOL) return;
+    }
     // row FFT; store (1/Mc) * spectrum in the row-pass layout of both precisions
     cx<float>* bt32 = (sd.btab != sd.btab64) ? (cx<float>*)sd.btab : nullptr;
     cx<double>* bt64 = (cx<double>*)sd.btab64;
@@ -273,20 +358,8 @@ sig_kernel(SigArgs<T> a) {
     return;
   }
 
-  if constexpr (MODE == SIG_VERIFY) {
+  if constexpr (MODE == SIG_VERIFY || MODE == SIGT_VCOL || MODE == SIGT_VROW || MODE == SIGT_VCOL2) {
     // FP64 DFT of d = y - x: max |d|, max(|Re|,|Im|) and count above Delta over k <= L/2
-    double ms = 0.0;
-    for (int64_t n = t; n < L; n += NT) ms = fmax(ms, fabs((double)ys[n] - (double)xs[n]));
-    ms = block_max<NT>(ms, red_d);
-    auto din = [&](int n1, int i) -> cx<T> {
-      const int64_t n = n1 + (int64_t)MA * i;
-      if (n >= L) return zero;
-      const T d = (T)((double)ys[n] - (double)xs[n]);
-      if (!blue) return cx<T>{d, T(0)};
-      return scal(chirp[n], d);
-    };
-    auto ident = [&](int, int, cx<T> v) { return v; };
-    col_pass(FF{}, TT{}, din, ident);
     double mf = 0.0;
     unsigned long long nv = 0;
     const double D = sd.Delta;
@@ -297,62 +370,71 @@ sig_kernel(SigArgs<T> a) {
         nv += (m > D) ? 1 : 0;
       }
     };
-    if (!blue) {
-      auto rop = [&](int k2, int k1, cx<T> v) {
-        acc(k2 + (int64_t)MB * k1, v);
-        return v;
-      };
-      row_pass(FF{}, rop);
-    } else {
-      auto mulb = [&](int k2, int k1, cx<T> v) { return cmul(v, btab[G::rpos(k2, k1)]); };
-      row_pass(TT{}, mulb);
-      auto fin = [&](int n1, int i, cx<T> c) {
+    auto ident = [&](int, int, cx<T> v) { return v; };
+    auto mulb = [&](int k2, int k1, cx<T> v) { return cmul(v, btab[G::rpos(k2, k1)]); };
+    auto fin = [&](int n1, int i, cx<T> c) {
+      const int64_t n = n1 + (int64_t)MA * i;
+      if (n < L) acc(n, cmul(chirp[n], c));
+      return c;
+    };
+    auto rop = [&](int k2, int k1, cx<T> v) {
+      acc(k2 + (int64_t)MB * k1, v);
+      return v;
+    };
+    if constexpr (MODE == SIG_VERIFY || MODE == SIGT_VCOL) {
+      auto din = [&](int n1, int i) -> cx<T> {
         const int64_t n = n1 + (int64_t)MA * i;
-        if (n < L) acc(n, cmul(chirp[n], c));
-        return c;
+        if (n >= L) return zero;
+        const T d = (T)((double)ys[n] - (double)xs[n]);
+        if (!blue) return cx<T>{d, T(0)};
+        return scal(chirp[n], d);
       };
+      col_pass(FF{}, TT{}, din, ident);
+      if constexpr (MODE == SIGT_VCOL) return;
+    }
+    if constexpr (MODE == SIGT_VROW) {
+      if (blue) {
+        row_pass(TT{}, mulb);
+      } else {
+        row_pass(FF{}, rop);
+        put_max(SP_VMAXF, mf);
+        put_sum(SP_VCNT, nv);
+      }
+      return;
+    }
+    if constexpr (MODE == SIGT_VCOL2) {
       col_pass(TT{}, FF{}, [&](int, int) { return zero; }, fin);
+      put_max(SP_VMAXF, mf);
+      put_sum(SP_VCNT, nv);
+      return;
     }
-    mf = block_max<NT>(mf, red_d);
-    nv = block_sum<NT>(nv, red_u);
-    if (t == 0) {
-      so->max_spatial = ms;
-      so->max_spectral = mf;
-      so->spectral_viol = nv;
+    if constexpr (MODE == SIG_VERIFY) {
+      double ms = 0.0;
+      for (int64_t n = t; n < L; n += NT) ms = fmax(ms, fabs((double)ys[n] - (double)xs[n]));
+      ms = block_max<NT>(ms, red_d);
+      if (!blue) {
+        row_pass(FF{}, rop);
+      } else {
+        row_pass(TT{}, mulb);
+        col_pass(TT{}, FF{}, [&](int, int) { return zero; }, fin);
+      }
+      mf = block_max<NT>(mf, red_d);
+      nv = block_sum<NT>(nv, red_u);
+      if (t == 0) {
+        so->max_spatial = ms;
+        so->max_spectral = mf;
+        so->spectral_viol = nv;
+      }
+      return;
     }
-    return;
   }
 
-  // ------------------------------------------------------------------ SIG_RUN
+  // ------------------------------------------------------------------ the loop
   const double Ep64 = sd.Ep;
   const T Ep = to_t<T>(sd.Ep);
-  const T D = to_t<T>(sd.Delta);
+  const T D = to_t<T>(sd.Dc);
   const T Dp = to_t<T>(sd.Dp);
   const T invL = T(1) / (T)L;
-  // eps0 = x_hat - x in FP64, guard clip
-  unsigned long long guard = 0, nonfin = 0;
-  for (int64_t n = t; n < L; n += NT) {
-    double e = (double)xbs[n] - (double)xs[n];
-    if (!isfinite(e)) {
-      ++nonfin;
-      e = 0.0;
-    }
-    guard += (fabs(e) > Ep64) ? 1 : 0;
-    eps[n] = (T)clipv(e, Ep64);
-  }
-  guard = block_sum<NT>(guard, red_u);
-  nonfin = block_sum<NT>(nonfin, red_u);
-  if (nonfin) {
-    if (t == 0) {
-      so->nonfinite = nonfin;
-      so->nonfinite_stop = 1;
-      so->rounds = 0;
-      so->converged = 0;
-    }
-    return;
-  }
-  __syncthreads();
-
   auto ein = [&](int n1, int i) -> cx<T> {  // a = eps (times the chirp)
     const int64_t n = n1 + (int64_t)MA * i;
     if (n >= L) return zero;
@@ -360,78 +442,142 @@ sig_kernel(SigArgs<T> a) {
     return blue ? scal(chirp[n], e) : cx<T>{e, T(0)};
   };
   auto ident = [&](int, int, cx<T> v) { return v; };
-  col_pass(FF{}, TT{}, ein, ident);
-
-  int k = 0;
-  unsigned long long v0 = 0, vk = 0, sclip = 0;
-  for (;;) {
-    unsigned long long cnt = 0;
-    if (!blue) {
-      // row: the forward DFT completes here -> count + clip -> inverse row FFT
-      auto rop = [&](int k2, int k1, cx<T> X) {
-        const int64_t kk = k2 + (int64_t)MB * k1;
-        if (kk <= L / 2 && (fabs(X.re) > D || fabs(X.im) > D)) ++cnt;
-        return cx<T>{clipv(X.re, Dp), clipv(X.im, Dp)};
-      };
-      row_pass(TT{}, rop);
-    } else {
-      auto mulb = [&](int k2, int k1, cx<T> v) { return cmul(v, btab[(int64_t)G::rpos(k2, k1)]); };
-      row_pass(TT{}, mulb);
-      // column: X = w c -> count + clip -> start the inverse DFT with conj(X') w
-      auto fop = [&](int n1, int i, cx<T> c) -> cx<T> {
-        const int64_t n = n1 + (int64_t)MA * i;
-        if (n >= L) return zero;
-        const cx<T> w = chirp[n];
-        const cx<T> X = cmul(w, c);
-        if (n <= L / 2 && (fabs(X.re) > D || fabs(X.im) > D)) ++cnt;
-        const cx<T> Xc{clipv(X.re, Dp), -clipv(X.im, Dp)};
-        return cmul(Xc, w);
-      };
-      col_pass(TT{}, TT{}, [&](int, int) { return zero; }, fop);
-    }
-    cnt = block_sum<NT>(cnt, red_u);
-    if (k == 0) v0 = cnt;
-    vk = cnt;
-    if ((!a.fixed && cnt == 0) || k >= a.max_iter) break;
+  auto mulb = [&](int k2, int k1, cx<T> v) { return cmul(v, btab[(int64_t)G::rpos(k2, k1)]); };
+  unsigned long long cnt = 0, sc = 0;
+  // row: the forward DFT completes here -> count + clip -> inverse row FFT (power of two)
+  auto rop = [&](int k2, int k1, cx<T> X) {
+    const int64_t kk = k2 + (int64_t)MB * k1;
+    if (kk <= L / 2 && (fabs(X.re) > D || fabs(X.im) > D)) ++cnt;
+    return cx<T>{clipv(X.re, Dp), clipv(X.im, Dp)};
+  };
+  // column: X = w c -> count + clip -> start the inverse DFT with conj(X') w (Bluestein)
+  auto fop = [&](int n1, int i, cx<T> c) -> cx<T> {
+    const int64_t n = n1 + (int64_t)MA * i;
+    if (n >= L) return zero;
+    const cx<T> w = chirp[n];
+    const cx<T> X = cmul(w, c);
+    if (n <= L / 2 && (fabs(X.re) > D || fabs(X.im) > D)) ++cnt;
+    const cx<T> Xc{clipv(X.re, Dp), -clipv(X.im, Dp)};
+    return cmul(Xc, w);
+  };
+  // column: finish the inverse DFT, spatial clip, start the next forward DFT
+  auto sop = [&](int n1, int i, cx<T> c) -> cx<T> {
+    const int64_t n = n1 + (int64_t)MA * i;
+    if (n >= L) return zero;
+    T e;
     if (blue) {
-      auto mulb = [&](int k2, int k1, cx<T> v) { return cmul(v, btab[(int64_t)G::rpos(k2, k1)]); };
-      row_pass(TT{}, mulb);
+      const cx<T> w = chirp[n];
+      e = (w.re * c.re - w.im * c.im) * invL;  // Re(conj(w c)) / L
+    } else {
+      e = c.re * invL;
     }
-    // column: finish the inverse DFT, spatial clip, start the next forward DFT
-    unsigned long long sc = 0;
-    auto sop = [&](int n1, int i, cx<T> c) -> cx<T> {
-      const int64_t n = n1 + (int64_t)MA * i;
-      if (n >= L) return zero;
-      T e;
-      if (blue) {
-        const cx<T> w = chirp[n];
-        e = (w.re * c.re - w.im * c.im) * invL;  // Re(conj(w c)) / L
-      } else {
-        e = c.re * invL;
-      }
-      if (fabs(e) > Ep) ++sc;
-      e = clipv(e, Ep);
-      eps[n] = e;
-      return blue ? scal(chirp[n], e) : cx<T>{e, T(0)};
-    };
-    col_pass(TT{}, TT{}, [&](int, int) { return zero; }, sop);
-    sclip += block_sum<NT>(sc, red_u);
-    ++k;
-  }
-  __syncthreads();
-  // y = x + eps in FP64, rounded once, closing clamp
+    if (fabs(e) > Ep) ++sc;
+    e = clipv(e, Ep);
+    eps[n] = e;
+    return blue ? scal(chirp[n], e) : cx<T>{e, T(0)};
+  };
   const double Eb = sd.E;
-  for (int64_t n = t; n < L; n += NT)
-    ys[n] = closing_clamp<TIO>(round_io<TIO>((double)xs[n] + (double)eps[n]), xs[n], Eb);
-  if (t == 0) {
-    so->rounds = k;
-    so->converged = (vk == 0) ? 1 : 0;
-    so->viol0 = v0;
-    so->violf = vk;
-    so->s_clipped = sclip;
-    so->s_guard = guard;
-    so->nonfinite = 0;
-    so->nonfinite_stop = 0;
+
+  if constexpr (MODE == SIGT_EPS0 || MODE == SIG_RUN) {
+    // eps0 = x_hat - x in FP64, guard clip
+    unsigned long long guard = 0, nonfin = 0;
+    for (int64_t n = n_lo + t; n < n_hi; n += NT) {
+      double e = (double)xbs[n] - (double)xs[n];
+      if (!isfinite(e)) {
+        ++nonfin;
+        e = 0.0;
+      }
+      guard += (fabs(e) > Ep64) ? 1 : 0;
+      eps[n] = (T)clipv(e, Ep64);
+    }
+    if constexpr (MODE == SIGT_EPS0) {
+      put_sum(SP_SCLIP, guard);
+      put_sum(SP_NONFIN, nonfin);
+      return;
+    }
+    if constexpr (MODE == SIG_RUN) {
+      guard = block_sum<NT>(guard, red_u);
+      nonfin = block_sum<NT>(nonfin, red_u);
+      if (nonfin) {
+        if (t == 0) {
+          so->nonfinite = nonfin;
+          so->nonfinite_stop = 1;
+          so->rounds = 0;
+          so->converged = 0;
+        }
+        return;
+      }
+      __syncthreads();
+      col_pass(FF{}, TT{}, ein, ident);
+      int k = 0;
+      unsigned long long v0 = 0, vk = 0, sclip = 0;
+      for (;;) {
+        cnt = 0;
+        if (!blue) {
+          row_pass(TT{}, rop);
+        } else {
+          row_pass(TT{}, mulb);
+          col_pass(TT{}, TT{}, [&](int, int) { return zero; }, fop);
+        }
+        cnt = block_sum<NT>(cnt, red_u);
+        if (k == 0) v0 = cnt;
+        vk = cnt;
+        if ((!a.fixed && cnt == 0) || k >= a.max_iter) break;
+        if (blue) row_pass(TT{}, mulb);
+        sc = 0;
+        col_pass(TT{}, TT{}, [&](int, int) { return zero; }, sop);
+        sclip += block_sum<NT>(sc, red_u);
+        ++k;
+      }
+      __syncthreads();
+      // y = x + eps in FP64, rounded once, closing clamp
+      for (int64_t n = t; n < L; n += NT)
+        ys[n] = closing_clamp<TIO>(round_io<TIO>((double)xs[n] + (double)eps[n]), xs[n], Eb);
+      if (t == 0) {
+        so->rounds = k;
+        so->converged = (vk == 0) ? 1 : 0;
+        so->viol0 = v0;
+        so->violf = vk;
+        so->s_clipped = sclip;
+        so->s_guard = guard;
+        so->nonfinite = 0;
+        so->nonfinite_stop = 0;
+      }
+      return;
+    }
+  }
+  if constexpr (MODE == SIGT_CIN) {
+    col_pass(FF{}, TT{}, ein, ident);
+    return;
+  }
+  if constexpr (MODE == SIGT_RMUL) {
+    row_pass(TT{}, mulb);
+    return;
+  }
+  if constexpr (MODE == SIGT_RCHECK) {
+    row_pass(TT{}, rop);
+    put_sum(SP_VIOL, cnt);
+    return;
+  }
+  if constexpr (MODE == SIGT_CCHECK) {
+    col_pass(TT{}, TT{}, [&](int, int) { return zero; }, fop);
+    put_sum(SP_VIOL, cnt);
+    return;
+  }
+  if constexpr (MODE == SIGT_CSPAT) {
+    col_pass(TT{}, TT{}, [&](int, int) { return zero; }, sop);
+    put_sum(SP_SCLIP, sc);
+    return;
+  }
+  if constexpr (MODE == SIGT_Y) {
+    double ms = 0.0;
+    for (int64_t n = n_lo + t; n < n_hi; n += NT) {
+      const TIO yv = closing_clamp<TIO>(round_io<TIO>((double)xs[n] + (double)eps[n]), xs[n], Eb);
+      ys[n] = yv;
+      ms = fmax(ms, fabs((double)yv - (double)xs[n]));
+    }
+    put_max(SP_VMAXS, ms);
+    return;
   }
 }
 

@@ -7,15 +7,14 @@
 
 namespace ffcz {
 
-// Columns per block used by the strided-axis kernels of this dtype and length.
-int col_block_cols(int dtype, int L);
-// Rows per block of the last-axis kernels computing in this dtype.
-int row_block_rows(int dtype, int H);
+// Columns per block used by the strided-axis kernels of this dtype, length and
+// tile variant (only the loop modes COL_FWD / COL_INV / COL_XPASS have variant 1).
+int col_block_cols(int dtype, int L, int v);
+// Rows per block of the last-axis kernels computing in this dtype (variant 1
+// exists for ROW_INIT / ROW_LOOP / ROW_FINAL).
+int row_block_rows(int dtype, int H, int v);
 
 // dtype 0: float, 1: double.  args points to a ColArgs<T>.
-hipError_t launch_col(int dtype, int mode, int L, const void* args, int64_t nblocks, hipStream_t s);
-// tdtype: compute type (0 float, 1 double); iodtype: storage type of the real fields.
-hipError_t launch_row(int tdtype, int iodtype, int mode, int H, const void* args, int64_t nblocks,
-                      hipStream_t s);
+hipError_t launch_col(int dtype, int mode, int L, int v, const void* args, int64_t nblocks, hipStream_t s);
 
 }  // namespace ffcz

@@ -4,12 +4,13 @@
 
 namespace ffcz {
 
-template <int MODE>
+// V: tile variant (columns per block = pick_C >> V), chosen per size by the tuner
+template <int MODE, int V>
 static hipError_t go(int L, const ColArgs<double>& a, int64_t nb, hipStream_t s) {
   switch (L) {
 #define FFCZ_CASE(LL)                                                               \
   case LL: {                                                                        \
-    constexpr int C = pick_C<double>(LL);                                              \
+    constexpr int C = tile_cols<double>(LL, V);                                          \
     constexpr int NT = C * (LL / pick_E(LL));                                       \
     hipLaunchKernelGGL((col_kernel<double, LL, C, MODE>), dim3((unsigned)nb), dim3(NT), 0, s, a); \
     return hipGetLastError();                                                       \
@@ -21,16 +22,16 @@ static hipError_t go(int L, const ColArgs<double>& a, int64_t nb, hipStream_t s)
   }
 }
 
-hipError_t launch_col_f64(int mode, int L, const void* args, int64_t nb, hipStream_t s) {
+hipError_t launch_col_f64(int mode, int L, int v, const void* args, int64_t nb, hipStream_t s) {
   const ColArgs<double>& a = *static_cast<const ColArgs<double>*>(args);
   switch (mode) {
-    case COL_FWD: return go<COL_FWD>(L, a, nb, s);
-    case COL_INV: return go<COL_INV>(L, a, nb, s);
-    case COL_XPASS: return go<COL_XPASS>(L, a, nb, s);
-    case COL_XBACK: return go<COL_XBACK>(L, a, nb, s);
-    case COL_FWD_NS: return go<COL_FWD_NS>(L, a, nb, s);
-    case COL_INV_NS: return go<COL_INV_NS>(L, a, nb, s);
-    case COL_VERIFY: return go<COL_VERIFY>(L, a, nb, s);
+    case COL_FWD: return v ? go<COL_FWD, 1>(L, a, nb, s) : go<COL_FWD, 0>(L, a, nb, s);
+    case COL_INV: return v ? go<COL_INV, 1>(L, a, nb, s) : go<COL_INV, 0>(L, a, nb, s);
+    case COL_XPASS: return v ? go<COL_XPASS, 1>(L, a, nb, s) : go<COL_XPASS, 0>(L, a, nb, s);
+    case COL_XBACK: return go<COL_XBACK, 0>(L, a, nb, s);
+    case COL_FWD_NS: return go<COL_FWD_NS, 0>(L, a, nb, s);
+    case COL_INV_NS: return go<COL_INV_NS, 0>(L, a, nb, s);
+    case COL_VERIFY: return go<COL_VERIFY, 0>(L, a, nb, s);
     default: return hipErrorInvalidValue;
   }
 }

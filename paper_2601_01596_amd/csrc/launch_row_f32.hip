@@ -4,14 +4,16 @@
 
 namespace ffcz {
 
-template <typename T, typename TIO, int MODE>
+// V: tile variant (rows per block = pick_rows >> V), chosen per size by the tuner
+template <typename T, typename TIO, int MODE, int V>
 static hipError_t go(int H, const RowArgs<T, TIO>& a, int64_t nb, hipStream_t s) {
   switch (H) {
 #define FFCZ_CASE(HH)                                                                  \
   case HH: {                                                                           \
-    constexpr int R = pick_rows<T>(HH);                                                   \
-    constexpr int NT = R * (HH / pick_E_row(HH));                                          \
-    hipLaunchKernelGGL((row_kernel<T, TIO, HH, R, MODE>), dim3((unsigned)nb), dim3(NT), 0, s, a); \
+    constexpr int R = tile_rows<T>(HH, V);                                                \
+    constexpr int EE = row_E(HH, V);                                                       \
+    constexpr int NT = R * (HH / EE);                                                      \
+    hipLaunchKernelGGL((row_kernel<T, TIO, HH, R, MODE, EE>), dim3((unsigned)nb), dim3(NT), 0, s, a); \
     return hipGetLastError();                                                          \
   }
     FFCZ_CASE(1) FFCZ_CASE(2) FFCZ_CASE(4) FFCZ_CASE(8) FFCZ_CASE(16) FFCZ_CASE(32)
@@ -21,15 +23,19 @@ static hipError_t go(int H, const RowArgs<T, TIO>& a, int64_t nb, hipStream_t s)
   }
 }
 
-hipError_t launch_row_f32(int mode, int H, const void* args, int64_t nb, hipStream_t s) {
+hipError_t launch_row_f32(int mode, int H, int v, const void* args, int64_t nb, hipStream_t s) {
   const RowArgs<float, float>& a = *static_cast<const RowArgs<float, float>*>(args);
   switch (mode) {
-    case ROW_INIT: return go<float, float, ROW_INIT>(H, a, nb, s);
-    case ROW_LOOP: return go<float, float, ROW_LOOP>(H, a, nb, s);
-    case ROW_FINAL: return go<float, float, ROW_FINAL>(H, a, nb, s);
-    case ROW_BINIT: return go<float, float, ROW_BINIT>(H, a, nb, s);
-    case ROW_BLOOP: return go<float, float, ROW_BLOOP>(H, a, nb, s);
-    case ROW_BFINAL: return go<float, float, ROW_BFINAL>(H, a, nb, s);
+    case ROW_INIT:
+      return v == 2 ? go<float, float, ROW_INIT, 2>(H, a, nb, s)
+                    : (v ? go<float, float, ROW_INIT, 1>(H, a, nb, s) : go<float, float, ROW_INIT, 0>(H, a, nb, s));
+    case ROW_LOOP:
+      return v == 2 ? go<float, float, ROW_LOOP, 2>(H, a, nb, s)
+                    : (v ? go<float, float, ROW_LOOP, 1>(H, a, nb, s) : go<float, float, ROW_LOOP, 0>(H, a, nb, s));
+    case ROW_FINAL: return go<float, float, ROW_FINAL, 0>(H, a, nb, s);
+    case ROW_BINIT: return go<float, float, ROW_BINIT, 0>(H, a, nb, s);
+    case ROW_BLOOP: return go<float, float, ROW_BLOOP, 0>(H, a, nb, s);
+    case ROW_BFINAL: return go<float, float, ROW_BFINAL, 0>(H, a, nb, s);
     default: return hipErrorInvalidValue;
   }
 }

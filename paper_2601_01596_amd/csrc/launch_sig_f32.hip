@@ -1,32 +1,25 @@
-// Dispatch of the per-signal kernels (float data).
-#include "kernels_sig.hpp"
+// Dispatch of the per-signal kernels on float data: the FP32 loop (one-block and
+// tiled passes) and the one-block FP64 verification.
 #include "launch.hpp"
+#include "sig_dispatch.hpp"
 
 namespace ffcz {
 
-template <typename T, typename TIO, int MODE>
-static hipError_t go(int lgMc, const SigArgs<T>& a, int nb, hipStream_t s) {
-  switch (lgMc) {
-#define FFCZ_CASE(LG, MA, MB)                                                                       \
-  case LG: {                                                                                         \
-    hipLaunchKernelGGL((sig_kernel<T, TIO, MA, MB, MODE>), dim3((unsigned)nb), dim3((SigGeom<T, MA, MB>::NT)), 0, s, a); \
-    return hipGetLastError();                                                                       \
-  }
-    FFCZ_CASE(2, 2, 2) FFCZ_CASE(3, 4, 2) FFCZ_CASE(4, 4, 4) FFCZ_CASE(5, 8, 4) FFCZ_CASE(6, 8, 8)
-    FFCZ_CASE(7, 16, 8) FFCZ_CASE(8, 16, 16) FFCZ_CASE(9, 32, 16) FFCZ_CASE(10, 32, 32)
-    FFCZ_CASE(11, 64, 32) FFCZ_CASE(12, 64, 64) FFCZ_CASE(13, 128, 64) FFCZ_CASE(14, 128, 128)
-    FFCZ_CASE(15, 256, 128) FFCZ_CASE(16, 256, 256) FFCZ_CASE(17, 512, 256) FFCZ_CASE(18, 512, 512)
-    FFCZ_CASE(19, 1024, 512) FFCZ_CASE(20, 1024, 1024)
-#undef FFCZ_CASE
+hipError_t launch_sig_f32(int mode, int lgMc, const void* args, int nsig, hipStream_t s) {
+  const SigArgs<float>& a = *static_cast<const SigArgs<float>*>(args);
+  switch (mode) {
+    case SIG_RUN: return sig_go<float, float, SIG_RUN>(lgMc, a, nsig, s);
+    case SIG_VERIFY:
+      return sig_go<double, float, SIG_VERIFY>(lgMc, *static_cast<const SigArgs<double>*>(args), nsig, s);
+    case SIGT_EPS0: return sig_go<float, float, SIGT_EPS0>(lgMc, a, nsig, s);
+    case SIGT_CIN: return sig_go<float, float, SIGT_CIN>(lgMc, a, nsig, s);
+    case SIGT_RMUL: return sig_go<float, float, SIGT_RMUL>(lgMc, a, nsig, s);
+    case SIGT_RCHECK: return sig_go<float, float, SIGT_RCHECK>(lgMc, a, nsig, s);
+    case SIGT_CCHECK: return sig_go<float, float, SIGT_CCHECK>(lgMc, a, nsig, s);
+    case SIGT_CSPAT: return sig_go<float, float, SIGT_CSPAT>(lgMc, a, nsig, s);
+    case SIGT_Y: return sig_go<float, float, SIGT_Y>(lgMc, a, nsig, s);
     default: return hipErrorInvalidValue;
   }
-}
-
-hipError_t launch_sig_f32(int mode, int lgMc, const void* args, int nb, hipStream_t s) {
-  // the FP32 loop; its FP64 verification (double compute, float data)
-  if (mode == SIG_RUN) return go<float, float, SIG_RUN>(lgMc, *static_cast<const SigArgs<float>*>(args), nb, s);
-  if (mode == SIG_VERIFY) return go<double, float, SIG_VERIFY>(lgMc, *static_cast<const SigArgs<double>*>(args), nb, s);
-  return hipErrorInvalidValue;
 }
 
 }  // namespace ffcz

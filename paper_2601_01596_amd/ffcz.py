@@ -31,7 +31,8 @@ E_HIP = -5
 
 EXPORTS = ("ffcz_version", "ffcz_last_error", "ffcz_default_options", "ffcz_workspace_bytes",
            "ffcz_mask_bytes", "ffcz_suggest_margin", "ffcz_correct", "ffcz_correct_backward",
-           "ffcz_batched_workspace_bytes", "ffcz_correct_batched", "ffcz_profile_enable", "ffcz_profile_read")
+           "ffcz_batched_workspace_bytes", "ffcz_correct_batched", "ffcz_profile_enable", "ffcz_profile_read",
+           "ffcz_copy", "ffcz_set_tuning", "ffcz_clear_tuning")
 
 PROFILE_KINDS = ("init", "y_fwd", "x_pass", "y_inv", "z_pass", "finalize", "verify_z", "verify_y", "verify_x",
                  "adjoint_z", "adjoint_y", "adjoint_x")
@@ -46,6 +47,7 @@ class Options(ctypes.Structure):
         ("viol_per_round", ctypes.c_void_p),
         ("graph_chunk", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
+        ("tiled_1d_lg", ctypes.c_int32),
     ]
 
 
@@ -62,10 +64,12 @@ class Stats(ctypes.Structure):
         ("max_spectral_err", ctypes.c_double),
         ("spectral_viol", ctypes.c_int64),
         ("margin_used", ctypes.c_double),
+        ("status", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class Instance(ctypes.Structure):
@@ -134,6 +138,12 @@ def lib() -> ctypes.CDLL:
         L.ffcz_profile_enable.restype = None
         L.ffcz_profile_read.argtypes = [ctypes.POINTER(Profile)]
         L.ffcz_profile_read.restype = ctypes.c_int32
+        L.ffcz_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.ffcz_copy.restype = ctypes.c_int32
+        L.ffcz_set_tuning.argtypes = [ctypes.c_int32, ctypes.c_char_p]
+        L.ffcz_set_tuning.restype = ctypes.c_int32
+        L.ffcz_clear_tuning.argtypes = []
+        L.ffcz_clear_tuning.restype = None
         _lib = L
     return _lib
 
@@ -225,6 +235,21 @@ def ffcz_profile_read() -> dict:
     return {k: (pr.ms[i], int(pr.count[i])) for i, k in enumerate(PROFILE_KINDS)}
 
 
+def ffcz_set_tuning(mode: int, cache_path=None) -> int:
+    """Tile tuning mode (0 default tiles, 1 tune on first use, 2 narrowest) and cache file."""
+    p = None if cache_path is None else str(cache_path).encode()
+    return int(lib().ffcz_set_tuning(int(mode), p))
+
+
+def ffcz_clear_tuning() -> None:
+    lib().ffcz_clear_tuning()
+
+
+def ffcz_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream: int) -> int:
+    return int(lib().ffcz_copy(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr), int(nbytes),
+                               ctypes.c_void_p(stream)))
+
+
 # ---------------------------------------------------------------- torch conveniences
 
 def _torch():
@@ -248,6 +273,20 @@ def _check_tensor(t, name):
         raise FFCzError(E_INVALID, f"{name} must be contiguous")
 
 
+def copy_(dst, src):
+    """dst[:] = src with the library's streaming copy kernel, on the current stream."""
+    torch = _torch()
+    if dst.numel() * dst.element_size() != src.numel() * src.element_size():
+        raise ValueError("copy_: byte sizes differ")
+    if not (dst.is_contiguous() and src.is_contiguous()):
+        raise ValueError("copy_: tensors must be contiguous")
+    st = ffcz_copy(dst.data_ptr(), src.data_ptr(), src.numel() * src.element_size(),
+                   torch.cuda.current_stream(src.device).cuda_stream)
+    if st < 0:
+        raise FFCzError(st, ffcz_last_error())
+    return dst
+
+
 def workspace(dtype_code: int, shape, max_iter: int, device=None):
     torch = _torch()
     nbytes = ffcz_workspace_bytes(dtype_code, shape, max_iter)
@@ -268,7 +307,7 @@ class Result:
 
 def correct(x, xb, eps_s: float, delta_f: float, max_iter: int, *, margin: float = 0.0, fixed: bool = False,
             verify: bool = True, record_masks: bool = False, record_viol: bool = False, chunk: int = 4,
-            out=None, ws=None, check: bool = True) -> Result:
+            graph: bool = True, out=None, ws=None, check: bool = True) -> Result:
     """Run ``ffcz_correct`` on device tensors ``x`` (original) and ``xb`` (base)."""
     torch = _torch()
     _check_tensor(x, "x")
@@ -285,6 +324,7 @@ def correct(x, xb, eps_s: float, delta_f: float, max_iter: int, *, margin: float
     opts.fixed_iterations = 1 if fixed else 0
     opts.verify_fp64 = 1 if verify else 0
     opts.graph_chunk = int(chunk)
+    opts.use_graph = 1 if graph else 0
     masks = None
     if record_masks:
         masks = torch.zeros(ffcz_mask_bytes(shape, max_iter), dtype=torch.uint8, device=x.device)
@@ -303,7 +343,7 @@ def correct(x, xb, eps_s: float, delta_f: float, max_iter: int, *, margin: float
 
 
 def correct_batched(members, max_iter: int, *, margin: float = 0.0, fixed: bool = False, verify: bool = True,
-                    chunk: int = 4, ws=None, check: bool = True):
+                    chunk: int = 4, graph: bool = True, tiled_1d_lg: int = 0, ws=None, check: bool = True):
     """``ffcz_correct_batched`` over ``members = [(x, xb, eps_s, delta_f), ...]`` (device tensors).
 
     Returns ``(outputs, status, per-member stats dicts)``.
@@ -336,6 +376,9 @@ def correct_batched(members, max_iter: int, *, margin: float = 0.0, fixed: bool 
     opts.fixed_iterations = 1 if fixed else 0
     opts.verify_fp64 = 1 if verify else 0
     opts.graph_chunk = int(chunk)
+    opts.use_graph = 1 if graph else 0
+    if tiled_1d_lg:
+        opts.tiled_1d_lg = int(tiled_1d_lg)
     stats = (Stats * len(insts))()
     stream = torch.cuda.current_stream(dev).cuda_stream
     st = ffcz_correct_batched(dt, insts, max_iter, opts, ws.data_ptr(), ws.numel(), stream, stats)

@@ -67,6 +67,7 @@ def test_1d_members_any_length(dt):
     probs = [_member((L,), 100 + i, dt) for i, L in enumerate(LENGTHS)]
     ys, st, stats = _run(probs)
     assert st == F.OK, (st, F.ffcz_last_error(), stats)
+    assert all(s["status"] == F.OK for s in stats)
     for p, y, s, L in zip(probs, ys, stats, LENGTHS):
         say(f"[batched] L={L} rounds={s['rounds']}")
         _check(p, y, s, dt)
@@ -79,6 +80,22 @@ def test_2d_group_mixed_with_1d(dt):
     ys, st, stats = _run(probs)
     assert st == F.OK, (st, F.ffcz_last_error(), stats)
     for p, y, s in zip(probs, ys, stats):
+        _check(p, y, s, dt)
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_tiled_1d_passes_match_one_block_bitwise(dt):
+    # the same passes split over many blocks per signal: identical bits, counts and maxima
+    lengths = [4096, 5000, 31000, 65536, 100003, 131072]
+    probs = [_member((L,), 600 + i, dt) for i, L in enumerate(lengths)]
+    probs.append(_member((64, 128), 650, dt))  # a 2D group, so the 1D members run beside it
+    ys_t, st_t, stats_t = _run(probs, tiled_1d_lg=12)
+    ys_b, st_b, stats_b = _run(probs, tiled_1d_lg=21)
+    assert st_t == F.OK and st_b == F.OK, (st_t, st_b, F.ffcz_last_error())
+    for p, a, b, sa, sb in zip(probs, ys_t, ys_b, stats_t, stats_b):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), p.x.shape
+        assert sa == sb, (p.x.shape, sa, sb)
+    for p, y, s in zip(probs[:-1], ys_t, stats_t):
         _check(p, y, s, dt)
 
 
@@ -98,11 +115,12 @@ def test_batched_statuses():
     b = _member((64, 64), 501, np.float32, q=50.0)
     ys, st, stats = _run([a, b], max_iter=0)
     assert st == F.NOT_CONVERGED and all(s["rounds"] == 0 for s in stats)
+    assert [s["status"] for s in stats] == [F.NOT_CONVERGED, F.NOT_CONVERGED]
     bad = a.xb.copy()
     bad[17] = np.nan
     mem = [(torch.from_numpy(a.x).cuda(), torch.from_numpy(bad).cuda(), a.E, a.Delta)]
     _, st, stats = F.correct_batched(mem, 10, check=False)
-    assert st == F.E_NONFINITE and stats[0]["nonfinite"] == 1
+    assert st == F.E_NONFINITE and stats[0]["nonfinite"] == 1 and stats[0]["status"] == F.E_NONFINITE
 
 
 @pytest.mark.timeout(900)
@@ -120,7 +138,11 @@ def test_full_batch_eeg_and_diffraction():
     say("[full] batched correction")
     outs, st, stats = F.correct_batched(mem, 200, check=False)
     torch.cuda.synchronize()
-    assert st == F.OK, (st, F.ffcz_last_error())
+    bad = [(i, tuple(probs[i].x.shape), s) for i, s in enumerate(stats) if s["status"] != F.OK]
+    for i, shp, s in bad[:8]:
+        say(f"[full] member {i} shape {shp} E {probs[i].E:.6g} Delta {probs[i].Delta:.6g}: {s}")
+    assert st == max([s["status"] for s in stats] + [F.OK])
+    assert st == F.OK and not bad, (st, F.ffcz_last_error(), len(bad))
     for (x, _, E, D), y, s in zip(mem, outs, stats):
         assert s["max_spatial_err"] <= E and s["max_spectral_err"] <= D
         d = y.double() - x.double()

@@ -155,32 +155,78 @@ def test_grad256_fixed50_adjoint_vs_oracle_and_finite_differences():
     ref = O.adjoint(orc.masks, gy_o)
     rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
     cos = float(np.sum(g * ref) / (np.linalg.norm(g) * np.linalg.norm(ref)))
-    say(f"[grad] vs oracle adjoint: rel L2 {rel:.2e} cosine {cos:.8f}")
-    assert rel <= 1e-4 and cos >= 0.9999
+    # The FP32 forward and the FP64 oracle take the same clip decisions except for entries that
+    # sit on a bound: an entry clipped in one round is clipped again in the next at a value
+    # within rounding of the bound, where the keep-bit (the subgradient choice) is decided by
+    # rounding.  Step the oracle's own trajectory and require every differing bit to sit within
+    # FP32 noise (1e-5 relative) of its bound.
+    Ep = p.E * (1 - mu)
+    Dp = O.spectral_thresholds(p.Delta, mu, np.float32)[1]
+    eps, _, _ = O.project_s(p.xb.astype(np.float64) - p.x.astype(np.float64), Ep)
+    assert np.array_equal(gm.s[0], orc.masks.s[0])
+    flips = total = 0
+    for k in range(1, K + 1):
+        d = O.fft(eps)
+        dcl, kre, kim = O.project_f(d, Dp)
+        pre = O.ifft(dcl, eps.shape)
+        eps, ks, _ = O.project_s(pre, Ep)
+        assert np.array_equal(kre, orc.masks.f_re[k]) and np.array_equal(ks, orc.masks.s[k])
+        for a, b_, v, thr in ((gm.f_re[k], kre, d.real, Dp), (gm.f_im[k], kim, d.imag, Dp), (gm.s[k], ks, pre, Ep)):
+            bad = a != b_
+            flips += int(bad.sum())
+            total += bad.size
+            gap = np.abs(np.abs(v[bad]) - thr)
+            assert np.all(gap <= 1e-5 * thr), (k, int(bad.sum()), float(gap.max(initial=0.0)) / thr)
+    # the oracle's adjoint on the GPU's masks but the oracle's output isolates the flips
+    mixed = O.adjoint(gm, gy_o)
+    rel_arith = np.linalg.norm(g - mixed) / np.linalg.norm(mixed)
+    rel_flips = np.linalg.norm(mixed - ref) / np.linalg.norm(ref)
+    say(f"[grad] vs oracle adjoint: rel L2 {rel:.2e} cosine {cos:.8f}; bits on a bound that differ {flips} of "
+        f"{total}; same masks {rel_arith:.2e}, flips alone {rel_flips:.2e}")
+    assert rel_arith <= 1e-4
+    assert rel <= 2e-3 and cos >= 0.99999
 
-    # central finite differences of the same map in FP64 (h = 1e-3 data units) at 64 voxels
-    say("[grad] finite differences at 64 voxels (FP64 forward on the GPU)")
+    # Central finite differences of the FP64 map at 64 voxels, against that map's own adjoint
+    # (FP64 forward with masks, FP64 backward on the GPU).  The map is piecewise linear:
+    # h = 1e-6 data units (about 1e-4 E) stays on the linear piece, while 1e-3 (0.1 E) moves the
+    # perturbed voxel across its own spatial clip (errors up to 5 % of max|g| at 64^3).  The FP32
+    # gradient differs from the FP64 one only through the bound-sitting bits above.
+    say("[grad] finite differences at 64 voxels (FP64 forward and adjoint on the GPU)")
     x64 = x.double()
     xb64 = xb.detach().double()
     ws = F.workspace(F.F64, (n, n, n), K, x.device)
     out = torch.empty_like(x64)
-    h = 1e-3
+    h = 1e-6
     vox = np.random.default_rng(55).integers(0, n, size=(64, 3))
+    # the FP64 forward projects onto Delta (1 - mu), the FP32 one onto Delta (1 - 2 mu): hand the
+    # FP64 call the bound that gives the same projection (with fixed rounds the check is unused)
+    d64 = Dp / (1.0 - mu)
+    # the loss is evaluated on the host in FP64 (deterministic sums: the GPU bin sums use atomics,
+    # whose order changes the last bits, which h = 1e-6 would amplify)
+    xh = p.x.astype(np.float64)
+    r64 = F.correct(x64, xb64, p.E, d64, K, margin=mu, fixed=True, verify=False, record_masks=True, ws=ws)
+    gy64 = torch.from_numpy(SP.loss_grad(r64.y.cpu().numpy(), xh, NB)).cuda()
+    g64 = F.correct_backward(gy64, r64.masks, K, ws=ws).cpu().numpy()
+    rel64 = np.linalg.norm(g - g64) / np.linalg.norm(g64)
+    say(f"[grad] FP32 vs FP64 gradient: rel L2 {rel64:.2e}")
+    assert rel64 <= 2e-3
 
     def loss_at(xbv):
-        rr = F.correct(x64, xbv, p.E, p.Delta, K, margin=mu, fixed=True, verify=False, ws=ws, out=out)
-        return float(_loss_torch(rr.y, px, b_idx, wt))
+        rr = F.correct(x64, xbv, p.E, d64, K, margin=mu, fixed=True, verify=False, ws=ws, out=out)
+        return SP.loss(rr.y.cpu().numpy(), xh, NB)
 
-    gmax = float(np.abs(g).max())
+    gmax = float(np.abs(g64).max())
     bad = []
+    worst = 0.0
     for (i, j, k) in vox:
         xp = xb64.clone()
         xp[i, j, k] += h
         xm = xb64.clone()
         xm[i, j, k] -= h
         fd = (loss_at(xp) - loss_at(xm)) / (2 * h)
-        gv = g[i, j, k]
+        gv = g64[i, j, k]
+        worst = max(worst, abs(fd - gv) / gmax)
         if abs(fd - gv) > 1e-3 * abs(gv) + 1e-4 * gmax:
             bad.append((int(i), int(j), int(k), fd, gv))
-    say(f"[grad] finite-difference mismatches: {len(bad)} of 64 {bad[:3]}")
+    say(f"[grad] finite differences: max |fd - g| / max|g| = {worst:.2e}; mismatches {len(bad)} of 64 {bad[:3]}")
     assert not bad

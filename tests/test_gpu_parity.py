@@ -80,6 +80,23 @@ def test_shapes_fp32(shape):
     assert abs(int(v[0]) - orc.viol[0]) <= 2 + 1e-3 * orc.viol[0]
 
 
+@pytest.mark.parametrize("shape", [(2048, 64), (2048, 4, 8)])
+def test_leading_2048_fp32(shape):
+    # 2048 is the longest leading extent in FP32 (FP64 stops at 1024); its FP64 check runs
+    # the 2048-point column transform in FP64
+    test_shapes_fp32(shape)
+
+
+@pytest.mark.parametrize("dt,shape", [(np.float32, (2048, 2048)), (np.float64, (1024, 4096))])
+def test_largest_2d_extents(dt, shape):
+    O.set_workers(max(1, min(16, O.default_workers())))
+    p = _problem(shape, 13, dt)
+    y, res = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter)
+    mu = res.stats["margin_used"]
+    orc = O.correct(p.x, p.xb, p.E, p.Delta, p.max_iter, mu=mu)
+    (_check_fp64 if dt == np.float64 else _check_fp32)(p, y, res, orc)
+
+
 def test_lognormal64_fp32_and_fp64():
     # the 512^3 lognormal recipe (k^-2.5, E = 1e-4 range, 95th percentile) at 64^3
     for dt in (np.float32, np.float64):
@@ -157,7 +174,8 @@ def test_fixed_rounds_masks_match_oracle(dt):
     orc = O.correct(p.x, p.xb, p.E, p.Delta, K, mu=mu, fixed=True, record_masks=True)
     assert rel_err(y, orc.y) <= (1e-12 if dt == np.float64 else 1e-5)
     gm = unpack_masks(res.masks.cpu().numpy(), p.x.shape, K)
-    Ep, Dp = p.E * (1 - mu), p.Delta * (1 - mu)
+    Ep = p.E * (1 - mu)
+    Dp = O.spectral_thresholds(p.Delta, mu, dt)[1]
     np.testing.assert_array_equal(gm.s[0], orc.masks.s[0])  # guard clip runs in FP64
     for k in range(1, K + 1):
         prev = O.correct(p.x, p.xb, p.E, p.Delta, k - 1, mu=mu, fixed=True, verify_output=False).eps
@@ -220,3 +238,90 @@ def test_autograd_function_gradient():
     r = F.correct(x, xb.detach(), p.E, p.Delta, 3, fixed=True, verify=False, record_masks=True)
     ref = F.correct_backward(w, r.masks, 3)
     assert torch.equal(xb.grad, ref)
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (64, 128)])
+def test_graph_replays_match_plain_launches(shape):
+    """The round chunk captured in a hipGraph and replayed gives the plain-launch result,
+    bit for bit, on every replay, with unrelated device work and synchronisations between."""
+    import torch
+    p = _problem(shape, 61, np.float32, q=90.0)
+    x = torch.from_numpy(p.x).cuda()
+    xb = torch.from_numpy(p.xb).cuda()
+    ref = F.correct(x, xb, p.E, p.Delta, p.max_iter, graph=False, chunk=2)
+    for rep in range(4):
+        junk = torch.randn(1 << 20, device="cuda").sum()  # other work between replays
+        torch.cuda.synchronize()
+        r = F.correct(x, xb, p.E, p.Delta, p.max_iter, graph=True, chunk=2)
+        torch.cuda.synchronize()
+        assert r.status == ref.status and r.stats == ref.stats, rep
+        assert torch.equal(r.y, ref.y), rep
+        del junk
+
+
+@pytest.mark.parametrize("nbytes", [16, 1000, (1 << 20) + 48, (64 << 20) + 7])
+def test_copy_kernel_bit_exact(nbytes):
+    import torch
+    src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, generator=torch.Generator().manual_seed(nbytes)).cuda()
+    dst = torch.zeros_like(src)
+    F.copy_(dst, src)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+
+
+@pytest.mark.parametrize("dt,shape", [(np.float32, (32, 64, 128)), (np.float64, (64, 32, 256)),
+                                      (np.float32, (256, 512)), (np.float32, (2048, 128))])
+def test_tile_variants_bit_identical(dt, shape):
+    # every tiling the tuner may pick computes the same bits: default tiles vs the narrowest
+    p = _problem(shape, 71, dt)
+    try:
+        F.ffcz_set_tuning(0)
+        y0, r0 = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter, record_viol=True)
+        F.ffcz_set_tuning(2)
+        y1, r1 = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter, record_viol=True)
+    finally:
+        F.ffcz_set_tuning(1)
+    assert r0.status == F.OK and r1.status == F.OK
+    assert np.array_equal(y0.view(np.uint8), y1.view(np.uint8))
+    assert r0.stats == r1.stats
+    assert np.array_equal(r0.viol.cpu().numpy(), r1.viol.cpu().numpy())
+
+
+@pytest.mark.parametrize("dt,shape", [(np.float32, (32, 64, 256)), (np.float64, (16, 32, 512)),
+                                      (np.float32, (128, 1024)), (np.float64, (64, 128))])
+def test_radix8_last_axis_plan_matches_oracle(dt, shape):
+    # the radix-8 last-axis plan rounds differently from radix 16 but meets the same bars
+    p = _problem(shape, 77, dt)
+    try:
+        F.ffcz_set_tuning(3)
+        y, res = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter, record_viol=True)
+    finally:
+        F.ffcz_set_tuning(1)
+    orc = O.correct(p.x, p.xb, p.E, p.Delta, p.max_iter, mu=res.stats["margin_used"])
+    (_check_fp64 if dt == np.float64 else _check_fp32)(p, y, res, orc)
+    if dt == np.float64:
+        assert list(res.viol.cpu().numpy()[: orc.rounds + 1]) == orc.viol
+
+
+def test_tuning_cache_file_roundtrip(tmp_path):
+    import json
+    path = tmp_path / "plans.json"
+    p = _problem((64, 64, 128), 73, np.float32)
+    try:
+        F.ffcz_clear_tuning()
+        assert F.ffcz_set_tuning(1, str(path)) == F.OK
+        y0, r0 = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter)
+        doc = json.loads(path.read_text())
+        keys = list(doc["entries"])
+        nvar = {"y": 2, "x": 2, "z": 3}
+        assert len(keys) == 3 and all(len(doc["entries"][k]["ms"]) == nvar[k.split()[2]] for k in keys), doc
+        assert {k.split()[2] for k in keys} == {"y", "x", "z"}
+        # a fresh table read back from the file takes the same decisions without timing
+        F.ffcz_clear_tuning()
+        assert F.ffcz_set_tuning(1, str(path)) == F.OK
+        y1, r1 = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter)
+        assert np.array_equal(y0.view(np.uint8), y1.view(np.uint8))
+        assert F.ffcz_set_tuning(4) == F.E_INVALID
+    finally:
+        F.ffcz_set_tuning(1, "")
+        F.ffcz_clear_tuning()
