@@ -35,11 +35,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Sources that define the x-pass kernel; the committed counter summary applies only while they
-# are unchanged.
-XPASS_SOURCES = ("paper_2601_01596_amd/csrc/kernels_col.hpp", "paper_2601_01596_amd/csrc/fft_engine.hpp",
-                 "paper_2601_01596_amd/csrc/common.hpp", "paper_2601_01596_amd/csrc/launch_col_f32.hip")
-TRAFFIC_FILE = "profiles/xpass_lognormal512_fp32_traffic.md"
+# Sources that define the loop-pass kernels; the committed counter summary applies only while
+# they are unchanged.
+PASS_SOURCES = ("paper_2601_01596_amd/csrc/kernels_col.hpp", "paper_2601_01596_amd/csrc/kernels_row.hpp",
+                "paper_2601_01596_amd/csrc/fft_engine.hpp", "paper_2601_01596_amd/csrc/common.hpp",
+                "paper_2601_01596_amd/csrc/launch_col_f32.hip", "paper_2601_01596_amd/csrc/launch_row_f32.hip")
+TRAFFIC_FILE = "profiles/loop_passes_lognormal512_fp32_traffic.md"
+
+
+def tuned_variant(tuning, kind):
+    """The plan variant the library kept for a 512^3 FP32 loop pass (0 if it was not tuned)."""
+    tag = {"y_fwd": " y ", "y_inv": " y ", "x_pass": " x ", "z_pass": " z "}[kind]
+    for key, v in tuning.items():
+        if tag in key and " f32 " in key:
+            return int(v.get("choice", 0))
+    return 0
 
 
 def sources_digest(paths):
@@ -51,10 +61,10 @@ def sources_digest(paths):
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of the x-pass from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary (copy-calibrated), or None if that summary is missing, for another kernel, or older
-    than the kernel sources."""
+def measured_traffic(kind, variant):
+    """HBM bytes per launch of a loop pass from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (copy-calibrated), or None if that summary is missing, was taken for another plan
+    variant, or is older than the kernel sources."""
     try:
         with open(os.path.join(ROOT, TRAFFIC_FILE)) as fh:
             lines = fh.read().splitlines()
@@ -65,10 +75,10 @@ def measured_traffic(kernel):
         if ":" in ln and not ln.startswith(("#", "|", " ")):
             k, v = ln.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel") != kernel or kv.get("kernel_sources_sha256") != sources_digest(XPASS_SOURCES):
+    if kv.get("kernel_sources_sha256") != sources_digest(PASS_SOURCES) or kv.get(f"variant.{kind}") != str(variant):
         return None
     try:
-        return int(kv["traffic_bytes_per_launch"])
+        return int(kv[f"traffic_bytes_per_launch.{kind}"])
     except (KeyError, ValueError):
         return None
 
@@ -369,7 +379,7 @@ def main():
                                f"clamp + verification", "shape": [n, n, n], "max_iter": 500},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("x_pass") if dom == "x_pass" else None, "kernel": dom,
+                     "traffic": measured_traffic(dom, tuned_variant(tuning, dom)), "kernel": dom,
                      "bytes_per_launch": bpl, "avg_ms": ms_avg},
         "cpu_baseline": cpu,
         "extra": extra,

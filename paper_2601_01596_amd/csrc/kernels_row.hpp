@@ -120,7 +120,30 @@ row_kernel(RowArgs<T, TIO> a) {
   // ------------------------------------------------------------------ load
   // Unrolled in batches of BL so each lane keeps BL global loads in flight.
   constexpr int BL = 8;
-  if constexpr (spec_in) {
+  // FP32 spectra move two entries per 16-byte access: pair m of a row holds entries 2m, 2m+1
+  // (the last pair of a row reaches into its padding, which is read but never written)
+  constexpr bool pairs = sizeof(cx<T>) == 8 && H >= 2;
+  constexpr int NPR = (NC + 1) / 2;  // pairs per row
+  if constexpr (spec_in && pairs) {
+    constexpr int NLP = (ROWS * NPR + NT - 1) / NT;  // every load of the lane in flight at once
+    float4 tmp[NLP];
+#pragma unroll
+    for (int u = 0; u < NLP; ++u) {
+      const int f = t + u * NT;
+      const int r = f / NPR, m = f - r * NPR;
+      tmp[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (f < ROWS * NPR && r < nrow) tmp[u] = *reinterpret_cast<const float4*>(a.src + rowaddr(row0 + r) + 2 * m);
+    }
+#pragma unroll
+    for (int u = 0; u < NLP; ++u) {
+      const int f = t + u * NT;
+      if (f < ROWS * NPR) {
+        const int r = f / NPR, m = f - r * NPR;
+        lds[r * LP + 2 * m] = cx<T>{(T)tmp[u].x, (T)tmp[u].y};
+        if (2 * m + 1 < NC) lds[r * LP + 2 * m + 1] = cx<T>{(T)tmp[u].z, (T)tmp[u].w};
+      }
+    }
+  } else if constexpr (spec_in) {
     constexpr int NL = (ROWS * NC + NT - 1) / NT;
 #pragma unroll
     for (int b0 = 0; b0 < NL; b0 += BL) {
@@ -256,28 +279,44 @@ row_kernel(RowArgs<T, TIO> a) {
   __syncthreads();
 
   // ------------------------------------------------------------------ store
-  if constexpr (spec_out) {
+  // entry k of the row's R2C output from the packed transform in LDS
+  auto unpack = [&](const cx<T>* zr, int k) -> cx<T> {
+    if (k == H) {
+      const cx<T> z0 = zr[0];
+      return cx<T>{z0.re - z0.im, T(0)};
+    }
+    const cx<T> Zk = zr[k];
+    const cx<T> Zm = zr[(H - k) & (H - 1)];
+    const cx<T> ev = scal(Zk + conjg(Zm), T(0.5));
+    const cx<T> d = Zk - conjg(Zm);
+    const cx<T> od = cx<T>{d.im * T(0.5), -d.re * T(0.5)};  // d / (2i)
+    return ev + cmul(rtw[k], od);
+  };
+  if constexpr (spec_out && pairs) {
+    constexpr int NSP = (ROWS * NPR + NT - 1) / NT;
+#pragma unroll
+    for (int it = 0; it < NSP; ++it) {
+      const int f = t + it * NT;
+      const int r = f / NPR, m = f - r * NPR;
+      if (f < ROWS * NPR && r < nrow) {
+        const cx<T>* zr = lds + r * LP;
+        const cx<T> X0 = unpack(zr, 2 * m);
+        cx<T>* out = a.dst + rowaddr(row0 + r) + 2 * m;
+        if (2 * m + 1 < NC) {
+          const cx<T> X1 = unpack(zr, 2 * m + 1);
+          *reinterpret_cast<float4*>(out) = make_float4((float)X0.re, (float)X0.im, (float)X1.re, (float)X1.im);
+        } else {
+          *out = X0;
+        }
+      }
+    }
+  } else if constexpr (spec_out) {
     constexpr int NS = (ROWS * NC + NT - 1) / NT;
 #pragma unroll
     for (int it = 0; it < NS; ++it) {
       const int f = t + it * NT;
       const int r = f / NC, k = f - r * NC;
-      if (f < ROWS * NC && r < nrow) {
-        const cx<T>* zr = lds + r * LP;
-        cx<T> X;
-        if (k == H) {
-          const cx<T> z0 = zr[0];
-          X = cx<T>{z0.re - z0.im, T(0)};
-        } else {
-          const cx<T> Zk = zr[k];
-          const cx<T> Zm = zr[(H - k) & (H - 1)];
-          const cx<T> ev = scal(Zk + conjg(Zm), T(0.5));
-          const cx<T> d = Zk - conjg(Zm);
-          const cx<T> od = cx<T>{d.im * T(0.5), -d.re * T(0.5)};  // d / (2i)
-          X = ev + cmul(rtw[k], od);
-        }
-        a.dst[rowaddr(row0 + r) + k] = X;
-      }
+      if (f < ROWS * NC && r < nrow) a.dst[rowaddr(row0 + r) + k] = unpack(lds + r * LP, k);
     }
   } else {
     // ROW_FINAL: y = x + eps formed in FP64, rounded once, clamped;  ROW_BFINAL: store g
