@@ -40,7 +40,7 @@ hipError_t launch_col_f32(int mode, int L, int v, const void* args, int64_t nb, 
 hipError_t launch_col_f64(int mode, int L, int v, const void* args, int64_t nb, hipStream_t s);
 hipError_t launch_row_f32(int mode, int H, int v, const void* args, int64_t nb, hipStream_t s);
 hipError_t launch_row_f64(int mode, int H, int v, const void* args, int64_t nb, hipStream_t s);
-hipError_t launch_row_verify_f32io(int H, const void* args, int64_t nb, hipStream_t s);
+hipError_t launch_row_verify_f32io(int H, int v, const void* args, int64_t nb, hipStream_t s);
 hipError_t launch_sig_f32(int mode, int lgMc, const void* args, int nb, hipStream_t s);
 hipError_t launch_sig_f64(int mode, int lgMc, const void* args, int nb, hipStream_t s);
 hipError_t launch_sigt_f64(int mode, int iodt, int lgMc, const void* args, int nb, hipStream_t s);
@@ -190,7 +190,7 @@ struct Plan {
   // tile variants of the loop passes (y-forward/inverse, x-pass, last-axis init/loop/final)
   int vy = 0, vx = 0, vz = 0;
   // blocks of each pass per instance (one partial slot per block)
-  int64_t zbpi = 0, vzbpi = 0, xbpi = 0, vxbpi = 0;
+  int64_t zbpi = 0, ibpi = 0, vzbpi = 0, xbpi = 0, vxbpi = 0;  // ibpi: the init pass (default tiles)
   int64_t pmax = 0;
   size_t off_state = 0, off_viol = 0, off_init = 0, off_part = 0, off_twT = 0, off_tw64 = 0, off_Z = 0,
          off_A = 0, off_W = 0, bytes = 0;
@@ -223,6 +223,10 @@ int ceil_lg(int64_t v) {
   return r;
 }
 
+// The FP64 last-axis verification pass runs the radix-8 plan: half the registers
+// per lane of radix 16, so twice the lanes of an FP64 row tile stay resident.
+constexpr int kVerifyRowPlan = 2;
+
 // Choose the loop passes' tile variants and the per-instance block counts that follow.
 void set_variants(Plan& p, int vy, int vx, int vz) {
   p.vy = vy;
@@ -230,8 +234,10 @@ void set_variants(Plan& p, int vy, int vx, int vz) {
   p.vz = vz;
   const int64_t outer_x = p.nd == 3 ? p.n[1] : 1;
   const int Cx = col_block_cols(p.dt, p.Lx, vx), Cx64 = col_block_cols(1, p.Lx, 0);
-  const int Rz = row_block_rows(p.dt, p.H, vz), Rz64 = row_block_rows(1, p.H, 0);
+  const int Rz = row_block_rows(p.dt, p.H, vz), Rz64 = row_block_rows(1, p.H, kVerifyRowPlan);
   p.zbpi = (p.nrows + Rz - 1) / Rz;
+  const int Ri = row_block_rows(p.dt, p.H, 0);
+  p.ibpi = (p.nrows + Ri - 1) / Ri;
   p.vzbpi = (p.nrows + Rz64 - 1) / Rz64;
   p.xbpi = outer_x * ((p.ncols + Cx - 1) / Cx);
   p.vxbpi = outer_x * ((p.ncols + Cx64 - 1) / Cx64);
@@ -458,7 +464,8 @@ __global__ void __launch_bounds__(256) ulp_batch_kernel(const MarginJob* jobs, d
 // non-finite input).
 __global__ void __launch_bounds__(1024) ctl_kernel(DevState* st0, unsigned long long* viol0, int64_t vstride,
                                                    const unsigned long long* xpart, int64_t xbpi,
-                                                   const unsigned long long* zpart, int64_t zbpi) {
+                                                   const unsigned long long* zpart, int64_t zbpi,
+                                                   int64_t ibpi) {
   __shared__ unsigned long long rx[16], rz[16];
   const int64_t b = blockIdx.x;
   DevState* st = st0 + b;
@@ -466,7 +473,9 @@ __global__ void __launch_bounds__(1024) ctl_kernel(DevState* st0, unsigned long 
   const int t = threadIdx.x;
   unsigned long long sx = 0, sz = 0;
   for (int64_t i = t; i < xbpi; i += blockDim.x) sx += xpart[b * xbpi + i];
-  for (int64_t i = t; i < zbpi; i += blockDim.x) sz += zpart[b * zbpi + i];
+  // the checked iterate came from the init pass (round 0) or from a z-pass, whose tiles may differ
+  const int64_t nz = st->round == 0 ? ibpi : zbpi;
+  for (int64_t i = t; i < nz; i += blockDim.x) sz += zpart[b * nz + i];
   sx = wave_sum_u64(sx);
   sz = wave_sum_u64(sz);
   if ((t & 63) == 0) {
@@ -558,7 +567,7 @@ struct Ctx {
 
 hipError_t launch_ctl(const Ctx& c, unsigned long long* viol, int64_t vstride) {
   hipLaunchKernelGGL(ctl_kernel, dim3((unsigned)c.p->B), dim3(1024), 0, c.s, c.st(), viol, vstride, c.part(Ctx::PX),
-                     c.p->xbpi, c.part(Ctx::PZ), c.p->zbpi);
+                     c.p->xbpi, c.part(Ctx::PZ), c.p->zbpi, c.p->ibpi);
   return hipGetLastError();
 }
 
@@ -650,14 +659,14 @@ hipError_t run_row(int tdt, int iodt, int mode, int v, const Plan& p, int64_t pi
   const int64_t nb = a.bpi * p.B;
   a.plane = plane;
   a.lg_rpp = p.lg_rpp;
-  if (mode == ROW_VERIFY && tdt == 1 && iodt == 0) return launch_row_verify_f32io(p.H, &a, nb, s);
+  if (mode == ROW_VERIFY && tdt == 1 && iodt == 0) return launch_row_verify_f32io(p.H, v, &a, nb, s);
   return tdt == 0 ? launch_row_f32(mode, p.H, v, &a, nb, s) : launch_row_f64(mode, p.H, v, &a, nb, s);
 }
 
 template <typename T>
 hipError_t row_T(int mode, const Ctx& c, const void* src, void* dst, uint32_t* smask) {
   const Plan& p = *c.p;
-  const int v = (mode == ROW_INIT || mode == ROW_LOOP) ? p.vz : 0;
+  const int v = mode == ROW_LOOP ? p.vz : 0;
   const void* tw = (const char*)c.twT() + sizeof(cx<T>) * (v == 2 ? p.twz8 : p.twz);
   return run_row<T, T>(p.dt, p.dt, mode, v, p, p.pitch, p.plane, src, dst, tw, c.st(), c.part(Ctx::PZ), smask, c.s);
 }
@@ -705,7 +714,8 @@ hipError_t enqueue_verify(const Ctx& c) {
   const char* tb = (const char*)c.tw64();
   void* W = c.W();
   hipError_t e = timed(PK_VZ, -1, c.s, [&] {
-    return run_row<double, T>(1, p.dt, ROW_VERIFY, 0, p, p.pitch64, p.plane64, nullptr, W, tb + 16 * p.twz, c.st(),
+    return run_row<double, T>(1, p.dt, ROW_VERIFY, kVerifyRowPlan, p, p.pitch64, p.plane64, nullptr, W,
+                              tb + 16 * (kVerifyRowPlan == 2 ? p.twz8 : p.twz), c.st(),
                               c.part(Ctx::PVZ), nullptr, c.s);
   });
   if (e != hipSuccess) return e;
@@ -1037,6 +1047,24 @@ int32_t tune_plan(Plan& p, char* ws, hipStream_t s, bool rec) {
   }
   set_variants(p, vy, vx, vz);
   return FFCZ_OK;
+}
+
+// Tune a group's passes ahead of a mixed batch, before the 1D members start on
+// the side stream (their work would disturb the timings): a neutral state (loop
+// not done, no masks) and the twiddles are written, then tune_plan runs on the
+// group's own workspace.  The decisions land in the process-wide table.
+template <typename T>
+int32_t pretune_group(const Plan& p0, char* ws, hipStream_t s) {
+  Plan p = p0;
+  Ctx c{&p, ws, s};
+  StateInit one;
+  memset(&one, 0, sizeof(one));
+  one.max_iter = 1;
+  hipLaunchKernelGGL(state_init_kernel, dim3((unsigned)std::max<int64_t>(1, (p.B + 255) / 256)), dim3(256), 0, s,
+                     c.st(), p.B, (const StateInit*)nullptr, one, (unsigned long long*)nullptr, (int64_t)0);
+  HIPCHK(hipGetLastError());
+  HIPCHK(write_twiddles(c));
+  return tune_plan<T>(p, ws, s, false);
 }
 
 // One correction over the B instances of a plan.  inst[b] supplies pointers and bounds.
@@ -2041,6 +2069,11 @@ int32_t ffcz_correct_batched(int32_t dtype, int32_t count, const ffcz_instance* 
   hipStream_t s1 = s;
   SigWorker worker;
   if (!bp.sig_ids.empty() && !bp.groups.empty()) {
+    for (size_t g = 0; g < bp.groups.size(); ++g) {
+      r = dtype == FFCZ_F32 ? pretune_group<float>(bp.gplans[g], w + bp.goff[g], s)
+                            : pretune_group<double>(bp.gplans[g], w + bp.goff[g], s);
+      if (r != FFCZ_OK) return r;
+    }
     HIPCHK(g_streams.ready());
     s1 = g_streams.side;
     HIPCHK(hipEventRecord(g_streams.fork, s));
@@ -2099,6 +2132,7 @@ int32_t ffcz_correct_backward(int32_t dtype, int32_t ndim, const int64_t* shape,
   int32_t r = make_plan(dtype, ndim, shape, rounds, 1, p);
   if (r != FFCZ_OK) return r;
   if (!masks || !gy || !gb) return fail(FFCZ_E_INVALID, "null pointer");
+  if (((uintptr_t)gy & 15) || ((uintptr_t)gb & 15)) return fail(FFCZ_E_WORKSPACE, "gradients must be 16-byte aligned");
   if (!ws || ws_bytes < p.bytes) return fail(FFCZ_E_WORKSPACE, "workspace smaller than ffcz_workspace_bytes()");
   if ((uintptr_t)ws & 255) return fail(FFCZ_E_WORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;

@@ -122,6 +122,44 @@ __host__ __device__ constexpr int pick_rows(int H) {
   return r;
 }
 
+// LDS rows of the last-axis passes.  Lanes run rows-fastest (ROWS rows x 64/ROWS
+// indices per wave) and rows sit an odd pitch H + 1 apart, which keeps a wave's
+// accesses on distinct banks while a wave spans many rows.  With few rows per
+// block (long rows) the indices of one row collide instead, so for those shapes
+// entry i of a row moves to i + (i >> 5) (one skip per 32 entries) and the pitch
+// takes a pad chosen by a model of the kernel's LDS access patterns (the
+// compute-mapping reads and writes, the Stockham exchanges, the R2C unpack, the
+// row-major loads and stores): the worst slot load drops from 8-32 lanes to 3
+// (8-byte entries) or 5-6 (16-byte).  Shapes whose odd pitch stays below four
+// times the unavoidable 2 (4) lanes per slot keep it: there the skew's index
+// arithmetic costs more than it saves (measured on the 256-entry rows).
+__host__ __device__ constexpr int row_lds_pad(int H, int R, int E, int S) {
+  if (H == 512 && R == 4 && E == 16 && S == 16) return 6;
+  if (H == 512 && R == 8 && E == 16 && S == 8) return 8;
+  if (H == 1024 && R == 2 && E == 16 && S == 16) return 0;
+  if (H == 1024 && R == 4 && E == 8 && S == 16) return 2;
+  if (H == 1024 && R == 4 && E == 16 && S == 8) return 5;
+  if (H == 1024 && R == 4 && E == 16 && S == 16) return 4;
+  if (H == 1024 && R == 8 && E == 8 && S == 8) return 2;
+  if (H == 1024 && R == 8 && E == 16 && S == 8) return 2;
+  if (H == 2048 && R == 1 && E == 16 && S == 16) return 0;
+  if (H == 2048 && R == 2 && E == 8 && S == 16) return 7;
+  if (H == 2048 && R == 2 && E == 16 && S == 8) return 15;
+  if (H == 2048 && R == 2 && E == 16 && S == 16) return 0;
+  if (H == 2048 && R == 4 && E == 8 && S == 8) return 5;
+  if (H == 2048 && R == 4 && E == 16 && S == 8) return 5;
+  return -1;  // no skew: odd pitch
+}
+__host__ __device__ constexpr int row_lds_shift(int H, int R, int E, int S) {
+  return row_lds_pad(H, R, E, S) >= 0 ? 5 : 0;
+}
+template <typename T>
+__host__ __device__ constexpr int row_lds_pitch(int H, int R, int E) {
+  return row_lds_pad(H, R, E, (int)sizeof(cx<T>)) >= 0
+             ? H + (H >> 5) + 1 + row_lds_pad(H, R, E, (int)sizeof(cx<T>))
+             : H + 1;
+}
+
 // Plans the tuner chooses between.  Column passes: variant 1 halves the tile
 // width.  Last-axis passes: variant 1 halves the rows per block; variant 2
 // uses radix-8 stages (8 elements per lane, twice the lanes per row) where the

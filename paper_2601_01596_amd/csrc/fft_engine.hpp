@@ -188,8 +188,15 @@ __host__ __device__ inline int host_twsize(int L, int E) {
   return s;
 }
 
-// Element (b, i) of the LDS batch lives at lds[i*SI + b*SB].
-template <typename T, int L, int E, bool INV, int SI, int SB, int s>
+// Element (b, i) of the LDS batch lives at lds[sk(i)*SI + b*SB], with sk(i) = i
+// (SK = 0) or i + (i >> SK) (a skip every 2^SK entries, against bank conflicts).
+template <int SK>
+__device__ __forceinline__ int lds_skew(int i) {
+  if constexpr (SK > 0) return i + (i >> SK);
+  else return i;
+}
+
+template <typename T, int L, int E, bool INV, int SI, int SB, int s, int SK = 0>
 __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], cx<T>* lds, const cx<T>* tw, int b, int j) {
   using S = Sched<L, E>;
   if constexpr (s < S::nst) {
@@ -222,22 +229,32 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], cx<T>* lds, const cx<T
       for (int i = 0; i < NB; ++i) {
         const int jb = j + i * P;
         const int base = (jb / Ns) * (Ns * R) + (jb & (Ns - 1));
+        if constexpr (SK > 0 && (Ns * R) % (1 << SK) == 0) {
+          // with Ns R a multiple of 2^SK, sk(base + r Ns) = sk-part of base + sk(r Ns):
+          // one lane base, compile-time offsets
+          const int lb = base + (jb / Ns) * ((Ns * R) >> SK) + ((jb & (Ns - 1)) >> SK);
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[(base + r * Ns) * SI + b * SB] = u[i][r];
+          for (int r = 0; r < R; ++r) lds[(lb + lds_skew<SK>(r * Ns)) * SI + b * SB] = u[i][r];
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) lds[lds_skew<SK>(base + r * Ns) * SI + b * SB] = u[i][r];
+        }
       }
       __syncthreads();
+      // j < P and P a power of two: sk(j + qP) = sk(j) + sk(qP), a lane base plus constants
+      const int sj = lds_skew<SK>(j);
 #pragma unroll
-      for (int q = 0; q < E; ++q) v[q] = lds[(j + q * P) * SI + b * SB];
-      fft_stages<T, L, E, INV, SI, SB, s + 1>(v, lds, tw, b, j);
+      for (int q = 0; q < E; ++q) v[q] = lds[(sj + lds_skew<SK>(q * P)) * SI + b * SB];
+      fft_stages<T, L, E, INV, SI, SB, s + 1, SK>(v, lds, tw, b, j);
     }
   }
 }
 
 // Length-L transform of the lane's registers.  Contains __syncthreads() when
 // the schedule has more than one stage: every lane of the block must call it.
-template <typename T, int L, int E, bool INV, int SI, int SB>
+template <typename T, int L, int E, bool INV, int SI, int SB, int SK = 0>
 __device__ __forceinline__ void fft(cx<T> (&v)[E], cx<T>* lds, const cx<T>* tw, int b, int j) {
-  fft_stages<T, L, E, INV, SI, SB, 0>(v, lds, tw, b, j);
+  fft_stages<T, L, E, INV, SI, SB, 0, SK>(v, lds, tw, b, j);
 }
 
 // ---------------------------------------------------------------------------

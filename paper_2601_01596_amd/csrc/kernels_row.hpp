@@ -49,12 +49,16 @@ __device__ __forceinline__ TIO closing_clamp(TIO y, TIO x, double E) {
   return (fabs((double)y - (double)x) <= E) ? y : x;
 }
 
+// Long radix-16 rows need more than the 128 registers of four waves per SIMD.
+__host__ __device__ constexpr int row_min_waves(int H, int E) { return (H >= 512 && E == 16) ? 3 : 4; }
+
 template <typename T, typename TIO, int H, int ROWS, int MODE, int E>
-__global__ void __launch_bounds__(ROWS*(H / E), 4)
+__global__ void __launch_bounds__(ROWS*(H / E), row_min_waves(H, E))
 row_kernel(RowArgs<T, TIO> a) {
   constexpr int P = H / E;
   constexpr int NT = ROWS * P;
-  constexpr int LP = H + 1;            // LDS row pitch (odd for H >= 2)
+  constexpr int LP = row_lds_pitch<T>(H, ROWS, E);               // LDS row pitch (entries)
+  constexpr int SKW = row_lds_shift(H, ROWS, E, (int)sizeof(cx<T>));  // 0, or entry i at i + (i >> SKW)
   constexpr int NC = H + 1;            // spectrum entries per row
   using S = Sched<H, E>;
   constexpr int TW = S::twsize;
@@ -90,6 +94,7 @@ row_kernel(RowArgs<T, TIO> a) {
   const int j = t / ROWS;
   const int nrow = (int)((a.rows_per_inst - lrow0) < ROWS ? (a.rows_per_inst - lrow0) : ROWS);
   cx<T>* lrow = lds + rl * LP;
+  const int sj = lds_skew<SKW>(j);  // j < P, P a power of two: lds_skew<SKW>(j + qP) = sj + lds_skew<SKW>(qP)
   const cx<T>* rtw = tws + TW;
 
   for (int i = t; i < TW + H; i += NT) tws[i] = a.tw[i];
@@ -124,23 +129,31 @@ row_kernel(RowArgs<T, TIO> a) {
   // (the last pair of a row reaches into its padding, which is read but never written)
   constexpr bool pairs = sizeof(cx<T>) == 8 && H >= 2;
   constexpr int NPR = (NC + 1) / 2;  // pairs per row
+  // FP32 real fields move four reals (two packed entries) per 16-byte access
+  constexpr bool io4 = sizeof(TIO) == 4 && H >= 2;
+  constexpr int HQ = H / 2;  // 16-byte groups per real row
   if constexpr (spec_in && pairs) {
-    constexpr int NLP = (ROWS * NPR + NT - 1) / NT;  // every load of the lane in flight at once
-    float4 tmp[NLP];
+    constexpr int NLP = (ROWS * NPR + NT - 1) / NT;
+    constexpr int BLP = NLP < 8 ? NLP : 8;  // loads per lane in flight
 #pragma unroll
-    for (int u = 0; u < NLP; ++u) {
-      const int f = t + u * NT;
-      const int r = f / NPR, m = f - r * NPR;
-      tmp[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (f < ROWS * NPR && r < nrow) tmp[u] = *reinterpret_cast<const float4*>(a.src + rowaddr(row0 + r) + 2 * m);
-    }
+    for (int u0 = 0; u0 < NLP; u0 += BLP) {
+      float4 tmp[BLP];
 #pragma unroll
-    for (int u = 0; u < NLP; ++u) {
-      const int f = t + u * NT;
-      if (f < ROWS * NPR) {
+      for (int u = 0; u < BLP; ++u) {
+        const int f = t + (u0 + u) * NT;
         const int r = f / NPR, m = f - r * NPR;
-        lds[r * LP + 2 * m] = cx<T>{(T)tmp[u].x, (T)tmp[u].y};
-        if (2 * m + 1 < NC) lds[r * LP + 2 * m + 1] = cx<T>{(T)tmp[u].z, (T)tmp[u].w};
+        tmp[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (u0 + u < NLP && f < ROWS * NPR && r < nrow)
+          tmp[u] = *reinterpret_cast<const float4*>(a.src + rowaddr(row0 + r) + 2 * m);
+      }
+#pragma unroll
+      for (int u = 0; u < BLP; ++u) {
+        const int f = t + (u0 + u) * NT;
+        if (u0 + u < NLP && f < ROWS * NPR) {
+          const int r = f / NPR, m = f - r * NPR;
+          lds[r * LP + lds_skew<SKW>(2 * m)] = cx<T>{(T)tmp[u].x, (T)tmp[u].y};
+          if (2 * m + 1 < NC) lds[r * LP + lds_skew<SKW>(2 * m + 1)] = cx<T>{(T)tmp[u].z, (T)tmp[u].w};
+        }
       }
     }
   } else if constexpr (spec_in) {
@@ -159,62 +172,100 @@ row_kernel(RowArgs<T, TIO> a) {
         const int f = t + (b0 + u) * NT;
         if (b0 + u < NL && f < ROWS * NC) {
           const int r = f / NC, k = f - r * NC;
-          lds[r * LP + k] = tmp[u];
+          lds[r * LP + lds_skew<SKW>(k)] = tmp[u];
         }
       }
     }
   } else {
     // real rows -> packed pairs; INIT also forms eps0 = x_hat - x in FP64 and clips it
     const double Ep = st->Ep;
-    constexpr int NL = (ROWS * H + NT - 1) / NT;
-#pragma unroll
-    for (int b0 = 0; b0 < NL; b0 += BL) {
-      V2 xa[BL], xbv[BL];
-#pragma unroll
-      for (int u = 0; u < BL; ++u) {
-        const int f = t + (b0 + u) * NT;
-        const int r = f / H, m = f - r * H;
-        const bool ok = b0 + u < NL && f < ROWS * H && r < nrow;
-        const int64_t gi = (lrow0 + r) * H + m;
-        if constexpr (MODE != ROW_BINIT) {
-          if (ok) xa[u] = x2[gi];
-        }
-        if (ok) xbv[u] = b2[gi];
-      }
-#pragma unroll
-      for (int u = 0; u < BL; ++u) {
-        const int f = t + (b0 + u) * NT;
-        if (!(b0 + u < NL && f < ROWS * H)) continue;
-        const int r = f / H, m = f - r * H;
-        double e0 = 0.0, e1 = 0.0;
-        if (r < nrow) {
-          if constexpr (MODE == ROW_BINIT) {
-            const uint32_t w = sbits[r * SW + (2 * m) / 32];
-            const int sh = (2 * m) & 31;
-            e0 = ((w >> sh) & 1u) ? (double)xbv[u].x : 0.0;
-            e1 = ((w >> (sh + 1)) & 1u) ? (double)xbv[u].y : 0.0;
-          } else {
-            e0 = (double)xbv[u].x - (double)xa[u].x;
-            e1 = (double)xbv[u].y - (double)xa[u].y;
-            if constexpr (MODE == ROW_INIT) {
-              const bool f0 = isfinite(e0), f1 = isfinite(e1);
-              if (!f0 || !f1) {
-                atomicAdd(&st->nonfinite, (unsigned long long)((!f0) + (!f1)));
-                e0 = f0 ? e0 : 0.0;
-                e1 = f1 ? e1 : 0.0;
-              }
-              const bool k0 = fabs(e0) <= Ep, k1 = fabs(e1) <= Ep;
-              cnt += (!k0) + (!k1);
-              e0 = clipv(e0, Ep);
-              e1 = clipv(e1, Ep);
-              if (rec)
-                atomicOr(&sbits[r * SW + (2 * m) / 32], ((uint32_t)k0 | ((uint32_t)k1 << 1)) << ((2 * m) & 31));
-            } else {
-              mx = fmax(mx, fmax(fabs(e0), fabs(e1)));
+    // packed entry m of row r from (x, second field) reals 2m, 2m+1
+    auto pack = [&](int r, int m, double xa0, double xa1, double b0, double b1) -> cx<T> {
+      double e0 = 0.0, e1 = 0.0;
+      if (r < nrow) {
+        if constexpr (MODE == ROW_BINIT) {
+          const uint32_t w = sbits[r * SW + (2 * m) / 32];
+          const int sh = (2 * m) & 31;
+          e0 = ((w >> sh) & 1u) ? b0 : 0.0;
+          e1 = ((w >> (sh + 1)) & 1u) ? b1 : 0.0;
+        } else {
+          e0 = b0 - xa0;
+          e1 = b1 - xa1;
+          if constexpr (MODE == ROW_INIT) {
+            const bool f0 = isfinite(e0), f1 = isfinite(e1);
+            if (!f0 || !f1) {
+              atomicAdd(&st->nonfinite, (unsigned long long)((!f0) + (!f1)));
+              e0 = f0 ? e0 : 0.0;
+              e1 = f1 ? e1 : 0.0;
             }
+            const bool k0 = fabs(e0) <= Ep, k1 = fabs(e1) <= Ep;
+            cnt += (!k0) + (!k1);
+            e0 = clipv(e0, Ep);
+            e1 = clipv(e1, Ep);
+            if (rec)
+              atomicOr(&sbits[r * SW + (2 * m) / 32], ((uint32_t)k0 | ((uint32_t)k1 << 1)) << ((2 * m) & 31));
+          } else {
+            mx = fmax(mx, fmax(fabs(e0), fabs(e1)));
           }
         }
-        lds[r * LP + m] = cx<T>{(T)e0, (T)e1};  // rounded once to the working type
+      }
+      return cx<T>{(T)e0, (T)e1};  // rounded once to the working type
+    };
+    if constexpr (io4) {
+      // FP32 fields: four reals (two packed entries) per 16-byte load, BQ loads of each field per
+      // lane in flight (more spills: the FP64 difference, clip and mask work needs the registers)
+      constexpr int NLQ = (ROWS * HQ + NT - 1) / NT;
+      constexpr int BQ = NLQ < 4 ? NLQ : 4;
+      const float4* x4 = reinterpret_cast<const float4*>(st->px);
+      const float4* b4 = reinterpret_cast<const float4*>(MODE == ROW_VERIFY ? (const void*)st->py : st->pxb);
+#pragma unroll
+      for (int q0 = 0; q0 < NLQ; q0 += BQ) {
+        float4 xa[BQ], xbv[BQ];
+#pragma unroll
+        for (int u = 0; u < BQ; ++u) {
+          const int f = t + (q0 + u) * NT;
+          const int r = f / HQ, q = f - r * HQ;
+          const bool ok = q0 + u < NLQ && f < ROWS * HQ && r < nrow;
+          const int64_t gi = (lrow0 + r) * HQ + q;
+          xa[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+          xbv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+          if constexpr (MODE != ROW_BINIT) {
+            if (ok) xa[u] = x4[gi];
+          }
+          if (ok) xbv[u] = b4[gi];
+        }
+#pragma unroll
+        for (int u = 0; u < BQ; ++u) {
+          const int f = t + (q0 + u) * NT;
+          if (!(q0 + u < NLQ && f < ROWS * HQ)) continue;
+          const int r = f / HQ, q = f - r * HQ;
+          lds[r * LP + lds_skew<SKW>(2 * q)] = pack(r, 2 * q, xa[u].x, xa[u].y, xbv[u].x, xbv[u].y);
+          lds[r * LP + lds_skew<SKW>(2 * q + 1)] = pack(r, 2 * q + 1, xa[u].z, xa[u].w, xbv[u].z, xbv[u].w);
+        }
+      }
+    } else {
+      constexpr int NL = (ROWS * H + NT - 1) / NT;
+#pragma unroll
+      for (int b0 = 0; b0 < NL; b0 += BL) {
+        V2 xa[BL], xbv[BL];
+#pragma unroll
+        for (int u = 0; u < BL; ++u) {
+          const int f = t + (b0 + u) * NT;
+          const int r = f / H, m = f - r * H;
+          const bool ok = b0 + u < NL && f < ROWS * H && r < nrow;
+          const int64_t gi = (lrow0 + r) * H + m;
+          if constexpr (MODE != ROW_BINIT) {
+            if (ok) xa[u] = x2[gi];
+          }
+          if (ok) xbv[u] = b2[gi];
+        }
+#pragma unroll
+        for (int u = 0; u < BL; ++u) {
+          const int f = t + (b0 + u) * NT;
+          if (!(b0 + u < NL && f < ROWS * H)) continue;
+          const int r = f / H, m = f - r * H;
+          lds[r * LP + lds_skew<SKW>(m)] = pack(r, m, (double)xa[u].x, (double)xa[u].y, (double)xbv[u].x, (double)xbv[u].y);
+        }
       }
     }
   }
@@ -226,8 +277,8 @@ row_kernel(RowArgs<T, TIO> a) {
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const int k = j + q * P;
-      cx<T> A = lrow[k];
-      cx<T> B = lrow[H - k];
+      cx<T> A = lrow[sj + lds_skew<SKW>(q * P)];
+      cx<T> B = lrow[lds_skew<SKW>(H - k)];
       if (k == 0) {
         A.im = T(0);
         B.im = T(0);
@@ -236,7 +287,7 @@ row_kernel(RowArgs<T, TIO> a) {
       const cx<T> df = cmulc(A - conjg(B), rtw[k]);  // W^-k (A - B*)
       v[q] = cx<T>{sm.re - df.im, sm.im + df.re};    // sm + i * df
     }
-    fft<T, H, E, true, 1, LP>(v, lds, tws, rl, j);
+    fft<T, H, E, true, 1, LP, SKW>(v, lds, tws, rl, j);
     const T sc = (T)st->inv_n;
     if constexpr (MODE == ROW_FINAL) {
       // the source holds only the last-axis R2C of eps, so the C2R scale is 1/n_last
@@ -270,12 +321,12 @@ row_kernel(RowArgs<T, TIO> a) {
     }
   } else {
 #pragma unroll
-    for (int q = 0; q < E; ++q) v[q] = lrow[j + q * P];
+    for (int q = 0; q < E; ++q) v[q] = lrow[sj + lds_skew<SKW>(q * P)];
   }
-  if constexpr (spec_out) fft<T, H, E, false, 1, LP>(v, lds, tws, rl, j);
+  if constexpr (spec_out) fft<T, H, E, false, 1, LP, SKW>(v, lds, tws, rl, j);
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < E; ++q) lrow[j + q * P] = v[q];
+  for (int q = 0; q < E; ++q) lrow[sj + lds_skew<SKW>(q * P)] = v[q];
   __syncthreads();
 
   // ------------------------------------------------------------------ store
@@ -285,8 +336,8 @@ row_kernel(RowArgs<T, TIO> a) {
       const cx<T> z0 = zr[0];
       return cx<T>{z0.re - z0.im, T(0)};
     }
-    const cx<T> Zk = zr[k];
-    const cx<T> Zm = zr[(H - k) & (H - 1)];
+    const cx<T> Zk = zr[lds_skew<SKW>(k)];
+    const cx<T> Zm = zr[lds_skew<SKW>((H - k) & (H - 1))];
     const cx<T> ev = scal(Zk + conjg(Zm), T(0.5));
     const cx<T> d = Zk - conjg(Zm);
     const cx<T> od = cx<T>{d.im * T(0.5), -d.re * T(0.5)};  // d / (2i)
@@ -322,7 +373,46 @@ row_kernel(RowArgs<T, TIO> a) {
     // ROW_FINAL: y = x + eps formed in FP64, rounded once, clamped;  ROW_BFINAL: store g
     V2* y2 = reinterpret_cast<V2*>(st->py);
     const double Eb = st->E;
+    auto out_of = [&](TIO xv, T e) -> TIO {
+      if constexpr (MODE == ROW_FINAL) return closing_clamp<TIO>(round_io<TIO>((double)xv + (double)e), xv, Eb);
+      else return (TIO)e;
+    };
     constexpr int NS = (ROWS * H + NT - 1) / NT;
+    if constexpr (io4) {
+      // FP32 fields: four reals per 16-byte access
+      constexpr int NSQ = (ROWS * HQ + NT - 1) / NT;
+      constexpr int BQ = NSQ < 8 ? NSQ : 8;
+      const float4* x4 = reinterpret_cast<const float4*>(st->px);
+      float4* y4 = reinterpret_cast<float4*>(st->py);
+#pragma unroll
+      for (int q0 = 0; q0 < NSQ; q0 += BQ) {
+        float4 xa[BQ];
+        if constexpr (MODE == ROW_FINAL) {
+#pragma unroll
+          for (int u = 0; u < BQ; ++u) {
+            const int f = t + (q0 + u) * NT;
+            const int r = f / HQ, q = f - r * HQ;
+            if (q0 + u < NSQ && f < ROWS * HQ && r < nrow) xa[u] = x4[(lrow0 + r) * HQ + q];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < BQ; ++u) {
+          const int f = t + (q0 + u) * NT;
+          const int r = f / HQ, q = f - r * HQ;
+          if (q0 + u < NSQ && f < ROWS * HQ && r < nrow) {
+            const cx<T> e0 = lds[r * LP + lds_skew<SKW>(2 * q)], e1 = lds[r * LP + lds_skew<SKW>(2 * q + 1)];
+            float4 o;
+            if constexpr (MODE == ROW_FINAL) {
+              o = make_float4(out_of(xa[u].x, e0.re), out_of(xa[u].y, e0.im), out_of(xa[u].z, e1.re),
+                              out_of(xa[u].w, e1.im));
+            } else {
+              o = make_float4((float)e0.re, (float)e0.im, (float)e1.re, (float)e1.im);
+            }
+            y4[(lrow0 + r) * HQ + q] = o;
+          }
+        }
+      }
+    } else {
 #pragma unroll
     for (int b0 = 0; b0 < NS; b0 += BL) {
       V2 xa[BL];
@@ -339,11 +429,11 @@ row_kernel(RowArgs<T, TIO> a) {
         const int f = t + (b0 + u) * NT;
         const int r = f / H, m = f - r * H;
         if (b0 + u < NS && f < ROWS * H && r < nrow) {
-          const cx<T> e = lds[r * LP + m];
+          const cx<T> e = lds[r * LP + lds_skew<SKW>(m)];
           V2 out;
           if constexpr (MODE == ROW_FINAL) {
-            out.x = closing_clamp<TIO>(round_io<TIO>((double)xa[u].x + (double)e.re), xa[u].x, Eb);
-            out.y = closing_clamp<TIO>(round_io<TIO>((double)xa[u].y + (double)e.im), xa[u].y, Eb);
+            out.x = out_of(xa[u].x, e.re);
+            out.y = out_of(xa[u].y, e.im);
           } else {
             out.x = (TIO)e.re;
             out.y = (TIO)e.im;
@@ -351,6 +441,7 @@ row_kernel(RowArgs<T, TIO> a) {
           y2[(lrow0 + r) * H + m] = out;
         }
       }
+    }
     }
   }
 

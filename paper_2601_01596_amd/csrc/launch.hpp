@@ -10,8 +10,8 @@ namespace ffcz {
 // Columns per block used by the strided-axis kernels of this dtype, length and
 // tile variant (only the loop modes COL_FWD / COL_INV / COL_XPASS have variant 1).
 int col_block_cols(int dtype, int L, int v);
-// Rows per block of the last-axis kernels computing in this dtype (variant 1
-// exists for ROW_INIT / ROW_LOOP / ROW_FINAL).
+// Rows per block of the last-axis kernels computing in this dtype (plan variants
+// 1 and 2 exist for ROW_LOOP, variant 2 for ROW_VERIFY).
 int row_block_rows(int dtype, int H, int v);
 
 // dtype 0: float, 1: double.  args points to a ColArgs<T>.

@@ -26,9 +26,7 @@ static hipError_t go(int H, const RowArgs<T, TIO>& a, int64_t nb, hipStream_t s)
 hipError_t launch_row_f32(int mode, int H, int v, const void* args, int64_t nb, hipStream_t s) {
   const RowArgs<float, float>& a = *static_cast<const RowArgs<float, float>*>(args);
   switch (mode) {
-    case ROW_INIT:
-      return v == 2 ? go<float, float, ROW_INIT, 2>(H, a, nb, s)
-                    : (v ? go<float, float, ROW_INIT, 1>(H, a, nb, s) : go<float, float, ROW_INIT, 0>(H, a, nb, s));
+    case ROW_INIT: return go<float, float, ROW_INIT, 0>(H, a, nb, s);
     case ROW_LOOP:
       return v == 2 ? go<float, float, ROW_LOOP, 2>(H, a, nb, s)
                     : (v ? go<float, float, ROW_LOOP, 1>(H, a, nb, s) : go<float, float, ROW_LOOP, 0>(H, a, nb, s));

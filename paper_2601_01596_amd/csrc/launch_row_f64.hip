@@ -26,14 +26,12 @@ static hipError_t go(int H, const RowArgs<T, TIO>& a, int64_t nb, hipStream_t s)
 hipError_t launch_row_f64(int mode, int H, int v, const void* args, int64_t nb, hipStream_t s) {
   const RowArgs<double, double>& a = *static_cast<const RowArgs<double, double>*>(args);
   switch (mode) {
-    case ROW_INIT:
-      return v == 2 ? go<double, double, ROW_INIT, 2>(H, a, nb, s)
-                    : (v ? go<double, double, ROW_INIT, 1>(H, a, nb, s) : go<double, double, ROW_INIT, 0>(H, a, nb, s));
+    case ROW_INIT: return go<double, double, ROW_INIT, 0>(H, a, nb, s);
     case ROW_LOOP:
       return v == 2 ? go<double, double, ROW_LOOP, 2>(H, a, nb, s)
                     : (v ? go<double, double, ROW_LOOP, 1>(H, a, nb, s) : go<double, double, ROW_LOOP, 0>(H, a, nb, s));
     case ROW_FINAL: return go<double, double, ROW_FINAL, 0>(H, a, nb, s);
-    case ROW_VERIFY: return go<double, double, ROW_VERIFY, 0>(H, a, nb, s);
+    case ROW_VERIFY: return v == 2 ? go<double, double, ROW_VERIFY, 2>(H, a, nb, s) : go<double, double, ROW_VERIFY, 0>(H, a, nb, s);
     case ROW_BINIT: return go<double, double, ROW_BINIT, 0>(H, a, nb, s);
     case ROW_BLOOP: return go<double, double, ROW_BLOOP, 0>(H, a, nb, s);
     case ROW_BFINAL: return go<double, double, ROW_BFINAL, 0>(H, a, nb, s);
@@ -42,9 +40,9 @@ hipError_t launch_row_f64(int mode, int H, int v, const void* args, int64_t nb, 
 }
 
 // FP64 verification of an FP32 output: compute in double, read float fields.
-hipError_t launch_row_verify_f32io(int H, const void* args, int64_t nb, hipStream_t s) {
+hipError_t launch_row_verify_f32io(int H, int v, const void* args, int64_t nb, hipStream_t s) {
   const RowArgs<double, float>& a = *static_cast<const RowArgs<double, float>*>(args);
-  return go<double, float, ROW_VERIFY, 0>(H, a, nb, s);
+  return v == 2 ? go<double, float, ROW_VERIFY, 2>(H, a, nb, s) : go<double, float, ROW_VERIFY, 0>(H, a, nb, s);
 }
 
 }  // namespace ffcz
