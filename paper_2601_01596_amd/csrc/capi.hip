@@ -168,6 +168,15 @@ int squeeze(int32_t ndim, const int64_t* shape, int64_t* sq) {
   return nd;
 }
 
+// Partial-sum slots of the on-device margin reduction of one field: a field of
+// n points uses ulp_slots(n) of them (about 16 Ki points per slot), the same
+// in a single call and in a batch, so both derive the same mu.
+constexpr int kUlpSlots = 1024;
+__host__ __device__ inline int ulp_slots(int64_t n) {
+  const int64_t k = (n + 16383) / 16384;
+  return (int)(k < 1 ? 1 : (k > kUlpSlots ? kUlpSlots : k));
+}
+
 struct Plan {
   int dt = 0;        // 0 f32, 1 f64
   int nd = 0;        // squeezed ndim
@@ -192,14 +201,14 @@ struct Plan {
   // blocks of each pass per instance (one partial slot per block)
   int64_t zbpi = 0, ibpi = 0, vzbpi = 0, xbpi = 0, vxbpi = 0;  // ibpi: the init pass (default tiles)
   int64_t pmax = 0;
-  size_t off_state = 0, off_viol = 0, off_init = 0, off_part = 0, off_twT = 0, off_tw64 = 0, off_Z = 0,
+  size_t off_state = 0, off_ulp = 0, off_viol = 0, off_init = 0, off_part = 0, off_twT = 0, off_tw64 = 0, off_Z = 0,
          off_A = 0, off_W = 0, bytes = 0;
   int32_t max_iter = 0;
   int64_t s_row_w32 = 0, s_plane_bytes = 0, f_row_bytes = 0, f_plane_bytes = 0;
 };
 
 struct StateInit {
-  double E, Ep, Delta, Dc, Dp, inv_n;
+  double E, Ep, Delta, Dc, Dp, inv_n, mu;
   int32_t max_iter, fixed, record_masks, pad;
   const void* px;
   const void* pxb;
@@ -211,7 +220,7 @@ struct StateInit {
 // output moves every spectral component by up to mu Delta when it is rounded,
 // and a coefficient accepted just below the check is never clipped, so the
 // check runs mu Delta below Delta and the projection mu Delta below the check.
-void spectral_thresholds(int dt, double delta, double mu, double* dc, double* dp) {
+__host__ __device__ void spectral_thresholds(int dt, double delta, double mu, double* dc, double* dp) {
   const double rho = dt == FFCZ_F64 ? 0.0 : mu;
   *dc = delta * (1.0 - rho);
   *dp = delta * (1.0 - rho - mu);
@@ -299,6 +308,8 @@ int32_t make_plan(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max
   size_t off = 0;
   p.off_state = off;
   off = align_up(off + sizeof(DevState) * (size_t)B, 256);
+  p.off_ulp = off;  // margin reduction: kUlpSlots partial sums, then mu
+  off = align_up(off + sizeof(double) * (kUlpSlots + 1), 256);
   p.off_viol = off;
   off = align_up(off + sizeof(unsigned long long) * ((size_t)max_iter + 2) * (size_t)B, 256);
   p.off_init = off;
@@ -349,30 +360,36 @@ struct TwJobs {
 
 // Stage twiddles exp(-2 pi i m r / (Ns R)) and R2C twiddles exp(-2 pi i k / 2L),
 // evaluated in FP64 with an exactly reduced argument and rounded once.
-__global__ void twiddle_kernel(void* base, TwJobs jobs) {
+// blockIdx.y picks one of two tables (base0/jobs0 or base1/jobs1), so a plan's
+// working-precision and FP64 tables take one launch.
+__global__ void twiddle_kernel(void* base0, TwJobs jobs0, void* base1, TwJobs jobs1) {
+  void* const base = blockIdx.y ? base1 : base0;
+  const TwJobs& jobs = blockIdx.y ? jobs1 : jobs0;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t acc = 0;
   for (int jj = 0; jj < jobs.n; ++jj) {
     const TwJob& jb = jobs.j[jj];
-    StageDesc d[32];
-    const int ns = host_stages(jb.L, jb.E, d);
-    int tsz = 0;
-    for (int s = 0; s < ns; ++s)
-      if (d[s].ns > 1) tsz += d[s].ns * (d[s].radix - 1);
+    // the stage plan of host_twsize, walked without a table (no per-lane scratch)
+    const int64_t tsz = jb.E > 1 && jb.L > 1 ? host_twsize(jb.L, jb.E) : 0;
     const int64_t cnt = tsz + (jb.rtw ? jb.L : 0);
     if (gid < acc + cnt) {
       const int64_t e = gid - acc;
       double num, den;  // angle = -2 pi num / den
       if (e < tsz) {
-        int s = 0;
-        for (; s < ns; ++s) {
-          if (d[s].ns > 1 && e >= d[s].off && e < d[s].off + d[s].ns * (d[s].radix - 1)) break;
+        const int lgE = ilog2c(jb.E), a = ilog2c(jb.L) / lgE;
+        const int r0 = jb.L >> (a * lgE);
+        int64_t ns = r0 > 1 ? r0 : 1, off = 0;
+        for (int t = 0; t < a; ++t, ns *= jb.E) {
+          if (ns == 1) continue;
+          const int64_t own = ns * (jb.E - 1);
+          if (e < off + own) break;
+          off += own;
         }
-        const int64_t loc = e - d[s].off;
-        const int64_t m = loc / (d[s].radix - 1);
-        const int64_t r = loc % (d[s].radix - 1) + 1;
+        const int64_t loc = e - off;
+        const int64_t m = loc / (jb.E - 1);
+        const int64_t r = loc % (jb.E - 1) + 1;
         num = (double)(m * r);
-        den = (double)d[s].ns * d[s].radix;
+        den = (double)ns * jb.E;
       } else {
         num = (double)(e - tsz);
         den = 2.0 * jb.L;
@@ -405,6 +422,7 @@ __global__ void state_init_kernel(DevState* st, int64_t B, const StateInit* arr,
     s.Dc = p.Dc;
     s.Dp = p.Dp;
     s.inv_n = p.inv_n;
+    s.mu = p.mu;
     s.max_iter = p.max_iter;
     s.fixed = p.fixed;
     s.record_masks = p.record_masks;
@@ -416,46 +434,111 @@ __global__ void state_init_kernel(DevState* st, int64_t B, const StateInit* arr,
   for (int64_t i = t; i < nviol; i += (int64_t)gridDim.x * blockDim.x) viol[i] = 0ull;
 }
 
-template <typename T>
-__global__ void ulp_kernel(const T* x, int64_t n, DevState* st) {
-  __shared__ double red[16];
-  double s = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const float a = fabsf((float)x[i]);
-    const double u = (double)nextafterf(a, INFINITY) - (double)a;
-    s += u * u;
-  }
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double b = 0.0;
-    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) b += red[w];
-    atomicAdd(&st->ulp2_sum, b);
-  }
+// Suggested FP32 margin for a field of N points with bound Delta:
+// mu = max(2^-16, 8 sigma sqrt(N/2) / Delta), sigma^2 = mean(ulp(x)^2) / 12, at
+// most 1/2.  Rounding y to FP32 moves each Re/Im component of its spectrum by
+// sigma sqrt(N/2) rms (N independent roundings of variance ulp^2/12, half of
+// each in the real part).  A non-finite sum gives 2^-16 (NaN) or 1/2 (Inf);
+// such inputs stop the correction anyway.
+__host__ __device__ double margin_from_ulp2(double ulp2_sum, int64_t N, double D) {
+  const double sigma = sqrt(ulp2_sum / (double)N / 12.0);
+  const double m = D > 0 ? 8.0 * sigma * sqrt((double)N / 2.0) / D : 0.5;
+  const double lo = 0x1p-16;
+  const double a = lo < m ? m : lo;
+  return a < 0.5 ? a : 0.5;
 }
 
-// Sums of ulp(x)^2 of many FP32 fields in one launch: blockIdx.y picks the
-// field, the blocks along x stride over it.
+// One field of a margin computation: x (FP32, N points) and its bound Delta.
 struct MarginJob {
   const float* x;
   int64_t n;
+  double D;
 };
 
-__global__ void __launch_bounds__(256) ulp_batch_kernel(const MarginJob* jobs, double* sums) {
+// ulp(v)^2 = (nextafter(|v|, +Inf) - |v|)^2 from the exponent field e of v:
+// 2^(2 max(e, 1) - 300), exact in FP64; FLT_MAX steps to Inf, Inf and NaN give NaN.
+__device__ inline double ulp2f(float v) {
+  const uint32_t b = __float_as_uint(v) & 0x7fffffffu;
+  const uint32_t e = b >> 23;
+  if (e == 255u) return __longlong_as_double(0x7ff8000000000000ll);
+  if (b == 0x7f7fffffu) return __longlong_as_double(0x7ff0000000000000ll);
+  const int64_t ex = 2 * (int64_t)(e > 0u ? e : 1u) - 300 + 1023;
+  return __longlong_as_double(ex << 52);
+}
+
+// Partial sums of ulp(x)^2.  blockIdx.y picks the field (jobs[y], or `one`
+// when jobs is null); its points are cut into nb = ulp_slots(n) contiguous
+// slices of a multiple of 4 points, and block b < nb stores the sum over slice
+// b in part[y * kUlpSlots + b] (blocks past nb have nothing to do).  No
+// atomics: margin_kernel adds the slots in a fixed order, so mu does not
+// depend on scheduling.  Aligned slices stream 16-byte vectors, four in flight
+// per lane.
+__global__ void __launch_bounds__(256) ulp_part_kernel(MarginJob one, const MarginJob* jobs, double* part) {
   __shared__ double red[4];
-  const MarginJob jb = jobs[blockIdx.y];
+  const MarginJob jb = jobs ? jobs[blockIdx.y] : one;
+  const int64_t nb = ulp_slots(jb.n);
+  if ((int64_t)blockIdx.x >= nb) return;
+  const int64_t slice = ((jb.n + nb - 1) / nb + 3) & ~int64_t(3);
+  const int64_t lo = std::min<int64_t>(jb.n, (int64_t)blockIdx.x * slice);
+  const int64_t hi = std::min<int64_t>(jb.n, lo + slice);
+  const float* x = jb.x;
   double s = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < jb.n; i += (int64_t)gridDim.x * blockDim.x) {
-    const float a = fabsf(jb.x[i]);
-    const double u = (double)nextafterf(a, INFINITY) - (double)a;
-    s += u * u;
+  int64_t i0 = lo;
+  if (((uintptr_t)(x + lo) & 15) == 0) {
+    const float4* x4 = (const float4*)(x + lo);
+    const int64_t n4 = (hi - lo) >> 2;
+    constexpr int U = 4;
+    int64_t k = threadIdx.x;
+    for (; k + (U - 1) * 256 < n4; k += U * 256) {
+      float4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = x4[k + u * 256];
+#pragma unroll
+      for (int u = 0; u < U; ++u) s += ulp2f(v[u].x) + ulp2f(v[u].y) + ulp2f(v[u].z) + ulp2f(v[u].w);
+    }
+    for (; k < n4; k += 256) {
+      const float4 v = x4[k];
+      s += ulp2f(v.x) + ulp2f(v.y) + ulp2f(v.z) + ulp2f(v.w);
+    }
+    i0 = lo + 4 * n4;
   }
+  for (int64_t i = i0 + threadIdx.x; i < hi; i += 256) s += ulp2f(x[i]);
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(&sums[blockIdx.y], red[0] + red[1] + red[2] + red[3]);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * kUlpSlots + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
+
+// One block per field: add its ulp_slots(n) partial sums in a fixed order and
+// derive mu.  mu_out[field] receives it when given; st (one state per field), when
+// given, receives mu and the bounds that depend on it (E (1 - mu) and the
+// spectral check and projection thresholds), the same values the host fills
+// in when mu is supplied.
+__global__ void __launch_bounds__(256) margin_kernel(const double* part, MarginJob one, const MarginJob* jobs, int dt,
+                                                     double* mu_out, DevState* st) {
+  __shared__ double red[4];
+  const MarginJob jb = jobs ? jobs[blockIdx.x] : one;
+  const int nslot = ulp_slots(jb.n);
+  const double* pp = part + (int64_t)blockIdx.x * kUlpSlots;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nslot; k += 256) s += pp[k];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double mu = margin_from_ulp2((red[0] + red[1]) + (red[2] + red[3]), jb.n, jb.D);
+  if (mu_out) mu_out[blockIdx.x] = mu;
+  if (st) {
+    DevState* t = st + blockIdx.x;
+    t->mu = mu;
+    t->Ep = t->E * (1.0 - mu);
+    double dc, dp;
+    spectral_thresholds(dt, t->Delta, mu, &dc, &dp);
+    t->Dc = dc;
+    t->Dp = dp;
+  }
+}
+
 
 // Per-round control, one block per instance: sum the x-pass partials into
 // v_k, fold the spatial-clip partials of the z-pass that produced the checked
@@ -491,6 +574,8 @@ __global__ void __launch_bounds__(1024) ctl_kernel(DevState* st0, unsigned long 
     }
     const int k = st->round;
     viol0[b * vstride + k] = vx;
+    if (k == 0) st->v_first = vx;
+    st->v_last = vx;
     if (k == 0) st->s_guard = vz;
     else st->s_clipped_total += vz;
     int stop = 0;
@@ -574,23 +659,20 @@ hipError_t launch_ctl(const Ctx& c, unsigned long long* viol, int64_t vstride) {
 hipError_t write_twiddles(const Ctx& c) {
   const Plan& p = *c.p;
   // table 0: working precision (read by the loop kernels); table 1: FP64 (verification)
+  TwJobs jobs[2];
   for (int tab = 0; tab < 2; ++tab) {
-    const int dbl = (tab == 1 || p.dt == FFCZ_F64) ? 1 : 0;
-    TwJobs jobs;
-    memset(&jobs, 0, sizeof(jobs));
-    jobs.dbl = dbl;
+    memset(&jobs[tab], 0, sizeof(TwJobs));
+    jobs[tab].dbl = (tab == 1 || p.dt == FFCZ_F64) ? 1 : 0;
     int n = 0;
-    jobs.j[n++] = TwJob{p.twz, p.H, p.Ez, 1};
-    jobs.j[n++] = TwJob{p.twz8, p.H, p.Ez8, 1};
-    if (p.Ly) jobs.j[n++] = TwJob{p.twy, p.Ly, p.Ey, 0};
-    jobs.j[n++] = TwJob{p.twx, p.Lx, p.Ex, 0};
-    jobs.n = n;
-    const int nb = (int)((p.twT + 255) / 256);
-    hipLaunchKernelGGL(twiddle_kernel, dim3(nb), dim3(256), 0, c.s, tab ? c.tw64() : c.twT(), jobs);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    jobs[tab].j[n++] = TwJob{p.twz, p.H, p.Ez, 1};
+    jobs[tab].j[n++] = TwJob{p.twz8, p.H, p.Ez8, 1};
+    if (p.Ly) jobs[tab].j[n++] = TwJob{p.twy, p.Ly, p.Ey, 0};
+    jobs[tab].j[n++] = TwJob{p.twx, p.Lx, p.Ex, 0};
+    jobs[tab].n = n;
   }
-  return hipSuccess;
+  const int nb = (int)((p.twT + 255) / 256);
+  hipLaunchKernelGGL(twiddle_kernel, dim3(nb, 2), dim3(256), 0, c.s, c.twT(), jobs[0], c.tw64(), jobs[1]);
+  return hipGetLastError();
 }
 
 // Geometry of a strided-axis pass.
@@ -814,43 +896,9 @@ double bits_to_double(unsigned long long b) {
   return d;
 }
 
-// Suggested FP32 margin for one field of N points (reads x once on the device).
-// mu = max(2^-16, 8 sigma sqrt(N/2) / Delta) with sigma^2 = mean(ulp(x)^2) / 12:
-// the rounding of y to FP32 moves each Re/Im component by sigma sqrt(N/2) rms.
-double margin_from_ulp2(double ulp2_sum, int64_t N, double D) {
-  const double sigma = std::sqrt(ulp2_sum / (double)N / 12.0);
-  const double m = D > 0 ? 8.0 * sigma * std::sqrt((double)N / 2.0) / D : 0.5;
-  return std::min(0.5, std::max(std::ldexp(1.0, -16), m));
-}
-
 __global__ void zero_u64_kernel(unsigned long long* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0ull;
-}
-
-__global__ void zero_f64_kernel(double* p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.0;
-}
-
-int32_t margin_for(int dt, int64_t N, const void* x, double D, DevState* scratch, hipStream_t s, double* mu) {
-  if (dt == FFCZ_F64) {
-    *mu = std::ldexp(1.0, -16);
-    return FFCZ_OK;
-  }
-  StateInit si;
-  memset(&si, 0, sizeof(si));
-  hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, s, scratch, (int64_t)1, (const StateInit*)nullptr, si,
-                     (unsigned long long*)nullptr, (int64_t)0);
-  HIPCHK(hipGetLastError());
-  const int nb = (int)std::min<int64_t>(4096, (N + 255) / 256);
-  hipLaunchKernelGGL(ulp_kernel<float>, dim3(nb), dim3(256), 0, s, (const float*)x, N, scratch);
-  HIPCHK(hipGetLastError());
-  HIPCHK(g_host_misc.reserve(sizeof(DevState)));
-  HIPCHK(hipMemcpyAsync(g_host_misc.p, scratch, sizeof(DevState), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  *mu = margin_from_ulp2(((DevState*)g_host_misc.p)->ulp2_sum, N, D);
-  return FFCZ_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1067,7 +1115,9 @@ int32_t pretune_group(const Plan& p0, char* ws, hipStream_t s) {
   return tune_plan<T>(p, ws, s, false);
 }
 
-// One correction over the B instances of a plan.  inst[b] supplies pointers and bounds.
+// One correction over the B instances of a plan.  inst[b] supplies pointers and
+// bounds, mus[b] the margins; mus null (one FP32 instance) derives mu from x on
+// the device, between the state set-up and the first pass.
 template <typename T>
 int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* mus, int32_t max_iter,
                       const ffcz_options& o, char* ws, hipStream_t s, ffcz_stats* stats, int32_t* status) {
@@ -1085,10 +1135,12 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
     StateInit si;
     memset(&si, 0, sizeof(si));
     si.E = inst[b].eps_s;
-    si.Ep = inst[b].eps_s * (1.0 - mus[b]);
+    const double mu = mus ? mus[b] : 0.0;  // without mus, margin_kernel rewrites the mu-dependent fields
+    si.Ep = inst[b].eps_s * (1.0 - mu);
     si.Delta = inst[b].delta_f;
-    spectral_thresholds(p.dt, inst[b].delta_f, mus[b], &si.Dc, &si.Dp);
+    spectral_thresholds(p.dt, inst[b].delta_f, mu, &si.Dc, &si.Dp);
     si.inv_n = 1.0 / (double)p.N;
+    si.mu = mu;
     si.max_iter = max_iter;
     si.fixed = o.fixed_iterations ? 1 : 0;
     si.record_masks = rec ? 1 : 0;
@@ -1111,6 +1163,18 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
   hipLaunchKernelGGL(state_init_kernel, dim3((unsigned)std::max<int64_t>(1, (nthr + 255) / 256)), dim3(256), 0, s,
                      c.st(), p.B, arr, one, viol, nviol);
   HIPCHK(hipGetLastError());
+  if (!mus) {
+    if (p.B != 1 || p.dt != FFCZ_F32) return fail(FFCZ_E_INVALID, "device margin needs one FP32 instance");
+    const int nsl = ulp_slots(p.N);
+    double* slots = (double*)(ws + p.off_ulp);
+    const MarginJob one_job{(const float*)inst[0].x_orig, p.N, inst[0].delta_f};
+    hipLaunchKernelGGL(ulp_part_kernel, dim3((unsigned)nsl), dim3(256), 0, s, one_job, (const MarginJob*)nullptr,
+                       slots);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(margin_kernel, dim3(1), dim3(256), 0, s, (const double*)slots, one_job,
+                       (const MarginJob*)nullptr, (int)p.dt, (double*)nullptr, c.st());
+    HIPCHK(hipGetLastError());
+  }
   HIPCHK(write_twiddles(c));
   {
     const int32_t tr = tune_plan<T>(p, ws, s, rec);
@@ -1174,18 +1238,9 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
     return FFCZ_OK;
   }
   HIPCHK(hipMemcpyAsync(hs, c.st(), sizeof(DevState) * p.B, hipMemcpyDeviceToHost, s));
-  HIPCHK(g_host_misc.reserve(sizeof(unsigned long long) * 2 * p.B));
-  unsigned long long* hv = (unsigned long long*)g_host_misc.p;
   HIPCHK(hipStreamSynchronize(s));
   int maxr = 0;
-  for (int64_t b = 0; b < p.B; ++b) {
-    const int64_t vb = b * vstr;
-    HIPCHK(hipMemcpyAsync(&hv[2 * b], viol + vb, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&hv[2 * b + 1], viol + vb + hs[b].round, sizeof(unsigned long long),
-                          hipMemcpyDeviceToHost, s));
-    maxr = std::max(maxr, hs[b].round);
-  }
-  HIPCHK(hipStreamSynchronize(s));
+  for (int64_t b = 0; b < p.B; ++b) maxr = std::max(maxr, hs[b].round);
   prof_settle(maxr);
   for (int64_t b = 0; b < p.B; ++b) {
     const DevState& h = hs[b];
@@ -1195,15 +1250,15 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
       memset(&st, 0, sizeof(st));
       st.rounds = h.round;
       st.converged = h.converged;
-      st.f_viol_initial = (int64_t)hv[2 * b];
-      st.f_viol_final = (int64_t)hv[2 * b + 1];
+      st.f_viol_initial = (int64_t)h.v_first;
+      st.f_viol_final = (int64_t)h.v_last;
       st.s_clipped_total = (int64_t)h.s_clipped_total;
       st.s_guard = (int64_t)h.s_guard;
       st.nonfinite = (int64_t)h.nonfinite;
       st.max_spatial_err = o.verify_fp64 ? ms : NAN;
       st.max_spectral_err = o.verify_fp64 ? mf : NAN;
       st.spectral_viol = (int64_t)h.spectral_viol;
-      st.margin_used = mus[b];
+      st.margin_used = h.mu;
     }
     int32_t r = FFCZ_OK;
     if (h.nonfinite) r = FFCZ_E_NONFINITE;
@@ -1368,14 +1423,15 @@ hipError_t write_mc_tabs(int dt, int lgMc, char* base, const McTabs& t, hipStrea
                        sig_rows_per_tile(dbl, lgMc));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    TwJobs jobs;
-    memset(&jobs, 0, sizeof(jobs));
-    jobs.dbl = dbl;
-    jobs.n = 1;
-    jobs.j[0] = TwJob{0, MA, pick_E(MA), 0};
-    hipLaunchKernelGGL(twiddle_kernel, dim3(64), dim3(256), 0, s, base + (pass ? t.twa_64 : t.twa), jobs);
-    jobs.j[0] = TwJob{0, MB, pick_E(MB), 0};
-    hipLaunchKernelGGL(twiddle_kernel, dim3(64), dim3(256), 0, s, base + (pass ? t.twb_64 : t.twb), jobs);
+    TwJobs ja, jb;
+    memset(&ja, 0, sizeof(ja));
+    ja.dbl = dbl;
+    ja.n = 1;
+    jb = ja;
+    ja.j[0] = TwJob{0, MA, pick_E(MA), 0};
+    jb.j[0] = TwJob{0, MB, pick_E(MB), 0};
+    hipLaunchKernelGGL(twiddle_kernel, dim3(64, 2), dim3(256), 0, s, (void*)(base + (pass ? t.twa_64 : t.twa)), ja,
+                       (void*)(base + (pass ? t.twb_64 : t.twb)), jb);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -1397,7 +1453,7 @@ struct BatchPlan {
   std::map<int, size_t> mc_off;             // lgMc -> table offset
   std::map<int, McTabs> mc_tab;
   std::vector<size_t> sig_off;
-  size_t off_desc = 0, off_sstats = 0, off_order = 0, off_scratch = 0, off_mjobs = 0, off_msum = 0;
+  size_t off_desc = 0, off_sstats = 0, off_order = 0, off_mjobs = 0, off_msum = 0;
   // length classes run as tiled passes: partial slots [kind][signal][tile] per class
   std::map<int, size_t> tpart_off;
   std::map<int, int> tpart_tiles;
@@ -1479,12 +1535,10 @@ int32_t batch_plan(int32_t dt, int32_t count, const ffcz_instance* inst, int32_t
   off = align_up(off + sizeof(SigStats) * (size_t)std::max(ns, 1), 256);
   bp.off_order = off;
   off = align_up(off + sizeof(int32_t) * (size_t)std::max(ns, 1), 256);
-  bp.off_scratch = off;  // one DevState for the margin reductions
-  off = align_up(off + sizeof(DevState), 256);
-  bp.off_mjobs = off;  // margin jobs (x pointer, length) and their ulp^2 sums
+  bp.off_mjobs = off;  // margin jobs (x pointer, length, bound)
   off = align_up(off + sizeof(MarginJob) * (size_t)std::max(count, 1), 256);
-  bp.off_msum = off;
-  off = align_up(off + sizeof(double) * (size_t)std::max(count, 1), 256);
+  bp.off_msum = off;  // margin partial sums (kUlpSlots per member), then the members' mu
+  off = align_up(off + sizeof(double) * (size_t)(kUlpSlots + 1) * (size_t)std::max(count, 1), 256);
   bp.bytes = off;
   return FFCZ_OK;
 }
@@ -1943,9 +1997,26 @@ int32_t ffcz_suggest_margin(int32_t dtype, int32_t ndim, const int64_t* shape, c
   if (r != FFCZ_OK) return r;
   if (!x || !mu_out) return fail(FFCZ_E_INVALID, "null pointer");
   if (!std::isfinite(delta_f) || delta_f < 0) return fail(FFCZ_E_INVALID, "delta_f must be finite and >= 0");
-  if (dtype == FFCZ_F32 && (!ws || ws_bytes < p.off_state + sizeof(DevState)))
+  if (dtype == FFCZ_F64) {
+    *mu_out = std::ldexp(1.0, -16);
+    return FFCZ_OK;
+  }
+  if (!ws || ws_bytes < p.off_ulp + sizeof(double) * (kUlpSlots + 1))
     return fail(FFCZ_E_WORKSPACE, "workspace too small");
-  return margin_for(dtype, p.N, x, delta_f, (DevState*)((char*)ws + p.off_state), (hipStream_t)stream, mu_out);
+  hipStream_t s = (hipStream_t)stream;
+  double* slots = (double*)((char*)ws + p.off_ulp);
+  const int nsl = ulp_slots(p.N);
+  const MarginJob job{(const float*)x, p.N, delta_f};
+  hipLaunchKernelGGL(ulp_part_kernel, dim3((unsigned)nsl), dim3(256), 0, s, job, (const MarginJob*)nullptr, slots);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(margin_kernel, dim3(1), dim3(256), 0, s, (const double*)slots, job,
+                     (const MarginJob*)nullptr, (int)FFCZ_F32, slots + kUlpSlots, (DevState*)nullptr);
+  HIPCHK(hipGetLastError());
+  HIPCHK(g_host_misc.reserve(sizeof(double)));
+  HIPCHK(hipMemcpyAsync(g_host_misc.p, slots + kUlpSlots, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *mu_out = *(const double*)g_host_misc.p;
+  return FFCZ_OK;
 }
 
 int32_t ffcz_correct(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x, const void* xb, void* y,
@@ -1967,12 +2038,10 @@ int32_t ffcz_correct(int32_t dtype, int32_t ndim, const int64_t* shape, const vo
   if (o.masks_out && p.dt == FFCZ_F64 && col_block_cols(1, p.Lx, 0) < 8)
     return fail(FFCZ_E_SHAPE, "mask recording needs at least 8 columns per block");
   hipStream_t s = (hipStream_t)stream;
-  double mu = o.margin_rel;
-  if (!(mu > 0.0)) {
-    int32_t st = margin_for(dtype, p.N, x, delta_f, (DevState*)((char*)ws + p.off_state), s, &mu);
-    if (st != FFCZ_OK) return st;
-  }
+  // no margin given: FP64 takes 2^-16, FP32 derives mu from x on the device (no host round trip)
+  double mu = o.margin_rel > 0.0 ? o.margin_rel : (dtype == FFCZ_F64 ? std::ldexp(1.0, -16) : 0.0);
   if (!(mu < 1.0)) return fail(FFCZ_E_INVALID, "margin_rel must be in [0, 1)");
+  const double* mus = mu > 0.0 ? &mu : nullptr;
   ffcz_instance in;
   memset(&in, 0, sizeof(in));
   in.ndim = ndim;
@@ -1983,8 +2052,8 @@ int32_t ffcz_correct(int32_t dtype, int32_t ndim, const int64_t* shape, const vo
   in.eps_s = eps_s;
   in.delta_f = delta_f;
   int32_t status = FFCZ_OK;
-  r = dtype == FFCZ_F32 ? correct_group<float>(p, &in, &mu, max_iter, o, (char*)ws, s, stats, &status)
-                        : correct_group<double>(p, &in, &mu, max_iter, o, (char*)ws, s, stats, &status);
+  r = dtype == FFCZ_F32 ? correct_group<float>(p, &in, mus, max_iter, o, (char*)ws, s, stats, &status)
+                        : correct_group<double>(p, &in, mus, max_iter, o, (char*)ws, s, stats, &status);
   if (r != FFCZ_OK) return r;
   if (stats) stats->status = status;
   if (status == FFCZ_E_NONFINITE) return fail(FFCZ_E_NONFINITE, "x or x_hat holds NaN or Inf");
@@ -2040,27 +2109,29 @@ int32_t ffcz_correct_batched(int32_t dtype, int32_t count, const ffcz_instance* 
     } else {
       HIPCHK(g_host_misc.reserve(sizeof(MarginJob) * count + sizeof(double) * count));
       MarginJob* hj = (MarginJob*)g_host_misc.p;
-      double* hs = (double*)(hj + count);
+      double* hmu = (double*)(hj + count);
       int64_t nmax = 1;
       for (int i = 0; i < count; ++i) {
-        hj[i] = MarginJob{(const float*)inst[i].x_orig, Ns[i]};
+        hj[i] = MarginJob{(const float*)inst[i].x_orig, Ns[i], inst[i].delta_f};
         nmax = std::max(nmax, Ns[i]);
       }
       MarginJob* dj = (MarginJob*)(w + bp.off_mjobs);
-      double* dsum = (double*)(w + bp.off_msum);
+      double* dpart = (double*)(w + bp.off_msum);
+      double* dmu = dpart + (size_t)count * kUlpSlots;
       HIPCHK(hipMemcpyAsync(dj, hj, sizeof(MarginJob) * count, hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(zero_f64_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, dsum, (int64_t)count);
-      HIPCHK(hipGetLastError());
-      const unsigned bx = (unsigned)std::min<int64_t>(64, (nmax + 255) / 256);
+      const unsigned bx = (unsigned)ulp_slots(nmax);
       for (int c0 = 0; c0 < count; c0 += 65535) {  // grid y holds at most 65535 fields
         const int nc = std::min(65535, count - c0);
-        hipLaunchKernelGGL(ulp_batch_kernel, dim3(bx, (unsigned)nc), dim3(256), 0, s, (const MarginJob*)dj + c0,
-                           dsum + c0);
+        hipLaunchKernelGGL(ulp_part_kernel, dim3(bx, (unsigned)nc), dim3(256), 0, s, MarginJob{},
+                           (const MarginJob*)dj + c0, dpart + (size_t)c0 * kUlpSlots);
         HIPCHK(hipGetLastError());
       }
-      HIPCHK(hipMemcpyAsync(hs, dsum, sizeof(double) * count, hipMemcpyDeviceToHost, s));
+      hipLaunchKernelGGL(margin_kernel, dim3((unsigned)count), dim3(256), 0, s, (const double*)dpart, MarginJob{},
+                         (const MarginJob*)dj, (int)FFCZ_F32, dmu, (DevState*)nullptr);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(hmu, dmu, sizeof(double) * count, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      for (int i = 0; i < count; ++i) mus[i] = margin_from_ulp2(hs[i], Ns[i], inst[i].delta_f);
+      for (int i = 0; i < count; ++i) mus[i] = hmu[i];
     }
   }
   std::vector<int32_t> status(count, FFCZ_OK);

@@ -21,9 +21,10 @@ struct DevState {
   // counters
   unsigned long long nonfinite, s_guard, s_clipped_total;
   unsigned long long max_spatial_bits, max_spectral_bits, spectral_viol;
-  // margin suggestion: sum of ulp^2 (FP64), count
-  double ulp2_sum;
-  unsigned long long ulp_cnt;
+  // the margin mu in use (given, or derived on the device from x before the first pass)
+  double mu;
+  // violation counts of the first and of the last check (ctl_kernel), so the host reads one struct
+  unsigned long long v_first, v_last;
   // the instance's data (device pointers): x, x_hat (or dL/dy), y (or dL/dx_hat)
   const void* px;
   const void* pxb;

@@ -152,39 +152,17 @@ struct Sched {
   static constexpr int twsize = twoff(nst);
 };
 
-// Host-side mirror of Sched for runtime L (twiddle table generation).
-struct StageDesc {
-  int ns, radix, off;
-};
-__host__ __device__ inline int host_stages(int L, int E, StageDesc* out) {
-  if (E <= 1 || L <= 1) return 0;
-  const int lgL = ilog2c(L), lgE = ilog2c(E);
-  const int a = lgL / lgE;
-  const int r0 = L >> (a * lgE);
-  int n = 0, ns = 1, off = 0;
-  if (r0 > 1) {
-    out[n++] = {ns, r0, off};
-    ns *= r0;
-  }
-  for (int t = 0; t < a; ++t) {
-    out[n++] = {ns, E, off};
-    if (ns > 1) off += ns * (E - 1);
-    ns *= E;
-  }
-  // offsets: recompute so that stages with ns == 1 own no entries
-  off = 0;
-  for (int t = 0; t < n; ++t) {
-    out[t].off = off;
-    if (out[t].ns > 1) off += out[t].ns * (out[t].radix - 1);
-  }
-  return n;
-}
+// Twiddle-table entries of the stage plan for a runtime length L (the plan Sched
+// fixes at compile time): an optional radix-r0 stage at span 1, then radix-E stages
+// at spans r0 E^t; a stage of span ns > 1 owns ns (radix - 1) entries, in stage
+// order (the span-1 stage owns none).
 __host__ __device__ inline int host_twsize(int L, int E) {
-  StageDesc d[32];
-  const int n = host_stages(L, E, d);
-  int s = 0;
-  for (int t = 0; t < n; ++t)
-    if (d[t].ns > 1) s += d[t].ns * (d[t].radix - 1);
+  if (E <= 1 || L <= 1) return 0;
+  const int lgE = ilog2c(E), a = ilog2c(L) / lgE;
+  const int r0 = L >> (a * lgE);
+  int s = 0, ns = r0 > 1 ? r0 : 1;
+  for (int t = 0; t < a; ++t, ns *= E)
+    if (ns > 1) s += ns * (E - 1);
   return s;
 }
 

@@ -103,9 +103,10 @@ def test_batched_matches_single_calls_bitwise():
     import torch
     probs = [_member((64, 128), 400 + i, np.float32) for i in range(3)]
     ys, st, stats = _run(probs)
-    for p, y in zip(probs, ys):
+    for p, y, s in zip(probs, ys, stats):
         r = F.correct(torch.from_numpy(p.x).cuda(), torch.from_numpy(p.xb).cuda(), p.E, p.Delta, 200)
         assert np.array_equal(r.y.cpu().numpy().view(np.uint32), y.view(np.uint32))
+        assert r.stats["margin_used"] == s["margin_used"]  # same slot rule and fold order
 
 
 def test_batched_statuses():

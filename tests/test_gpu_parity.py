@@ -325,3 +325,46 @@ def test_tuning_cache_file_roundtrip(tmp_path):
     finally:
         F.ffcz_set_tuning(1, "")
         F.ffcz_clear_tuning()
+
+
+@pytest.mark.parametrize("shape, offset", [((8,), 0), ((4096,), 1), ((16, 4096), 3), ((32, 64), 2),
+                                           ((64, 64, 64), 0), ((2, 4, 128), 1), ((1024, 2048), 0)])
+def test_device_margin_matches_oracle(shape, offset):
+    """The FP32 margin derived on the device (slot partial sums of ulp(x)^2, folded in a fixed
+    order) against the oracle's formula, from unaligned starts too.  A correction that derives
+    its own margin reports exactly the suggested value."""
+    import torch
+    rng = np.random.default_rng(sum(shape) + offset)
+    n = int(np.prod(shape))
+    x = (rng.standard_normal(n + offset) * 10.0 ** rng.uniform(-3, 3, n + offset)).astype(np.float32)
+    xt = torch.from_numpy(x).cuda()[offset:].reshape(shape)
+    D = 0.37
+    ws = F.workspace(F.F32, shape, 4, xt.device)
+    stream = torch.cuda.current_stream().cuda_stream
+    mu = F.ffcz_suggest_margin(F.F32, shape, xt.data_ptr(), D, ws.data_ptr(), ws.numel(), stream)
+    ref = O.suggest_margin(x[offset:].reshape(shape), D)
+    assert abs(mu - ref) <= 1e-12 * ref, (mu, ref)
+    if offset == 0:
+        xb = (xt + 1e-3).contiguous()
+        r = F.correct(xt, xb, 2e-3, D, 4, ws=ws)
+        assert r.stats["margin_used"] == mu
+    mu64 = F.ffcz_suggest_margin(F.F64, shape, xt.data_ptr(), D, ws.data_ptr(), ws.numel(), stream)
+    assert mu64 == 2.0 ** -16
+
+
+def test_device_margin_ragged_lengths_in_a_batch():
+    """Batched 1D members of any length: slices of a multiple of 4 points with a ragged last
+    slot; each member's margin against the oracle's formula."""
+    import torch
+    rng = np.random.default_rng(77)
+    lens = [2, 3, 7, 4097, 16385, 100003, 262147]
+    mem, xs = [], []
+    for n in lens:
+        x = (rng.standard_normal(n) * 10.0 ** rng.uniform(-3, 3, n)).astype(np.float32)
+        xs.append(x)
+        xt = torch.from_numpy(x).cuda()
+        mem.append((xt, (xt + 1e-3).contiguous(), 2e-3, 0.37 * np.sqrt(n)))
+    _, st, stats = F.correct_batched(mem, 4, check=False)
+    for x, m, s in zip(xs, mem, stats):
+        ref = O.suggest_margin(x, m[3])
+        assert abs(s["margin_used"] - ref) <= 1e-12 * ref, (x.size, s["margin_used"], ref)
