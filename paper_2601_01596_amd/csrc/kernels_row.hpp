@@ -352,13 +352,13 @@ row_kernel(RowArgs<T, TIO> a) {
       if (f < ROWS * NPR && r < nrow) {
         const cx<T>* zr = lds + r * LP;
         const cx<T> X0 = unpack(zr, 2 * m);
-        cx<T>* out = a.dst + rowaddr(row0 + r) + 2 * m;
-        if (2 * m + 1 < NC) {
-          const cx<T> X1 = unpack(zr, 2 * m + 1);
-          *reinterpret_cast<float4*>(out) = make_float4((float)X0.re, (float)X0.im, (float)X1.re, (float)X1.im);
-        } else {
-          *out = X0;
-        }
+        // the last pair of a row holds entry H and the first padding entry of the row
+        // (the pitch is a multiple of 16 above H + 1), stored as zero: every pair is one
+        // 16-byte store (a branch with a lone 8-byte store gets split into 4 + 12 bytes)
+        cx<T> X1{T(0), T(0)};
+        if (2 * m + 1 < NC) X1 = unpack(zr, 2 * m + 1);
+        *reinterpret_cast<float4*>(a.dst + rowaddr(row0 + r) + 2 * m) =
+            make_float4((float)X0.re, (float)X0.im, (float)X1.re, (float)X1.im);
       }
     }
   } else if constexpr (spec_out) {

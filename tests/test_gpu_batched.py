@@ -109,6 +109,23 @@ def test_batched_matches_single_calls_bitwise():
         assert r.stats["margin_used"] == s["margin_used"]  # same slot rule and fold order
 
 
+def test_batched_narrow_tiles_bitwise():
+    # a group of same-shape 2D members under the narrowest tiles against the default tiles
+    # (a group's blocks are numbered across its members)
+    probs = [_member((512, 1024), 420 + i, np.float32) for i in range(5)]
+    try:
+        F.ffcz_set_tuning(0)
+        ys0, st0, s0 = _run(probs)
+        F.ffcz_set_tuning(2)
+        ys4, st4, s4 = _run(probs)
+    finally:
+        F.ffcz_set_tuning(1)
+    assert st0 == F.OK and st4 == F.OK
+    for a, b in zip(ys0, ys4):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    assert s0 == s4
+
+
 def test_batched_statuses():
     # a member capped at 0 rounds reports NOT_CONVERGED; a NaN member reports NONFINITE
     import torch

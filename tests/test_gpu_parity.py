@@ -270,21 +270,31 @@ def test_copy_kernel_bit_exact(nbytes):
 
 
 @pytest.mark.parametrize("dt,shape", [(np.float32, (32, 64, 128)), (np.float64, (64, 32, 256)),
-                                      (np.float32, (256, 512)), (np.float32, (2048, 128))])
+                                      (np.float32, (256, 512)), (np.float32, (2048, 128)),
+                                      (np.float32, (2, 4, 512)), (np.float32, (4, 8, 1024)),
+                                      (np.float32, (64, 2048)), (np.float32, (8, 4096)),
+                                      (np.float32, (256, 256, 512))])
 def test_tile_variants_bit_identical(dt, shape):
     # every tiling the tuner may pick computes the same bits: default tiles vs the narrowest
+    # (mode 2), masks included
     p = _problem(shape, 71, dt)
+    K = 3
+    runs = []
     try:
-        F.ffcz_set_tuning(0)
-        y0, r0 = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter, record_viol=True)
-        F.ffcz_set_tuning(2)
-        y1, r1 = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter, record_viol=True)
+        for mode in (0, 2):
+            F.ffcz_set_tuning(mode)
+            y, r = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter, record_viol=True)
+            yk, rk = run_gpu(p.x, p.xb, p.E, p.Delta, K, fixed=True, record_masks=True)
+            runs.append((y, r, rk.masks.cpu().numpy()))
     finally:
         F.ffcz_set_tuning(1)
-    assert r0.status == F.OK and r1.status == F.OK
-    assert np.array_equal(y0.view(np.uint8), y1.view(np.uint8))
-    assert r0.stats == r1.stats
-    assert np.array_equal(r0.viol.cpu().numpy(), r1.viol.cpu().numpy())
+    y0, r0, m0 = runs[0]
+    for y1, r1, m1 in runs[1:]:
+        assert r0.status == F.OK and r1.status == F.OK
+        assert np.array_equal(y0.view(np.uint8), y1.view(np.uint8))
+        assert r0.stats == r1.stats
+        assert np.array_equal(r0.viol.cpu().numpy(), r1.viol.cpu().numpy())
+        assert np.array_equal(m0, m1)
 
 
 @pytest.mark.parametrize("dt,shape", [(np.float32, (32, 64, 256)), (np.float64, (16, 32, 512)),
