@@ -217,8 +217,9 @@ int32_t ffcz_profile_read(ffcz_profile* out);
 /* Plan tuning of the loop passes.  Each pass (y-forward/inverse, x-pass,
  * last-axis pass) can run with a few tilings (columns or rows per block) that
  * give bit-identical results and differ only in speed; the last-axis passes
- * also have a radix-8 stage plan (the default is radix 16), which rounds
- * differently.
+ * also have a radix-8 stage plan (the default is radix 16) and, for FP32 rows of
+ * 256 entries, a direct form (rows moved straight between HBM and registers),
+ * both of which round differently.
  *   mode 0  always the default plans;
  *   mode 1  (default) on the first use of a pass geometry on a device
  *           architecture, time every variant once on the call's own workspace
@@ -226,7 +227,9 @@ int32_t ffcz_profile_read(ffcz_profile* out);
  *           stream is being captured or masks are recorded) and keep the
  *           fastest for the rest of the process;
  *   mode 2  always the narrower tilings (for testing);
- *   mode 3  always the radix-8 last-axis plan (for testing).
+ *   mode 3  always the radix-8 last-axis plan (for testing);
+ *   mode 4  always the direct last-axis loop pass (FP32 rows of 256 entries,
+ *           lanes index-fastest; elsewhere the narrower tiling; for testing).
  * cache_path: JSON file of decisions, read now and rewritten after each new
  * decision; NULL keeps the current path, "" stops persisting.  The initial
  * mode and path come from FFCZ_AUTOTUNE (0 selects mode 0) and

@@ -1005,6 +1005,10 @@ int32_t tune_pass(const std::string& key, hipStream_t s, bool may_time, float ke
       *out = nvar > 2 ? 2 : 0;
       return FFCZ_OK;
     }
+    if (g_tuner.mode == 4) {  // the direct (index-fastest) last-axis loop pass
+      *out = nvar > 3 ? 3 : 0;
+      return FFCZ_OK;
+    }
     auto it = g_tuner.tab.find(key);
     if (it != g_tuner.tab.end() && it->second.choice < nvar) {
       *out = it->second.choice;
@@ -1890,7 +1894,7 @@ int32_t ffcz_version(void) { return 100; }
 const char* ffcz_last_error(void) { return g_err.c_str(); }
 
 int32_t ffcz_set_tuning(int32_t mode, const char* cache_path) {
-  if (mode < 0 || mode > 3) return fail(FFCZ_E_INVALID, "tuning mode must be 0, 1, 2 or 3");
+  if (mode < 0 || mode > 4) return fail(FFCZ_E_INVALID, "tuning mode must be 0 to 4");
   std::lock_guard<std::mutex> g(g_tuner.m);
   g_tuner.init_locked();
   g_tuner.mode = mode;

@@ -164,10 +164,13 @@ __host__ __device__ constexpr int row_lds_pitch(int H, int R, int E) {
 // Plans the tuner chooses between.  Column passes: variant 1 halves the tile
 // width.  Last-axis passes: variant 1 halves the rows per block; variant 2
 // uses radix-8 stages (8 elements per lane, twice the lanes per row) where the
-// default is radix 16.  Variants 0 and 1 compute identical bits; variant 2
-// rounds differently.
+// default is radix 16; variant 3 is the FP32 loop pass of 256-entry rows with
+// lanes index-fastest and rows moved straight between HBM and registers
+// (elsewhere it runs variant 1, whose rows per block it shares).  Variants 0 and
+// 1 compute identical bits; variants 2 and 3 round differently (other stages,
+// other fused multiply-adds).
 constexpr int kColVariants = 2;
-constexpr int kRowVariants = 3;
+constexpr int kRowVariants = 4;
 template <typename T>
 __host__ __device__ constexpr int tile_cols(int L, int v) {
   return (pick_C<T>(L) >> v) < 1 ? 1 : (pick_C<T>(L) >> v);
@@ -183,7 +186,9 @@ __host__ __device__ constexpr int rows_for_E(int H, int E) {
 }
 template <typename T>
 __host__ __device__ constexpr int tile_rows(int H, int v) {
-  return v == 2 ? rows_for_E<T>(H, row_E(H, 2)) : ((pick_rows<T>(H) >> v) < 1 ? 1 : (pick_rows<T>(H) >> v));
+  if (v == 2) return rows_for_E<T>(H, row_E(H, 2));
+  if (v == 3) v = 1;
+  return (pick_rows<T>(H) >> v) < 1 ? 1 : (pick_rows<T>(H) >> v);
 }
 
 }  // namespace ffcz

@@ -28,6 +28,12 @@ hipError_t launch_row_f32(int mode, int H, int v, const void* args, int64_t nb, 
   switch (mode) {
     case ROW_INIT: return go<float, float, ROW_INIT, 0>(H, a, nb, s);
     case ROW_LOOP:
+      if (v == 3) {
+        if (H != 256) return go<float, float, ROW_LOOP, 1>(H, a, nb, s);
+        static_assert(tile_rows<float>(256, 3) == 16, "the direct pass runs 16-row tiles");
+        hipLaunchKernelGGL((row_loop_direct_kernel<16>), dim3((unsigned)nb), dim3(16 * 16), 0, s, a);
+        return hipGetLastError();
+      }
       return v == 2 ? go<float, float, ROW_LOOP, 2>(H, a, nb, s)
                     : (v ? go<float, float, ROW_LOOP, 1>(H, a, nb, s) : go<float, float, ROW_LOOP, 0>(H, a, nb, s));
     case ROW_FINAL: return go<float, float, ROW_FINAL, 0>(H, a, nb, s);

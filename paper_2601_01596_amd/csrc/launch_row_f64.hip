@@ -28,6 +28,7 @@ hipError_t launch_row_f64(int mode, int H, int v, const void* args, int64_t nb, 
   switch (mode) {
     case ROW_INIT: return go<double, double, ROW_INIT, 0>(H, a, nb, s);
     case ROW_LOOP:
+      // variant 3 (FP32 only) falls back to variant 1, whose tiles it shares
       return v == 2 ? go<double, double, ROW_LOOP, 2>(H, a, nb, s)
                     : (v ? go<double, double, ROW_LOOP, 1>(H, a, nb, s) : go<double, double, ROW_LOOP, 0>(H, a, nb, s));
     case ROW_FINAL: return go<double, double, ROW_FINAL, 0>(H, a, nb, s);

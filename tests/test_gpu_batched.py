@@ -109,21 +109,29 @@ def test_batched_matches_single_calls_bitwise():
         assert r.stats["margin_used"] == s["margin_used"]  # same slot rule and fold order
 
 
-def test_batched_narrow_tiles_bitwise():
-    # a group of same-shape 2D members under the narrowest tiles against the default tiles
-    # (a group's blocks are numbered across its members)
-    probs = [_member((512, 1024), 420 + i, np.float32) for i in range(5)]
+@pytest.mark.parametrize("shape", [(512, 1024), (256, 512)])
+def test_batched_tilings(shape):
+    # a group of same-shape 2D members (its blocks are numbered across the members): the
+    # narrowest tiles (mode 2) give the default tiles' bits; the direct last-axis loop pass
+    # (mode 4, 256-entry rows) rounds differently and meets the oracle's bars per member
+    probs = [_member(shape, 420 + i, np.float32) for i in range(5)]
+    runs = []
     try:
-        F.ffcz_set_tuning(0)
-        ys0, st0, s0 = _run(probs)
-        F.ffcz_set_tuning(2)
-        ys4, st4, s4 = _run(probs)
+        for mode in (0, 2, 4):
+            F.ffcz_set_tuning(mode)
+            runs.append(_run(probs))
     finally:
         F.ffcz_set_tuning(1)
-    assert st0 == F.OK and st4 == F.OK
-    for a, b in zip(ys0, ys4):
+    ys0, st0, s0 = runs[0]
+    ys2, st2, s2 = runs[1]
+    assert st0 == F.OK and st2 == F.OK
+    for a, b in zip(ys0, ys2):
         assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
-    assert s0 == s4
+    assert s0 == s2
+    ys4, st4, s4 = runs[2]
+    assert st4 == F.OK
+    for p, y, s in zip(probs, ys4, s4):
+        _check(p, y, s, np.float32)
 
 
 def test_batched_statuses():

@@ -162,13 +162,19 @@ def test_deterministic_bitwise():
     assert r1.stats == r2.stats
 
 
-@pytest.mark.parametrize("dt", [np.float64, np.float32])
-def test_fixed_rounds_masks_match_oracle(dt):
+@pytest.mark.parametrize("dt,shape,mode", [(np.float64, (16, 16, 64), 1), (np.float32, (16, 16, 64), 1),
+                                           (np.float32, (8, 8, 512), 4)])
+def test_fixed_rounds_masks_match_oracle(dt, shape, mode):
     """Clip keep-masks equal the oracle's; in FP32 a bit may differ only where the
-    oracle's pre-clip value lies within FP32 noise (1e-5 relative) of its bound."""
-    p = _problem((16, 16, 64), 21, dt, q=85.0, r=5e-2)
+    oracle's pre-clip value lies within FP32 noise (1e-5 relative) of its bound.  Mode 4
+    runs the direct last-axis loop pass (256-entry rows)."""
+    p = _problem(shape, 21, dt, q=85.0, r=5e-2)
     K = 5
-    y, res = run_gpu(p.x, p.xb, p.E, p.Delta, K, fixed=True, record_masks=True)
+    try:
+        F.ffcz_set_tuning(mode)
+        y, res = run_gpu(p.x, p.xb, p.E, p.Delta, K, fixed=True, record_masks=True)
+    finally:
+        F.ffcz_set_tuning(1)
     assert res.stats["rounds"] == K
     mu = res.stats["margin_used"]
     orc = O.correct(p.x, p.xb, p.E, p.Delta, K, mu=mu, fixed=True, record_masks=True)
@@ -297,13 +303,17 @@ def test_tile_variants_bit_identical(dt, shape):
         assert np.array_equal(m0, m1)
 
 
-@pytest.mark.parametrize("dt,shape", [(np.float32, (32, 64, 256)), (np.float64, (16, 32, 512)),
-                                      (np.float32, (128, 1024)), (np.float64, (64, 128))])
-def test_radix8_last_axis_plan_matches_oracle(dt, shape):
-    # the radix-8 last-axis plan rounds differently from radix 16 but meets the same bars
+@pytest.mark.parametrize("mode,dt,shape", [(3, np.float32, (32, 64, 256)), (3, np.float64, (16, 32, 512)),
+                                           (3, np.float32, (128, 1024)), (3, np.float64, (64, 128)),
+                                           (4, np.float32, (16, 32, 512)), (4, np.float32, (2, 4, 512)),
+                                           (4, np.float32, (256, 512)), (4, np.float64, (16, 32, 512))])
+def test_rounding_plans_match_oracle(mode, dt, shape):
+    # the radix-8 last-axis plan (mode 3) and the direct last-axis loop pass (mode 4, FP32 rows
+    # of 256 entries; FP64 runs the narrow tiles) round differently from the default plan but
+    # meet the same bars
     p = _problem(shape, 77, dt)
     try:
-        F.ffcz_set_tuning(3)
+        F.ffcz_set_tuning(mode)
         y, res = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter, record_viol=True)
     finally:
         F.ffcz_set_tuning(1)
@@ -323,7 +333,7 @@ def test_tuning_cache_file_roundtrip(tmp_path):
         y0, r0 = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter)
         doc = json.loads(path.read_text())
         keys = list(doc["entries"])
-        nvar = {"y": 2, "x": 2, "z": 3}
+        nvar = {"y": 2, "x": 2, "z": 4}
         assert len(keys) == 3 and all(len(doc["entries"][k]["ms"]) == nvar[k.split()[2]] for k in keys), doc
         assert {k.split()[2] for k in keys} == {"y", "x", "z"}
         # a fresh table read back from the file takes the same decisions without timing
@@ -331,7 +341,7 @@ def test_tuning_cache_file_roundtrip(tmp_path):
         assert F.ffcz_set_tuning(1, str(path)) == F.OK
         y1, r1 = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter)
         assert np.array_equal(y0.view(np.uint8), y1.view(np.uint8))
-        assert F.ffcz_set_tuning(4) == F.E_INVALID
+        assert F.ffcz_set_tuning(5) == F.E_INVALID
     finally:
         F.ffcz_set_tuning(1, "")
         F.ffcz_clear_tuning()
