@@ -237,6 +237,10 @@ int ceil_lg(int64_t v) {
 constexpr int kVerifyRowPlan = 2;
 
 // Choose the loop passes' tile variants and the per-instance block counts that follow.
+// Plan of the init and closing last-axis passes: the direct form (variant 3) when the
+// loop pass runs it on 256-entry FP32 rows, else the default tiles.
+int init_variant(const Plan& p) { return (p.vz == 3 && p.dt == FFCZ_F32 && p.H == 256) ? 3 : 0; }
+
 void set_variants(Plan& p, int vy, int vx, int vz) {
   p.vy = vy;
   p.vx = vx;
@@ -245,7 +249,7 @@ void set_variants(Plan& p, int vy, int vx, int vz) {
   const int Cx = col_block_cols(p.dt, p.Lx, vx), Cx64 = col_block_cols(1, p.Lx, 0);
   const int Rz = row_block_rows(p.dt, p.H, vz), Rz64 = row_block_rows(1, p.H, kVerifyRowPlan);
   p.zbpi = (p.nrows + Rz - 1) / Rz;
-  const int Ri = row_block_rows(p.dt, p.H, 0);
+  const int Ri = row_block_rows(p.dt, p.H, init_variant(p));
   p.ibpi = (p.nrows + Ri - 1) / Ri;
   p.vzbpi = (p.nrows + Rz64 - 1) / Rz64;
   p.xbpi = outer_x * ((p.ncols + Cx - 1) / Cx);
@@ -748,7 +752,7 @@ hipError_t run_row(int tdt, int iodt, int mode, int v, const Plan& p, int64_t pi
 template <typename T>
 hipError_t row_T(int mode, const Ctx& c, const void* src, void* dst, uint32_t* smask) {
   const Plan& p = *c.p;
-  const int v = mode == ROW_LOOP ? p.vz : 0;
+  const int v = mode == ROW_LOOP ? p.vz : ((mode == ROW_INIT || mode == ROW_FINAL) ? init_variant(p) : 0);
   const void* tw = (const char*)c.twT() + sizeof(cx<T>) * (v == 2 ? p.twz8 : p.twz);
   return run_row<T, T>(p.dt, p.dt, mode, v, p, p.pitch, p.plane, src, dst, tw, c.st(), c.part(Ctx::PZ), smask, c.s);
 }

@@ -493,20 +493,21 @@ __device__ __forceinline__ cx<float> row16_partner(cx<float> z) {
   return cx<float>{row16_partner(z.re), row16_partner(z.im)};
 }
 
-// The loop's last-axis pass (ROW_LOOP) for FP32 rows of 256 entries, with lanes
-// index-fastest: the 16 lanes of a row are one DPP row, lane j keeps entries
-// j + 16q.  Spectrum entries move straight between HBM and registers (16 lanes
-// cover 128 contiguous bytes of a row per access), the C2R and R2C partners
-// k <-> H - k come from lane (16 - j) mod 16 by DPP, and LDS carries only the
-// transform's own exchange: the 16 x 16 transpose of a row, with entry i at
-// i + (i >> 4) and rows 272 entries apart, so a wave's four rows fill every
-// 8-byte slot exactly twice on the write and on the read.  row_kernel stages
-// the whole tile through LDS on the way in and out; this pass moves about 40 %
-// less LDS data.  Same transform engine and formulas as row_kernel's ROW_LOOP;
-// the compiler fuses multiply-adds differently in the two kernels, so results
-// can differ in the last bit (a plan that rounds differently, like radix 8).
-template <int ROWS>
-__global__ void __launch_bounds__(ROWS * 16, 4) row_loop_direct_kernel(RowArgs<float, float> a) {
+// Last-axis passes for FP32 rows of 256 entries with lanes index-fastest: the 16
+// lanes of a row are one DPP row, lane j keeps entries j + 16q.  Spectrum entries
+// (and the real pairs r[2m], r[2m+1] of the fields) move straight between HBM and
+// registers (16 lanes cover 128 contiguous bytes of a row per access), the C2R and
+// R2C partners k <-> H - k come from lane (16 - j) mod 16 by DPP, and LDS carries
+// only the transform's own exchange: the 16 x 16 transpose of a row, with entry i
+// at i + (i >> 4) and rows 272 entries apart, so a wave's four rows fill every
+// 8-byte slot exactly twice on the write and on the read.  row_kernel stages the
+// whole tile through LDS on the way in and out; the loop pass moves about 40 %
+// less LDS data this way.  Modes ROW_INIT, ROW_LOOP and ROW_FINAL, with
+// row_kernel's formulas; the compiler fuses multiply-adds differently in the two
+// kernels, so results can differ in the last bit (a plan that rounds differently,
+// like radix 8).
+template <int MODE, int ROWS>
+__global__ void __launch_bounds__(ROWS * 16, 4) row_direct_kernel(RowArgs<float, float> a) {
   using T = float;
   constexpr int H = 256, E = 16, P = 16;
   constexpr int NT = ROWS * P;
@@ -516,18 +517,22 @@ __global__ void __launch_bounds__(ROWS * 16, 4) row_loop_direct_kernel(RowArgs<f
   constexpr int TW = S::twsize;
   constexpr int NW = (NT + 63) / 64;
   constexpr int SW = 2 * (H / 32);
+  constexpr bool rec_s = (MODE == ROW_INIT || MODE == ROW_LOOP);
+  static_assert(MODE == ROW_INIT || MODE == ROW_LOOP || MODE == ROW_FINAL, "init, loop or final");
   static_assert(S::nst == 2 && (H - 1) + ((H - 1) >> SKW) < LP, "one 16 x 16 exchange per transform");
 
   __shared__ cx<T> lds[ROWS * LP];
   __shared__ cx<T> tws[TW + H];
   __shared__ unsigned long long red_u[NW];
-  __shared__ uint32_t sbits[ROWS * SW];
+  __shared__ uint32_t sbits[rec_s ? ROWS * SW : 1];
 
   const int64_t inst = (int64_t)blockIdx.x / a.bpi;
   const int64_t lrow0 = ((int64_t)blockIdx.x - inst * a.bpi) * ROWS;
   const int64_t row0 = inst * a.rows_per_inst + lrow0;
   DevState* st = a.st + inst;
-  if (*(volatile int32_t*)&st->done) return;
+  if constexpr (MODE == ROW_LOOP) {
+    if (*(volatile int32_t*)&st->done) return;
+  }
   auto rowaddr = [&](int64_t R) -> int64_t {
     return (R >> a.lg_rpp) * a.plane + (R & ((int64_t(1) << a.lg_rpp) - 1)) * a.pitch;
   };
@@ -537,91 +542,166 @@ __global__ void __launch_bounds__(ROWS * 16, 4) row_loop_direct_kernel(RowArgs<f
   const int nrow = (int)((a.rows_per_inst - lrow0) < ROWS ? (a.rows_per_inst - lrow0) : ROWS);
   const bool valid = rl < nrow;
   const cx<T>* rtw = tws + TW;
+  const int64_t g0 = (lrow0 + rl) * H;  // first real pair of the row in the fields
 
   for (int i = t; i < TW + H; i += NT) tws[i] = a.tw[i];
-  const int kround = *(volatile int32_t*)&st->round;
-  const bool rec = st->record_masks != 0;
-  if (rec)
-    for (int i = t; i < ROWS * SW; i += NT) sbits[i] = 0u;
-
-  // entries j + 16q of the row, and the Nyquist entry for lane 0
-  cx<T> x[E];
-  cx<T> nyq{T(0), T(0)};
-  const int64_t rbase = valid ? rowaddr(row0 + rl) : 0;
-#pragma unroll
-  for (int q = 0; q < E; ++q) x[q] = valid ? a.src[rbase + j + q * P] : cx<T>{T(0), T(0)};
-  if (valid && j == 0) nyq = a.src[rbase + H];
-  __syncthreads();  // twiddles (and cleared mask words) visible
-
-  // C2R: Z'[k] = (X[k] + X[H-k]*) + i W^-k (X[k] - X[H-k]*)
-  cx<T> v[E];
-#pragma unroll
-  for (int q = 0; q < E; ++q) {
-    const int k = j + q * P;
-    cx<T> A = x[q];
-    const cx<T> Bp = row16_partner(x[E - 1 - q]);
-    const cx<T> own = (q == 0) ? nyq : x[(E - q) & (E - 1)];
-    cx<T> B = (j == 0) ? own : Bp;
-    if (k == 0) {
-      A.im = T(0);
-      B.im = T(0);
-    }
-    const cx<T> sm = A + conjg(B);
-    const cx<T> df = cmulc(A - conjg(B), rtw[k]);
-    v[q] = cx<T>{sm.re - df.im, sm.im + df.re};
+  int kround = 0;
+  bool rec = false;
+  if constexpr (rec_s) {
+    if (MODE == ROW_LOOP) kround = *(volatile int32_t*)&st->round;
+    rec = st->record_masks != 0;
+    if (rec)
+      for (int i = t; i < ROWS * SW; i += NT) sbits[i] = 0u;
   }
-  fft<T, H, E, true, 1, LP, SKW>(v, lds, tws, rl, j);
   unsigned long long cnt = 0;
-  {
-    const T sc = (T)st->inv_n;
-    const T Ep = to_t<T>(st->Ep);
+  cx<T> v[E];
+  const int64_t rbase = valid ? rowaddr(row0 + rl) : 0;
+
+  if constexpr (MODE == ROW_INIT) {
+    // eps0 = x_hat - x in FP64 for the real pairs m = j + 16q, guard clip (+ s-mask)
+    const float2* x2 = reinterpret_cast<const float2*>(st->px);
+    const float2* b2 = reinterpret_cast<const float2*>(st->pxb);
+    const double Ep = st->Ep;
+    __syncthreads();  // cleared mask words visible
+    // two batches of 8 pairs per field (all 16 of both fields do not fit the registers
+    // next to the FP64 arithmetic)
+    constexpr int BQ = 8;
+    float2 xa[BQ], xb[BQ];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      if (q % BQ == 0) {
+#pragma unroll
+        for (int u = 0; u < BQ; ++u) {
+          xa[u] = make_float2(0.f, 0.f);
+          xb[u] = make_float2(0.f, 0.f);
+          if (valid) {
+            xa[u] = x2[g0 + j + (q + u) * P];
+            xb[u] = b2[g0 + j + (q + u) * P];
+          }
+        }
+      }
+      const int m = j + q * P;
+      const int u = q % BQ;
+      double e0 = (double)xb[u].x - (double)xa[u].x, e1 = (double)xb[u].y - (double)xa[u].y;
+      if (valid) {
+        const bool f0 = isfinite(e0), f1 = isfinite(e1);
+        if (!f0 || !f1) {
+          atomicAdd(&st->nonfinite, (unsigned long long)((!f0) + (!f1)));
+          e0 = f0 ? e0 : 0.0;
+          e1 = f1 ? e1 : 0.0;
+        }
+        const bool k0 = fabs(e0) <= Ep, k1 = fabs(e1) <= Ep;
+        cnt += (!k0) + (!k1);
+        e0 = clipv(e0, Ep);
+        e1 = clipv(e1, Ep);
+        if (rec) atomicOr(&sbits[rl * SW + (2 * m) / 32], ((uint32_t)k0 | ((uint32_t)k1 << 1)) << ((2 * m) & 31));
+      } else {
+        e0 = 0.0;
+        e1 = 0.0;
+      }
+      v[q] = cx<T>{(T)e0, (T)e1};
+    }
+  } else {
+    // spectrum entries j + 16q of the row, and the Nyquist entry for lane 0
+    cx<T> x[E];
+    cx<T> nyq{T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < E; ++q) x[q] = valid ? a.src[rbase + j + q * P] : cx<T>{T(0), T(0)};
+    if (valid && j == 0) nyq = a.src[rbase + H];
+    __syncthreads();  // twiddles (and cleared mask words) visible
+    // C2R: Z'[k] = (X[k] + X[H-k]*) + i W^-k (X[k] - X[H-k]*)
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const int k = j + q * P;
-      T e0 = v[q].re * sc, e1 = v[q].im * sc;
-      const bool k0 = fabs(e0) <= Ep, k1 = fabs(e1) <= Ep;
-      if (valid) cnt += (!k0) + (!k1);
-      e0 = clipv(e0, Ep);
-      e1 = clipv(e1, Ep);
-      v[q] = cx<T>{e0, e1};
-      if (rec && valid)
-        atomicOr(&sbits[rl * SW + (2 * k) / 32], ((uint32_t)k0 | ((uint32_t)k1 << 1)) << ((2 * k) & 31));
+      cx<T> A = x[q];
+      const cx<T> Bp = row16_partner(x[E - 1 - q]);
+      const cx<T> own = (q == 0) ? nyq : x[(E - q) & (E - 1)];
+      cx<T> B = (j == 0) ? own : Bp;
+      if (k == 0) {
+        A.im = T(0);
+        B.im = T(0);
+      }
+      const cx<T> sm = A + conjg(B);
+      const cx<T> df = cmulc(A - conjg(B), rtw[k]);
+      v[q] = cx<T>{sm.re - df.im, sm.im + df.re};
+    }
+    fft<T, H, E, true, 1, LP, SKW>(v, lds, tws, rl, j);
+    if constexpr (MODE == ROW_LOOP) {
+      // 1/N, ProjectOntoSCube (+ s-mask)
+      const T sc = (T)st->inv_n;
+      const T Ep = to_t<T>(st->Ep);
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int k = j + q * P;
+        T e0 = v[q].re * sc, e1 = v[q].im * sc;
+        const bool k0 = fabs(e0) <= Ep, k1 = fabs(e1) <= Ep;
+        if (valid) cnt += (!k0) + (!k1);
+        e0 = clipv(e0, Ep);
+        e1 = clipv(e1, Ep);
+        v[q] = cx<T>{e0, e1};
+        if (rec && valid)
+          atomicOr(&sbits[rl * SW + (2 * k) / 32], ((uint32_t)k0 | ((uint32_t)k1 << 1)) << ((2 * k) & 31));
+      }
+    } else {
+      // the source holds only the last-axis R2C of eps, so the C2R scale is 1/n_last
+      const T scz = T(1) / T(2 * H);
+#pragma unroll
+      for (int q = 0; q < E; ++q) v[q] = scal(v[q], scz);
     }
   }
-  fft<T, H, E, false, 1, LP, SKW>(v, lds, tws, rl, j);
 
-  // R2C: X[k] = (Z[k] + Z[H-k]*)/2 - i W^k (Z[k] - Z[H-k]*)/2, X[H] = Re Z0 - Im Z0
-  cx<T>* dst = a.dst + rbase;
+  if constexpr (MODE == ROW_FINAL) {
+    // y = x + eps formed in FP64, rounded once, clamped (closing clamp)
+    const float2* x2 = reinterpret_cast<const float2*>(st->px);
+    float2* y2 = reinterpret_cast<float2*>(st->py);
+    const double Eb = st->E;
+    // all loads of x first: the clamp's loop between them would otherwise serialise them
+    float2 xv[E];
 #pragma unroll
-  for (int q = 0; q < E; ++q) {
-    const int k = j + q * P;
-    const cx<T> Zk = v[q];
-    const cx<T> Zp = row16_partner(v[E - 1 - q]);
-    const cx<T> own = v[(E - q) & (E - 1)];  // lane 0: Z[H - 16q], Z[0] for q = 0
-    const cx<T> Zm = (j == 0) ? own : Zp;
-    const cx<T> ev = scal(Zk + conjg(Zm), T(0.5));
-    const cx<T> d = Zk - conjg(Zm);
-    const cx<T> od = cx<T>{d.im * T(0.5), -d.re * T(0.5)};
-    const cx<T> X = ev + cmul(rtw[k], od);
-    if (valid) dst[k] = X;
-  }
-  // entry H and the row's first padding entry (zero) as one 16-byte store
-  if (valid && j == 0) *reinterpret_cast<float4*>(dst + H) = make_float4(v[0].re - v[0].im, 0.f, 0.f, 0.f);
+    for (int q = 0; q < E; ++q) xv[q] = valid ? x2[g0 + j + q * P] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      if (valid)
+        y2[g0 + j + q * P] =
+            make_float2(closing_clamp<float>(round_io<float>((double)xv[q].x + (double)v[q].re), xv[q].x, Eb),
+                        closing_clamp<float>(round_io<float>((double)xv[q].y + (double)v[q].im), xv[q].y, Eb));
+    }
+  } else {
+    fft<T, H, E, false, 1, LP, SKW>(v, lds, tws, rl, j);
+    // R2C: X[k] = (Z[k] + Z[H-k]*)/2 - i W^k (Z[k] - Z[H-k]*)/2, X[H] = Re Z0 - Im Z0
+    cx<T>* dst = a.dst + rbase;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int k = j + q * P;
+      const cx<T> Zk = v[q];
+      const cx<T> Zp = row16_partner(v[E - 1 - q]);
+      const cx<T> own = v[(E - q) & (E - 1)];  // lane 0: Z[H - 16q], Z[0] for q = 0
+      const cx<T> Zm = (j == 0) ? own : Zp;
+      const cx<T> ev = scal(Zk + conjg(Zm), T(0.5));
+      const cx<T> d = Zk - conjg(Zm);
+      const cx<T> od = cx<T>{d.im * T(0.5), -d.re * T(0.5)};
+      const cx<T> X = ev + cmul(rtw[k], od);
+      if (valid) dst[k] = X;
+    }
+    // entry H and the row's first padding entry (zero) as one 16-byte store
+    if (valid && j == 0) *reinterpret_cast<float4*>(dst + H) = make_float4(v[0].re - v[0].im, 0.f, 0.f, 0.f);
 
-  cnt = wave_sum_u64(cnt);
-  if ((t & 63) == 0) red_u[t >> 6] = cnt;
-  __syncthreads();
-  if (t == 0) {
-    unsigned long long s = 0;
-    for (int w = 0; w < NW; ++w) s += red_u[w];
-    a.part[blockIdx.x] = s;
-  }
-  if (rec) {
-    uint32_t* plane = a.smask + (int64_t)kround * a.s_plane;
-    for (int i = t; i < ROWS * SW; i += NT) {
-      const int r = i / SW;
-      const int w = i - r * SW;
-      if (r < nrow && w < a.s_row_w32) plane[(row0 + r) * a.s_row_w32 + w] = sbits[i];
+    // one partial per block (guard-clip or s-clip count), reduced by the control kernel
+    cnt = wave_sum_u64(cnt);
+    if ((t & 63) == 0) red_u[t >> 6] = cnt;
+    __syncthreads();
+    if (t == 0) {
+      unsigned long long s2 = 0;
+      for (int w = 0; w < NW; ++w) s2 += red_u[w];
+      a.part[blockIdx.x] = s2;
+    }
+    if (rec) {
+      uint32_t* plane = a.smask + (int64_t)kround * a.s_plane;
+      for (int i = t; i < ROWS * SW; i += NT) {
+        const int r = i / SW;
+        const int w = i - r * SW;
+        if (r < nrow && w < a.s_row_w32) plane[(row0 + r) * a.s_row_w32 + w] = sbits[i];
+      }
     }
   }
 }

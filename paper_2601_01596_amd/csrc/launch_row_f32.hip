@@ -23,20 +23,24 @@ static hipError_t go(int H, const RowArgs<T, TIO>& a, int64_t nb, hipStream_t s)
   }
 }
 
+// The direct passes (lanes index-fastest) of 256-entry rows, 16 rows per block.
+template <int MODE>
+static hipError_t go_direct(const RowArgs<float, float>& a, int64_t nb, hipStream_t s) {
+  static_assert(tile_rows<float>(256, 3) == 16, "the direct passes run 16-row tiles");
+  hipLaunchKernelGGL((row_direct_kernel<MODE, 16>), dim3((unsigned)nb), dim3(16 * 16), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_row_f32(int mode, int H, int v, const void* args, int64_t nb, hipStream_t s) {
   const RowArgs<float, float>& a = *static_cast<const RowArgs<float, float>*>(args);
+  const bool direct = v == 3 && H == 256;
   switch (mode) {
-    case ROW_INIT: return go<float, float, ROW_INIT, 0>(H, a, nb, s);
+    case ROW_INIT: return direct ? go_direct<ROW_INIT>(a, nb, s) : go<float, float, ROW_INIT, 0>(H, a, nb, s);
     case ROW_LOOP:
-      if (v == 3) {
-        if (H != 256) return go<float, float, ROW_LOOP, 1>(H, a, nb, s);
-        static_assert(tile_rows<float>(256, 3) == 16, "the direct pass runs 16-row tiles");
-        hipLaunchKernelGGL((row_loop_direct_kernel<16>), dim3((unsigned)nb), dim3(16 * 16), 0, s, a);
-        return hipGetLastError();
-      }
+      if (v == 3) return direct ? go_direct<ROW_LOOP>(a, nb, s) : go<float, float, ROW_LOOP, 1>(H, a, nb, s);
       return v == 2 ? go<float, float, ROW_LOOP, 2>(H, a, nb, s)
                     : (v ? go<float, float, ROW_LOOP, 1>(H, a, nb, s) : go<float, float, ROW_LOOP, 0>(H, a, nb, s));
-    case ROW_FINAL: return go<float, float, ROW_FINAL, 0>(H, a, nb, s);
+    case ROW_FINAL: return direct ? go_direct<ROW_FINAL>(a, nb, s) : go<float, float, ROW_FINAL, 0>(H, a, nb, s);
     case ROW_BINIT: return go<float, float, ROW_BINIT, 0>(H, a, nb, s);
     case ROW_BLOOP: return go<float, float, ROW_BLOOP, 0>(H, a, nb, s);
     case ROW_BFINAL: return go<float, float, ROW_BFINAL, 0>(H, a, nb, s);

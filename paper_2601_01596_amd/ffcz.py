@@ -99,11 +99,20 @@ _lib = None
 
 
 def lib() -> ctypes.CDLL:
-    """Load ``libffcz.so`` (built by ``paper_2601_01596_amd.build``); raises if absent."""
+    """Load ``libffcz.so`` (built by ``paper_2601_01596_amd.build``); raises if absent.
+
+    torch ships its own HIP runtime under the same sonames as the system's.  It is
+    imported first, so the library's ``libamdhip64.so.7`` resolves to the runtime
+    torch already loaded: with the library loaded first, torch would bring in a
+    second runtime and the library's would see no device."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise FFCzError(E_HIP, f"{LIB_PATH} is missing: run python -m paper_2601_01596_amd.build")
+        try:
+            import torch  # noqa: F401
+        except ImportError:  # plain C-ABI use without torch: the system runtime
+            pass
         L = ctypes.CDLL(LIB_PATH)
         i64p = ctypes.POINTER(ctypes.c_int64)
         L.ffcz_version.restype = ctypes.c_int32

@@ -388,3 +388,27 @@ def test_device_margin_ragged_lengths_in_a_batch():
     for x, m, s in zip(xs, mem, stats):
         ref = O.suggest_margin(x, m[3])
         assert abs(s["margin_used"] - ref) <= 1e-12 * ref, (x.size, s["margin_used"], ref)
+
+
+def test_library_loaded_before_torch():
+    """A process that loads the library before it imports torch (the binding loads torch's
+    HIP runtime first, so there is one runtime in the process): one small correction in a
+    fresh interpreter, checked for status OK."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("from paper_2601_01596_amd import ffcz as F\n"
+            "F.ffcz_set_tuning(1)\n"
+            "import torch\n"
+            "g = torch.Generator(device='cpu').manual_seed(5)\n"
+            "x = torch.randn(8, 16, 32, dtype=torch.float64, generator=g).cuda()\n"
+            "xb = (x + 1e-3 * torch.randn(8, 16, 32, dtype=torch.float64, generator=g).cuda()).contiguous()\n"
+            "r = F.correct(x, xb, 2e-3, 0.05, 20, check=False)\n"
+            "print('status', r.status, F.ffcz_last_error(), flush=True)\n")
+    env = dict(os.environ, PYTHONPATH=root + os.pathsep + os.environ.get("PYTHONPATH", ""))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                         timeout=180)
+    lines = [ln for ln in out.stdout.splitlines() if ln.startswith("status")]
+    assert out.returncode == 0 and lines, (out.returncode, out.stdout[-2000:], out.stderr[-2000:])
+    assert lines[-1].split()[1] in (str(F.OK), str(F.NOT_CONVERGED)), lines[-1]
