@@ -113,16 +113,6 @@ __host__ __device__ constexpr int pick_C(int L) {
 // Elements per lane of the last-axis transforms (radix-16 stages from H = 64 on).
 __host__ __device__ constexpr int pick_E_row(int H) { return H >= 64 ? 16 : pick_E(H); }
 
-// Rows per block for the last-axis passes: up to 64 (one row per lane of a
-// wave at a time), at most 1024 lanes and about 72 KiB of LDS.
-template <typename T>
-__host__ __device__ constexpr int pick_rows(int H) {
-  const int P = H / pick_E_row(H) > 0 ? H / pick_E_row(H) : 1;
-  int r = 64;
-  while (r > 1 && (r * P > 1024 || (long)r * (H + 1) * (long)sizeof(cx<T>) > 72 * 1024)) r /= 2;
-  return r;
-}
-
 // LDS rows of the last-axis passes.  Lanes run rows-fastest (ROWS rows x 64/ROWS
 // indices per wave) and rows sit an odd pitch H + 1 apart, which keeps a wave's
 // accesses on distinct banks while a wave spans many rows.  With few rows per
@@ -135,20 +125,31 @@ __host__ __device__ constexpr int pick_rows(int H) {
 // times the unavoidable 2 (4) lanes per slot keep it: there the skew's index
 // arithmetic costs more than it saves (measured on the 256-entry rows).
 __host__ __device__ constexpr int row_lds_pad(int H, int R, int E, int S) {
+  if (H == 512 && R == 2 && E == 16 && S == 16) return 0;
   if (H == 512 && R == 4 && E == 16 && S == 16) return 6;
   if (H == 512 && R == 8 && E == 16 && S == 8) return 8;
+  if (H == 1024 && R == 1 && E == 16 && S == 16) return 0;
+  if (H == 1024 && R == 2 && E == 8 && S == 16) return 7;
+  if (H == 1024 && R == 2 && E == 16 && S == 8) return 15;
   if (H == 1024 && R == 2 && E == 16 && S == 16) return 0;
+  if (H == 1024 && R == 4 && E == 8 && S == 8) return 12;
   if (H == 1024 && R == 4 && E == 8 && S == 16) return 2;
   if (H == 1024 && R == 4 && E == 16 && S == 8) return 5;
   if (H == 1024 && R == 4 && E == 16 && S == 16) return 4;
   if (H == 1024 && R == 8 && E == 8 && S == 8) return 2;
   if (H == 1024 && R == 8 && E == 16 && S == 8) return 2;
+  if (H == 2048 && R == 1 && E == 16 && S == 8) return 0;
   if (H == 2048 && R == 1 && E == 16 && S == 16) return 0;
+  if (H == 2048 && R == 1 && E == 8 && S == 8) return 0;
+  if (H == 2048 && R == 1 && E == 8 && S == 16) return 0;
+  if (H == 2048 && R == 2 && E == 8 && S == 8) return 7;
   if (H == 2048 && R == 2 && E == 8 && S == 16) return 7;
   if (H == 2048 && R == 2 && E == 16 && S == 8) return 15;
   if (H == 2048 && R == 2 && E == 16 && S == 16) return 0;
   if (H == 2048 && R == 4 && E == 8 && S == 8) return 5;
+  if (H == 2048 && R == 4 && E == 8 && S == 16) return 2;
   if (H == 2048 && R == 4 && E == 16 && S == 8) return 5;
+  if (H == 2048 && R == 8 && E == 16 && S == 8) return 2;
   return -1;  // no skew: odd pitch
 }
 __host__ __device__ constexpr int row_lds_shift(int H, int R, int E, int S) {
@@ -160,6 +161,30 @@ __host__ __device__ constexpr int row_lds_pitch(int H, int R, int E) {
              ? H + (H >> 5) + 1 + row_lds_pad(H, R, E, (int)sizeof(cx<T>))
              : H + 1;
 }
+
+// LDS bytes of a last-axis block: its rows at their pitch, the stage and R2C
+// twiddle tables, per-wave partial words and the rows' mask words.
+template <typename T>
+__host__ __device__ constexpr long row_lds_bytes(int H, int R, int E) {
+  const long cs = (long)sizeof(cx<T>);
+  const int P = H / E > 0 ? H / E : 1;
+  const long nw = (R * P + 63) / 64;
+  const long sw = 2 * (H >= 32 ? H / 32 : 1);
+  return R * (long)row_lds_pitch<T>(H, R, E) * cs + (long)(host_twsize(H, E) + H) * cs + 16 * nw + 4 * R * sw;
+}
+// Rows per block of a last-axis plan with E elements per lane: up to 64 (one row
+// per lane of a wave at a time), at most 1024 lanes, and at most 78 KiB of LDS,
+// so that two blocks share a CU (the twiddle tables alone take 16 KiB at 1024
+// FP32 entries; counting only the rows left one block per CU there).
+template <typename T>
+__host__ __device__ constexpr int rows_for_E(int H, int E) {
+  const int P = H / E > 0 ? H / E : 1;
+  int r = 64;
+  while (r > 1 && (r * P > 1024 || row_lds_bytes<T>(H, r, E) > 78 * 1024)) r /= 2;
+  return r;
+}
+template <typename T>
+__host__ __device__ constexpr int pick_rows(int H) { return rows_for_E<T>(H, pick_E_row(H)); }
 
 // Plans the tuner chooses between.  Column passes: variant 1 halves the tile
 // width.  Last-axis passes: variant 1 halves the rows per block; variant 2
@@ -177,13 +202,7 @@ __host__ __device__ constexpr int tile_cols(int L, int v) {
 }
 // Elements per lane of a last-axis plan.
 __host__ __device__ constexpr int row_E(int H, int v) { return (v == 2 && pick_E_row(H) == 16) ? 8 : pick_E_row(H); }
-template <typename T>
-__host__ __device__ constexpr int rows_for_E(int H, int E) {
-  const int P = H / E > 0 ? H / E : 1;
-  int r = 64;
-  while (r > 1 && (r * P > 1024 || (long)r * (H + 1) * (long)sizeof(cx<T>) > 72 * 1024)) r /= 2;
-  return r;
-}
+
 template <typename T>
 __host__ __device__ constexpr int tile_rows(int H, int v) {
   if (v == 2) return rows_for_E<T>(H, row_E(H, 2));

@@ -156,7 +156,7 @@ struct Sched {
 // fixes at compile time): an optional radix-r0 stage at span 1, then radix-E stages
 // at spans r0 E^t; a stage of span ns > 1 owns ns (radix - 1) entries, in stage
 // order (the span-1 stage owns none).
-__host__ __device__ inline int host_twsize(int L, int E) {
+__host__ __device__ constexpr int host_twsize(int L, int E) {
   if (E <= 1 || L <= 1) return 0;
   const int lgE = ilog2c(E), a = ilog2c(L) / lgE;
   const int r0 = L >> (a * lgE);
