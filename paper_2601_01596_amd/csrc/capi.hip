@@ -237,9 +237,11 @@ int ceil_lg(int64_t v) {
 constexpr int kVerifyRowPlan = 2;
 
 // Choose the loop passes' tile variants and the per-instance block counts that follow.
-// Plan of the init and closing last-axis passes: the direct form (variant 3) when the
-// loop pass runs it on 256-entry FP32 rows, else the default tiles.
-int init_variant(const Plan& p) { return (p.vz == 3 && p.dt == FFCZ_F32 && p.H == 256) ? 3 : 0; }
+// Plan of the init, closing and adjoint last-axis passes: the direct form (variant 3)
+// when the loop pass runs it on 128- or 256-entry FP32 rows, else the default tiles.
+int init_variant(const Plan& p) {
+  return (p.vz == 3 && p.dt == FFCZ_F32 && (p.H == 128 || p.H == 256)) ? 3 : 0;
+}
 
 void set_variants(Plan& p, int vy, int vx, int vz) {
   p.vy = vy;
@@ -752,7 +754,7 @@ hipError_t run_row(int tdt, int iodt, int mode, int v, const Plan& p, int64_t pi
 template <typename T>
 hipError_t row_T(int mode, const Ctx& c, const void* src, void* dst, uint32_t* smask) {
   const Plan& p = *c.p;
-  const int v = mode == ROW_LOOP ? p.vz : ((mode == ROW_INIT || mode == ROW_FINAL) ? init_variant(p) : 0);
+  const int v = mode == ROW_LOOP ? p.vz : init_variant(p);
   const void* tw = (const char*)c.twT() + sizeof(cx<T>) * (v == 2 ? p.twz8 : p.twz);
   return run_row<T, T>(p.dt, p.dt, mode, v, p, p.pitch, p.plane, src, dst, tw, c.st(), c.part(Ctx::PZ), smask, c.s);
 }
@@ -1062,6 +1064,14 @@ constexpr float kColKeep = 0.90f;
 // stream is being captured or masks are recorded (the loop kernels would write
 // mask planes); mask recording also keeps the default x-pass tiles, whose
 // width the 1-bit mask words assume.
+// Table key of a plan's last-axis loop pass.
+std::string tune_key_z(const Plan& p) {
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%s z H=%d rows=%lld", (device_arch() + (p.dt == FFCZ_F32 ? " f32" : " f64")).c_str(), p.H,
+           (long long)(p.nrows * p.B));
+  return buf;
+}
+
 template <typename T>
 int32_t tune_plan(Plan& p, char* ws, hipStream_t s, bool rec) {
   const std::string pre = device_arch() + (p.dt == FFCZ_F32 ? " f32" : " f64");
@@ -1093,8 +1103,7 @@ int32_t tune_plan(Plan& p, char* ws, hipStream_t s, bool rec) {
     if (r != FFCZ_OK) return r;
   }
   if (p.H >= 64) {
-    snprintf(buf, sizeof(buf), "%s z H=%d rows=%lld", pre.c_str(), p.H, (long long)(p.nrows * p.B));
-    int32_t r = tune_pass(buf, s, may_time, 0.98f, kRowVariants, [&](int v) {
+    int32_t r = tune_pass(tune_key_z(p), s, may_time, 0.98f, kRowVariants, [&](int v) {
       return run_row<T, T>(p.dt, p.dt, ROW_LOOP, v, p, p.pitch, p.plane, c.A(), c.A(),
                            twb + sizeof(cx<T>) * (v == 2 ? p.twz8 : p.twz), c.st(),
                            c.part(Ctx::PZ), nullptr, s);
@@ -2215,6 +2224,14 @@ int32_t ffcz_correct_backward(int32_t dtype, int32_t ndim, const int64_t* shape,
   if (!ws || ws_bytes < p.bytes) return fail(FFCZ_E_WORKSPACE, "workspace smaller than ffcz_workspace_bytes()");
   if ((uintptr_t)ws & 255) return fail(FFCZ_E_WORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;
+  // the last-axis plan the table holds for this geometry (no timing here): the adjoint's
+  // last-axis passes take the direct form where the forward loop pass does
+  if (p.H >= 64) {
+    int vz = 0;
+    r = tune_pass(tune_key_z(p), s, false, 0.98f, kRowVariants, [](int) { return hipSuccess; }, &vz);
+    if (r != FFCZ_OK) return r;
+    set_variants(p, 0, 0, vz);
+  }
   if (dtype == FFCZ_F32) return backward_impl<float>(p, rounds, masks, gy, gb, ws, s);
   return backward_impl<double>(p, rounds, masks, gy, gb, ws, s);
 }

@@ -482,49 +482,70 @@ row_kernel(RowArgs<T, TIO> a) {
 
 namespace ffcz {
 
-// Lane (16 - j) mod 16 of the lane's row of 16 lanes (j = lane mod 16, j >= 1):
-// DPP row_mirror (lane i <- 15 - i), then row_shr:1 (lane i <- i - 1).  Lane 0 of
-// the row receives 0; callers take its partner from its own registers.
-__device__ __forceinline__ float row16_partner(float x) {
-  const int m = __builtin_amdgcn_mov_dpp(__float_as_int(x), 0x140, 0xF, 0xF, false);
+// Lane (P - j) mod P of the lane's group of P = 16 or 8 lanes (j = lane mod P,
+// j >= 1): DPP row_mirror (lane i <- 15 - i within a row of 16) or row_half_mirror
+// (lane i <- 7 - i within each half-row of 8), then row_shr:1 (lane i <- i - 1).
+// Lane 0 of each group receives another group's value or 0; callers take its
+// partner from its own registers.
+template <int P>
+__device__ __forceinline__ float group_partner(float x) {
+  static_assert(P == 16 || P == 8, "a row or half-row of DPP lanes");
+  const int m = __builtin_amdgcn_mov_dpp(__float_as_int(x), P == 16 ? 0x140 : 0x141, 0xF, 0xF, false);
   return __int_as_float(__builtin_amdgcn_mov_dpp(m, 0x111, 0xF, 0xF, true));
 }
-__device__ __forceinline__ cx<float> row16_partner(cx<float> z) {
-  return cx<float>{row16_partner(z.re), row16_partner(z.im)};
+template <int P>
+__device__ __forceinline__ cx<float> group_partner(cx<float> z) {
+  return cx<float>{group_partner<P>(z.re), group_partner<P>(z.im)};
 }
 
-// Last-axis passes for FP32 rows of 256 entries with lanes index-fastest: the 16
-// lanes of a row are one DPP row, lane j keeps entries j + 16q.  Spectrum entries
-// (and the real pairs r[2m], r[2m+1] of the fields) move straight between HBM and
-// registers (16 lanes cover 128 contiguous bytes of a row per access), the C2R and
-// R2C partners k <-> H - k come from lane (16 - j) mod 16 by DPP, and LDS carries
-// only the transform's own exchange: the 16 x 16 transpose of a row, with entry i
-// at i + (i >> 4) and rows 272 entries apart, so a wave's four rows fill every
-// 8-byte slot exactly twice on the write and on the read.  row_kernel stages the
-// whole tile through LDS on the way in and out; the loop pass moves about 40 %
-// less LDS data this way.  Modes ROW_INIT, ROW_LOOP and ROW_FINAL, with
-// row_kernel's formulas; the compiler fuses multiply-adds differently in the two
-// kernels, so results can differ in the last bit (a plan that rounds differently,
-// like radix 8).
-template <int MODE, int ROWS>
-__global__ void __launch_bounds__(ROWS * 16, 4) row_direct_kernel(RowArgs<float, float> a) {
+// Row pitch (entries) of the direct passes: H entries skewed as i + (i >> log2 P),
+// rounded up to = P mod 32 8-byte slots, so the 64 / P rows of a wave fill every
+// slot exactly twice in the transform's exchange (write: entry P r + ..., read:
+// entry j + P q).
+__host__ __device__ constexpr int direct_lds_pitch(int H) {
+  const int P = H / 16;
+  const int need = (H - 1) + ((H - 1) >> ilog2c(P)) + 1;
+  int lp = need;
+  while (lp % 32 != P % 32) ++lp;
+  return lp;
+}
+
+// Last-axis passes for FP32 rows of H = 128 or 256 entries with lanes
+// index-fastest: the P = H / 16 lanes of a row are one DPP group, lane j keeps
+// entries j + P q (q < 16).  Spectrum entries (and the real pairs r[2m], r[2m+1]
+// of the fields) move straight between HBM and registers (P lanes cover 8 P
+// contiguous bytes of a row per access), the C2R and R2C partners k <-> H - k come
+// from lane (P - j) mod P by DPP, and LDS carries only the transform's own
+// exchange, with entry i at i + (i >> log2 P) and rows direct_lds_pitch(H) apart
+// (every 8-byte slot taken exactly twice per wave access).  row_kernel stages the
+// whole tile through LDS on the way in and out; the loop pass moves about 40 % less
+// LDS data this way.  Modes: ROW_INIT, ROW_LOOP, ROW_FINAL and the adjoint's
+// ROW_BINIT, ROW_BLOOP, ROW_BFINAL, with row_kernel's formulas; the compiler fuses
+// multiply-adds differently in the two kernels, so results can differ in the last
+// bit (a plan that rounds differently, like radix 8).
+template <int MODE, int H, int ROWS>
+__global__ void __launch_bounds__(ROWS * (H / 16), 4) row_direct_kernel(RowArgs<float, float> a) {
   using T = float;
-  constexpr int H = 256, E = 16, P = 16;
+  constexpr int E = 16, P = H / E;
   constexpr int NT = ROWS * P;
-  constexpr int SKW = 4;
-  constexpr int LP = 272;  // 271 skewed entries, = 16 mod 32 slots
+  constexpr int SKW = ilog2c(P);
+  constexpr int LP = direct_lds_pitch(H);
   using S = Sched<H, E>;
   constexpr int TW = S::twsize;
   constexpr int NW = (NT + 63) / 64;
   constexpr int SW = 2 * (H / 32);
   constexpr bool rec_s = (MODE == ROW_INIT || MODE == ROW_LOOP);
-  static_assert(MODE == ROW_INIT || MODE == ROW_LOOP || MODE == ROW_FINAL, "init, loop or final");
-  static_assert(S::nst == 2 && (H - 1) + ((H - 1) >> SKW) < LP, "one 16 x 16 exchange per transform");
+  constexpr bool use_s = (MODE == ROW_BINIT || MODE == ROW_BLOOP || MODE == ROW_BFINAL);
+  constexpr bool spec_in = (MODE == ROW_LOOP || MODE == ROW_FINAL || MODE == ROW_BLOOP || MODE == ROW_BFINAL);
+  constexpr bool spec_out = (MODE == ROW_INIT || MODE == ROW_LOOP || MODE == ROW_BINIT || MODE == ROW_BLOOP);
+  static_assert(H == 128 || H == 256, "rows of 128 or 256 entries");
+  static_assert(MODE != ROW_VERIFY, "the verification runs in FP64");
+  static_assert(S::nst == 2, "one exchange per transform");
 
   __shared__ cx<T> lds[ROWS * LP];
   __shared__ cx<T> tws[TW + H];
   __shared__ unsigned long long red_u[NW];
-  __shared__ uint32_t sbits[rec_s ? ROWS * SW : 1];
+  __shared__ uint32_t sbits[(rec_s || use_s) ? ROWS * SW : 1];
 
   const int64_t inst = (int64_t)blockIdx.x / a.bpi;
   const int64_t lrow0 = ((int64_t)blockIdx.x - inst * a.bpi) * ROWS;
@@ -543,6 +564,8 @@ __global__ void __launch_bounds__(ROWS * 16, 4) row_direct_kernel(RowArgs<float,
   const bool valid = rl < nrow;
   const cx<T>* rtw = tws + TW;
   const int64_t g0 = (lrow0 + rl) * H;  // first real pair of the row in the fields
+  // s-mask bits 2m, 2m+1 of this row (real pair m)
+  auto sbit = [&](int m, int b) -> bool { return (sbits[rl * SW + (2 * m) / 32] >> (((2 * m) & 31) + b)) & 1u; };
 
   for (int i = t; i < TW + H; i += NT) tws[i] = a.tw[i];
   int kround = 0;
@@ -553,12 +576,19 @@ __global__ void __launch_bounds__(ROWS * 16, 4) row_direct_kernel(RowArgs<float,
     if (rec)
       for (int i = t; i < ROWS * SW; i += NT) sbits[i] = 0u;
   }
+  if constexpr (use_s) {
+    // the rows' mask words, coalesced
+    for (int i = t; i < ROWS * SW; i += NT) {
+      const int r = i / SW, w = i - r * SW;
+      sbits[i] = (r < nrow && w < a.s_row_w32) ? a.smask[(row0 + r) * a.s_row_w32 + w] : 0u;
+    }
+  }
   unsigned long long cnt = 0;
   cx<T> v[E];
   const int64_t rbase = valid ? rowaddr(row0 + rl) : 0;
 
   if constexpr (MODE == ROW_INIT) {
-    // eps0 = x_hat - x in FP64 for the real pairs m = j + 16q, guard clip (+ s-mask)
+    // eps0 = x_hat - x in FP64 for the real pairs m = j + P q, guard clip (+ s-mask)
     const float2* x2 = reinterpret_cast<const float2*>(st->px);
     const float2* b2 = reinterpret_cast<const float2*>(st->pxb);
     const double Ep = st->Ep;
@@ -601,20 +631,33 @@ __global__ void __launch_bounds__(ROWS * 16, 4) row_direct_kernel(RowArgs<float,
       }
       v[q] = cx<T>{(T)e0, (T)e1};
     }
+  } else if constexpr (MODE == ROW_BINIT) {
+    // g * s-mask for the real pairs m = j + P q (dL/dy arrives in pxb)
+    const float2* g2 = reinterpret_cast<const float2*>(st->pxb);
+    float2 gv[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) gv[q] = valid ? g2[g0 + j + q * P] : make_float2(0.f, 0.f);
+    __syncthreads();  // mask words visible
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int m = j + q * P;
+      v[q] = valid ? cx<T>{sbit(m, 0) ? gv[q].x : T(0), sbit(m, 1) ? gv[q].y : T(0)} : cx<T>{T(0), T(0)};
+    }
   } else {
-    // spectrum entries j + 16q of the row, and the Nyquist entry for lane 0
+    static_assert(spec_in, "");
+    // spectrum entries j + P q of the row, and the Nyquist entry for lane 0
     cx<T> x[E];
     cx<T> nyq{T(0), T(0)};
 #pragma unroll
     for (int q = 0; q < E; ++q) x[q] = valid ? a.src[rbase + j + q * P] : cx<T>{T(0), T(0)};
     if (valid && j == 0) nyq = a.src[rbase + H];
-    __syncthreads();  // twiddles (and cleared mask words) visible
+    __syncthreads();  // twiddles (and mask words) visible
     // C2R: Z'[k] = (X[k] + X[H-k]*) + i W^-k (X[k] - X[H-k]*)
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const int k = j + q * P;
       cx<T> A = x[q];
-      const cx<T> Bp = row16_partner(x[E - 1 - q]);
+      const cx<T> Bp = group_partner<P>(x[E - 1 - q]);
       const cx<T> own = (q == 0) ? nyq : x[(E - q) & (E - 1)];
       cx<T> B = (j == 0) ? own : Bp;
       if (k == 0) {
@@ -642,31 +685,54 @@ __global__ void __launch_bounds__(ROWS * 16, 4) row_direct_kernel(RowArgs<float,
         if (rec && valid)
           atomicOr(&sbits[rl * SW + (2 * k) / 32], ((uint32_t)k0 | ((uint32_t)k1 << 1)) << ((2 * k) & 31));
       }
-    } else {
+    } else if constexpr (MODE == ROW_FINAL) {
       // the source holds only the last-axis R2C of eps, so the C2R scale is 1/n_last
       const T scz = T(1) / T(2 * H);
 #pragma unroll
       for (int q = 0; q < E; ++q) v[q] = scal(v[q], scz);
+    } else {
+      // adjoint: 1/N, g * s-mask
+      const T sc = (T)st->inv_n;
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int k = j + q * P;
+        v[q].re = sbit(k, 0) ? v[q].re * sc : T(0);
+        v[q].im = sbit(k, 1) ? v[q].im * sc : T(0);
+      }
     }
   }
 
-  if constexpr (MODE == ROW_FINAL) {
-    // y = x + eps formed in FP64, rounded once, clamped (closing clamp)
-    const float2* x2 = reinterpret_cast<const float2*>(st->px);
+  if constexpr (MODE == ROW_FINAL || MODE == ROW_BFINAL) {
+    // FINAL: y = x + eps formed in FP64, rounded once, clamped (closing clamp);
+    // BFINAL: the gradient pairs
     float2* y2 = reinterpret_cast<float2*>(st->py);
-    const double Eb = st->E;
-    // all loads of x first: the clamp's loop between them would otherwise serialise them
-    float2 xv[E];
+    if constexpr (MODE == ROW_FINAL) {
+      const float2* x2 = reinterpret_cast<const float2*>(st->px);
+      const double Eb = st->E;
+      // the loads of x in two batches of 8, each issued before its clamps (the clamp's
+      // loop between loads would otherwise serialise them; 16 at once spill)
+      constexpr int BQ = 8;
+      float2 xv[BQ];
 #pragma unroll
-    for (int q = 0; q < E; ++q) xv[q] = valid ? x2[g0 + j + q * P] : make_float2(0.f, 0.f);
+      for (int q0 = 0; q0 < E; q0 += BQ) {
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-      if (valid)
-        y2[g0 + j + q * P] =
-            make_float2(closing_clamp<float>(round_io<float>((double)xv[q].x + (double)v[q].re), xv[q].x, Eb),
-                        closing_clamp<float>(round_io<float>((double)xv[q].y + (double)v[q].im), xv[q].y, Eb));
+        for (int u = 0; u < BQ; ++u) xv[u] = valid ? x2[g0 + j + (q0 + u) * P] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < BQ; ++u) {
+          const int q = q0 + u;
+          if (valid)
+            y2[g0 + j + q * P] =
+                make_float2(closing_clamp<float>(round_io<float>((double)xv[u].x + (double)v[q].re), xv[u].x, Eb),
+                            closing_clamp<float>(round_io<float>((double)xv[u].y + (double)v[q].im), xv[u].y, Eb));
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < E; ++q)
+        if (valid) y2[g0 + j + q * P] = make_float2(v[q].re, v[q].im);
     }
   } else {
+    static_assert(spec_out, "");
     fft<T, H, E, false, 1, LP, SKW>(v, lds, tws, rl, j);
     // R2C: X[k] = (Z[k] + Z[H-k]*)/2 - i W^k (Z[k] - Z[H-k]*)/2, X[H] = Re Z0 - Im Z0
     cx<T>* dst = a.dst + rbase;
@@ -674,8 +740,8 @@ __global__ void __launch_bounds__(ROWS * 16, 4) row_direct_kernel(RowArgs<float,
     for (int q = 0; q < E; ++q) {
       const int k = j + q * P;
       const cx<T> Zk = v[q];
-      const cx<T> Zp = row16_partner(v[E - 1 - q]);
-      const cx<T> own = v[(E - q) & (E - 1)];  // lane 0: Z[H - 16q], Z[0] for q = 0
+      const cx<T> Zp = group_partner<P>(v[E - 1 - q]);
+      const cx<T> own = v[(E - q) & (E - 1)];  // lane 0: Z[H - P q], Z[0] for q = 0
       const cx<T> Zm = (j == 0) ? own : Zp;
       const cx<T> ev = scal(Zk + conjg(Zm), T(0.5));
       const cx<T> d = Zk - conjg(Zm);
@@ -685,7 +751,9 @@ __global__ void __launch_bounds__(ROWS * 16, 4) row_direct_kernel(RowArgs<float,
     }
     // entry H and the row's first padding entry (zero) as one 16-byte store
     if (valid && j == 0) *reinterpret_cast<float4*>(dst + H) = make_float4(v[0].re - v[0].im, 0.f, 0.f, 0.f);
+  }
 
+  if constexpr (rec_s) {
     // one partial per block (guard-clip or s-clip count), reduced by the control kernel
     cnt = wave_sum_u64(cnt);
     if ((t & 63) == 0) red_u[t >> 6] = cnt;

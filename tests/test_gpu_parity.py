@@ -163,11 +163,11 @@ def test_deterministic_bitwise():
 
 
 @pytest.mark.parametrize("dt,shape,mode", [(np.float64, (16, 16, 64), 1), (np.float32, (16, 16, 64), 1),
-                                           (np.float32, (8, 8, 512), 4)])
+                                           (np.float32, (8, 8, 512), 4), (np.float32, (8, 16, 256), 4)])
 def test_fixed_rounds_masks_match_oracle(dt, shape, mode):
     """Clip keep-masks equal the oracle's; in FP32 a bit may differ only where the
     oracle's pre-clip value lies within FP32 noise (1e-5 relative) of its bound.  Mode 4
-    runs the direct last-axis loop pass (256-entry rows)."""
+    runs the direct last-axis passes (rows of 128 and 256 entries)."""
     p = _problem(shape, 21, dt, q=85.0, r=5e-2)
     K = 5
     try:
@@ -200,13 +200,17 @@ def test_fixed_rounds_masks_match_oracle(dt, shape, mode):
 
 @pytest.mark.parametrize("dt,shape", [(np.float64, (16, 16, 64)), (np.float32, (16, 16, 64)),
                                       (np.float64, (32, 128)), (np.float32, (8, 32, 32))])
-def test_backward_matches_oracle_adjoint(dt, shape):
+def test_backward_matches_oracle_adjoint(dt, shape, mode=1):
     import torch
     p = _problem(shape, 31, dt, q=85.0, r=5e-2)
     K = 4
-    y, res = run_gpu(p.x, p.xb, p.E, p.Delta, K, fixed=True, record_masks=True)
-    g = np.random.default_rng(32).standard_normal(shape).astype(dt)
-    gb = F.correct_backward(torch.from_numpy(g).cuda(), res.masks, K).cpu().numpy()
+    try:
+        F.ffcz_set_tuning(mode)
+        y, res = run_gpu(p.x, p.xb, p.E, p.Delta, K, fixed=True, record_masks=True)
+        g = np.random.default_rng(32).standard_normal(shape).astype(dt)
+        gb = F.correct_backward(torch.from_numpy(g).cuda(), res.masks, K).cpu().numpy()
+    finally:
+        F.ffcz_set_tuning(1)
     gm = unpack_masks(res.masks.cpu().numpy(), shape, K)
     ref = O.adjoint(gm, g.astype(np.float64))          # oracle fed the GPU's own masks
     tol = 1e-12 if dt == np.float64 else 1e-5
@@ -215,6 +219,13 @@ def test_backward_matches_oracle_adjoint(dt, shape):
     ref2 = O.adjoint(orc.masks, g.astype(np.float64))  # oracle's own trajectory
     rel_l2 = np.linalg.norm(gb - ref2) / np.linalg.norm(ref2)
     assert rel_l2 <= (1e-12 if dt == np.float64 else 1e-4)
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 256), (8, 16, 512), (32, 256)])
+def test_direct_last_axis_backward_matches_oracle_adjoint(shape):
+    # mode 4: the forward and the adjoint run the direct last-axis passes (rows of 128 and
+    # 256 entries)
+    test_backward_matches_oracle_adjoint(np.float32, shape, mode=4)
 
 
 def test_backward_dot_product_identity():
@@ -306,7 +317,9 @@ def test_tile_variants_bit_identical(dt, shape):
 @pytest.mark.parametrize("mode,dt,shape", [(3, np.float32, (32, 64, 256)), (3, np.float64, (16, 32, 512)),
                                            (3, np.float32, (128, 1024)), (3, np.float64, (64, 128)),
                                            (4, np.float32, (16, 32, 512)), (4, np.float32, (2, 4, 512)),
-                                           (4, np.float32, (256, 512)), (4, np.float64, (16, 32, 512))])
+                                           (4, np.float32, (256, 512)), (4, np.float64, (16, 32, 512)),
+                                           (4, np.float32, (16, 32, 256)), (4, np.float32, (4, 8, 256)),
+                                           (4, np.float32, (64, 256))])
 def test_rounding_plans_match_oracle(mode, dt, shape):
     # the radix-8 last-axis plan (mode 3) and the direct last-axis loop pass (mode 4, FP32 rows
     # of 256 entries; FP64 runs the narrow tiles) round differently from the default plan but
