@@ -115,7 +115,8 @@ const char* ffcz_last_error(void);
 void ffcz_default_options(ffcz_options* opts);
 
 /* Workspace bytes ffcz_correct / ffcz_correct_backward / ffcz_suggest_margin
- * need for this dtype, shape and round cap.  0 if the shape is unsupported.
+ * need for this dtype, shape and round cap (a negative cap counts as 0; the
+ * calls themselves reject it).  0 if the shape is unsupported.
  * Holds two half-spectrum buffers, the twiddle tables and the loop state. */
 size_t ffcz_workspace_bytes(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max_iter);
 

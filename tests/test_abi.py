@@ -48,6 +48,8 @@ def test_size_queries_and_shape_rules():
     assert ffcz.ffcz_workspace_bytes(ffcz.F32, (64, 63, 64), 10) == 0   # not a power of two
     assert ffcz.ffcz_workspace_bytes(ffcz.F32, (2, 2, 2, 2), 10) == 0   # ndim 4
     assert ffcz.ffcz_workspace_bytes(ffcz.F64, (1, 64, 1), 10) > 0       # squeezes to 1D
+    assert ffcz.ffcz_workspace_bytes(ffcz.F32, (0, 64, 64), 10) == 0     # an empty extent
+    assert ffcz.ffcz_batched_workspace_bytes(ffcz.F32, [], 10) > 0       # an empty batch
     # masks: (K+1) s-planes of 64*64 rows x 1 word + K f-pairs of 64*64 rows x 1 word
     assert ffcz.ffcz_mask_bytes((64, 64, 64), 3) == 4 * 4096 * 8 + 3 * 2 * 4096 * 8
     assert ffcz.ffcz_mask_bytes((8, 8, 256), 1) == 2 * 64 * 4 * 8 + 2 * 64 * 3 * 8

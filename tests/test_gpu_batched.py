@@ -134,6 +134,29 @@ def test_batched_tilings(shape):
         _check(p, y, s, np.float32)
 
 
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_longest_1d_members(dt):
+    # the longest 1D members: 2^19 points (four-step DFT, work length 2^19) and 300007 points
+    # (Bluestein, work length 2^20), each against the oracle
+    probs = [_member((n,), 600 + i, dt) for i, n in enumerate((1 << 19, 300007))]
+    ys, st, stats = _run(probs)
+    assert st == F.OK, (st, F.ffcz_last_error(), stats)
+    for p, y, s in zip(probs, ys, stats):
+        _check(p, y, s, dt)
+
+
+def test_empty_batch():
+    # a batch of no members: a workspace size, then a call that does nothing and succeeds
+    import torch
+    for dt in (F.F32, F.F64):
+        n = F.ffcz_batched_workspace_bytes(dt, [], 10)
+        assert n > 0, F.ffcz_last_error()
+        ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+        stream = torch.cuda.current_stream().cuda_stream
+        assert F.ffcz_correct_batched(dt, [], 10, None, ws.data_ptr(), n, stream, None) == F.OK
+    torch.cuda.synchronize()
+
+
 def test_batched_statuses():
     # a member capped at 0 rounds reports NOT_CONVERGED; a NaN member reports NONFINITE
     import torch
