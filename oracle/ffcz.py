@@ -13,7 +13,7 @@ What is computed (paper Sec. IV):
 * the loop of Alg. 1: FFT, CheckConvergence, ProjectOntoFCube (clip Re and Im),
   IFFT, ProjectOntoSCube (clip eps), until no frequency component violates.
 
-Readings taken where the paper is silent (all listed in the design doc):
+Readings taken where the paper is silent:
 
 * Projections use the bounds shrunk by ``(1 - mu)`` with ``mu = 2**-16`` (the
   ``m = 16`` shrink of Sec. IV-B), while the check uses the unshrunk bounds.

@@ -1,7 +1,7 @@
 """GPU parity of the HIP correction path against the FP64 CPU oracle.
 
 Every call goes through the C ABI (``paper_2601_01596_amd.ffcz`` -> libffcz.so).
-Tolerances (written here, derived in the design doc):
+Tolerances (derived from the arithmetic of each precision):
   FP64: rounds and every per-check violation count equal to the oracle's;
         max|y_gpu - y_orc| <= 1e-12 * max|y_orc|.
   FP32: rounds equal or off by one (then the oracle is re-run for the GPU's
