@@ -87,6 +87,7 @@ __host__ __device__ constexpr int imax2(int a, int b) { return a > b ? a : b; }
 template <typename T, int MA, int MB>
 struct SigGeom {
   static constexpr int Mc = MA * MB;
+  static constexpr int MB_ = MB;
   static constexpr int EA = pick_E(MA), EB = pick_E(MB);
   static constexpr int PA = MA / EA, PB = MB / EB;
   static constexpr int NTMAX = 512;
@@ -129,6 +130,20 @@ __host__ __device__ constexpr bool sig_tiled(int m) { return m >= SIGT_CHIRP; }
 __host__ __device__ constexpr bool sig_row_tiled(int m) {
   return m == SIGT_BROW || m == SIGT_RMUL || m == SIGT_RCHECK || m == SIGT_VROW;
 }
+// tiled passes that work on element chunks only (no transform, no LDS)
+__host__ __device__ constexpr bool sig_elem_tiled(int m) {
+  return m == SIGT_CHIRP || m == SIGT_EPS0 || m == SIGT_Y;
+}
+// LDS entries a mode needs: a tiled launch runs one kind of pass, so it holds only
+// that pass's tile (a column tile of an FP64 2^19 class is half a row tile), which
+// lets more blocks share a compute unit
+template <typename G, int MODE>
+__host__ __device__ constexpr int sig_lds_entries() {
+  if constexpr (!sig_tiled(MODE)) return G::LDS;
+  else if constexpr (sig_row_tiled(MODE)) return G::RR * G::LPA;
+  else if constexpr (sig_elem_tiled(MODE)) return 1;
+  else return G::CC * G::MB_;
+}
 
 // Block-wide sum / max, result broadcast to every lane.
 template <int NT>
@@ -163,7 +178,7 @@ sig_kernel(SigArgs<T> a) {
   constexpr int LPA = G::LPA;
   constexpr int Mc = MA * MB;
   constexpr int BL = 8;
-  __shared__ cx<T> lds[G::LDS];
+  __shared__ cx<T> lds[sig_lds_entries<G, MODE>()];
   __shared__ unsigned long long red_u[NT / 64 + 1];
   __shared__ double red_d[NT / 64 + 1];
 
@@ -254,18 +269,28 @@ sig_kernel(SigArgs<T> a) {
     cx<T>* lrow = lds + rl * LPA;
     for (int r0 = rtlo * RR; r0 < rthi * RR; r0 += RR) {
       constexpr int NL = (RR * MA + NT - 1) / NT;
+      // FP64 staging defines every entry on every path (zero where a ragged tile ends),
+      // or the batch lands in scratch memory, and a tile of whole block-wide steps
+      // (t < NT) drops the per-lane guard.  FP32 keeps the guarded loads (fewer
+      // registers live).
+      constexpr bool f64 = sizeof(T) == 8;
+      constexpr bool whole = f64 && NL * NT == RR * MA;
 #pragma unroll
       for (int b0 = 0; b0 < NL; b0 += BL) {
         cx<T> tmp[BL];
 #pragma unroll
         for (int u = 0; u < BL; ++u) {
           const int f = t + (b0 + u) * NT;
-          if (b0 + u < NL && f < RR * MA) tmp[u] = conv[(int64_t)r0 * MA + f];
+          if constexpr (f64) {
+            tmp[u] = (b0 + u < NL && (whole || f < RR * MA)) ? conv[(int64_t)r0 * MA + f] : cx<T>{T(0), T(0)};
+          } else if (b0 + u < NL && f < RR * MA) {
+            tmp[u] = conv[(int64_t)r0 * MA + f];
+          }
         }
 #pragma unroll
         for (int u = 0; u < BL; ++u) {
           const int f = t + (b0 + u) * NT;
-          if (b0 + u < NL && f < RR * MA) lds[(f / MA) * LPA + (f % MA)] = tmp[u];
+          if (b0 + u < NL && (whole || f < RR * MA)) lds[(f / MA) * LPA + (f % MA)] = tmp[u];
         }
       }
       __syncthreads();
