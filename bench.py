@@ -91,6 +91,8 @@ def pass_bytes(kind, N, M, s, c):
         return 2 * N * s + M * c
     if kind == "finalize":
         return M * c + 2 * N * s
+    if kind == "finalize_verify":  # closing pass fused with the verification's last-axis R2C
+        return M * c + 2 * N * s + M * 16
     if kind == "verify_z":
         return 2 * N * s + M * 16
     if kind == "verify_y":
@@ -315,8 +317,10 @@ def main():
     bpl = pass_bytes(dom, N, M, s, c)
     achieved = bpl / (ms_avg * 1e-3) / 1e9
     per_round_ms = sum(prof[k][0] / max(1, prof[k][1]) for k in ("y_fwd", "x_pass", "y_inv", "z_pass"))
+    fused_final = prof.get("verify_z", (0.0, 0))[1] == 0 and prof.get("verify_y", (0.0, 0))[1] > 0
     passes = {k: {"avg_ms": v[0] / v[1], "launches": v[1],
-                  "GBps": pass_bytes(k, N, M, s, c) / (v[0] / v[1] * 1e-3) / 1e9}
+                  "GBps": pass_bytes("finalize_verify" if (k == "finalize" and fused_final) else k, N, M, s, c)
+                  / (v[0] / v[1] * 1e-3) / 1e9}
               for k, v in prof.items() if v[1] > 0}
 
     try:

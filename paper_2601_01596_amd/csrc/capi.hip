@@ -40,7 +40,7 @@ hipError_t launch_col_f32(int mode, int L, int v, const void* args, int64_t nb, 
 hipError_t launch_col_f64(int mode, int L, int v, const void* args, int64_t nb, hipStream_t s);
 hipError_t launch_row_f32(int mode, int H, int v, const void* args, int64_t nb, hipStream_t s);
 hipError_t launch_row_f64(int mode, int H, int v, const void* args, int64_t nb, hipStream_t s);
-hipError_t launch_row_verify_f32io(int H, int v, const void* args, int64_t nb, hipStream_t s);
+hipError_t launch_row_f64_f32io(int mode, int H, int v, const void* args, int64_t nb, hipStream_t s);
 hipError_t launch_sig_f32(int mode, int lgMc, const void* args, int nb, hipStream_t s);
 hipError_t launch_sig_f64(int mode, int lgMc, const void* args, int nb, hipStream_t s);
 hipError_t launch_sigt_f64(int mode, int iodt, int lgMc, const void* args, int nb, hipStream_t s);
@@ -236,6 +236,14 @@ int ceil_lg(int64_t v) {
 // per lane of radix 16, so twice the lanes of an FP64 row tile stay resident.
 constexpr int kVerifyRowPlan = 2;
 
+// FP64 fields: the closing pass runs on the radix-8 tiles of the verification and, when
+// verification is on, goes on to the verification's last-axis R2C in the same pass (x and
+// y read once): rows of up to 512 entries, where those tiles still hold 4 or more rows.  The
+// closing pass takes the same form with verification off, so y does not depend on it.  (For
+// FP32 fields the fused pass would move the closing C2R into FP64 arithmetic, and measured
+// slower than the two passes.)
+bool final_fused(const Plan& p) { return p.dt == FFCZ_F64 && p.H >= 2 && p.H <= 512; }
+
 // Choose the loop passes' tile variants and the per-instance block counts that follow.
 // Plan of the init, closing and adjoint last-axis passes: the direct form (variant 3)
 // when the loop pass runs it on 128- or 256-entry FP32 rows, else the default tiles.
@@ -337,8 +345,9 @@ int32_t make_plan(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max
   off = align_up(off + spec, 256);
   p.off_A = off;
   off = align_up(off + spec, 256);
-  // the FP64 verification spectrum reuses Z..A (contiguous) once y is written
-  p.off_W = p.off_Z;
+  // the FP64 verification spectrum reuses Z..A (contiguous) once y is written; the fused
+  // closing pass reads Z while it writes, so there it starts at A (free once the loop ends)
+  p.off_W = final_fused(p) ? p.off_A : p.off_Z;
   const size_t spec64 = 16 * nplanes * (size_t)p.plane64;
   if (p.off_W + spec64 > off) off = align_up(p.off_W + spec64, 256);
   p.bytes = off;
@@ -729,12 +738,14 @@ hipError_t run_col(int dt, int mode, int v, const ColGeom& g, const Plan& p, con
 template <typename T, typename TIO>
 hipError_t run_row(int tdt, int iodt, int mode, int v, const Plan& p, int64_t pitch, int64_t plane, const void* src,
                    void* dst, const void* tw, DevState* st, unsigned long long* part, uint32_t* smask,
-                   hipStream_t s) {
+                   hipStream_t s, int64_t spitch = -1, int64_t splane = -1) {
   RowArgs<T, TIO> a;
   memset(&a, 0, sizeof(a));
   a.src = (const cx<T>*)src;
   a.dst = (cx<T>*)dst;
   a.pitch = pitch;
+  a.spitch = spitch < 0 ? pitch : spitch;
+  a.splane = splane < 0 ? plane : splane;
   a.rows_per_inst = p.nrows;
   const int R = row_block_rows(tdt, p.H, v);
   a.bpi = (p.nrows + R - 1) / R;
@@ -747,7 +758,7 @@ hipError_t run_row(int tdt, int iodt, int mode, int v, const Plan& p, int64_t pi
   const int64_t nb = a.bpi * p.B;
   a.plane = plane;
   a.lg_rpp = p.lg_rpp;
-  if (mode == ROW_VERIFY && tdt == 1 && iodt == 0) return launch_row_verify_f32io(p.H, v, &a, nb, s);
+  if (tdt == 1 && iodt == 0) return launch_row_f64_f32io(mode, p.H, v, &a, nb, s);
   return tdt == 0 ? launch_row_f32(mode, p.H, v, &a, nb, s) : launch_row_f64(mode, p.H, v, &a, nb, s);
 }
 
@@ -797,16 +808,19 @@ hipError_t enqueue_round(const Ctx& c, int r, unsigned long long* viol, int64_t 
 // FP64 verification: last-axis R2C of y - x (max |y - x|), then the y and x
 // transforms of that spectrum with the max-reduce in the x-pass.
 template <typename T>
-hipError_t enqueue_verify(const Ctx& c) {
+hipError_t enqueue_verify(const Ctx& c, bool z_done) {
   const Plan& p = *c.p;
   const char* tb = (const char*)c.tw64();
   void* W = c.W();
-  hipError_t e = timed(PK_VZ, -1, c.s, [&] {
-    return run_row<double, T>(1, p.dt, ROW_VERIFY, kVerifyRowPlan, p, p.pitch64, p.plane64, nullptr, W,
-                              tb + 16 * (kVerifyRowPlan == 2 ? p.twz8 : p.twz), c.st(),
-                              c.part(Ctx::PVZ), nullptr, c.s);
-  });
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  if (!z_done) {
+    e = timed(PK_VZ, -1, c.s, [&] {
+      return run_row<double, T>(1, p.dt, ROW_VERIFY, kVerifyRowPlan, p, p.pitch64, p.plane64, nullptr, W,
+                                tb + 16 * (kVerifyRowPlan == 2 ? p.twz8 : p.twz), c.st(),
+                                c.part(Ctx::PVZ), nullptr, c.s);
+    });
+    if (e != hipSuccess) return e;
+  }
   if (p.nd == 3) {
     e = timed(PK_VY, -1, c.s, [&] {
       return run_col<double>(1, COL_FWD_NS, 0, geom_y(p, p.pitch64, p.plane64), p, W, W, tb + 16 * p.twy, c.st(),
@@ -822,6 +836,25 @@ hipError_t enqueue_verify(const Ctx& c) {
   hipLaunchKernelGGL(stats_kernel, dim3((unsigned)p.B), dim3(1024), 0, c.s, c.st(), c.part(Ctx::PVZ), p.vzbpi,
                      c.part(Ctx::PVX), c.part(Ctx::PVX + 1), p.vxbpi);
   return hipGetLastError();
+}
+
+// Closing pass (y = x + eps, FP64 closing clamp) and, when asked, the FP64 verification.
+template <typename T>
+hipError_t enqueue_final(const Ctx& c, bool verify) {
+  const Plan& p = *c.p;
+  if (!final_fused(p)) {
+    hipError_t e = timed(PK_FINAL, -1, c.s, [&] { return row_T<T>(ROW_FINAL, c, c.Z(), nullptr, nullptr); });
+    if (e != hipSuccess || !verify) return e;
+    return enqueue_verify<T>(c, false);
+  }
+  const char* tb = (const char*)c.tw64();
+  const int mode = verify ? ROW_FINALV : ROW_FINAL;
+  hipError_t e = timed(PK_FINAL, -1, c.s, [&] {
+    return run_row<double, T>(1, p.dt, mode, 2, p, p.pitch64, p.plane64, c.Z(), c.W(), tb + 16 * p.twz8, c.st(),
+                              c.part(Ctx::PVZ), nullptr, c.s, p.pitch, p.plane);
+  });
+  if (e != hipSuccess || !verify) return e;
+  return enqueue_verify<T>(c, true);
 }
 
 // pinned host staging (one per thread), grown on demand
@@ -1247,8 +1280,7 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
         return fail(FFCZ_E_HIP, "loop did not report completion (device state inconsistent)");
     }
   }
-  HIPCHK(timed(PK_FINAL, -1, s, [&] { return row_T<T>(ROW_FINAL, c, c.Z(), nullptr, nullptr); }));
-  if (o.verify_fp64) HIPCHK(enqueue_verify<T>(c));
+  HIPCHK(enqueue_final<T>(c, o.verify_fp64 != 0));
   if (!sync_needed) {
     prof_settle(max_iter);
     for (int64_t b = 0; b < p.B; ++b) status[b] = FFCZ_OK;

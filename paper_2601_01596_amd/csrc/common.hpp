@@ -48,7 +48,9 @@ enum RowMode : int {
   ROW_VERIFY = 3,  // d = y - x in FP64, max |d|, FP64 R2C
   ROW_BINIT = 4,   // g * s-mask, R2C        (adjoint)
   ROW_BLOOP = 5,   // C2R, 1/N, g * s-mask, R2C (adjoint)
-  ROW_BFINAL = 6   // C2R, 1/N, g * s-mask, store (adjoint)
+  ROW_BFINAL = 6,  // C2R, 1/N, g * s-mask, store (adjoint)
+  ROW_FINALV = 7   // FP64 fields: ROW_FINAL, then d = y - x from the stored y: max |d|, FP64 R2C (the
+                   // last-axis pass of the verification, without re-reading x and y)
 };
 
 template <typename T>
@@ -89,6 +91,10 @@ struct RowArgs {
   int64_t plane;     // complex entries per plane of rows (src / dst spectra)
   int32_t lg_rpp;    // log2 of the rows per plane
   int32_t pad2;
+  // source spectrum layout (complex entries per row / plane); differs from pitch / plane
+  // only where a pass reads one precision and writes another (ROW_FINALV)
+  int64_t spitch;
+  int64_t splane;
 };
 
 // FP64 bound -> working type, rounded toward zero (a tighter bound in FP32).

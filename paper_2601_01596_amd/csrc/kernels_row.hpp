@@ -65,11 +65,18 @@ row_kernel(RowArgs<T, TIO> a) {
   constexpr int NW = (NT + 63) / 64;
   constexpr int SW = 2 * (H >= 32 ? H / 32 : 1);  // uint32 words per s-mask row (64-bit padded)
   using V2 = typename Vec2<TIO>::type;
-  constexpr bool spec_in = (MODE == ROW_LOOP || MODE == ROW_FINAL || MODE == ROW_BLOOP || MODE == ROW_BFINAL);
+  constexpr bool finalv = MODE == ROW_FINALV;  // FP64 fields only
+  constexpr bool final_y = (MODE == ROW_FINAL || finalv);  // forms and stores y
+  constexpr bool spec_in = (MODE == ROW_LOOP || final_y || MODE == ROW_BLOOP || MODE == ROW_BFINAL);
   constexpr bool spec_out = (MODE == ROW_INIT || MODE == ROW_LOOP || MODE == ROW_VERIFY || MODE == ROW_BINIT ||
-                             MODE == ROW_BLOOP);
+                             MODE == ROW_BLOOP || finalv);
   constexpr bool rec_s = (MODE == ROW_INIT || MODE == ROW_LOOP);
   constexpr bool use_s = (MODE == ROW_BINIT || MODE == ROW_BLOOP || MODE == ROW_BFINAL);
+  // the final passes read the loop's spectrum in the field's precision (TIO), which is
+  // the working precision except for an FP64 final of an FP32 field
+  using SrcT = typename std::conditional<final_y, TIO, T>::type;
+  const cx<SrcT>* src = reinterpret_cast<const cx<SrcT>*>(a.src);
+  static_assert(!finalv || (sizeof(T) == 8 && sizeof(TIO) == 8), "the fused closing pass serves FP64 fields");
 
   __shared__ cx<T> lds[ROWS * LP];
   __shared__ cx<T> tws[TW + H];
@@ -88,6 +95,9 @@ row_kernel(RowArgs<T, TIO> a) {
   // first entry of spectrum row R (rows are grouped in planes of 2^lg_rpp rows)
   auto rowaddr = [&](int64_t R) -> int64_t {
     return (R >> a.lg_rpp) * a.plane + (R & ((int64_t(1) << a.lg_rpp) - 1)) * a.pitch;
+  };
+  auto srowaddr = [&](int64_t R) -> int64_t {
+    return (R >> a.lg_rpp) * a.splane + (R & ((int64_t(1) << a.lg_rpp) - 1)) * a.spitch;
   };
   const int t = threadIdx.x;
   const int rl = t % ROWS;  // compute mapping: rows fastest
@@ -128,11 +138,12 @@ row_kernel(RowArgs<T, TIO> a) {
   // FP32 spectra move two entries per 16-byte access: pair m of a row holds entries 2m, 2m+1
   // (the last pair of a row reaches into its padding, which is read but never written)
   constexpr bool pairs = sizeof(cx<T>) == 8 && H >= 2;
+  constexpr bool pairs_in = sizeof(cx<SrcT>) == 8 && H >= 2;
   constexpr int NPR = (NC + 1) / 2;  // pairs per row
   // FP32 real fields move four reals (two packed entries) per 16-byte access
   constexpr bool io4 = sizeof(TIO) == 4 && H >= 2;
   constexpr int HQ = H / 2;  // 16-byte groups per real row
-  if constexpr (spec_in && pairs) {
+  if constexpr (spec_in && pairs_in) {
     constexpr int NLP = (ROWS * NPR + NT - 1) / NT;
     constexpr int BLP = NLP < 8 ? NLP : 8;  // loads per lane in flight
 #pragma unroll
@@ -144,7 +155,7 @@ row_kernel(RowArgs<T, TIO> a) {
         const int r = f / NPR, m = f - r * NPR;
         tmp[u] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (u0 + u < NLP && f < ROWS * NPR && r < nrow)
-          tmp[u] = *reinterpret_cast<const float4*>(a.src + rowaddr(row0 + r) + 2 * m);
+          tmp[u] = *reinterpret_cast<const float4*>(src + srowaddr(row0 + r) + 2 * m);
       }
 #pragma unroll
       for (int u = 0; u < BLP; ++u) {
@@ -165,7 +176,11 @@ row_kernel(RowArgs<T, TIO> a) {
       for (int u = 0; u < BL; ++u) {
         const int f = t + (b0 + u) * NT;
         const int r = f / NC, k = f - r * NC;
-        tmp[u] = (b0 + u < NL && f < ROWS * NC && r < nrow) ? a.src[rowaddr(row0 + r) + k] : cx<T>{T(0), T(0)};
+        tmp[u] = cx<T>{T(0), T(0)};
+        if (b0 + u < NL && f < ROWS * NC && r < nrow) {
+          const cx<SrcT> z = src[srowaddr(row0 + r) + k];
+          tmp[u] = cx<T>{(T)z.re, (T)z.im};
+        }
       }
 #pragma unroll
       for (int u = 0; u < BL; ++u) {
@@ -289,7 +304,7 @@ row_kernel(RowArgs<T, TIO> a) {
     }
     fft<T, H, E, true, 1, LP, SKW>(v, lds, tws, rl, j);
     const T sc = (T)st->inv_n;
-    if constexpr (MODE == ROW_FINAL) {
+    if constexpr (final_y) {
       // the source holds only the last-axis R2C of eps, so the C2R scale is 1/n_last
       const T scz = T(1) / T(2 * H);
 #pragma unroll
@@ -323,7 +338,7 @@ row_kernel(RowArgs<T, TIO> a) {
 #pragma unroll
     for (int q = 0; q < E; ++q) v[q] = lrow[sj + lds_skew<SKW>(q * P)];
   }
-  if constexpr (spec_out) fft<T, H, E, false, 1, LP, SKW>(v, lds, tws, rl, j);
+  if constexpr (spec_out && !finalv) fft<T, H, E, false, 1, LP, SKW>(v, lds, tws, rl, j);
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < E; ++q) lrow[sj + lds_skew<SKW>(q * P)] = v[q];
@@ -343,6 +358,100 @@ row_kernel(RowArgs<T, TIO> a) {
     const cx<T> od = cx<T>{d.im * T(0.5), -d.re * T(0.5)};  // d / (2i)
     return ev + cmul(rtw[k], od);
   };
+  if constexpr (!spec_out || finalv) {
+    // ROW_FINAL / ROW_FINALV: y = x + eps formed in FP64, rounded once, clamped;  ROW_BFINAL:
+    // store g.  ROW_FINALV puts d = y - x (FP64, from the stored y) back into the row's LDS
+    // entries and keeps max |d|.
+    V2* y2 = reinterpret_cast<V2*>(st->py);
+    const double Eb = st->E;
+    auto out_of = [&](TIO xv, T e) -> TIO {
+      if constexpr (final_y) return closing_clamp<TIO>(round_io<TIO>((double)xv + (double)e), xv, Eb);
+      else return (TIO)e;
+    };
+    constexpr int NS = (ROWS * H + NT - 1) / NT;
+    if constexpr (io4) {
+      // FP32 fields: four reals per 16-byte access
+      constexpr int NSQ = (ROWS * HQ + NT - 1) / NT;
+      constexpr int BQ = NSQ < 8 ? NSQ : 8;
+      const float4* x4 = reinterpret_cast<const float4*>(st->px);
+      float4* y4 = reinterpret_cast<float4*>(st->py);
+#pragma unroll
+      for (int q0 = 0; q0 < NSQ; q0 += BQ) {
+        float4 xa[BQ];
+        if constexpr (final_y) {
+#pragma unroll
+          for (int u = 0; u < BQ; ++u) {
+            const int f = t + (q0 + u) * NT;
+            const int r = f / HQ, q = f - r * HQ;
+            if (q0 + u < NSQ && f < ROWS * HQ && r < nrow) xa[u] = x4[(lrow0 + r) * HQ + q];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < BQ; ++u) {
+          const int f = t + (q0 + u) * NT;
+          const int r = f / HQ, q = f - r * HQ;
+          if (q0 + u < NSQ && f < ROWS * HQ && r < nrow) {
+            const cx<T> e0 = lds[r * LP + lds_skew<SKW>(2 * q)], e1 = lds[r * LP + lds_skew<SKW>(2 * q + 1)];
+            float4 o;
+            if constexpr (final_y) {
+              o = make_float4(out_of(xa[u].x, e0.re), out_of(xa[u].y, e0.im), out_of(xa[u].z, e1.re),
+                              out_of(xa[u].w, e1.im));
+            } else {
+              o = make_float4((float)e0.re, (float)e0.im, (float)e1.re, (float)e1.im);
+            }
+            y4[(lrow0 + r) * HQ + q] = o;
+          }
+        }
+      }
+    } else {
+#pragma unroll
+    for (int b0 = 0; b0 < NS; b0 += BL) {
+      V2 xa[BL];
+      if constexpr (final_y) {
+#pragma unroll
+        for (int u = 0; u < BL; ++u) {
+          const int f = t + (b0 + u) * NT;
+          const int r = f / H, m = f - r * H;
+          if (b0 + u < NS && f < ROWS * H && r < nrow) xa[u] = x2[(lrow0 + r) * H + m];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < BL; ++u) {
+        const int f = t + (b0 + u) * NT;
+        const int r = f / H, m = f - r * H;
+        if (b0 + u < NS && f < ROWS * H && r < nrow) {
+          const cx<T> e = lds[r * LP + lds_skew<SKW>(m)];
+          V2 out;
+          if constexpr (final_y) {
+            out.x = out_of(xa[u].x, e.re);
+            out.y = out_of(xa[u].y, e.im);
+          } else {
+            out.x = (TIO)e.re;
+            out.y = (TIO)e.im;
+          }
+          y2[(lrow0 + r) * H + m] = out;
+          if constexpr (finalv) {
+            const double d0 = (double)out.x - (double)xa[u].x, d1 = (double)out.y - (double)xa[u].y;
+            mx = fmax(mx, fmax(fabs(d0), fabs(d1)));
+            lds[r * LP + lds_skew<SKW>(m)] = cx<T>{(T)d0, (T)d1};
+          }
+        }
+      }
+    }
+    }
+  }
+  if constexpr (finalv) {
+    // FP64 R2C of d: each lane rewrites only LDS entries it read above, so the barrier
+    // before the transform is the only one needed
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < E; ++q) v[q] = lrow[sj + lds_skew<SKW>(q * P)];
+    fft<T, H, E, false, 1, LP, SKW>(v, lds, tws, rl, j);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < E; ++q) lrow[sj + lds_skew<SKW>(q * P)] = v[q];
+    __syncthreads();
+  }
   if constexpr (spec_out && pairs) {
     constexpr int NSP = (ROWS * NPR + NT - 1) / NT;
 #pragma unroll
@@ -369,84 +478,10 @@ row_kernel(RowArgs<T, TIO> a) {
       const int r = f / NC, k = f - r * NC;
       if (f < ROWS * NC && r < nrow) a.dst[rowaddr(row0 + r) + k] = unpack(lds + r * LP, k);
     }
-  } else {
-    // ROW_FINAL: y = x + eps formed in FP64, rounded once, clamped;  ROW_BFINAL: store g
-    V2* y2 = reinterpret_cast<V2*>(st->py);
-    const double Eb = st->E;
-    auto out_of = [&](TIO xv, T e) -> TIO {
-      if constexpr (MODE == ROW_FINAL) return closing_clamp<TIO>(round_io<TIO>((double)xv + (double)e), xv, Eb);
-      else return (TIO)e;
-    };
-    constexpr int NS = (ROWS * H + NT - 1) / NT;
-    if constexpr (io4) {
-      // FP32 fields: four reals per 16-byte access
-      constexpr int NSQ = (ROWS * HQ + NT - 1) / NT;
-      constexpr int BQ = NSQ < 8 ? NSQ : 8;
-      const float4* x4 = reinterpret_cast<const float4*>(st->px);
-      float4* y4 = reinterpret_cast<float4*>(st->py);
-#pragma unroll
-      for (int q0 = 0; q0 < NSQ; q0 += BQ) {
-        float4 xa[BQ];
-        if constexpr (MODE == ROW_FINAL) {
-#pragma unroll
-          for (int u = 0; u < BQ; ++u) {
-            const int f = t + (q0 + u) * NT;
-            const int r = f / HQ, q = f - r * HQ;
-            if (q0 + u < NSQ && f < ROWS * HQ && r < nrow) xa[u] = x4[(lrow0 + r) * HQ + q];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < BQ; ++u) {
-          const int f = t + (q0 + u) * NT;
-          const int r = f / HQ, q = f - r * HQ;
-          if (q0 + u < NSQ && f < ROWS * HQ && r < nrow) {
-            const cx<T> e0 = lds[r * LP + lds_skew<SKW>(2 * q)], e1 = lds[r * LP + lds_skew<SKW>(2 * q + 1)];
-            float4 o;
-            if constexpr (MODE == ROW_FINAL) {
-              o = make_float4(out_of(xa[u].x, e0.re), out_of(xa[u].y, e0.im), out_of(xa[u].z, e1.re),
-                              out_of(xa[u].w, e1.im));
-            } else {
-              o = make_float4((float)e0.re, (float)e0.im, (float)e1.re, (float)e1.im);
-            }
-            y4[(lrow0 + r) * HQ + q] = o;
-          }
-        }
-      }
-    } else {
-#pragma unroll
-    for (int b0 = 0; b0 < NS; b0 += BL) {
-      V2 xa[BL];
-      if constexpr (MODE == ROW_FINAL) {
-#pragma unroll
-        for (int u = 0; u < BL; ++u) {
-          const int f = t + (b0 + u) * NT;
-          const int r = f / H, m = f - r * H;
-          if (b0 + u < NS && f < ROWS * H && r < nrow) xa[u] = x2[(lrow0 + r) * H + m];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < BL; ++u) {
-        const int f = t + (b0 + u) * NT;
-        const int r = f / H, m = f - r * H;
-        if (b0 + u < NS && f < ROWS * H && r < nrow) {
-          const cx<T> e = lds[r * LP + lds_skew<SKW>(m)];
-          V2 out;
-          if constexpr (MODE == ROW_FINAL) {
-            out.x = out_of(xa[u].x, e.re);
-            out.y = out_of(xa[u].y, e.im);
-          } else {
-            out.x = (TIO)e.re;
-            out.y = (TIO)e.im;
-          }
-          y2[(lrow0 + r) * H + m] = out;
-        }
-      }
-    }
-    }
   }
 
   // ------------------------------------------------------------------ partials and masks
-  if constexpr (MODE == ROW_INIT || MODE == ROW_LOOP || MODE == ROW_VERIFY) {
+  if constexpr (MODE == ROW_INIT || MODE == ROW_LOOP || MODE == ROW_VERIFY || finalv) {
     cnt = wave_sum_u64(cnt);
     mx = wave_max_f64(mx);
     if ((t & 63) == 0) {
@@ -462,7 +497,7 @@ row_kernel(RowArgs<T, TIO> a) {
         m = fmax(m, red_d[w]);
       }
       // one partial per block, reduced by the control / statistics kernels
-      if constexpr (MODE == ROW_VERIFY) a.part[blockIdx.x] = (unsigned long long)__double_as_longlong(m);
+      if constexpr (MODE == ROW_VERIFY || finalv) a.part[blockIdx.x] = (unsigned long long)__double_as_longlong(m);
       else a.part[blockIdx.x] = s;
     }
     if constexpr (rec_s) {
@@ -556,6 +591,9 @@ __global__ void __launch_bounds__(ROWS * (H / 16), 4) row_direct_kernel(RowArgs<
   }
   auto rowaddr = [&](int64_t R) -> int64_t {
     return (R >> a.lg_rpp) * a.plane + (R & ((int64_t(1) << a.lg_rpp) - 1)) * a.pitch;
+  };
+  auto srowaddr = [&](int64_t R) -> int64_t {
+    return (R >> a.lg_rpp) * a.splane + (R & ((int64_t(1) << a.lg_rpp) - 1)) * a.spitch;
   };
   const int t = threadIdx.x;
   const int j = t & (P - 1);

@@ -31,7 +31,8 @@ hipError_t launch_row_f64(int mode, int H, int v, const void* args, int64_t nb, 
       // variant 3 (FP32 only) falls back to variant 1, whose tiles it shares
       return v == 2 ? go<double, double, ROW_LOOP, 2>(H, a, nb, s)
                     : (v ? go<double, double, ROW_LOOP, 1>(H, a, nb, s) : go<double, double, ROW_LOOP, 0>(H, a, nb, s));
-    case ROW_FINAL: return go<double, double, ROW_FINAL, 0>(H, a, nb, s);
+    case ROW_FINAL: return v == 2 ? go<double, double, ROW_FINAL, 2>(H, a, nb, s) : go<double, double, ROW_FINAL, 0>(H, a, nb, s);
+    case ROW_FINALV: return go<double, double, ROW_FINALV, 2>(H, a, nb, s);
     case ROW_VERIFY: return v == 2 ? go<double, double, ROW_VERIFY, 2>(H, a, nb, s) : go<double, double, ROW_VERIFY, 0>(H, a, nb, s);
     case ROW_BINIT: return go<double, double, ROW_BINIT, 0>(H, a, nb, s);
     case ROW_BLOOP: return go<double, double, ROW_BLOOP, 0>(H, a, nb, s);
@@ -41,8 +42,9 @@ hipError_t launch_row_f64(int mode, int H, int v, const void* args, int64_t nb, 
 }
 
 // FP64 verification of an FP32 output: compute in double, read float fields.
-hipError_t launch_row_verify_f32io(int H, int v, const void* args, int64_t nb, hipStream_t s) {
+hipError_t launch_row_f64_f32io(int mode, int H, int v, const void* args, int64_t nb, hipStream_t s) {
   const RowArgs<double, float>& a = *static_cast<const RowArgs<double, float>*>(args);
+  if (mode != ROW_VERIFY) return hipErrorInvalidValue;
   return v == 2 ? go<double, float, ROW_VERIFY, 2>(H, a, nb, s) : go<double, float, ROW_VERIFY, 0>(H, a, nb, s);
 }
 

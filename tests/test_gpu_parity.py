@@ -314,6 +314,25 @@ def test_tile_variants_bit_identical(dt, shape):
         assert np.array_equal(m0, m1)
 
 
+@pytest.mark.parametrize("dt,shape", [(np.float32, (32, 64, 512)), (np.float64, (16, 32, 256)),
+                                      (np.float32, (8, 4, 256)), (np.float32, (2, 512)),
+                                      (np.float32, (1024,)), (np.float64, (4, 16)),
+                                      (np.float32, (16, 2048)), (np.float64, (4, 4096))])
+def test_output_independent_of_verification(dt, shape):
+    # rows of up to 512 entries close in one pass that also starts the FP64 verification
+    # (longer rows keep two passes); y is the same bits with verification off, and the
+    # verified maxima match the oracle's FP64 re-verification of that y
+    p = _problem(shape, 83, dt)
+    y1, r1 = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter)
+    y0, r0 = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter, verify=False)
+    assert r1.status == F.OK and r0.status in (F.OK, F.NOT_CONVERGED)
+    assert np.array_equal(y1.view(np.uint8), y0.view(np.uint8))
+    assert r1.stats["rounds"] == r0.stats["rounds"]
+    ms, mf, _, _ = O.verify(p.x, y1, p.E, p.Delta)
+    assert r1.stats["max_spatial_err"] == pytest.approx(ms, rel=1e-12, abs=0.0)
+    assert r1.stats["max_spectral_err"] == pytest.approx(mf, rel=1e-9)
+
+
 @pytest.mark.parametrize("mode,dt,shape", [(3, np.float32, (32, 64, 256)), (3, np.float64, (16, 32, 512)),
                                            (3, np.float32, (128, 1024)), (3, np.float64, (64, 128)),
                                            (4, np.float32, (16, 32, 512)), (4, np.float32, (2, 4, 512)),
