@@ -174,7 +174,9 @@ __device__ __forceinline__ int lds_skew(int i) {
   else return i;
 }
 
-template <typename T, int L, int E, bool INV, int SI, int SB, int s, int SK = 0>
+// SPL: exchange the real parts, then the imaginary parts, through an LDS area of one real
+// per entry (half the footprint, two more barriers per exchange; same arithmetic, same bits).
+template <typename T, int L, int E, bool INV, int SI, int SB, int s, int SK = 0, bool SPL = false>
 __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], cx<T>* lds, const cx<T>* tw, int b, int j) {
   using S = Sched<L, E>;
   if constexpr (s < S::nst) {
@@ -202,37 +204,58 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[E], cx<T>* lds, const cx<T
 #pragma unroll
         for (int r = 0; r < R; ++r) v[i + r * NB] = u[i][r];
     } else {
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < NB; ++i) {
+      // slot of element r of lane group i (the write side of the exchange)
+      auto wslot = [&](int i, int r) -> int {
         const int jb = j + i * P;
         const int base = (jb / Ns) * (Ns * R) + (jb & (Ns - 1));
         if constexpr (SK > 0 && (Ns * R) % (1 << SK) == 0) {
           // with Ns R a multiple of 2^SK, sk(base + r Ns) = sk-part of base + sk(r Ns):
           // one lane base, compile-time offsets
           const int lb = base + (jb / Ns) * ((Ns * R) >> SK) + ((jb & (Ns - 1)) >> SK);
-#pragma unroll
-          for (int r = 0; r < R; ++r) lds[(lb + lds_skew<SK>(r * Ns)) * SI + b * SB] = u[i][r];
+          return (lb + lds_skew<SK>(r * Ns)) * SI + b * SB;
         } else {
-#pragma unroll
-          for (int r = 0; r < R; ++r) lds[lds_skew<SK>(base + r * Ns) * SI + b * SB] = u[i][r];
+          return lds_skew<SK>(base + r * Ns) * SI + b * SB;
         }
-      }
-      __syncthreads();
+      };
       // j < P and P a power of two: sk(j + qP) = sk(j) + sk(qP), a lane base plus constants
       const int sj = lds_skew<SK>(j);
+      if constexpr (SPL) {
+        T* lr = reinterpret_cast<T*>(lds);
 #pragma unroll
-      for (int q = 0; q < E; ++q) v[q] = lds[(sj + lds_skew<SK>(q * P)) * SI + b * SB];
-      fft_stages<T, L, E, INV, SI, SB, s + 1, SK>(v, lds, tw, b, j);
+        for (int h = 0; h < 2; ++h) {
+          __syncthreads();
+#pragma unroll
+          for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int r = 0; r < R; ++r) lr[wslot(i, r)] = h ? u[i][r].im : u[i][r].re;
+          __syncthreads();
+#pragma unroll
+          for (int q = 0; q < E; ++q) {
+            const T x = lr[(sj + lds_skew<SK>(q * P)) * SI + b * SB];
+            if (h) v[q].im = x;
+            else v[q].re = x;
+          }
+        }
+      } else {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+          for (int r = 0; r < R; ++r) lds[wslot(i, r)] = u[i][r];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < E; ++q) v[q] = lds[(sj + lds_skew<SK>(q * P)) * SI + b * SB];
+      }
+      fft_stages<T, L, E, INV, SI, SB, s + 1, SK, SPL>(v, lds, tw, b, j);
     }
   }
 }
 
 // Length-L transform of the lane's registers.  Contains __syncthreads() when
 // the schedule has more than one stage: every lane of the block must call it.
-template <typename T, int L, int E, bool INV, int SI, int SB, int SK = 0>
+template <typename T, int L, int E, bool INV, int SI, int SB, int SK = 0, bool SPL = false>
 __device__ __forceinline__ void fft(cx<T> (&v)[E], cx<T>* lds, const cx<T>* tw, int b, int j) {
-  fft_stages<T, L, E, INV, SI, SB, 0, SK>(v, lds, tw, b, j);
+  fft_stages<T, L, E, INV, SI, SB, 0, SK, SPL>(v, lds, tw, b, j);
 }
 
 // ---------------------------------------------------------------------------

@@ -16,7 +16,10 @@ col_kernel(ColArgs<T> a) {
   using S = Sched<L, E>;
   constexpr int TW = S::twsize;
   constexpr int NW = (NT + 63) / 64;
-  __shared__ cx<T> lds[S::nst > 1 ? L * C : 1];
+  // the FP64 verification pass stores nothing, so registers allow four blocks per CU;
+  // its exchange goes through LDS one real part at a time to let them fit
+  constexpr bool SPL = (MODE == COL_VERIFY && sizeof(T) == 8);
+  __shared__ cx<T> lds[S::nst > 1 ? (SPL ? L * C / 2 : L * C) : 1];
   __shared__ cx<T> tws[TW > 0 ? TW : 1];
   __shared__ unsigned long long red_u[NW];
   __shared__ double red_d[NW];
@@ -112,7 +115,7 @@ col_kernel(ColArgs<T> a) {
     }
     fft<T, L, E, true, C, 1>(v, lds, tws, c, j);
   } else if constexpr (MODE == COL_VERIFY) {
-    fft<T, L, E, false, C, 1>(v, lds, tws, c, j);
+    fft<T, L, E, false, C, 1, 0, SPL>(v, lds, tws, c, j);
     const double D = st->Delta;
     unsigned long long cnt = 0;
     double mx = 0.0;
