@@ -99,14 +99,20 @@ def test_tiled_1d_passes_match_one_block_bitwise(dt):
         _check(p, y, s, dt)
 
 
-def test_batched_matches_single_calls_bitwise():
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_batched_matches_single_calls_bitwise(dt):
+    # a group of same-shape members and single calls run the same passes (FP64 fields: the
+    # closing pass fused with the verification's first pass, over 3 instances or 1)
     import torch
-    probs = [_member((64, 128), 400 + i, np.float32) for i in range(3)]
+    probs = [_member((64, 128), 400 + i, dt) for i in range(3)]
     ys, st, stats = _run(probs)
+    assert st == F.OK, (st, F.ffcz_last_error())
     for p, y, s in zip(probs, ys, stats):
         r = F.correct(torch.from_numpy(p.x).cuda(), torch.from_numpy(p.xb).cuda(), p.E, p.Delta, 200)
-        assert np.array_equal(r.y.cpu().numpy().view(np.uint32), y.view(np.uint32))
+        assert np.array_equal(r.y.cpu().numpy().view(np.uint8), y.view(np.uint8))
         assert r.stats["margin_used"] == s["margin_used"]  # same slot rule and fold order
+        assert r.stats["max_spatial_err"] == s["max_spatial_err"]
+        assert r.stats["max_spectral_err"] == s["max_spectral_err"]
 
 
 @pytest.mark.parametrize("shape", [(512, 1024), (256, 512)])
