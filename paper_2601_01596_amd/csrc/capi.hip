@@ -246,7 +246,8 @@ bool final_fused(const Plan& p) { return p.dt == FFCZ_F64 && p.H >= 2 && p.H <= 
 
 // Choose the loop passes' tile variants and the per-instance block counts that follow.
 // Plan of the init, closing and adjoint last-axis passes: the direct form (variant 3)
-// when the loop pass runs it on 128- or 256-entry FP32 rows, else the default tiles.
+// when the loop pass runs it on 128- or 256-entry FP32 rows, else the default tiles
+// (the closing pass of FP64 fields with rows of up to 512 entries: see final_fused).
 int init_variant(const Plan& p) {
   return (p.vz == 3 && p.dt == FFCZ_F32 && (p.H == 128 || p.H == 256)) ? 3 : 0;
 }

@@ -11,7 +11,8 @@ namespace ffcz {
 // tile variant (only the loop modes COL_FWD / COL_INV / COL_XPASS have variant 1).
 int col_block_cols(int dtype, int L, int v);
 // Rows per block of the last-axis kernels computing in this dtype (plan variants
-// 1 and 2 exist for ROW_LOOP, variant 2 for ROW_VERIFY).
+// 1 and 2 exist for ROW_LOOP, variant 2 for ROW_VERIFY and, on FP64 fields, for
+// ROW_FINAL and ROW_FINALV).
 int row_block_rows(int dtype, int H, int v);
 
 // dtype 0: float, 1: double.  args points to a ColArgs<T>.
