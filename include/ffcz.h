@@ -214,6 +214,12 @@ typedef struct {
 } ffcz_profile;
 void ffcz_profile_enable(int32_t on);
 int32_t ffcz_profile_read(ffcz_profile* out);
+/* Time only the pass kinds whose bit (1 << kind index above) is set in kinds; the
+ * other launches run without events, so the timed passes' neighbours are not
+ * slowed by event records.  0 (the default) times every kind.  Applies to calls
+ * made on this host thread while profiling is enabled; ffcz_profile_enable does
+ * not change it. */
+void ffcz_profile_select(uint32_t kinds);
 
 /* Plan tuning of the loop passes.  Each pass (y-forward/inverse, x-pass,
  * last-axis pass) can run with a few tilings (columns or rows per block) that

@@ -116,6 +116,7 @@ struct ProfEv {
 };
 struct Profiler {
   bool on = false;
+  uint32_t kinds = 0;  // kinds timed (bit per kind); 0: every kind
   std::vector<ProfEv> pending;
   std::vector<hipEvent_t> pool;
   double ms[PK_COUNT] = {0};
@@ -136,7 +137,7 @@ thread_local Profiler g_prof;
 // Wrap one launch.  round < 0 marks launches that always do work.
 template <typename F>
 hipError_t timed(int kind, int round, hipStream_t s, F&& launch) {
-  if (!g_prof.on) return launch();
+  if (!g_prof.on || (g_prof.kinds != 0 && !((g_prof.kinds >> kind) & 1u))) return launch();
   ProfEv ev{g_prof.get(), g_prof.get(), kind, round, round < 0 ? 1 : -1};
   if (ev.a) (void)hipEventRecord(ev.a, s);
   hipError_t e = launch();
@@ -1988,6 +1989,8 @@ void ffcz_profile_enable(int32_t on) {
     g_prof.cnt[k] = 0;
   }
 }
+
+void ffcz_profile_select(uint32_t kinds) { g_prof.kinds = kinds; }
 
 int32_t ffcz_profile_read(ffcz_profile* out) {
   if (!out) return fail(FFCZ_E_INVALID, "null pointer");

@@ -32,6 +32,7 @@ E_HIP = -5
 EXPORTS = ("ffcz_version", "ffcz_last_error", "ffcz_default_options", "ffcz_workspace_bytes",
            "ffcz_mask_bytes", "ffcz_suggest_margin", "ffcz_correct", "ffcz_correct_backward",
            "ffcz_batched_workspace_bytes", "ffcz_correct_batched", "ffcz_profile_enable", "ffcz_profile_read",
+           "ffcz_profile_select",
            "ffcz_copy", "ffcz_set_tuning", "ffcz_clear_tuning")
 
 PROFILE_KINDS = ("init", "y_fwd", "x_pass", "y_inv", "z_pass", "finalize", "verify_z", "verify_y", "verify_x",
@@ -147,6 +148,8 @@ def lib() -> ctypes.CDLL:
         L.ffcz_profile_enable.restype = None
         L.ffcz_profile_read.argtypes = [ctypes.POINTER(Profile)]
         L.ffcz_profile_read.restype = ctypes.c_int32
+        L.ffcz_profile_select.argtypes = [ctypes.c_uint32]
+        L.ffcz_profile_select.restype = None
         L.ffcz_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L.ffcz_copy.restype = ctypes.c_int32
         L.ffcz_set_tuning.argtypes = [ctypes.c_int32, ctypes.c_char_p]
@@ -233,6 +236,14 @@ def ffcz_correct_batched(dtype: int, instances, max_iter: int, opts: Optional[Op
 
 def ffcz_profile_enable(on: bool) -> None:
     lib().ffcz_profile_enable(1 if on else 0)
+
+
+def ffcz_profile_select(kinds=None) -> None:
+    """Time only the named pass kinds (names from PROFILE_KINDS); None times every kind."""
+    mask = 0
+    for k in (kinds or ()):
+        mask |= 1 << PROFILE_KINDS.index(k)
+    lib().ffcz_profile_select(mask)
 
 
 def ffcz_profile_read() -> dict:

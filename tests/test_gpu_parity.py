@@ -444,3 +444,26 @@ def test_library_loaded_before_torch():
     lines = [ln for ln in out.stdout.splitlines() if ln.startswith("status")]
     assert out.returncode == 0 and lines, (out.returncode, out.stdout[-2000:], out.stderr[-2000:])
     assert lines[-1].split()[1] in (str(F.OK), str(F.NOT_CONVERGED)), lines[-1]
+
+
+def test_profile_select_times_only_the_chosen_passes():
+    # per-launch events around the selected pass kind only; the same launches of that kind
+    # are counted as with every kind timed, and the output does not change
+    p = _problem((32, 32, 64), 91, np.float32)
+    try:
+        F.ffcz_profile_select(["x_pass"])
+        F.ffcz_profile_enable(True)
+        y1, r1 = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter)
+        sel = F.ffcz_profile_read()
+        F.ffcz_profile_select(None)
+        y2, r2 = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter)
+        full = F.ffcz_profile_read()
+    finally:
+        F.ffcz_profile_enable(False)
+        F.ffcz_profile_select(None)
+    assert r1.status == F.OK and r2.status == F.OK
+    assert np.array_equal(y1.view(np.uint8), y2.view(np.uint8))
+    assert sel["x_pass"][1] == full["x_pass"][1] == r1.stats["rounds"] + 1
+    assert sel["x_pass"][0] > 0.0
+    assert all(v[1] == 0 for k, v in sel.items() if k != "x_pass")
+    assert full["init"][1] == 1 and full["finalize"][1] == 1 and full["verify_x"][1] == 1
