@@ -183,23 +183,27 @@ def copy_ceiling(F, torch, nbytes, reps):
 
 
 def cpu_baseline(prob, rounds_gpu):
-    """Oracle on the host cores; rounds capped at 3, time scaled by checks run."""
+    """Oracle on the host cores; rounds capped at 3, time scaled by checks run.  The
+    correction is repeated until about 10 s of host work (at most 3 runs); the mean counts."""
     from oracle import ffcz as O
     cores = O.default_workers()
     cores = max(1, min(16, cores))
     O.set_workers(cores)
     cap = max(0, min(rounds_gpu, 3))
-    t0 = time.perf_counter()
-    r = O.correct(prob.x, prob.xb, prob.E, prob.Delta, cap)
-    t = time.perf_counter() - t0
+    times = []
+    while not times or (sum(times) < 10.0 and len(times) < 3):
+        t0 = time.perf_counter()
+        r = O.correct(prob.x, prob.xb, prob.E, prob.Delta, cap)
+        times.append(time.perf_counter() - t0)
+    t = sum(times) / len(times)
     scale = (rounds_gpu + 1) / (r.rounds + 1)
     t_est = t * scale
     gbs = prob.x.nbytes / t_est / 1e9
     return {"value": gbs, "unit": "GB/s", "cores": cores, "kind": "oracle",
             "seconds_per_check": t / (r.rounds + 1), "host": host_description(),
             "sample": (f"full {'x'.join(map(str, prob.x.shape))} FP32 input, oracle run for {r.rounds} of "
-                       f"{rounds_gpu} rounds ({t:.1f} s incl. FP64 verification), time scaled by checks "
-                       f"({rounds_gpu + 1}/{r.rounds + 1})")}
+                       f"{rounds_gpu} rounds, {len(times)} runs of {t:.1f} s mean ({sum(times):.1f} s in all, "
+                       f"incl. FP64 verification), time scaled by checks ({rounds_gpu + 1}/{r.rounds + 1})")}
 
 
 def host_description():
