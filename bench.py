@@ -260,11 +260,14 @@ def batch_leg(F, torch, W, steps):
     nbytes = sum(p.x.nbytes for p in probs)
 
     def timed(members):
-        res = F.correct_batched(members, 200)
+        # outputs and workspace allocated once and reused, as for the single-field steps
+        outs = [torch.empty_like(m[0]) for m in members]
+        ws = F.batched_workspace(members, 200)
+        res = F.correct_batched(members, 200, ws=ws, outs=outs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            res = F.correct_batched(members, 200)
+            res = F.correct_batched(members, 200, ws=ws, outs=outs)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps, res
 

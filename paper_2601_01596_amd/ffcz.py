@@ -362,25 +362,55 @@ def correct(x, xb, eps_s: float, delta_f: float, max_iter: int, *, margin: float
     return Result(y=y, status=st, stats=stats.as_dict(), masks=masks, viol=viol)
 
 
+def batched_workspace(members, max_iter: int, device=None):
+    """A workspace of ``ffcz_batched_workspace_bytes`` bytes for ``members`` (only their
+    shapes and dtype count), for reuse across ``correct_batched`` calls."""
+    torch = _torch()
+    if not members:
+        raise FFCzError(E_INVALID, "no members")
+    dt = _dtype_code(members[0][0])
+    insts = []
+    for m in members:
+        x = m[0]
+        sh = list(x.shape) + [1] * (3 - x.dim())
+        insts.append(Instance(x.dim(), 0, (ctypes.c_int64 * 3)(*sh), 0, 0, 0, 0.0, 0.0))
+    nbytes = ffcz_batched_workspace_bytes(dt, insts, max_iter)
+    if nbytes == 0:
+        raise FFCzError(E_SHAPE, ffcz_last_error())
+    return torch.empty(nbytes, dtype=torch.uint8, device=device if device is not None else members[0][0].device)
+
+
 def correct_batched(members, max_iter: int, *, margin: float = 0.0, fixed: bool = False, verify: bool = True,
-                    chunk: int = 4, graph: bool = True, tiled_1d_lg: int = 0, ws=None, check: bool = True):
+                    chunk: int = 4, graph: bool = True, tiled_1d_lg: int = 0, ws=None, check: bool = True,
+                    outs=None):
     """``ffcz_correct_batched`` over ``members = [(x, xb, eps_s, delta_f), ...]`` (device tensors).
 
-    Returns ``(outputs, status, per-member stats dicts)``.
+    ``outs``: optional output tensors, one per member (same shape and dtype as its x);
+    allocated here when omitted.  Returns ``(outputs, status, per-member stats dicts)``.
     """
     torch = _torch()
     if not members:
         return [], OK, []
+    if outs is not None and len(outs) != len(members):
+        raise FFCzError(E_INVALID, "outs must hold one tensor per member")
     dt = _dtype_code(members[0][0])
-    outs, insts = [], []
-    for (x, xb, E, D) in members:
+    insts = []
+    given = outs
+    outs = []
+    for i, (x, xb, E, D) in enumerate(members):
         _check_tensor(x, "x")
         _check_tensor(xb, "xb")
         if x.shape != xb.shape or x.dtype != xb.dtype or _dtype_code(x) != dt:
             raise FFCzError(E_INVALID, "members must pair tensors of one dtype")
         if x.dim() < 1 or x.dim() > 3:
             raise FFCzError(E_SHAPE, "members must have 1 to 3 dimensions")
-        y = torch.empty_like(x)
+        if given is None:
+            y = torch.empty_like(x)
+        else:
+            y = given[i]
+            _check_tensor(y, "out")
+            if y.shape != x.shape or y.dtype != x.dtype:
+                raise FFCzError(E_INVALID, "each output must match its member's shape and dtype")
         outs.append(y)
         sh = list(x.shape) + [1] * (3 - x.dim())
         insts.append(Instance(x.dim(), 0, (ctypes.c_int64 * 3)(*sh), x.data_ptr(), xb.data_ptr(), y.data_ptr(),

@@ -209,3 +209,26 @@ def test_full_batch_eeg_and_diffraction():
         f"hedm max {max(rounds[512:])} mean {np.mean(rounds[512:]):.1f}")
     for i in list(range(0, 512, 97)) + [512, 575]:
         _check(probs[i], outs[i].cpu().numpy(), stats[i], np.float32)
+
+
+def test_batched_reuses_outputs_and_workspace():
+    # caller-held outputs and workspace, reused across calls: the same bits as a call that
+    # allocates its own; outputs of the wrong shape are refused
+    import torch
+    probs = [_member((64, 128), 700, np.float32), _member((5000,), 701, np.float32),
+             _member((32, 64), 702, np.float32)]
+    mem = [(torch.from_numpy(p.x).cuda(), torch.from_numpy(p.xb).cuda(), p.E, p.Delta) for p in probs]
+    ref, st0, stats0 = F.correct_batched(mem, 200)
+    outs = [torch.empty_like(m[0]) for m in mem]
+    ws = F.batched_workspace(mem, 200)
+    for _ in range(2):
+        got, st, stats = F.correct_batched(mem, 200, ws=ws, outs=outs)
+        torch.cuda.synchronize()
+        assert st == st0 == F.OK
+        assert all(g is o for g, o in zip(got, outs))
+        for a, b in zip(ref, got):
+            assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+        assert stats == stats0
+    bad = [torch.empty(3, device="cuda")] + outs[1:]
+    with pytest.raises(F.FFCzError):
+        F.correct_batched(mem, 200, ws=ws, outs=bad)
