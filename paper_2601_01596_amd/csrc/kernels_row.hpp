@@ -79,7 +79,11 @@ row_kernel(RowArgs<T, TIO> a) {
   static_assert(!finalv || (sizeof(T) == 8 && sizeof(TIO) == 8), "the fused closing pass serves FP64 fields");
 
   __shared__ cx<T> lds[ROWS * LP];
-  __shared__ cx<T> tws[TW + H];
+  // rows of 1024 entries and more: the twiddle tables (about two rows' worth) are read
+  // from global memory, where the caches hold them, so that more blocks fit a CU
+  constexpr bool twg = H >= 1024;
+  __shared__ cx<T> tws_l[twg ? 1 : TW + H];
+  const cx<T>* tws = twg ? a.tw : tws_l;
   __shared__ unsigned long long red_u[NW];
   __shared__ double red_d[NW];
   __shared__ uint32_t sbits[(rec_s || use_s) ? ROWS * SW : 1];
@@ -107,7 +111,8 @@ row_kernel(RowArgs<T, TIO> a) {
   const int sj = lds_skew<SKW>(j);  // j < P, P a power of two: lds_skew<SKW>(j + qP) = sj + lds_skew<SKW>(qP)
   const cx<T>* rtw = tws + TW;
 
-  for (int i = t; i < TW + H; i += NT) tws[i] = a.tw[i];
+  if constexpr (!twg)
+    for (int i = t; i < TW + H; i += NT) tws_l[i] = a.tw[i];
 
   int kround = 0;
   bool rec = false;
