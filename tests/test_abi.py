@@ -59,3 +59,27 @@ def test_options_defaults():
     from paper_2601_01596_amd import ffcz
     o = ffcz.ffcz_default_options()
     assert o.verify_fp64 == 1 and o.fixed_iterations == 0 and o.masks_out is None
+
+
+def test_batched_binding_argument_checks():
+    # refused on the host before any device work: host tensors, an outs list of the wrong
+    # length, a workspace for no members
+    import torch
+    from paper_2601_01596_amd import ffcz
+    x = torch.zeros(8, 16)
+    mem = [(x, x.clone(), 1e-3, 1.0)]
+    with pytest.raises(ffcz.FFCzError):
+        ffcz.correct_batched(mem, 10)
+    with pytest.raises(ffcz.FFCzError):
+        ffcz.correct_batched(mem, 10, outs=[])
+    with pytest.raises(ffcz.FFCzError):
+        ffcz.batched_workspace([], 10)
+    assert ffcz.correct_batched([], 10) == ([], ffcz.OK, [])
+
+
+def test_profile_select_names():
+    from paper_2601_01596_amd import ffcz
+    ffcz.ffcz_profile_select(["x_pass", "z_pass"])
+    ffcz.ffcz_profile_select(None)
+    with pytest.raises(ValueError):
+        ffcz.ffcz_profile_select(["no_such_pass"])
