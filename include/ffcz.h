@@ -20,10 +20,15 @@
  *    (float) or FFCZ_F64 (double).  FFCZ_F32 runs its transforms in FP32 with
  *    twiddle tables evaluated in FP64 and rounded once; the output clamp and
  *    the bound verification always run in FP64.
- *  - Shapes: 1 <= ndim <= 3; unit extents are squeezed away; every remaining
- *    extent must be a power of two, the last one between 2 and 4096 and the
- *    others at most 2048 (FP32) / 1024 (FP64).  Violation counts refer to the
- *    half-spectrum of the squeezed shape.
+ *  - Shapes: 1 <= ndim <= 3, every extent >= 1; unit extents are squeezed
+ *    away.  Fields of two or three remaining axes need every extent a power of
+ *    two, the last one between 2 and 4096 and the others at most 2048 (FP32) /
+ *    1024 (FP64).  A field with one remaining axis takes any length up to 2^19
+ *    (a single point included): powers of two from 2 to 4096 run on the same
+ *    passes as 2D/3D fields, every other length on the 1D signal path of
+ *    ffcz_correct_batched (four-step or Bluestein DFT), which records no masks
+ *    and no per-check counts.  Violation counts refer to the half-spectrum of
+ *    the squeezed shape.
  *  - stream is a hipStream_t (NULL = the null stream).  Work is stream-ordered.
  *  - Return value: an ffcz_status.  Negative values are errors (the output is
  *    unspecified); ffcz_last_error() then describes the cause.
@@ -134,7 +139,12 @@ size_t ffcz_mask_bytes(int32_t ndim, const int64_t* shape, int32_t rounds);
  * y = x + eps to FP32 perturbs every spectral component by about
  * sigma * sqrt(N/2) with sigma^2 = mean(ulp(x)^2)/12; mu keeps eight of these
  * inside the shrunk f-cube: mu = max(2^-16, 8 sigma sqrt(N/2) / Delta),
- * capped at 0.5.  Reads x (device) once; blocks until *mu_out is written. */
+ * capped at 0.5.  Reads x (device) once; blocks until *mu_out is written.
+ * The device reduction needs scratch: workspace (256-byte aligned) holds at
+ * least 1025 doubles (any ffcz_workspace_bytes() size does), and the result
+ * comes back through mu_out with a status as return value, so that the
+ * library allocates nothing.  Returns FFCZ_E_SHAPE / FFCZ_E_INVALID /
+ * FFCZ_E_WORKSPACE for an unsupported shape, bad argument or short workspace. */
 int32_t ffcz_suggest_margin(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x_orig,
                             double delta_f, void* workspace, size_t workspace_bytes, void* stream,
                             double* mu_out);
@@ -150,7 +160,11 @@ int32_t ffcz_suggest_margin(int32_t dtype, int32_t ndim, const int64_t* shape, c
  *   workspace / workspace_bytes  device scratch of ffcz_workspace_bytes() bytes
  *   stats   NULL or a host struct filled on return
  * The call blocks on the host once per graph_chunk rounds to read the device
- * done-flag, and at the end for the statistics. */
+ * done-flag, and at the end for the statistics and the status.  With
+ * fixed_iterations = 1, stats = NULL and verify_fp64 = 0 nothing is reported,
+ * so the call is fully asynchronous (no host synchronisation) and returns
+ * FFCZ_OK once the work is enqueued; non-finite input is then not detected
+ * (its entries are taken as zero error). */
 int32_t ffcz_correct(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x_orig,
                      const void* x_base, void* x_out, double eps_s, double delta_f,
                      int32_t max_iter, const ffcz_options* opts, void* workspace,
@@ -175,10 +189,12 @@ size_t ffcz_batched_workspace_bytes(int32_t dtype, int32_t count, const ffcz_ins
 /* Alg. 1 on many fields of uneven size in one call (the paper treats 1D, 2D
  * and 3D data alike, Sec. IV-C).  Members of the same 2D shape share every
  * launch (their spectra are stacked; each keeps its own bounds, counts and
- * done-flag); 1D members of any length 2..2^19 run one block per signal, the
- * whole loop inside one launch, with a length-L DFT by four-step FFTs and, for
- * lengths that are not powers of two, Bluestein's chirp-z convolution; 3D
- * members run one after another.  Options as in ffcz_correct except that masks
+ * done-flag); 1D members take any length 1..2^19, with a length-L DFT by
+ * four-step FFTs and, for lengths that are not powers of two, Bluestein's
+ * chirp-z convolution: those whose work length is below 2^tiled_1d_lg run one
+ * block per signal with the whole loop inside one launch, longer ones run as
+ * tiled passes (many blocks per signal) whose rounds the host enqueues in
+ * chunks, polling the signals' done-flags; 3D members run one after another.  Options as in ffcz_correct except that masks
  * and per-round counts are not recorded.  stats: NULL or a host array[count].
  * Returns the worst member status (negative if any member failed). */
 int32_t ffcz_correct_batched(int32_t dtype, int32_t count, const ffcz_instance* inst, int32_t max_iter,

@@ -12,7 +12,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .ffcz import DEFAULT_MU, project_s
+from .ffcz import DEFAULT_MU
 
 
 def dft_matrix_1d(n: int) -> np.ndarray:
@@ -34,6 +34,15 @@ def half_spectrum_indices(shape) -> np.ndarray:
     transform keeps: last-axis frequency ``0 .. n_last//2``."""
     idx = np.arange(int(np.prod(shape))).reshape(shape)
     return idx[..., : shape[-1] // 2 + 1].ravel()
+
+
+def clip_box(v: np.ndarray, b: float) -> np.ndarray:
+    """Euclidean projection onto the box ``[-b, b]`` per coordinate (Eq. 2, third line):
+    every coordinate beyond the bound is set to the bound, the rest are kept."""
+    out = np.array(v, dtype=np.float64, copy=True)
+    out[out > b] = b
+    out[out < -b] = -b
+    return out
 
 
 def dense_fft(eps: np.ndarray) -> np.ndarray:
@@ -58,7 +67,7 @@ def dense_correct(x, xb, E: float, Delta: float, max_iter: int, mu: float = DEFA
     Ep = E * (1.0 - mu)
     Dp = Delta * (1.0 - mu)
     eps = (np.asarray(xb, np.float64) - np.asarray(x, np.float64)).ravel()
-    eps, _, _ = project_s(eps, Ep)
+    eps = clip_box(eps, Ep)
     vh, vf = [], []
     max_imag = 0.0
     k = 0
@@ -69,9 +78,9 @@ def dense_correct(x, xb, E: float, Delta: float, max_iter: int, mu: float = DEFA
         vf.append(int(np.count_nonzero(bad)))
         if vf[-1] == 0 or k == max_iter:
             break
-        d = np.clip(d.real, -Dp, Dp) + 1j * np.clip(d.imag, -Dp, Dp)
+        d = clip_box(d.real, Dp) + 1j * clip_box(d.imag, Dp)
         e = Winv @ d
         max_imag = max(max_imag, float(np.max(np.abs(e.imag))))
-        eps, _, _ = project_s(e.real, Ep)
+        eps = clip_box(e.real, Ep)
         k += 1
     return eps.reshape(shape), k, vh, vf, max_imag

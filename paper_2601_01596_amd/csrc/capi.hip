@@ -169,6 +169,33 @@ int squeeze(int32_t ndim, const int64_t* shape, int64_t* sq) {
   return nd;
 }
 
+// Fields the multidimensional plan does not take -- after squeezing, a single point or
+// one axis whose length is not a power of two in [2, 4096] -- run on the 1D signal path
+// (four-step or Bluestein DFT of any length up to 2^19) as a batch of one.
+bool route_1d(int32_t ndim, const int64_t* shape) {
+  if (ndim < 1 || ndim > 3 || !shape) return false;
+  for (int i = 0; i < ndim; ++i)
+    if (shape[i] < 1) return false;
+  int64_t sq[3];
+  const int nd = squeeze(ndim, shape, sq);
+  if (nd == 0) return true;
+  return nd == 1 && !(is_pow2(sq[0]) && sq[0] >= 2 && sq[0] <= kMaxLast);
+}
+
+ffcz_instance one_instance(int32_t ndim, const int64_t* shape, const void* x, const void* xb, void* y, double E,
+                           double D) {
+  ffcz_instance in;
+  memset(&in, 0, sizeof(in));
+  in.ndim = ndim;
+  for (int i = 0; i < 3; ++i) in.shape[i] = i < ndim ? shape[i] : 1;
+  in.x_orig = x;
+  in.x_base = xb;
+  in.x_out = y;
+  in.eps_s = E;
+  in.delta_f = D;
+  return in;
+}
+
 // Partial-sum slots of the on-device margin reduction of one field: a field of
 // n points uses ulp_slots(n) of them (about 16 Ki points per slot), the same
 // in a single call and in a batch, so both derive the same mu.
@@ -876,7 +903,11 @@ struct HostBuf {
     return e;
   }
 };
-thread_local HostBuf g_host_state, g_host_init, g_host_misc, g_host_sig;
+thread_local HostBuf g_host_state, g_host_init, g_host_misc;
+// staging of the 1D members (descriptors, then their loop states), owned by the calling
+// thread and handed to the thread that drives those members, so that no pinned buffer is
+// allocated or freed per call on a short-lived thread (hipHostFree synchronises the device)
+thread_local HostBuf g_host_sig, g_host_sigstate;
 
 // Private streams (default priority): one to capture graphs on, one for the
 // 1D members of a batch, which run beside the grouped members.
@@ -1107,15 +1138,16 @@ std::string tune_key_z(const Plan& p) {
   return buf;
 }
 
+// no_time: take the table's decisions (or the defaults) without timing anything.
 template <typename T>
-int32_t tune_plan(Plan& p, char* ws, hipStream_t s, bool rec) {
+int32_t tune_plan(Plan& p, char* ws, hipStream_t s, bool rec, bool no_time = false) {
   const std::string pre = device_arch() + (p.dt == FFCZ_F32 ? " f32" : " f64");
   char buf[256];
   int vy = 0, vx = 0, vz = 0;
   Ctx c{&p, ws, s};
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIPCHK(hipStreamIsCapturing(s, &cs));
-  const bool may_time = !rec && cs == hipStreamCaptureStatusNone;
+  const bool may_time = !rec && !no_time && cs == hipStreamCaptureStatusNone;
   const char* twb = (const char*)c.twT();
   if (p.nd == 3 && p.Ly >= 64) {
     snprintf(buf, sizeof(buf), "%s y L=%d cols=%lld outer=%lld", pre.c_str(), p.Ly, (long long)p.ncols,
@@ -1170,9 +1202,14 @@ int32_t pretune_group(const Plan& p0, char* ws, hipStream_t s) {
 // One correction over the B instances of a plan.  inst[b] supplies pointers and
 // bounds, mus[b] the margins; mus null (one FP32 instance) derives mu from x on
 // the device, between the state set-up and the first pass.
+// host_state: when given (one entry per instance, ordinary host memory), the call
+// allocates nothing: the loop state is read back into it, the rounds run as plain
+// launches (no graph) and the tile plans come from the table or the defaults.
 template <typename T>
 int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* mus, int32_t max_iter,
-                      const ffcz_options& o, char* ws, hipStream_t s, ffcz_stats* stats, int32_t* status) {
+                      const ffcz_options& o, char* ws, hipStream_t s, ffcz_stats* stats, int32_t* status,
+                      DevState* host_state = nullptr) {
+  const bool no_alloc = host_state != nullptr;
   Plan p = p0;
   Ctx c{&p, ws, s};
   const int64_t vstride = max_iter + 2;
@@ -1229,23 +1266,24 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
   }
   HIPCHK(write_twiddles(c));
   {
-    const int32_t tr = tune_plan<T>(p, ws, s, rec);
+    const int32_t tr = tune_plan<T>(p, ws, s, rec, no_alloc);
     if (tr != FFCZ_OK) return tr;
   }
   HIPCHK(timed(PK_INIT, -1, s, [&] { return row_T<T>(ROW_INIT, c, nullptr, c.Z(), smask); }));
 
   const int chunk = o.graph_chunk > 0 ? o.graph_chunk : 4;
-  HIPCHK(g_host_state.reserve(sizeof(DevState) * p.B));
-  DevState* hs = (DevState*)g_host_state.p;
+  if (!no_alloc) HIPCHK(g_host_state.reserve(sizeof(DevState) * p.B));
+  DevState* hs = no_alloc ? host_state : (DevState*)g_host_state.p;
   int enq = 0;
-  const bool sync_needed = !(o.fixed_iterations && stats == nullptr);
+  // asynchronous only when nothing is reported: fixed rounds, no statistics, no verification
+  const bool sync_needed = !(o.fixed_iterations && stats == nullptr && !o.verify_fp64);
   if (o.fixed_iterations) {
     // exactly max_iter blocks plus the final check: no polling needed
     for (int r = 0; r <= max_iter; ++r) HIPCHK(enqueue_round<T>(c, r, viol, vstr, fmask, smask));
   } else {
     // a chunk of rounds, captured once in a hipGraph (unless per-launch timing is on)
     hipGraphExec_t gexec = nullptr;
-    if (o.use_graph && !g_prof.on) {
+    if (o.use_graph && !g_prof.on && !no_alloc) {
       GraphKey key{{(int64_t)p.dt, p.nd, p.B, p.n[0], p.n[1], p.n[2], (int64_t)(uintptr_t)ws, (int64_t)(uintptr_t)viol,
                     vstr, (int64_t)(uintptr_t)fmask, (int64_t)(uintptr_t)smask, chunk, max_iter, p.vy, p.vx, p.vz}};
       gexec = g_graphs.find(key);
@@ -1530,7 +1568,7 @@ int32_t batch_plan(int32_t dt, int32_t count, const ffcz_instance* inst, int32_t
     const int nd = squeeze(in.ndim, in.shape, sq);
     if (nd <= 1) {
       const int64_t L = nd == 0 ? 1 : sq[0];
-      if (L < 2 || L > (int64_t)1 << 19) return fail(FFCZ_E_SHAPE, "1D lengths must be in [2, 2^19]");
+      if (L > (int64_t)1 << 19) return fail(FFCZ_E_SHAPE, "1D lengths must be at most 2^19");
       bp.sig_ids.push_back(i);
       continue;
     }
@@ -1729,12 +1767,12 @@ hipError_t sig_launch(int dt, int mode, int lgMc, const BatchPlan& bp, char* ws,
 }
 
 int32_t run_sigs(const BatchPlan& bp, const ffcz_instance* inst, const double* mus, int32_t max_iter,
-                 const ffcz_options& o, char* ws, hipStream_t s) {
+                 const ffcz_options& o, char* ws, hipStream_t s, HostBuf& hsig, HostBuf& hstate) {
   const int ns = (int)bp.sig_ids.size();
   if (ns == 0) return FFCZ_OK;
   // own staging buffer: the grouped members reuse g_host_init while these copies may be in flight
-  HIPCHK(g_host_sig.reserve(sizeof(SigDesc) * ns + sizeof(int32_t) * ns));
-  SigDesc* hd = (SigDesc*)g_host_sig.p;
+  HIPCHK(hsig.reserve(sizeof(SigDesc) * ns + sizeof(int32_t) * ns));
+  SigDesc* hd = (SigDesc*)hsig.p;
   int32_t* ho = (int32_t*)(hd + ns);
   for (int k = 0; k < ns; ++k) {
     const ffcz_instance& in = inst[bp.sig_ids[k]];
@@ -1816,8 +1854,8 @@ int32_t run_sigs(const BatchPlan& bp, const ffcz_instance* inst, const double* m
   }
   // rounds in chunks; every round pass returns at entry once its signal's loop has ended
   const int chunk = o.graph_chunk > 0 ? o.graph_chunk : 4;
-  HIPCHK(g_host_state.reserve(sizeof(SigStats) * ns));
-  SigStats* hs = (SigStats*)g_host_state.p;
+  HIPCHK(hstate.reserve(sizeof(SigStats) * ns));
+  SigStats* hs = (SigStats*)hstate.p;
   for (int enq = 0;; enq += chunk) {
     for (int r = 0; r < chunk; ++r) {
       for (int lg : tiled) {
@@ -1911,6 +1949,18 @@ __global__ void __launch_bounds__(256) copy_kernel(uint4* __restrict__ dst, cons
 __global__ void copy_tail_kernel(unsigned char* __restrict__ dst, const unsigned char* __restrict__ src, int n) {
   if ((int)threadIdx.x < n) dst[threadIdx.x] = src[threadIdx.x];
 }
+
+// Makes the caller's stream wait for the side stream on every exit after the fork, so no
+// 1D launch still writes the caller's buffers once the call has returned.
+struct SideJoin {
+  hipStream_t s = nullptr, s1 = nullptr;
+  ~SideJoin() {
+    if (s1 && s1 != s) {
+      (void)hipEventRecord(g_streams.join, s1);
+      (void)hipStreamWaitEvent(s, g_streams.join, 0);
+    }
+  }
+};
 
 // The thread that drives the 1D members of a mixed batch; joined on every exit path.
 struct SigWorker {
@@ -2028,6 +2078,10 @@ void ffcz_default_options(ffcz_options* o) {
 }
 
 size_t ffcz_workspace_bytes(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max_iter) {
+  if (route_1d(ndim, shape)) {
+    const ffcz_instance in = one_instance(ndim, shape, nullptr, nullptr, nullptr, 0.0, 0.0);
+    return ffcz_batched_workspace_bytes(dtype, 1, &in, max_iter < 0 ? 0 : max_iter);
+  }
   Plan p;
   std::string keep = g_err;
   if (make_plan(dtype, ndim, shape, max_iter < 0 ? 0 : max_iter, 1, p) != FFCZ_OK) return 0;
@@ -2036,6 +2090,7 @@ size_t ffcz_workspace_bytes(int32_t dtype, int32_t ndim, const int64_t* shape, i
 }
 
 size_t ffcz_mask_bytes(int32_t ndim, const int64_t* shape, int32_t rounds) {
+  if (route_1d(ndim, shape)) return 0;  // the 1D signal path records no masks
   Plan p;
   std::string keep = g_err;
   if (rounds < 0 || make_plan(FFCZ_F32, ndim, shape, rounds, 1, p) != FFCZ_OK) return 0;
@@ -2045,21 +2100,32 @@ size_t ffcz_mask_bytes(int32_t ndim, const int64_t* shape, int32_t rounds) {
 
 int32_t ffcz_suggest_margin(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x, double delta_f,
                             void* ws, size_t ws_bytes, void* stream, double* mu_out) {
-  Plan p;
-  int32_t r = make_plan(dtype, ndim, shape, 0, 1, p);
-  if (r != FFCZ_OK) return r;
+  int64_t N = 1;
+  if (route_1d(ndim, shape)) {
+    int64_t sq[3];
+    const int nd = squeeze(ndim, shape, sq);
+    if (nd == 1) N = sq[0];
+    if (N > (int64_t)1 << 19) return fail(FFCZ_E_SHAPE, "1D lengths must be at most 2^19");
+    if (dtype != FFCZ_F32 && dtype != FFCZ_F64) return fail(FFCZ_E_INVALID, "dtype must be FFCZ_F32 or FFCZ_F64");
+  } else {
+    Plan p;
+    int32_t r = make_plan(dtype, ndim, shape, 0, 1, p);
+    if (r != FFCZ_OK) return r;
+    N = p.N;
+  }
   if (!x || !mu_out) return fail(FFCZ_E_INVALID, "null pointer");
   if (!std::isfinite(delta_f) || delta_f < 0) return fail(FFCZ_E_INVALID, "delta_f must be finite and >= 0");
   if (dtype == FFCZ_F64) {
     *mu_out = std::ldexp(1.0, -16);
     return FFCZ_OK;
   }
-  if (!ws || ws_bytes < p.off_ulp + sizeof(double) * (kUlpSlots + 1))
-    return fail(FFCZ_E_WORKSPACE, "workspace too small");
+  // the reduction's slots sit at the start of the workspace
+  if (!ws || ws_bytes < sizeof(double) * (kUlpSlots + 1) || ((uintptr_t)ws & 255))
+    return fail(FFCZ_E_WORKSPACE, "workspace too small or misaligned");
   hipStream_t s = (hipStream_t)stream;
-  double* slots = (double*)((char*)ws + p.off_ulp);
-  const int nsl = ulp_slots(p.N);
-  const MarginJob job{(const float*)x, p.N, delta_f};
+  double* slots = (double*)ws;
+  const int nsl = ulp_slots(N);
+  const MarginJob job{(const float*)x, N, delta_f};
   hipLaunchKernelGGL(ulp_part_kernel, dim3((unsigned)nsl), dim3(256), 0, s, job, (const MarginJob*)nullptr, slots);
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL(margin_kernel, dim3(1), dim3(256), 0, s, (const double*)slots, job,
@@ -2075,6 +2141,19 @@ int32_t ffcz_suggest_margin(int32_t dtype, int32_t ndim, const int64_t* shape, c
 int32_t ffcz_correct(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x, const void* xb, void* y,
                      double eps_s, double delta_f, int32_t max_iter, const ffcz_options* opts, void* ws,
                      size_t ws_bytes, void* stream, ffcz_stats* stats) {
+  if (route_1d(ndim, shape)) {
+    // one signal of any length on the 1D path, as a batch of one
+    if (opts && (opts->masks_out || opts->viol_per_round))
+      return fail(FFCZ_E_INVALID, "masks and per-check counts are recorded for power-of-two fields only");
+    if (!x || !xb || !y) return fail(FFCZ_E_INVALID, "null data pointer");
+    const ffcz_instance in = one_instance(ndim, shape, x, xb, y, eps_s, delta_f);
+    ffcz_stats st;
+    memset(&st, 0, sizeof(st));
+    const int32_t r = ffcz_correct_batched(dtype, 1, &in, max_iter, opts, ws, ws_bytes, stream, &st);
+    if (r == FFCZ_E_NONFINITE) g_err = "x or x_hat holds NaN or Inf";
+    if (stats && st.status == r) *stats = st;
+    return r;
+  }
   Plan p;
   int32_t r = make_plan(dtype, ndim, shape, max_iter, 1, p);
   if (r != FFCZ_OK) return r;
@@ -2191,6 +2270,7 @@ int32_t ffcz_correct_batched(int32_t dtype, int32_t count, const ffcz_instance* 
   // 1D members on a side stream forked from the caller's, driven by a worker thread (the tiled
   // classes poll their done-flags), so they run beside the grouped members' rounds
   hipStream_t s1 = s;
+  SideJoin side;  // declared before the worker: on an early return the worker is joined first
   SigWorker worker;
   if (!bp.sig_ids.empty() && !bp.groups.empty()) {
     for (size_t g = 0; g < bp.groups.size(); ++g) {
@@ -2202,18 +2282,22 @@ int32_t ffcz_correct_batched(int32_t dtype, int32_t count, const ffcz_instance* 
     s1 = g_streams.side;
     HIPCHK(hipEventRecord(g_streams.fork, s));
     HIPCHK(hipStreamWaitEvent(s1, g_streams.fork, 0));
+    side.s = s;
+    side.s1 = s1;
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
+    HostBuf& hsig = g_host_sig;  // this thread's buffers, lent to the worker
+    HostBuf& hstate = g_host_sigstate;
     worker.th = std::thread([&, dev, s1] {
       if (hipSetDevice(dev) != hipSuccess) {
         worker.rc = fail(FFCZ_E_HIP, "hipSetDevice failed on the 1D worker");
       } else {
-        worker.rc = run_sigs(bp, inst, mus.data(), max_iter, o, w, s1);
+        worker.rc = run_sigs(bp, inst, mus.data(), max_iter, o, w, s1, hsig, hstate);
       }
       if (worker.rc != FFCZ_OK) worker.err = g_err;
     });
   } else {
-    r = run_sigs(bp, inst, mus.data(), max_iter, o, w, s1);
+    r = run_sigs(bp, inst, mus.data(), max_iter, o, w, s1, g_host_sig, g_host_sigstate);
     if (r != FFCZ_OK) return r;
   }
   for (size_t g = 0; g < bp.groups.size(); ++g) {
@@ -2237,9 +2321,10 @@ int32_t ffcz_correct_batched(int32_t dtype, int32_t count, const ffcz_instance* 
   }
   if (s1 != s) {
     worker.join();
-    if (worker.rc != FFCZ_OK) return fail(worker.rc, worker.err);
+    side.s1 = nullptr;  // joined here, with its errors reported
     HIPCHK(hipEventRecord(g_streams.join, s1));
     HIPCHK(hipStreamWaitEvent(s, g_streams.join, 0));
+    if (worker.rc != FFCZ_OK) return fail(worker.rc, worker.err);
   }
   r = collect_sigs(bp, inst, mus.data(), o, w, s, stats, status.data());
   if (r != FFCZ_OK) return r;
@@ -2252,6 +2337,7 @@ int32_t ffcz_correct_batched(int32_t dtype, int32_t count, const ffcz_instance* 
 
 int32_t ffcz_correct_backward(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t rounds, const void* masks,
                               const void* gy, void* gb, void* ws, size_t ws_bytes, void* stream) {
+  if (route_1d(ndim, shape)) return fail(FFCZ_E_SHAPE, "the adjoint needs a power-of-two field (masks are recorded there)");
   Plan p;
   int32_t r = make_plan(dtype, ndim, shape, rounds, 1, p);
   if (r != FFCZ_OK) return r;

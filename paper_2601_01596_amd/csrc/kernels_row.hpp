@@ -39,14 +39,14 @@ __device__ __forceinline__ float round_io<float>(double v) { return __double2flo
 template <>
 __device__ __forceinline__ double round_io<double>(double v) { return v; }
 
-// Move y one representable step toward x until |y - x| <= E holds in FP64.
+// Move y one representable step toward x until |y - x| <= E holds in FP64.  The
+// loop ends: every step moves y strictly toward x, and y = x satisfies the test for
+// any E >= 0 (a NaN x or y fails the comparison and leaves at once).  With y the
+// rounding of x + eps, |eps| <= E, it takes at most a step or two.
 template <typename TIO>
 __device__ __forceinline__ TIO closing_clamp(TIO y, TIO x, double E) {
-  for (int it = 0; it < 64; ++it) {
-    if (fabs((double)y - (double)x) <= E) return y;
-    y = nextafter(y, x);
-  }
-  return (fabs((double)y - (double)x) <= E) ? y : x;
+  while (fabs((double)y - (double)x) > E) y = nextafter(y, x);
+  return y;
 }
 
 // Long radix-16 rows need more than the 128 registers of four waves per SIMD.

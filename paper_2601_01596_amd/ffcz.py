@@ -293,6 +293,27 @@ def _check_tensor(t, name):
         raise FFCzError(E_INVALID, f"{name} must be contiguous")
 
 
+def _check_like(t, ref, name):
+    """``t`` must be a contiguous tensor of ``ref``'s shape, dtype and device (a wrong
+    size would let the kernels write past it)."""
+    if not t.is_contiguous():
+        raise FFCzError(E_INVALID, f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(ref.shape) or t.dtype != ref.dtype or t.device != ref.device:
+        raise FFCzError(E_INVALID, f"{name} must match shape {tuple(ref.shape)}, dtype {ref.dtype} and "
+                                   f"device {ref.device}")
+
+
+def _check_bytes(t, nbytes: int, device, name):
+    """``t`` must be a contiguous uint8 device tensor on ``device`` of at least ``nbytes`` bytes."""
+    torch = _torch()
+    if not t.is_contiguous():
+        raise FFCzError(E_INVALID, f"{name} must be contiguous")
+    if t.dtype != torch.uint8 or t.device != device:
+        raise FFCzError(E_INVALID, f"{name} must be a uint8 tensor on {device}")
+    if t.numel() < nbytes:
+        raise FFCzError(E_WORKSPACE, f"{name} holds {t.numel()} bytes, {nbytes} needed")
+
+
 def copy_(dst, src):
     """dst[:] = src with the library's streaming copy kernel, on the current stream."""
     torch = _torch()
@@ -334,11 +355,19 @@ def correct(x, xb, eps_s: float, delta_f: float, max_iter: int, *, margin: float
     _check_tensor(xb, "xb")
     if x.shape != xb.shape or x.dtype != xb.dtype:
         raise FFCzError(E_INVALID, "x and xb must have the same shape and dtype")
+    if x.device != xb.device:
+        raise FFCzError(E_INVALID, "x and xb must be on one device")
     dt = _dtype_code(x)
     shape = tuple(x.shape)
-    y = torch.empty_like(x) if out is None else out
+    if out is None:
+        y = torch.empty_like(x)
+    else:
+        _check_like(out, x, "out")
+        y = out
     if ws is None:
         ws = workspace(dt, shape, max_iter, x.device)
+    else:
+        _check_bytes(ws, ffcz_workspace_bytes(dt, shape, max_iter), x.device, "ws")
     opts = ffcz_default_options()
     opts.margin_rel = float(margin)
     opts.fixed_iterations = 1 if fixed else 0
@@ -347,7 +376,10 @@ def correct(x, xb, eps_s: float, delta_f: float, max_iter: int, *, margin: float
     opts.use_graph = 1 if graph else 0
     masks = None
     if record_masks:
-        masks = torch.zeros(ffcz_mask_bytes(shape, max_iter), dtype=torch.uint8, device=x.device)
+        nb = ffcz_mask_bytes(shape, max_iter)
+        if nb == 0:
+            raise FFCzError(E_SHAPE, f"no masks are recorded for shape {shape}")
+        masks = torch.zeros(nb, dtype=torch.uint8, device=x.device)
         opts.masks_out = masks.data_ptr()
     viol = None
     if record_viol:
@@ -408,19 +440,22 @@ def correct_batched(members, max_iter: int, *, margin: float = 0.0, fixed: bool 
             y = torch.empty_like(x)
         else:
             y = given[i]
-            _check_tensor(y, "out")
-            if y.shape != x.shape or y.dtype != x.dtype:
-                raise FFCzError(E_INVALID, "each output must match its member's shape and dtype")
+            _check_like(y, x, "out")
         outs.append(y)
         sh = list(x.shape) + [1] * (3 - x.dim())
         insts.append(Instance(x.dim(), 0, (ctypes.c_int64 * 3)(*sh), x.data_ptr(), xb.data_ptr(), y.data_ptr(),
                               float(E), float(D)))
     dev = members[0][0].device
+    for x, xb, _, _ in members:
+        if x.device != dev or xb.device != dev:
+            raise FFCzError(E_INVALID, "every member must be on one device")
+    nbytes = ffcz_batched_workspace_bytes(dt, insts, max_iter)
+    if nbytes == 0:
+        raise FFCzError(E_SHAPE, ffcz_last_error())
     if ws is None:
-        nbytes = ffcz_batched_workspace_bytes(dt, insts, max_iter)
-        if nbytes == 0:
-            raise FFCzError(E_SHAPE, ffcz_last_error())
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    else:
+        _check_bytes(ws, nbytes, dev, "ws")
     opts = ffcz_default_options()
     opts.margin_rel = float(margin)
     opts.fixed_iterations = 1 if fixed else 0
@@ -443,8 +478,14 @@ def correct_backward(grad_y, masks, rounds: int, ws=None):
     _check_tensor(grad_y, "grad_y")
     dt = _dtype_code(grad_y)
     shape = tuple(grad_y.shape)
+    nb = ffcz_mask_bytes(shape, rounds)
+    if nb == 0:
+        raise FFCzError(E_SHAPE, f"no masks exist for shape {shape} and {rounds} rounds")
+    _check_bytes(masks, nb, grad_y.device, "masks")
     if ws is None:
         ws = workspace(dt, shape, rounds, grad_y.device)
+    else:
+        _check_bytes(ws, ffcz_workspace_bytes(dt, shape, rounds), grad_y.device, "ws")
     gb = torch.empty_like(grad_y)
     stream = torch.cuda.current_stream(grad_y.device).cuda_stream
     st = ffcz_correct_backward(dt, shape, rounds, masks.data_ptr(), grad_y.data_ptr(), gb.data_ptr(),
@@ -462,7 +503,8 @@ def _autograd():
 
         The forward records 1-bit clip masks per round; the backward replays the
         rounds in reverse with masks in place of clips (no stored iterates).
-        ``x`` is treated as a constant.
+        Since ``y = x + eps_K(x_hat - x)``, the gradient with respect to ``x`` is
+        ``dL/dy - dL/dx_hat`` (returned when ``x`` requires it).
         """
 
         @staticmethod
@@ -476,8 +518,10 @@ def _autograd():
         @staticmethod
         def backward(ctx, gy):
             (masks,) = ctx.saved_tensors
-            gb = correct_backward(gy.contiguous(), masks, ctx.K)
-            return gb, None, None, None, None, None
+            gy = gy.contiguous()
+            gb = correct_backward(gy, masks, ctx.K)
+            gx = gy - gb if ctx.needs_input_grad[1] else None
+            return gb, gx, None, None, None, None
 
     return FFCzCorrect
 

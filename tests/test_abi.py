@@ -45,7 +45,7 @@ def test_size_queries_and_shape_rules():
     w = ffcz.ffcz_workspace_bytes(ffcz.F32, (64, 64, 64), 200)
     # two FP32 half-spectra with 128-byte padded rows: 64*64*(33 -> 48) * 8 bytes each
     assert w >= 2 * 64 * 64 * 48 * 8
-    assert ffcz.ffcz_workspace_bytes(ffcz.F32, (64, 63, 64), 10) == 0   # not a power of two
+    assert ffcz.ffcz_workspace_bytes(ffcz.F32, (64, 63, 64), 10) == 0   # not a power of two (3D)
     assert ffcz.ffcz_workspace_bytes(ffcz.F32, (2, 2, 2, 2), 10) == 0   # ndim 4
     assert ffcz.ffcz_workspace_bytes(ffcz.F64, (1, 64, 1), 10) > 0       # squeezes to 1D
     assert ffcz.ffcz_workspace_bytes(ffcz.F32, (0, 64, 64), 10) == 0     # an empty extent
@@ -75,6 +75,43 @@ def test_batched_binding_argument_checks():
     with pytest.raises(ffcz.FFCzError):
         ffcz.batched_workspace([], 10)
     assert ffcz.correct_batched([], 10) == ([], ffcz.OK, [])
+
+
+def test_binding_checks_outputs_masks_and_workspaces():
+    # the checks behind correct(out=..., ws=...), correct_backward(masks, ws=...) and
+    # correct_batched(ws=..., outs=...), exercised on host tensors: a wrong shape, dtype,
+    # device, layout or byte count is refused before any pointer reaches the library
+    import torch
+    from paper_2601_01596_amd import ffcz
+    x = torch.zeros(8, 16)
+    ffcz._check_like(torch.empty(8, 16), x, "out")
+    for bad in (torch.empty(8, 15), torch.empty(8, 16, dtype=torch.float64), torch.empty(16, 8).t(),
+                torch.empty(8, 16, device="meta")):
+        with pytest.raises(ffcz.FFCzError):
+            ffcz._check_like(bad, x, "out")
+    cpu = torch.device("cpu")
+    ffcz._check_bytes(torch.empty(100, dtype=torch.uint8), 100, cpu, "ws")
+    for bad, n in ((torch.empty(99, dtype=torch.uint8), 100), (torch.empty(100, dtype=torch.float32), 100),
+                   (torch.empty(100, dtype=torch.uint8, device="meta"), 100),
+                   (torch.empty(200, dtype=torch.uint8)[::2], 100)):
+        with pytest.raises(ffcz.FFCzError):
+            ffcz._check_bytes(bad, n, cpu, "ws")
+    # host tensors are refused by every convenience
+    with pytest.raises(ffcz.FFCzError):
+        ffcz.correct(x, x.clone(), 1e-3, 1.0, 10)
+    with pytest.raises(ffcz.FFCzError):
+        ffcz.correct_backward(x, torch.zeros(10, dtype=torch.uint8), 1)
+
+
+def test_one_dimensional_fields_of_any_length_have_a_workspace():
+    # single 1D fields of any length up to 2^19 run on the signal path: a workspace, no masks
+    from paper_2601_01596_amd import ffcz
+    for L in (1, 3, 4097, 31000, 2 ** 19):
+        assert ffcz.ffcz_workspace_bytes(ffcz.F32, (L,), 200) > 0, L
+        assert ffcz.ffcz_mask_bytes((L,), 3) == 0
+    assert ffcz.ffcz_workspace_bytes(ffcz.F32, (1, 1, 1), 10) > 0
+    assert ffcz.ffcz_workspace_bytes(ffcz.F32, (2 ** 19 + 1,), 10) == 0
+    assert ffcz.ffcz_mask_bytes((4096,), 3) > 0  # powers of two up to 4096 keep the field passes
 
 
 def test_profile_select_names():

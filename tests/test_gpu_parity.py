@@ -76,8 +76,10 @@ def test_shapes_fp32(shape):
     y, res = run_gpu(p.x, p.xb, p.E, p.Delta, p.max_iter, record_viol=True)
     orc = O.correct(p.x, p.xb, p.E, p.Delta, p.max_iter, mu=res.stats["margin_used"])
     _check_fp32(p, y, res, orc)
+    # the violation count of every check both ran, within 0.1 % (+2)
     v = res.viol.cpu().numpy()
-    assert abs(int(v[0]) - orc.viol[0]) <= 2 + 1e-3 * orc.viol[0]
+    for k in range(min(res.stats["rounds"], orc.rounds) + 1):
+        assert abs(int(v[k]) - orc.viol[k]) <= 2 + 1e-3 * orc.viol[k], (k, int(v[k]), orc.viol[k])
 
 
 @pytest.mark.parametrize("shape", [(2048, 64), (2048, 4, 8)])

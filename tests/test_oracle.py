@@ -284,6 +284,45 @@ def test_suggest_margin_formula_on_constant_field():
     assert mu == pytest.approx(expect, rel=1e-12)
 
 
+def _rounding_noise(x32, eps):
+    """Re/Im of DFT(fl32(y) - y) for y = x + eps formed in FP64: the spectral
+    perturbation an FP32 output adds (Eq. 3 applied to the rounding errors)."""
+    y = x32.astype(np.float64) + eps
+    r = y.astype(np.float32).astype(np.float64) - y
+    D = ffcz.fft(r)
+    # interior last-axis frequencies: no self-conjugate entries, every Re and Im is a
+    # sum of N rounding errors weighted by cos^2 or sin^2 averaging 1/2
+    inner = D[..., 1: x32.shape[-1] // 2]
+    return np.concatenate([inner.real.ravel(), inner.imag.ravel()])
+
+
+@pytest.mark.parametrize("field", ["grf", "lognormal", "eeg"])
+def test_suggest_margin_matches_measured_fp32_rounding_noise(field):
+    # The margin is 8 standard deviations of the spectral perturbation that rounding
+    # y = x + eps to FP32 causes.  That standard deviation is a property of the data, not
+    # of the formula: measure it from DFT(fl32(y) - y) and require suggest_margin's
+    # sigma sqrt(N/2) to agree within 5 % both ways (a dropped 1/12 or sqrt(N) for
+    # sqrt(N/2) is off by 3.5x or 1.41x).  The largest perturbation must also stay
+    # inside the margin, which is what the margin is for.
+    if field == "grf":
+        x = W.grf((32, 32, 32), 2.0, 21)
+    elif field == "lognormal":
+        x = W.lognormal((32, 32, 32), 2.5, 22)
+    else:
+        x = W.eeg_signal(23, 31000)
+    x32 = x.astype(np.float32)
+    E = W.spatial_bound(x32, 1e-3)
+    eps = rng(24).uniform(-E, E, x.shape)
+    noise = _rounding_noise(x32, eps)
+    measured = float(np.sqrt(np.mean(noise * noise)))
+    D = 1.0
+    mu = ffcz.suggest_margin(x32, D)
+    assert mu > ffcz.DEFAULT_MU and mu < 0.5  # the formula, not a clamp, decides here
+    predicted = mu * D / 8.0
+    assert predicted == pytest.approx(measured, rel=0.05), (field, predicted / measured)
+    assert float(np.max(np.abs(noise))) <= mu * D
+
+
 # ---------------------------------------------------------------- adjoint
 
 def _fixed_map(x, E, D, K, mu):
