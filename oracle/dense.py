@@ -84,3 +84,34 @@ def dense_correct(x, xb, E: float, Delta: float, max_iter: int, mu: float = DEFA
         eps = clip_box(e.real, Ep)
         k += 1
     return eps.reshape(shape), k, vh, vf, max_imag
+
+
+def dense_correct_edits(x, xb, Ep: float, Dc: float, Dp: float, max_iter: int):
+    """Alg. 1 with dense matrices and its edit bookkeeping over the FULL spectrum.
+
+    The check counts ``|Re|, |Im| > Dc``, the f-projection clips to ``Dp`` and the
+    s-projection to ``Ep`` (the guard clip first).  Returns ``(eps, rounds,
+    spat_edits, freq_edits)``: every s-clip displacement summed per point (guard
+    included) and every f-clip displacement summed per coefficient, all N of them.
+    """
+    shape = x.shape
+    N = int(np.prod(shape))
+    W = dft_matrix(shape)
+    Winv = W.conj().T / N
+    raw = (np.asarray(xb, np.float64) - np.asarray(x, np.float64)).ravel()
+    eps = clip_box(raw, Ep)
+    spat = eps - raw
+    freq = np.zeros(N, dtype=np.complex128)
+    k = 0
+    while True:
+        d = W @ eps
+        bad = (np.abs(d.real) > Dc) | (np.abs(d.imag) > Dc)
+        if not np.any(bad) or k == max_iter:
+            break
+        dc = clip_box(d.real, Dp) + 1j * clip_box(d.imag, Dp)
+        freq += dc - d
+        e = (Winv @ dc).real
+        eps = clip_box(e, Ep)
+        spat += eps - e
+        k += 1
+    return eps.reshape(shape), k, spat.reshape(shape), freq.reshape(shape)

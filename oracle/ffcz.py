@@ -198,6 +198,8 @@ class Result:
     max_spatial_err: float
     max_spectral_err: float
     masks: Optional[Masks] = None
+    spat_edits: Optional[np.ndarray] = None   # sum of ProjectOntoSCube displacements (Alg. 1)
+    freq_edits: Optional[np.ndarray] = None   # sum of ProjectOntoFCube displacements, half-spectrum
 
 
 def _check_args(x, xb, E, Delta, max_iter):
@@ -216,7 +218,8 @@ def _check_args(x, xb, E, Delta, max_iter):
 
 def correct(x, xb, E: float, Delta: float, max_iter: int, *, mu: Optional[float] = None,
             fixed: bool = False, record_masks: bool = False, out_dtype=None,
-            verify_output: bool = True) -> Result:
+            verify_output: bool = True, progress=None, record_edits: bool = False,
+            thresholds: Optional[tuple] = None) -> Result:
     """Alg. 1 (alternating projection-correction), FP64 throughout.
 
     ``x``: original data, ``xb``: base-compressor reconstruction (same shape),
@@ -224,6 +227,12 @@ def correct(x, xb, E: float, Delta: float, max_iter: int, *, mu: Optional[float]
     ``max_iter``: cap on projection blocks.  ``fixed``: run exactly ``max_iter``
     blocks regardless of the check (used for differentiation).
     ``out_dtype``: dtype of ``y`` (default: the dtype of ``x``).
+    ``progress``: optional callable ``(k, v_k)`` invoked after each check (no effect on results).
+    ``record_edits``: keep the edit bookkeeping of Alg. 1 -- ``spat_edits`` sums every
+    displacement ``eps' - eps`` of ProjectOntoSCube (the guard clip included) and
+    ``freq_edits`` every ``delta' - delta`` of ProjectOntoFCube (half-spectrum), so that
+    ``eps_final = (x_hat - x) + spat_edits + IFFT(freq_edits)``.
+    ``thresholds``: ``(E_p, Delta_c, Delta_p)`` overriding the ones derived from ``mu``.
     """
     x = np.asarray(x)
     xb = np.asarray(xb)
@@ -233,14 +242,20 @@ def correct(x, xb, E: float, Delta: float, max_iter: int, *, mu: Optional[float]
         mu = DEFAULT_MU if out_dtype == np.float64 else suggest_margin(x, Delta)
     shape = x.shape
     x64 = x.astype(np.float64)
-    Ep = E * (1.0 - mu)
-    Dc, Dp = spectral_thresholds(Delta, mu, out_dtype)
+    if thresholds is None:
+        Ep = E * (1.0 - mu)
+        Dc, Dp = spectral_thresholds(Delta, mu, out_dtype)
+    else:
+        Ep, Dc, Dp = (float(v) for v in thresholds)
 
     # Alg. 1, first statement: the spatial error of the base reconstruction.
-    eps = xb.astype(np.float64) - x64
+    eps_raw = xb.astype(np.float64) - x64
     # Guard: the method starts inside the s-cube (Sec. IV-B).
-    eps, keep, n_guard = project_s(eps, Ep)
+    eps, keep, n_guard = project_s(eps_raw, Ep)
     masks = Masks([keep], [None], [None]) if record_masks else None
+    # edit bookkeeping (Alg. 1): the guard clip is the first ProjectOntoSCube displacement
+    spat_edits = (eps - eps_raw) if record_edits else None
+    freq_edits = None
 
     viol: List[int] = []
     s_clipped = [n_guard]
@@ -250,15 +265,22 @@ def correct(x, xb, E: float, Delta: float, max_iter: int, *, mu: Optional[float]
         delta = fft(eps)                          # FFT
         v = count_violations(delta, Dc)           # CheckConvergence
         viol.append(v)
+        if progress is not None:
+            progress(k, v)
         if v == 0 and not fixed:
             converged = True
             break
         if k == max_iter:
             converged = v == 0
             break
-        delta, kre, kim = project_f(delta, Dp)    # ProjectOntoFCube
-        eps = ifft(delta, shape)                  # IFFT
-        eps, ks, ns = project_s(eps, Ep)          # ProjectOntoSCube
+        delta_p, kre, kim = project_f(delta, Dp)  # ProjectOntoFCube
+        if record_edits:
+            d = delta_p - delta                   # freq_edits += delta' - delta
+            freq_edits = d if freq_edits is None else freq_edits + d
+        eps_pre = ifft(delta_p, shape)            # IFFT
+        eps, ks, ns = project_s(eps_pre, Ep)      # ProjectOntoSCube
+        if record_edits:
+            spat_edits = spat_edits + (eps - eps_pre)  # spat_edits += eps' - eps
         s_clipped.append(ns)
         if masks is not None:
             masks.s.append(ks)
@@ -278,9 +300,12 @@ def correct(x, xb, E: float, Delta: float, max_iter: int, *, mu: Optional[float]
         ms, mf, _, ok = verify(x, y, E, Delta)
         if not ok and status == OK:
             status = VERIFY_FAILED
+    if record_edits and freq_edits is None:
+        freq_edits = np.zeros(fft(np.zeros(shape)).shape, dtype=np.complex128)
     return Result(y=y, eps=eps, status=status, rounds=k, converged=converged,
                   viol=viol, s_clipped=s_clipped, margin=float(mu),
-                  max_spatial_err=ms, max_spectral_err=mf, masks=masks)
+                  max_spatial_err=ms, max_spectral_err=mf, masks=masks,
+                  spat_edits=spat_edits, freq_edits=freq_edits)
 
 
 def apply_f_mask(G: np.ndarray, keep_re: np.ndarray, keep_im: np.ndarray) -> np.ndarray:

@@ -6,7 +6,6 @@ Tolerances as in test_gpu_parity: FP64 1e-12 with equal rounds, FP32 1e-5 (round
 within one), FP64 re-verification of both bounds for every member.
 """
 
-import sys
 
 import numpy as np
 import pytest
@@ -14,13 +13,12 @@ import pytest
 from oracle import ffcz as O
 from paper_2601_01596_amd import ffcz as F
 from paper_2601_01596_amd import workloads as W
+from tests.progress import say
 from tests.gpu_util import rel_err
 
 pytestmark = pytest.mark.gpu
 
 
-def say(*a):
-    print(*a, file=sys.stderr, flush=True)
 
 
 def _member(shape, seed, dt, q=90.0, r=1e-2):

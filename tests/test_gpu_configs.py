@@ -9,7 +9,6 @@
 """
 
 import os
-import sys
 
 import numpy as np
 import pytest
@@ -18,6 +17,7 @@ from oracle import ffcz as O
 from oracle import spectrum as SP
 from paper_2601_01596_amd import ffcz as F
 from paper_2601_01596_amd import workloads as W
+from tests.progress import say
 from tests.gpu_util import rel_err, run_gpu, unpack_masks
 
 pytestmark = pytest.mark.gpu
@@ -27,8 +27,6 @@ def _workers():
     O.set_workers(max(1, min(16, O.default_workers())))
 
 
-def say(*a):
-    print(*a, file=sys.stderr, flush=True)
 
 
 def _fp64_reverify_torch(x, y, E, D):
@@ -113,10 +111,11 @@ def test_kolmogorov_1024_fp32_matches_oracle_at_full_size():
     del x, xb, r
     torch.cuda.empty_cache()
     say(f"[cfg] FP64 oracle at 1024^3 ({k} rounds on the GPU, mu {mu:.3e})")
-    orc = O.correct(p.x, p.xb, E, D, 500, mu=mu, verify_output=False)
+    prog = lambda kk, v: say(f"[cfg] oracle check {kk}: {v} violations")
+    orc = O.correct(p.x, p.xb, E, D, 500, mu=mu, verify_output=False, progress=prog)
     if k != orc.rounds:
         assert abs(k - orc.rounds) <= 1
-        orc = O.correct(p.x, p.xb, E, D, k, mu=mu, fixed=True, verify_output=False)
+        orc = O.correct(p.x, p.xb, E, D, k, mu=mu, fixed=True, verify_output=False, progress=prog)
     e = np.abs(y.astype(np.float64) - orc.y)
     rel = float(e.max()) / float(np.abs(orc.y).max())
     de = np.abs((y.astype(np.float64) - p.x.astype(np.float64)) - orc.eps)
@@ -250,7 +249,9 @@ def test_grad256_fixed50_adjoint_vs_oracle_and_finite_differences():
     gmax = float(np.abs(g64).max())
     bad = []
     worst = 0.0
-    for (i, j, k) in vox:
+    for vi, (i, j, k) in enumerate(vox):
+        if vi % 16 == 0:
+            say(f"[grad] finite differences: voxel {vi} of 64")
         xp = xb64.clone()
         xp[i, j, k] += h
         xm = xb64.clone()

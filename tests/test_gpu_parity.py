@@ -149,8 +149,14 @@ def test_argument_errors():
     r = F.correct(x, xb, 1.0, float("nan"), 5, check=False)
     assert r.status == F.E_INVALID
     ws = torch.empty(64, dtype=torch.uint8, device="cuda")
-    r = F.correct(x, xb, 1.0, 1.0, 5, ws=ws, check=False)
-    assert r.status == F.E_WORKSPACE
+    # the binding refuses a short workspace before the call; the C ABI refuses it too
+    with pytest.raises(F.FFCzError) as ei:
+        F.correct(x, xb, 1.0, 1.0, 5, ws=ws, check=False)
+    assert ei.value.status == F.E_WORKSPACE
+    y = torch.empty_like(x)
+    st = F.ffcz_correct(F.F32, (8, 8, 8), x.data_ptr(), xb.data_ptr(), y.data_ptr(), 1.0, 1.0, 5, None,
+                        ws.data_ptr(), ws.numel(), 0, None)
+    assert st == F.E_WORKSPACE
     bad = torch.zeros((8, 6, 8), dtype=torch.float32, device="cuda")
     with pytest.raises(F.FFCzError):
         F.correct(bad, bad.clone(), 1.0, 1.0, 5)
