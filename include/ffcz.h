@@ -14,7 +14,8 @@
  * Conventions shared by every entry point
  *  - Every data pointer is a DEVICE pointer, 16-byte aligned, owned by the
  *    caller.  The library allocates no device memory: scratch comes from the
- *    caller's workspace.  Fields are C-ordered (last axis contiguous); the
+ *    caller's workspace (ffcz_correct_noalloc: from a fixed device array that
+ *    the library holds per GPU).  Fields are C-ordered (last axis contiguous); the
  *    real-to-complex half-spectrum runs along the last axis.
  *  - dtype selects the storage type of x, x_hat, y and gradients: FFCZ_F32
  *    (float) or FFCZ_F64 (double).  FFCZ_F32 runs its transforms in FP32 with
@@ -169,6 +170,34 @@ int32_t ffcz_correct(int32_t dtype, int32_t ndim, const int64_t* shape, const vo
                      const void* x_base, void* x_out, double eps_s, double delta_f,
                      int32_t max_iter, const ffcz_options* opts, void* workspace,
                      size_t workspace_bytes, void* stream, ffcz_stats* stats);
+
+/* Bytes of the fixed device scratch array behind ffcz_correct_noalloc (64 MiB). */
+#define FFCZ_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* ffcz_correct for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same correction, with the workspace taken from a fixed device array of
+ * FFCZ_NOALLOC_SCRATCH_BYTES bytes that the library holds, one copy per GPU,
+ * from the first call on that GPU until the process ends.  The call allocates
+ * nothing (no hipMalloc, no pinned staging, no graph instantiation): the
+ * rounds run as plain launches and the tile plans come from the tuning table
+ * or the defaults (nothing is timed).
+ *   Arguments and results as ffcz_correct, without workspace / workspace_bytes.
+ *   Shapes: fields that run on the passes of 2D/3D fields (every remaining
+ *   extent a power of two, as documented above); other 1D lengths return
+ *   FFCZ_E_SHAPE.  A shape and round cap needing more than
+ *   FFCZ_NOALLOC_SCRATCH_BYTES of workspace (ffcz_workspace_bytes) returns
+ *   FFCZ_E_WORKSPACE (for example 128^3 FP32 needs about 21 MB, 256^3 FP32
+ *   about 151 MB: refused).
+ *   The current device (hipGetDevice) must be the one holding x_orig, x_base,
+ *   x_out and the stream's work.
+ *   Every call on one GPU uses that GPU's single array and leaves the last
+ *   call's contents in it (the call sets up whatever must start at zero):
+ *   calls that overlap on one GPU -- from two host threads, or on two streams
+ *   not ordered with each other -- race on it and give undefined results. */
+int32_t ffcz_correct_noalloc(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x_orig,
+                             const void* x_base, void* x_out, double eps_s, double delta_f,
+                             int32_t max_iter, const ffcz_options* opts, void* stream, ffcz_stats* stats);
 
 /* One member of a batch: shape (ndim 1..3, unit extents squeezed), device
  * pointers as in ffcz_correct, and its own bounds. */

@@ -85,6 +85,11 @@ hipError_t launch_col(int dtype, int mode, int L, int v, const void* args, int64
 
 using namespace ffcz;
 
+// Scratch of ffcz_correct_noalloc: a fixed device array, one copy per GPU, held until the
+// process ends.
+constexpr size_t kScratchBytes = (size_t)FFCZ_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 namespace {
 
 thread_local std::string g_err;
@@ -1982,6 +1987,80 @@ int32_t worst(const std::vector<int32_t>& st) {
   return w;
 }
 
+// Checked arguments of a single-field call on the plan path.
+struct SingleCall {
+  Plan p;
+  ffcz_options o;
+  double mu = 0.0;
+  ffcz_instance in;
+};
+
+int32_t single_setup(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x, const void* xb, void* y,
+                     double eps_s, double delta_f, int32_t max_iter, const ffcz_options* opts, SingleCall& sc) {
+  int32_t r = make_plan(dtype, ndim, shape, max_iter, 1, sc.p);
+  if (r != FFCZ_OK) return r;
+  if (!x || !xb || !y) return fail(FFCZ_E_INVALID, "null data pointer");
+  if (x == xb || x == y) return fail(FFCZ_E_INVALID, "x_orig must not alias x_base or x_out");
+  if (!std::isfinite(eps_s) || eps_s < 0) return fail(FFCZ_E_INVALID, "eps_s must be finite and >= 0");
+  if (!std::isfinite(delta_f) || delta_f < 0) return fail(FFCZ_E_INVALID, "delta_f must be finite and >= 0");
+  if (((uintptr_t)x & 15) || ((uintptr_t)xb & 15) || ((uintptr_t)y & 15))
+    return fail(FFCZ_E_WORKSPACE, "workspace must be 256-byte and data 16-byte aligned");
+  if (opts) sc.o = *opts;
+  else ffcz_default_options(&sc.o);
+  if (sc.o.masks_out && sc.p.dt == FFCZ_F64 && col_block_cols(1, sc.p.Lx, 0) < 8)
+    return fail(FFCZ_E_SHAPE, "mask recording needs at least 8 columns per block");
+  // no margin given: FP64 takes 2^-16, FP32 derives mu from x on the device (no host round trip)
+  sc.mu = sc.o.margin_rel > 0.0 ? sc.o.margin_rel : (dtype == FFCZ_F64 ? std::ldexp(1.0, -16) : 0.0);
+  if (!(sc.mu < 1.0)) return fail(FFCZ_E_INVALID, "margin_rel must be in [0, 1)");
+  memset(&sc.in, 0, sizeof(sc.in));
+  sc.in.ndim = ndim;
+  for (int i = 0; i < ndim; ++i) sc.in.shape[i] = shape[i];
+  sc.in.x_orig = x;
+  sc.in.x_base = xb;
+  sc.in.x_out = y;
+  sc.in.eps_s = eps_s;
+  sc.in.delta_f = delta_f;
+  return FFCZ_OK;
+}
+
+// host_state: null for the ordinary call; else the no-allocation form (see correct_group).
+int32_t single_run(SingleCall& sc, char* ws, hipStream_t s, ffcz_stats* stats, DevState* host_state) {
+  const double* mus = sc.mu > 0.0 ? &sc.mu : nullptr;
+  int32_t status = FFCZ_OK;
+  const int32_t r =
+      sc.p.dt == FFCZ_F32
+          ? correct_group<float>(sc.p, &sc.in, mus, sc.p.max_iter, sc.o, ws, s, stats, &status, host_state)
+          : correct_group<double>(sc.p, &sc.in, mus, sc.p.max_iter, sc.o, ws, s, stats, &status, host_state);
+  if (r != FFCZ_OK) return r;
+  if (stats) stats->status = status;
+  if (status == FFCZ_E_NONFINITE) return fail(FFCZ_E_NONFINITE, "x or x_hat holds NaN or Inf");
+  if (status == FFCZ_VERIFY_FAILED) g_err = "FP64 re-verification failed";
+  return status;
+}
+
+// Scratch of ffcz_correct_noalloc (the array is declared at file scope, above): host
+// code never passes the array's name to a kernel (on the host it names a host-side
+// stand-in); it takes the device address hipGetSymbolAddress returns, once per device,
+// with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_m;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+int32_t scratch_on_current_device(char** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(FFCZ_E_HIP, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> g(g_scratch_m);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || ((uintptr_t)ptr & 255)) return fail(FFCZ_E_HIP, "scratch symbol address missing or misaligned");
+    g_scratch_ptr[dev] = (char*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FFCZ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2154,43 +2233,32 @@ int32_t ffcz_correct(int32_t dtype, int32_t ndim, const int64_t* shape, const vo
     if (stats && st.status == r) *stats = st;
     return r;
   }
-  Plan p;
-  int32_t r = make_plan(dtype, ndim, shape, max_iter, 1, p);
+  SingleCall sc;
+  int32_t r = single_setup(dtype, ndim, shape, x, xb, y, eps_s, delta_f, max_iter, opts, sc);
   if (r != FFCZ_OK) return r;
-  if (!x || !xb || !y) return fail(FFCZ_E_INVALID, "null data pointer");
-  if (x == xb || x == y) return fail(FFCZ_E_INVALID, "x_orig must not alias x_base or x_out");
-  if (!std::isfinite(eps_s) || eps_s < 0) return fail(FFCZ_E_INVALID, "eps_s must be finite and >= 0");
-  if (!std::isfinite(delta_f) || delta_f < 0) return fail(FFCZ_E_INVALID, "delta_f must be finite and >= 0");
-  if (!ws || ws_bytes < p.bytes) return fail(FFCZ_E_WORKSPACE, "workspace smaller than ffcz_workspace_bytes()");
-  if (((uintptr_t)ws & 255) || ((uintptr_t)x & 15) || ((uintptr_t)xb & 15) || ((uintptr_t)y & 15))
-    return fail(FFCZ_E_WORKSPACE, "workspace must be 256-byte and data 16-byte aligned");
-  ffcz_options o;
-  if (opts) o = *opts;
-  else ffcz_default_options(&o);
-  if (o.masks_out && p.dt == FFCZ_F64 && col_block_cols(1, p.Lx, 0) < 8)
-    return fail(FFCZ_E_SHAPE, "mask recording needs at least 8 columns per block");
-  hipStream_t s = (hipStream_t)stream;
-  // no margin given: FP64 takes 2^-16, FP32 derives mu from x on the device (no host round trip)
-  double mu = o.margin_rel > 0.0 ? o.margin_rel : (dtype == FFCZ_F64 ? std::ldexp(1.0, -16) : 0.0);
-  if (!(mu < 1.0)) return fail(FFCZ_E_INVALID, "margin_rel must be in [0, 1)");
-  const double* mus = mu > 0.0 ? &mu : nullptr;
-  ffcz_instance in;
-  memset(&in, 0, sizeof(in));
-  in.ndim = ndim;
-  for (int i = 0; i < ndim; ++i) in.shape[i] = shape[i];
-  in.x_orig = x;
-  in.x_base = xb;
-  in.x_out = y;
-  in.eps_s = eps_s;
-  in.delta_f = delta_f;
-  int32_t status = FFCZ_OK;
-  r = dtype == FFCZ_F32 ? correct_group<float>(p, &in, mus, max_iter, o, (char*)ws, s, stats, &status)
-                        : correct_group<double>(p, &in, mus, max_iter, o, (char*)ws, s, stats, &status);
+  if (!ws || ws_bytes < sc.p.bytes) return fail(FFCZ_E_WORKSPACE, "workspace smaller than ffcz_workspace_bytes()");
+  if ((uintptr_t)ws & 255) return fail(FFCZ_E_WORKSPACE, "workspace must be 256-byte and data 16-byte aligned");
+  return single_run(sc, (char*)ws, (hipStream_t)stream, stats, nullptr);
+}
+
+int32_t ffcz_correct_noalloc(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x, const void* xb,
+                             void* y, double eps_s, double delta_f, int32_t max_iter, const ffcz_options* opts,
+                             void* stream, ffcz_stats* stats) {
+  if (route_1d(ndim, shape))
+    return fail(FFCZ_E_SHAPE, "ffcz_correct_noalloc takes power-of-two fields only (the 1D signal path stages "
+                              "its descriptors in pinned host memory)");
+  SingleCall sc;
+  int32_t r = single_setup(dtype, ndim, shape, x, xb, y, eps_s, delta_f, max_iter, opts, sc);
   if (r != FFCZ_OK) return r;
-  if (stats) stats->status = status;
-  if (status == FFCZ_E_NONFINITE) return fail(FFCZ_E_NONFINITE, "x or x_hat holds NaN or Inf");
-  if (status == FFCZ_VERIFY_FAILED) g_err = "FP64 re-verification failed";
-  return status;
+  if (sc.p.bytes > kScratchBytes)
+    return fail(FFCZ_E_WORKSPACE, "ffcz_correct_noalloc: this shape and round cap need " +
+                                      std::to_string(sc.p.bytes) + " bytes of scratch, above the fixed " +
+                                      std::to_string(kScratchBytes) + " (FFCZ_NOALLOC_SCRATCH_BYTES)");
+  char* ws = nullptr;
+  r = scratch_on_current_device(&ws);
+  if (r != FFCZ_OK) return r;
+  DevState host_state;  // the loop state is read back into this (no pinned staging)
+  return single_run(sc, ws, (hipStream_t)stream, stats, &host_state);
 }
 
 size_t ffcz_batched_workspace_bytes(int32_t dtype, int32_t count, const ffcz_instance* inst, int32_t max_iter) {

@@ -33,7 +33,7 @@ EXPORTS = ("ffcz_version", "ffcz_last_error", "ffcz_default_options", "ffcz_work
            "ffcz_mask_bytes", "ffcz_suggest_margin", "ffcz_correct", "ffcz_correct_backward",
            "ffcz_batched_workspace_bytes", "ffcz_correct_batched", "ffcz_profile_enable", "ffcz_profile_read",
            "ffcz_profile_select",
-           "ffcz_copy", "ffcz_set_tuning", "ffcz_clear_tuning")
+           "ffcz_copy", "ffcz_set_tuning", "ffcz_clear_tuning", "ffcz_correct_noalloc")
 
 PROFILE_KINDS = ("init", "y_fwd", "x_pass", "y_inv", "z_pass", "finalize", "verify_z", "verify_y", "verify_x",
                  "adjoint_z", "adjoint_y", "adjoint_x")
@@ -133,6 +133,10 @@ def lib() -> ctypes.CDLL:
                                    ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                    ctypes.POINTER(Stats)]
         L.ffcz_correct.restype = ctypes.c_int32
+        L.ffcz_correct_noalloc.argtypes = [ctypes.c_int32, ctypes.c_int32, i64p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                           ctypes.POINTER(Options), ctypes.c_void_p, ctypes.POINTER(Stats)]
+        L.ffcz_correct_noalloc.restype = ctypes.c_int32
         L.ffcz_correct_backward.argtypes = [ctypes.c_int32, ctypes.c_int32, i64p, ctypes.c_int32, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                             ctypes.c_void_p]
@@ -211,6 +215,15 @@ def ffcz_correct(dtype: int, shape, x_ptr: int, xb_ptr: int, y_ptr: int, eps_s: 
                                   ctypes.byref(opts) if opts is not None else None, ctypes.c_void_p(ws_ptr),
                                   ws_bytes, ctypes.c_void_p(stream),
                                   ctypes.byref(stats) if stats is not None else None))
+
+
+def ffcz_correct_noalloc(dtype: int, shape, x_ptr: int, xb_ptr: int, y_ptr: int, eps_s: float, delta_f: float,
+                         max_iter: int, opts: Optional[Options], stream: int, stats: Optional[Stats]) -> int:
+    nd, arr = _shape(shape)
+    return int(lib().ffcz_correct_noalloc(dtype, nd, arr, ctypes.c_void_p(x_ptr), ctypes.c_void_p(xb_ptr),
+                                          ctypes.c_void_p(y_ptr), float(eps_s), float(delta_f), int(max_iter),
+                                          ctypes.byref(opts) if opts is not None else None,
+                                          ctypes.c_void_p(stream), ctypes.byref(stats) if stats is not None else None))
 
 
 def ffcz_correct_backward(dtype: int, shape, rounds: int, masks_ptr: int, grad_out_ptr: int, grad_base_ptr: int,
