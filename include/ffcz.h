@@ -199,6 +199,97 @@ int32_t ffcz_correct_noalloc(int32_t dtype, int32_t ndim, const int64_t* shape, 
                              const void* x_base, void* x_out, double eps_s, double delta_f,
                              int32_t max_iter, const ffcz_options* opts, void* stream, ffcz_stats* stats);
 
+/* ---------------------------------------------------------------------------
+ * Edit coding (Alg. 1 edit bookkeeping; CompactEdits and QuantizeEdits of
+ * Sec. IV-B and IV-D; applying edits, Sec. IV-B).
+ *
+ * The encoder runs the correction loop while summing every displacement of
+ * ProjectOntoSCube into the spatial edits s (the guard clip that puts the
+ * initial error inside the s-cube counts as the first) and every displacement
+ * of ProjectOntoFCube into the frequency edits f (a half-spectrum), so that
+ * eps_final = (x_hat - x) + s + IFFT(f).  The clip of the check that ends the
+ * loop never reaches the iterate and is not counted.  It then codes both:
+ *  - coordinates: s has N (the field's points, C order); f has 2 M, the Re and
+ *    Im parts of the M half-spectrum entries of the squeezed shape, entries in
+ *    C order, Re before Im;
+ *  - flags: bit i of byte b is set iff coordinate 8 b + i has a non-zero edit
+ *    (ceil(N / 8) and ceil(2 M / 8) bytes);
+ *  - codes: int32 rint(v / step), half to even, of the non-zero edits in
+ *    coordinate order (at the exclusive prefix count of the flags), with
+ *    step_s = 2 E 2^-m and step_f = 2 Delta 2^-m (each cube side cut into 2^m
+ *    steps; m = 16 in the paper).
+ * Shrinks: the paper shrinks both cubes by 2^-m so that dequantised edits stay
+ * inside.  The quantisation error of one domain also reaches the other through
+ * the transform, and the decoder rounds its output with no clamp, so by
+ * default the loop runs with q = safety 2^-m (safety 4) and
+ *   mu_f = max(q, output-rounding margin of ffcz_correct),
+ *   mu_s = q + spacing(max|x| + E) / E     (one output ulp),
+ * checking |Re|,|Im| > Delta (1 - mu_f), clipping to Delta (1 - 2 mu_f) and to
+ * E (1 - mu_s).  The decoded output is meant to be re-verified, not trusted. */
+
+typedef struct {
+  int32_t m;            /* code length (0: 16), at most 30                            */
+  int32_t pad;
+  double safety;        /* q = safety 2^-m (0: 4)                                     */
+  double mu_s;          /* given shrinks (both or neither; 0: derived as above)       */
+  double mu_f;
+  void* y_out;          /* nullable device field: also y = x + eps with the closing
+                           clamp of ffcz_correct, FP64-verified if opts asks for it  */
+  void* spat_edits_out; /* nullable device buffer: s, N values of dtype              */
+  void* freq_edits_out; /* nullable device buffer: f, 2 M values of dtype (Re, Im)   */
+} ffcz_encode_options;
+
+typedef struct {        /* host struct filled on return */
+  ffcz_stats loop;      /* the loop's statistics (verification fields: NaN without y_out) */
+  int64_t nnz_s;        /* spatial codes written (= set spatial flags)    */
+  int64_t nnz_f;        /* frequency codes written                        */
+  double step_s;        /* 2 E 2^-m                                       */
+  double step_f;        /* 2 Delta 2^-m                                   */
+  double mu_s;          /* shrinks in use                                 */
+  double mu_f;
+  int32_t m;
+  int32_t status;
+} ffcz_encode_stats;
+
+/* Fill *o with the defaults (m = 16, safety 4, derived shrinks, no extra outputs). */
+void ffcz_default_encode_options(ffcz_encode_options* o);
+
+/* Workspace bytes of ffcz_encode and ffcz_decode (the correction's workspace,
+ * both accumulators and the coding kernels' block offsets); 0 if unsupported. */
+size_t ffcz_encode_workspace_bytes(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max_iter);
+
+/* Alg. 1 with edit bookkeeping, CompactEdits and QuantizeEdits (lossless
+ * coding of the codes aside).
+ *   x_orig, x_base, eps_s, delta_f, max_iter, opts: as ffcz_correct (shapes
+ *     that run on the multidimensional passes only: every remaining extent a
+ *     power of two; other 1D lengths give FFCZ_E_SHAPE)
+ *   eopts       NULL for defaults
+ *   spat_flags  device, ceil(N / 8) bytes      spat_codes  device int32[N]
+ *   freq_flags  device, ceil(2 M / 8) bytes    freq_codes  device int32[2 M]
+ *     (codes: room for the worst case; the counts come back in stats)
+ *   workspace   ffcz_encode_workspace_bytes() bytes, 256-byte aligned
+ *   stats       NULL or a host struct filled on return
+ * Returns the loop's status (FFCZ_NOT_CONVERGED: the edits describe the last
+ * iterate), FFCZ_E_INVALID if a code does not fit int32.  Blocks until the
+ * code counts are known. */
+int32_t ffcz_encode(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x_orig, const void* x_base,
+                    double eps_s, double delta_f, int32_t max_iter, const ffcz_options* opts,
+                    const ffcz_encode_options* eopts, void* spat_flags, int32_t* spat_codes, void* freq_flags,
+                    int32_t* freq_codes, void* workspace, size_t workspace_bytes, void* stream,
+                    ffcz_encode_stats* stats);
+
+/* Applying edits (Sec. IV-B): y = x_hat + s + IFFT(f), with s and f
+ * dequantised from the flags and codes ffcz_encode wrote (code * step), the
+ * sum formed in FP64 and rounded once to dtype.  x_base is the base
+ * reconstruction the encoder was given; y must not alias it.  nnz_s / nnz_f:
+ * the number of codes in each set, checked against the set flags (a mismatch
+ * returns FFCZ_E_INVALID and leaves y unspecified).  Blocks until that check
+ * is read back. */
+int32_t ffcz_decode(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x_base,
+                    const void* spat_flags, const int32_t* spat_codes, int64_t nnz_s, const void* freq_flags,
+                    const int32_t* freq_codes, int64_t nnz_f, double step_s, double step_f, void* y_out,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
 /* One member of a batch: shape (ndim 1..3, unit extents squeezed), device
  * pointers as in ffcz_correct, and its own bounds. */
 typedef struct {

@@ -31,6 +31,7 @@
 
 #include "../../include/ffcz.h"
 #include "common.hpp"
+#include "kernels_edit.hpp"
 #include "kernels_sig.hpp"
 #include "launch.hpp"
 #include "sig_dispatch.hpp"
@@ -44,6 +45,10 @@ hipError_t launch_row_f64_f32io(int mode, int H, int v, const void* args, int64_
 hipError_t launch_sig_f32(int mode, int lgMc, const void* args, int nb, hipStream_t s);
 hipError_t launch_sig_f64(int mode, int lgMc, const void* args, int nb, hipStream_t s);
 hipError_t launch_sigt_f64(int mode, int iodt, int lgMc, const void* args, int nb, hipStream_t s);
+hipError_t launch_edit_row_f32(int mode, int H, const void* args, int64_t nb, hipStream_t s);
+hipError_t launch_edit_row_f64(int mode, int H, const void* args, int64_t nb, hipStream_t s);
+hipError_t launch_edit_col_f32(int mode, int L, const void* args, int64_t nb, hipStream_t s);
+hipError_t launch_edit_col_f64(int mode, int L, const void* args, int64_t nb, hipStream_t s);
 
 // Which instantiation family runs a mode: the loop in the data type, set-up and
 // verification in FP64 (SigArgs<double>).
@@ -79,6 +84,8 @@ int col_block_cols(int dtype, int L, int v) { return dtype == 0 ? tile_cols<floa
 int row_block_rows(int dtype, int H, int v) { return dtype == 0 ? tile_rows<float>(H, v) : tile_rows<double>(H, v); }
 
 hipError_t launch_col(int dtype, int mode, int L, int v, const void* args, int64_t nb, hipStream_t s) {
+  if (mode == COL_XEDIT || mode == COL_XUNDO)  // edit bookkeeping: default tiles only
+    return dtype == 0 ? launch_edit_col_f32(mode, L, args, nb, s) : launch_edit_col_f64(mode, L, args, nb, s);
   return dtype == 0 ? launch_col_f32(mode, L, v, args, nb, s) : launch_col_f64(mode, L, v, args, nb, s);
 }
 }  // namespace ffcz
@@ -241,7 +248,7 @@ struct Plan {
 };
 
 struct StateInit {
-  double E, Ep, Delta, Dc, Dp, inv_n, mu;
+  double E, Ep, Delta, Dc, Dp, inv_n, mu, mu_s;
   int32_t max_iter, fixed, record_masks, pad;
   const void* px;
   const void* pxb;
@@ -472,6 +479,7 @@ __global__ void state_init_kernel(DevState* st, int64_t B, const StateInit* arr,
     s.Dp = p.Dp;
     s.inv_n = p.inv_n;
     s.mu = p.mu;
+    s.mu_s = p.mu_s;
     s.max_iter = p.max_iter;
     s.fixed = p.fixed;
     s.record_masks = p.record_masks;
@@ -589,6 +597,80 @@ __global__ void __launch_bounds__(256) margin_kernel(const double* part, MarginJ
 }
 
 
+// max |x| partials of a field (one per slice, slices as in ulp_part_kernel), as the bits of
+// a non-negative double (which order as integers).
+template <typename TIO>
+__global__ void __launch_bounds__(256) absmax_part_kernel(const TIO* x, int64_t n, unsigned long long* part) {
+  __shared__ double red[4];
+  const int64_t nb = ulp_slots(n);
+  if ((int64_t)blockIdx.x >= nb) return;
+  const int64_t slice = (n + nb - 1) / nb;
+  const int64_t lo = std::min<int64_t>(n, (int64_t)blockIdx.x * slice);
+  const int64_t hi = std::min<int64_t>(n, lo + slice);
+  double m = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) m = fmax(m, fabs((double)x[i]));
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    part[blockIdx.x] = (unsigned long long)__double_as_longlong(fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
+}
+
+// Spacing of the dtype's grid just above v >= 0 (what an output of that size is rounded to).
+__device__ inline double grid_spacing(int dt, double v) {
+  if (dt == FFCZ_F32) {
+    const float f = __double2float_rn(v);
+    return (double)nextafterf(f, __builtin_huge_valf()) - (double)f;
+  }
+  return nextafter(v, __builtin_huge_val()) - v;
+}
+
+// Shrinks of the encoder, one block.  The paper shrinks both cubes by 2^-m so that the
+// quantised edits still land inside (Sec. IV-B).  That counts each edit's own rounding
+// only: the quantisation error of one domain also reaches the other through the
+// transform, and the decoder rounds its output without a clamp (it does not know x).  So
+// with q = safety 2^-m:
+//   mu_f = max(q, mu_out)  (mu_out: the output-rounding margin of the plain correction,
+//                           from the ulp partials for FP32 fields, 2^-16 for FP64),
+//   mu_s = q + spacing(max|x| + E) / E  (a whole output ulp, twice its rounding error),
+// capped at 1/4 and 1/2; the check runs at Delta (1 - mu_f), the f-projection at
+// Delta (1 - 2 mu_f) and the s-projection at E (1 - mu_s).
+__global__ void __launch_bounds__(256) encode_margin_kernel(const double* ulp_part, const unsigned long long* amax,
+                                                            int64_t n, int dt, double q, DevState* st) {
+  __shared__ double red[4];
+  __shared__ unsigned long long redm[4];
+  const int nslot = ulp_slots(n);
+  double s = 0.0;
+  unsigned long long mb = 0;
+  for (int k = threadIdx.x; k < nslot; k += 256) {
+    if (dt == FFCZ_F32) s += ulp_part[k];
+    mb = mb > amax[k] ? mb : amax[k];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off, 64);
+    const unsigned long long o = __shfl_xor(mb, off, 64);
+    mb = mb > o ? mb : o;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = s;
+    redm[threadIdx.x >> 6] = mb;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int w = 1; w < 4; ++w) redm[0] = redm[0] > redm[w] ? redm[0] : redm[w];
+  const double xm = __longlong_as_double((long long)redm[0]);
+  const double mu_out = dt == FFCZ_F32 ? margin_from_ulp2((red[0] + red[1]) + (red[2] + red[3]), n, st->Delta)
+                                       : 0x1p-16;
+  const double E = st->E;
+  const double mu_f = fmin(fmax(mu_out, q), 0.25);
+  const double mu_s = fmin(q + (E > 0.0 ? grid_spacing(dt, xm + E) / E : 0.0), 0.5);
+  st->mu = mu_f;
+  st->mu_s = mu_s;
+  st->Ep = E * (1.0 - mu_s);
+  st->Dc = st->Delta * (1.0 - mu_f);
+  st->Dp = st->Delta * (1.0 - 2.0 * mu_f);
+}
+
 // Per-round control, one block per instance: sum the x-pass partials into
 // v_k, fold the spatial-clip partials of the z-pass that produced the checked
 // iterate into the totals, and decide on the device whether the loop stops
@@ -688,6 +770,9 @@ struct Ctx {
   const Plan* p;
   char* ws;
   hipStream_t s;
+  // edit accumulators (encoder only): spatial, one value per point; frequency, laid out as Z
+  void* sacc = nullptr;
+  void* facc = nullptr;
   DevState* st() const { return (DevState*)(ws + p->off_state); }
   unsigned long long* viol() const { return (unsigned long long*)(ws + p->off_viol); }
   void* twT() const { return ws + p->off_twT; }
@@ -745,7 +830,7 @@ ColGeom geom_x(const Plan& p, int64_t pitch, int64_t plane) {
 template <typename T>
 hipError_t run_col(int dt, int mode, int v, const ColGeom& g, const Plan& p, const void* src, void* dst,
                    const void* tw, DevState* st, unsigned long long* part, uint8_t* fmask,
-                   hipStream_t s) {
+                   hipStream_t s, void* fedit = nullptr) {
   ColArgs<T> a;
   memset(&a, 0, sizeof(a));
   const int C = col_block_cols(dt, g.L, v);
@@ -765,6 +850,7 @@ hipError_t run_col(int dt, int mode, int v, const ColGeom& g, const Plan& p, con
   a.f_row_bytes = p.f_row_bytes;
   a.mrow_i = g.mrow_i;
   a.mrow_o = g.mrow_o;
+  a.fedit = (cx<T>*)fedit;
   const int64_t nb = g.outer * a.ncb;
   return launch_col(dt, mode, g.L, v, &a, nb, s);
 }
@@ -772,7 +858,7 @@ hipError_t run_col(int dt, int mode, int v, const ColGeom& g, const Plan& p, con
 template <typename T, typename TIO>
 hipError_t run_row(int tdt, int iodt, int mode, int v, const Plan& p, int64_t pitch, int64_t plane, const void* src,
                    void* dst, const void* tw, DevState* st, unsigned long long* part, uint32_t* smask,
-                   hipStream_t s, int64_t spitch = -1, int64_t splane = -1) {
+                   hipStream_t s, int64_t spitch = -1, int64_t splane = -1, void* sedit = nullptr) {
   RowArgs<T, TIO> a;
   memset(&a, 0, sizeof(a));
   a.src = (const cx<T>*)src;
@@ -792,6 +878,9 @@ hipError_t run_row(int tdt, int iodt, int mode, int v, const Plan& p, int64_t pi
   const int64_t nb = a.bpi * p.B;
   a.plane = plane;
   a.lg_rpp = p.lg_rpp;
+  a.sedit = (T*)sedit;
+  if (mode == ROW_INITE || mode == ROW_LOOPE || mode == ROW_DECODE)  // default tiles only
+    return tdt == 0 ? launch_edit_row_f32(mode, p.H, &a, nb, s) : launch_edit_row_f64(mode, p.H, &a, nb, s);
   if (tdt == 1 && iodt == 0) return launch_row_f64_f32io(mode, p.H, v, &a, nb, s);
   return tdt == 0 ? launch_row_f32(mode, p.H, v, &a, nb, s) : launch_row_f64(mode, p.H, v, &a, nb, s);
 }
@@ -799,6 +888,12 @@ hipError_t run_row(int tdt, int iodt, int mode, int v, const Plan& p, int64_t pi
 template <typename T>
 hipError_t row_T(int mode, const Ctx& c, const void* src, void* dst, uint32_t* smask) {
   const Plan& p = *c.p;
+  if (c.sacc && (mode == ROW_INIT || mode == ROW_LOOP)) {
+    // with edit bookkeeping: the staged pass on the default tiles
+    return run_row<T, T>(p.dt, p.dt, mode == ROW_INIT ? ROW_INITE : ROW_LOOPE, 0, p, p.pitch, p.plane, src, dst,
+                         (const char*)c.twT() + sizeof(cx<T>) * p.twz, c.st(), c.part(Ctx::PZ), smask, c.s, -1, -1,
+                         c.sacc);
+  }
   const int v = mode == ROW_LOOP ? p.vz : init_variant(p);
   const void* tw = (const char*)c.twT() + sizeof(cx<T>) * (v == 2 ? p.twz8 : p.twz);
   return run_row<T, T>(p.dt, p.dt, mode, v, p, p.pitch, p.plane, src, dst, tw, c.st(), c.part(Ctx::PZ), smask, c.s);
@@ -819,7 +914,8 @@ hipError_t enqueue_round(const Ctx& c, int r, unsigned long long* viol, int64_t 
     });
     if (e != hipSuccess) return e;
     e = timed(PK_XPASS, r, c.s, [&] {
-      return run_col<T>(p.dt, COL_XPASS, p.vx, geom_x(p, p.pitch, p.plane), p, c.A(), c.A(), twx, c.st(), px, fmask, c.s);
+      return run_col<T>(p.dt, c.facc ? COL_XEDIT : COL_XPASS, c.facc ? 0 : p.vx, geom_x(p, p.pitch, p.plane), p,
+                        c.A(), c.A(), twx, c.st(), px, fmask, c.s, c.facc);
     });
     if (e != hipSuccess) return e;
     e = launch_ctl(c, viol, vstride);
@@ -830,13 +926,35 @@ hipError_t enqueue_round(const Ctx& c, int r, unsigned long long* viol, int64_t 
     if (e != hipSuccess) return e;
   } else {
     e = timed(PK_XPASS, r, c.s, [&] {
-      return run_col<T>(p.dt, COL_XPASS, p.vx, geom_x(p, p.pitch, p.plane), p, c.Z(), c.A(), twx, c.st(), px, fmask, c.s);
+      return run_col<T>(p.dt, c.facc ? COL_XEDIT : COL_XPASS, c.facc ? 0 : p.vx, geom_x(p, p.pitch, p.plane), p,
+                        c.Z(), c.A(), twx, c.st(), px, fmask, c.s, c.facc);
     });
     if (e != hipSuccess) return e;
     e = launch_ctl(c, viol, vstride);
     if (e != hipSuccess) return e;
   }
   return timed(PK_ZPASS, r, c.s, [&] { return row_T<T>(ROW_LOOP, c, c.A(), c.Z(), smask); });
+}
+
+// The check that ends the loop (converged, or at the round cap) clips inside the x-pass, but
+// that clip never reaches the iterate; with edit bookkeeping its displacements went into
+// the frequency edits all the same.  Repeat that check's forward transforms from Z (which
+// still holds the last-axis R2C of the checked iterate) and subtract the same displacements.
+template <typename T>
+hipError_t enqueue_undo(const Ctx& c) {
+  const Plan& p = *c.p;
+  const char* twb = (const char*)c.twT();
+  const void* twy = twb + sizeof(cx<T>) * p.twy;
+  const void* twx = twb + sizeof(cx<T>) * p.twx;
+  if (p.nd == 3) {
+    hipError_t e = run_col<T>(p.dt, COL_FWD_NS, 0, geom_y(p, p.pitch, p.plane), p, c.Z(), c.A(), twy, c.st(), nullptr,
+                              nullptr, c.s);
+    if (e != hipSuccess) return e;
+    return run_col<T>(p.dt, COL_XUNDO, 0, geom_x(p, p.pitch, p.plane), p, c.A(), nullptr, twx, c.st(), nullptr,
+                      nullptr, c.s, c.facc);
+  }
+  return run_col<T>(p.dt, COL_XUNDO, 0, geom_x(p, p.pitch, p.plane), p, c.Z(), nullptr, twx, c.st(), nullptr,
+                    nullptr, c.s, c.facc);
 }
 
 // FP64 verification: last-axis R2C of y - x (max |y - x|), then the y and x
@@ -1204,6 +1322,53 @@ int32_t pretune_group(const Plan& p0, char* ws, hipStream_t s) {
   return tune_plan<T>(p, ws, s, false);
 }
 
+// Edit bookkeeping of an encoder call (null for a plain correction).
+struct EditCfg {
+  void* sacc;     // spatial accumulators: N values of the working type, C order
+  void* facc;     // frequency accumulators: laid out as the spectrum Z
+  bool derive;    // shrinks from x on the device; else mu_s / mu_f below
+  double q;       // safety 2^-m (derive)
+  double mu_s, mu_f;
+  bool want_y;    // close y = x + eps (and verify it when asked)
+  unsigned long long* amax;  // kUlpSlots partial slots of max |x| (derive)
+  double* mu_s_out;          // host: the spatial shrink in use, read back with the state
+};
+
+// Workspace of the encoder and decoder: the plan's, then the accumulators and the
+// coding kernels' block offsets.
+struct EditLayout {
+  int64_t ncs = 0, ncf = 0;  // spatial and frequency coordinates
+  int64_t nbs = 0, nbf = 0;  // coding blocks of each set
+  size_t off_S = 0, off_F = 0, off_offs = 0, off_offf = 0, off_tot = 0, off_amax = 0, bytes = 0;
+  int64_t spec_reals = 0;    // working-type reals of one spectrum buffer (padding included)
+};
+
+EditLayout edit_layout(const Plan& p) {
+  EditLayout L;
+  const size_t ts = p.dt == FFCZ_F32 ? 4 : 8;
+  L.ncs = p.N * p.B;
+  L.ncf = 2 * p.nrows * p.ncols * p.B;
+  L.nbs = (L.ncs + kEditBlockCoords - 1) / kEditBlockCoords;
+  L.nbf = (L.ncf + kEditBlockCoords - 1) / kEditBlockCoords;
+  const int64_t rpp = p.nd == 3 ? p.n[1] : p.nrows;
+  L.spec_reals = 2 * p.B * (p.nrows / rpp) * p.plane;
+  size_t off = align_up(p.bytes, 256);
+  L.off_S = off;
+  off = align_up(off + ts * (size_t)L.ncs, 256);
+  L.off_F = off;
+  off = align_up(off + ts * (size_t)L.spec_reals, 256);
+  L.off_offs = off;
+  off = align_up(off + 8 * (size_t)std::max<int64_t>(1, L.nbs), 256);
+  L.off_offf = off;
+  off = align_up(off + 8 * (size_t)std::max<int64_t>(1, L.nbf), 256);
+  L.off_tot = off;  // two totals and the status word
+  off = align_up(off + 8 * 4, 256);
+  L.off_amax = off;
+  off = align_up(off + 8 * (size_t)kUlpSlots, 256);
+  L.bytes = off;
+  return L;
+}
+
 // One correction over the B instances of a plan.  inst[b] supplies pointers and
 // bounds, mus[b] the margins; mus null (one FP32 instance) derives mu from x on
 // the device, between the state set-up and the first pass.
@@ -1213,10 +1378,14 @@ int32_t pretune_group(const Plan& p0, char* ws, hipStream_t s) {
 template <typename T>
 int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* mus, int32_t max_iter,
                       const ffcz_options& o, char* ws, hipStream_t s, ffcz_stats* stats, int32_t* status,
-                      DevState* host_state = nullptr) {
+                      DevState* host_state = nullptr, const EditCfg* ed = nullptr) {
   const bool no_alloc = host_state != nullptr;
   Plan p = p0;
   Ctx c{&p, ws, s};
+  if (ed) {
+    c.sacc = ed->sacc;
+    c.facc = ed->facc;
+  }
   const int64_t vstride = max_iter + 2;
   const bool user_viol = o.viol_per_round && p.B == 1;
   unsigned long long* viol = user_viol ? (unsigned long long*)o.viol_per_round : c.viol();
@@ -1235,6 +1404,13 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
     spectral_thresholds(p.dt, inst[b].delta_f, mu, &si.Dc, &si.Dp);
     si.inv_n = 1.0 / (double)p.N;
     si.mu = mu;
+    if (ed && !ed->derive) {  // the encoder's given shrinks
+      si.mu = ed->mu_f;
+      si.mu_s = ed->mu_s;
+      si.Ep = inst[b].eps_s * (1.0 - ed->mu_s);
+      si.Dc = inst[b].delta_f * (1.0 - ed->mu_f);
+      si.Dp = inst[b].delta_f * (1.0 - 2.0 * ed->mu_f);
+    }
     si.max_iter = max_iter;
     si.fixed = o.fixed_iterations ? 1 : 0;
     si.record_masks = rec ? 1 : 0;
@@ -1257,7 +1433,27 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
   hipLaunchKernelGGL(state_init_kernel, dim3((unsigned)std::max<int64_t>(1, (nthr + 255) / 256)), dim3(256), 0, s,
                      c.st(), p.B, arr, one, viol, nviol);
   HIPCHK(hipGetLastError());
-  if (!mus) {
+  if (ed && ed->derive) {
+    // the encoder's shrinks from x (ulp partials for the FP32 output margin, max |x|)
+    if (p.B != 1) return fail(FFCZ_E_INVALID, "the encoder takes one instance");
+    const int nsl = ulp_slots(p.N);
+    double* slots = (double*)(ws + p.off_ulp);
+    if (p.dt == FFCZ_F32) {
+      const MarginJob one_job{(const float*)inst[0].x_orig, p.N, inst[0].delta_f};
+      hipLaunchKernelGGL(ulp_part_kernel, dim3((unsigned)nsl), dim3(256), 0, s, one_job, (const MarginJob*)nullptr,
+                         slots);
+      HIPCHK(hipGetLastError());
+      hipLaunchKernelGGL(absmax_part_kernel<float>, dim3((unsigned)nsl), dim3(256), 0, s,
+                         (const float*)inst[0].x_orig, p.N, ed->amax);
+    } else {
+      hipLaunchKernelGGL(absmax_part_kernel<double>, dim3((unsigned)nsl), dim3(256), 0, s,
+                         (const double*)inst[0].x_orig, p.N, ed->amax);
+    }
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(encode_margin_kernel, dim3(1), dim3(256), 0, s, (const double*)slots,
+                       (const unsigned long long*)ed->amax, p.N, (int)p.dt, ed->q, c.st());
+    HIPCHK(hipGetLastError());
+  } else if (!mus) {
     if (p.B != 1 || p.dt != FFCZ_F32) return fail(FFCZ_E_INVALID, "device margin needs one FP32 instance");
     const int nsl = ulp_slots(p.N);
     double* slots = (double*)(ws + p.off_ulp);
@@ -1270,7 +1466,13 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
     HIPCHK(hipGetLastError());
   }
   HIPCHK(write_twiddles(c));
-  {
+  if (ed) {
+    // edit bookkeeping runs on the default tiles; the frequency accumulators start at zero
+    set_variants(p, 0, 0, 0);
+    const int64_t nr = edit_layout(p).spec_reals;
+    hipLaunchKernelGGL(zero_fill_kernel<T>, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, (T*)ed->facc, nr);
+    HIPCHK(hipGetLastError());
+  } else {
     const int32_t tr = tune_plan<T>(p, ws, s, rec, no_alloc);
     if (tr != FFCZ_OK) return tr;
   }
@@ -1290,11 +1492,14 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
     hipGraphExec_t gexec = nullptr;
     if (o.use_graph && !g_prof.on && !no_alloc) {
       GraphKey key{{(int64_t)p.dt, p.nd, p.B, p.n[0], p.n[1], p.n[2], (int64_t)(uintptr_t)ws, (int64_t)(uintptr_t)viol,
-                    vstr, (int64_t)(uintptr_t)fmask, (int64_t)(uintptr_t)smask, chunk, max_iter, p.vy, p.vx, p.vz}};
+                    vstr, (int64_t)(uintptr_t)fmask, (int64_t)(uintptr_t)smask, chunk, max_iter, p.vy, p.vx, p.vz,
+                    (int64_t)(uintptr_t)c.sacc, (int64_t)(uintptr_t)c.facc}};
       gexec = g_graphs.find(key);
       if (!gexec) {
         HIPCHK(g_streams.ready());
         Ctx cc{&p, ws, g_streams.cap};
+        cc.sacc = c.sacc;
+        cc.facc = c.facc;
         HIPCHK(hipStreamBeginCapture(g_streams.cap, hipStreamCaptureModeThreadLocal));
         hipError_t ce = hipSuccess;
         for (int r = 0; r < chunk && ce == hipSuccess; ++r) ce = enqueue_round<T>(cc, r, viol, vstr, fmask, smask);
@@ -1325,7 +1530,8 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
         return fail(FFCZ_E_HIP, "loop did not report completion (device state inconsistent)");
     }
   }
-  HIPCHK(enqueue_final<T>(c, o.verify_fp64 != 0));
+  if (ed) HIPCHK(enqueue_undo<T>(c));
+  if (!ed || ed->want_y) HIPCHK(enqueue_final<T>(c, o.verify_fp64 != 0));
   if (!sync_needed) {
     prof_settle(max_iter);
     for (int64_t b = 0; b < p.B; ++b) status[b] = FFCZ_OK;
@@ -1336,6 +1542,7 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
   int maxr = 0;
   for (int64_t b = 0; b < p.B; ++b) maxr = std::max(maxr, hs[b].round);
   prof_settle(maxr);
+  if (ed && ed->mu_s_out) *ed->mu_s_out = hs[0].mu_s;
   for (int64_t b = 0; b < p.B; ++b) {
     const DevState& h = hs[b];
     const double ms = bits_to_double(h.max_spatial_bits), mf = bits_to_double(h.max_spectral_bits);
@@ -2004,7 +2211,7 @@ int32_t single_setup(int32_t dtype, int32_t ndim, const int64_t* shape, const vo
   if (!std::isfinite(eps_s) || eps_s < 0) return fail(FFCZ_E_INVALID, "eps_s must be finite and >= 0");
   if (!std::isfinite(delta_f) || delta_f < 0) return fail(FFCZ_E_INVALID, "delta_f must be finite and >= 0");
   if (((uintptr_t)x & 15) || ((uintptr_t)xb & 15) || ((uintptr_t)y & 15))
-    return fail(FFCZ_E_WORKSPACE, "workspace must be 256-byte and data 16-byte aligned");
+    return fail(FFCZ_E_WORKSPACE, "data pointers must be 16-byte aligned");
   if (opts) sc.o = *opts;
   else ffcz_default_options(&sc.o);
   if (sc.o.masks_out && sc.p.dt == FFCZ_F64 && col_block_cols(1, sc.p.Lx, 0) < 8)
@@ -2036,6 +2243,144 @@ int32_t single_run(SingleCall& sc, char* ws, hipStream_t s, ffcz_stats* stats, D
   if (status == FFCZ_E_NONFINITE) return fail(FFCZ_E_NONFINITE, "x or x_hat holds NaN or Inf");
   if (status == FFCZ_VERIFY_FAILED) g_err = "FP64 re-verification failed";
   return status;
+}
+
+// CompactEdits + QuantizeEdits over one coordinate set: block counts, their scan, then
+// flags and codes.  tot receives the number of codes.
+template <typename T>
+hipError_t code_set(const EditSet<T>& set, int64_t nb, unsigned long long* offs, unsigned long long* tot,
+                    uint8_t* flags, int32_t* codes, double step, unsigned* status, hipStream_t s) {
+  if (nb == 0) {
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, tot, (int64_t)1);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(edit_count_kernel<T>, dim3((unsigned)nb), dim3(64 * kEditWaves), 0, s, set, offs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(edit_scan_kernel, dim3(1), dim3(1024), 0, s, offs, nb, tot);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(edit_write_kernel<T>, dim3((unsigned)nb), dim3(64 * kEditWaves), 0, s, set,
+                     (const unsigned long long*)offs, flags, codes, step, status);
+  return hipGetLastError();
+}
+
+// The inverse for the decoder: dense dequantised edits from flags and codes.
+template <typename TO>
+hipError_t expand_set(const EditSet<TO>& set, int64_t nb, unsigned long long* offs, unsigned long long* tot,
+                      const uint8_t* flags, const int32_t* codes, int64_t ncodes, double step, unsigned* status,
+                      hipStream_t s) {
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(flag_count_kernel, dim3((unsigned)nb), dim3(64 * kEditWaves), 0, s, flags, set.ncoord, offs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(edit_scan_kernel, dim3(1), dim3(1024), 0, s, offs, nb, tot);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(edit_expand_kernel<TO>, dim3((unsigned)nb), dim3(64 * kEditWaves), 0, s, set, flags, codes,
+                     ncodes, (const unsigned long long*)offs, step, (const unsigned long long*)tot, status);
+  return hipGetLastError();
+}
+
+template <typename T>
+EditSet<T> spatial_set(void* base, int64_t n) {
+  EditSet<T> e;
+  memset(&e, 0, sizeof(e));
+  e.val = (T*)base;
+  e.ncoord = n;
+  return e;
+}
+template <typename T>
+EditSet<T> freq_set(const Plan& p, void* spec) {
+  EditSet<T> e;
+  memset(&e, 0, sizeof(e));
+  e.val = (T*)spec;
+  e.ncoord = 2 * p.nrows * p.ncols;
+  e.freq = 1;
+  e.ncols = (int32_t)p.ncols;
+  e.pitch = p.pitch;
+  e.plane = p.plane;
+  e.lg_rpp = p.lg_rpp;
+  return e;
+}
+
+// Encoder after the loop: code both sets, export the accumulators when asked, and read
+// back the code counts and the status word.
+template <typename T>
+int32_t code_edits(const Plan& p, const EditLayout& L, char* ws, void* sflags, int32_t* scodes, void* fflags,
+                   int32_t* fcodes, double step_s, double step_f, void* sexp, void* fexp, hipStream_t s,
+                   int64_t* nnz_s, int64_t* nnz_f) {
+  unsigned long long* tot = (unsigned long long*)(ws + L.off_tot);
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, tot, (int64_t)4);
+  HIPCHK(hipGetLastError());
+  unsigned* status = (unsigned*)(tot + 2);
+  const EditSet<T> ss = spatial_set<T>(ws + L.off_S, L.ncs);
+  const EditSet<T> fs = freq_set<T>(p, ws + L.off_F);
+  HIPCHK(code_set<T>(ss, L.nbs, (unsigned long long*)(ws + L.off_offs), tot, (uint8_t*)sflags, scodes, step_s,
+                     status, s));
+  HIPCHK(code_set<T>(fs, L.nbf, (unsigned long long*)(ws + L.off_offf), tot + 1, (uint8_t*)fflags, fcodes, step_f,
+                     status, s));
+  if (sexp && L.ncs) {
+    hipLaunchKernelGGL(edit_export_kernel<T>, dim3((unsigned)((L.ncs + 255) / 256)), dim3(256), 0, s, ss, (T*)sexp);
+    HIPCHK(hipGetLastError());
+  }
+  if (fexp && L.ncf) {
+    hipLaunchKernelGGL(edit_export_kernel<T>, dim3((unsigned)((L.ncf + 255) / 256)), dim3(256), 0, s, fs, (T*)fexp);
+    HIPCHK(hipGetLastError());
+  }
+  unsigned long long h[3];
+  HIPCHK(hipMemcpyAsync(h, tot, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *nnz_s = (int64_t)h[0];
+  *nnz_f = (int64_t)h[1];
+  if ((unsigned)h[2] & kEditCodeRange)
+    return fail(FFCZ_E_INVALID, "an edit's code falls outside int32 (fewer code bits m, or a zero bound with edits)");
+  return FFCZ_OK;
+}
+
+// Decoder: y = x_hat + s + IFFT(f) from flags and codes (Sec. IV-B, applying edits).
+template <typename T>
+int32_t decode_impl(const Plan& p, const EditLayout& L, char* ws, const void* xb, const void* sflags,
+                    const int32_t* scodes, int64_t nnz_s, const void* fflags, const int32_t* fcodes, int64_t nnz_f,
+                    double step_s, double step_f, void* y, hipStream_t s) {
+  Ctx c{&p, ws, s};
+  StateInit si;
+  memset(&si, 0, sizeof(si));
+  si.inv_n = 1.0 / (double)p.N;
+  si.px = y;  // the expanded spatial edits, read back by the closing pass
+  si.pxb = xb;
+  si.py = y;
+  hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, s, c.st(), (int64_t)1, (const StateInit*)nullptr, si,
+                     c.viol(), (int64_t)1);
+  HIPCHK(hipGetLastError());
+  HIPCHK(write_twiddles(c));
+  unsigned long long* tot = (unsigned long long*)(ws + L.off_tot);
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, tot, (int64_t)4);
+  HIPCHK(hipGetLastError());
+  unsigned* status = (unsigned*)(tot + 2);
+  // spatial edits straight into y (the field's dtype), frequency edits into Z
+  HIPCHK(expand_set<T>(spatial_set<T>(y, L.ncs), L.nbs, (unsigned long long*)(ws + L.off_offs), tot,
+                       (const uint8_t*)sflags, scodes, nnz_s, step_s, status, s));
+  HIPCHK(expand_set<T>(freq_set<T>(p, c.Z()), L.nbf, (unsigned long long*)(ws + L.off_offf), tot + 1,
+                       (const uint8_t*)fflags, fcodes, nnz_f, step_f, status, s));
+  // inverse transforms: x, then y (3D), then the last-axis C2R with 1/N and the sum
+  const char* twb = (const char*)c.twT();
+  HIPCHK(run_col<T>(p.dt, COL_INV_NS, 0, geom_x(p, p.pitch, p.plane), p, c.Z(), c.Z(), twb + sizeof(cx<T>) * p.twx,
+                    c.st(), nullptr, nullptr, s));
+  if (p.nd == 3)
+    HIPCHK(run_col<T>(p.dt, COL_INV_NS, 0, geom_y(p, p.pitch, p.plane), p, c.Z(), c.Z(),
+                      twb + sizeof(cx<T>) * p.twy, c.st(), nullptr, nullptr, s));
+  const hipError_t de = run_row<T, T>(p.dt, p.dt, ROW_DECODE, 0, p, p.pitch, p.plane, c.Z(), nullptr,
+                                      twb + sizeof(cx<T>) * p.twz, c.st(), nullptr, nullptr, s);
+  HIPCHK(de);
+  unsigned long long h[3];
+  HIPCHK(hipMemcpyAsync(h, tot, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if ((unsigned)h[2] & kEditFlagCount)
+    return fail(FFCZ_E_INVALID, "the set flags and the code counts given disagree (spatial " +
+                                    std::to_string(h[0]) + " vs " + std::to_string(nnz_s) + ", frequency " +
+                                    std::to_string(h[1]) + " vs " + std::to_string(nnz_f) + ")");
+  return FFCZ_OK;
 }
 
 // Scratch of ffcz_correct_noalloc (the array is declared at file scope, above): host
@@ -2259,6 +2604,125 @@ int32_t ffcz_correct_noalloc(int32_t dtype, int32_t ndim, const int64_t* shape, 
   if (r != FFCZ_OK) return r;
   DevState host_state;  // the loop state is read back into this (no pinned staging)
   return single_run(sc, ws, (hipStream_t)stream, stats, &host_state);
+}
+
+size_t ffcz_encode_workspace_bytes(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max_iter) {
+  if (route_1d(ndim, shape)) return 0;
+  Plan p;
+  std::string keep = g_err;
+  if (make_plan(dtype, ndim, shape, max_iter < 0 ? 0 : max_iter, 1, p) != FFCZ_OK) return 0;
+  g_err = keep;
+  return edit_layout(p).bytes;
+}
+
+void ffcz_default_encode_options(ffcz_encode_options* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->m = 16;
+  o->safety = 4.0;
+}
+
+int32_t ffcz_encode(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x, const void* xb, double eps_s,
+                    double delta_f, int32_t max_iter, const ffcz_options* opts, const ffcz_encode_options* eopts,
+                    void* spat_flags, int32_t* spat_codes, void* freq_flags, int32_t* freq_codes, void* ws,
+                    size_t ws_bytes, void* stream, ffcz_encode_stats* est) {
+  if (route_1d(ndim, shape))
+    return fail(FFCZ_E_SHAPE, "the encoder takes fields that run on the multidimensional passes (power-of-two extents)");
+  ffcz_encode_options eo;
+  if (eopts) eo = *eopts;
+  else ffcz_default_encode_options(&eo);
+  const int m = eo.m > 0 ? eo.m : 16;
+  const double safety = eo.safety > 0.0 ? eo.safety : 4.0;
+  if (m > 30) return fail(FFCZ_E_INVALID, "code length m must be at most 30");
+  if (!std::isfinite(safety)) return fail(FFCZ_E_INVALID, "safety must be finite");
+  if (!(eo.mu_s >= 0.0 && eo.mu_s < 0.5) || !(eo.mu_f >= 0.0 && eo.mu_f < 0.25))
+    return fail(FFCZ_E_INVALID, "mu_s must lie in [0, 1/2) and mu_f in [0, 1/4)");
+  if ((eo.mu_s > 0.0) != (eo.mu_f > 0.0)) return fail(FFCZ_E_INVALID, "give both shrinks or neither");
+  SingleCall sc;
+  // without y_out the closing pass does not run and nothing is written to the output pointer
+  void* y = eo.y_out ? eo.y_out : const_cast<void*>(xb);
+  int32_t r = single_setup(dtype, ndim, shape, x, xb, y, eps_s, delta_f, max_iter, opts, sc);
+  if (r != FFCZ_OK) return r;
+  if (!spat_flags || !spat_codes || !freq_flags || !freq_codes) return fail(FFCZ_E_INVALID, "null flag or code buffer");
+  if (((uintptr_t)spat_flags & 15) || ((uintptr_t)spat_codes & 15) || ((uintptr_t)freq_flags & 15) ||
+      ((uintptr_t)freq_codes & 15) || ((uintptr_t)eo.spat_edits_out & 15) || ((uintptr_t)eo.freq_edits_out & 15))
+    return fail(FFCZ_E_WORKSPACE, "flag, code and edit buffers must be 16-byte aligned");
+  const EditLayout L = edit_layout(sc.p);
+  if (!ws || ws_bytes < L.bytes) return fail(FFCZ_E_WORKSPACE, "workspace smaller than ffcz_encode_workspace_bytes()");
+  if ((uintptr_t)ws & 255) return fail(FFCZ_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (!eo.y_out) sc.o.verify_fp64 = 0;
+  char* w = (char*)ws;
+  EditCfg ed;
+  ed.sacc = w + L.off_S;
+  ed.facc = w + L.off_F;
+  ed.derive = eo.mu_s == 0.0;
+  ed.q = safety * std::ldexp(1.0, -m);
+  ed.mu_s = eo.mu_s;
+  ed.mu_f = eo.mu_f;
+  ed.want_y = eo.y_out != nullptr;
+  ed.amax = (unsigned long long*)(w + L.off_amax);
+  double mu_s_used = 0.0;
+  ed.mu_s_out = &mu_s_used;
+  sc.mu = 0.5;  // placeholder: the encoder's own shrinks replace the margin (on the host or the device)
+  hipStream_t s = (hipStream_t)stream;
+  ffcz_stats lst;
+  memset(&lst, 0, sizeof(lst));
+  int32_t status = FFCZ_OK;
+  const double* mus = &sc.mu;
+  r = dtype == FFCZ_F32 ? correct_group<float>(sc.p, &sc.in, mus, max_iter, sc.o, w, s, &lst, &status, nullptr, &ed)
+                        : correct_group<double>(sc.p, &sc.in, mus, max_iter, sc.o, w, s, &lst, &status, nullptr, &ed);
+  if (r != FFCZ_OK) return r;
+  lst.status = status;
+  if (status == FFCZ_E_NONFINITE) return fail(FFCZ_E_NONFINITE, "x or x_hat holds NaN or Inf");
+  const double step_s = std::ldexp(2.0 * eps_s, -m), step_f = std::ldexp(2.0 * delta_f, -m);
+  int64_t nnz_s = 0, nnz_f = 0;
+  r = dtype == FFCZ_F32 ? code_edits<float>(sc.p, L, w, spat_flags, spat_codes, freq_flags, freq_codes, step_s,
+                                            step_f, eo.spat_edits_out, eo.freq_edits_out, s, &nnz_s, &nnz_f)
+                        : code_edits<double>(sc.p, L, w, spat_flags, spat_codes, freq_flags, freq_codes, step_s,
+                                             step_f, eo.spat_edits_out, eo.freq_edits_out, s, &nnz_s, &nnz_f);
+  if (r != FFCZ_OK) return r;
+  if (est) {
+    memset(est, 0, sizeof(*est));
+    est->loop = lst;
+    est->nnz_s = nnz_s;
+    est->nnz_f = nnz_f;
+    est->step_s = step_s;
+    est->step_f = step_f;
+    // the shrinks in use: the state read back by the loop
+    est->mu_f = lst.margin_used;
+    est->mu_s = mu_s_used;
+    est->m = m;
+    est->status = status;
+  }
+  if (status == FFCZ_VERIFY_FAILED) g_err = "FP64 re-verification of y failed";
+  return status;
+}
+
+int32_t ffcz_decode(int32_t dtype, int32_t ndim, const int64_t* shape, const void* xb, const void* spat_flags,
+                    const int32_t* spat_codes, int64_t nnz_s, const void* freq_flags, const int32_t* freq_codes,
+                    int64_t nnz_f, double step_s, double step_f, void* y, void* ws, size_t ws_bytes, void* stream) {
+  if (route_1d(ndim, shape))
+    return fail(FFCZ_E_SHAPE, "the decoder takes fields that run on the multidimensional passes (power-of-two extents)");
+  Plan p;
+  int32_t r = make_plan(dtype, ndim, shape, 0, 1, p);
+  if (r != FFCZ_OK) return r;
+  const EditLayout L = edit_layout(p);
+  if (!xb || !y || !spat_flags || !freq_flags) return fail(FFCZ_E_INVALID, "null pointer");
+  if ((nnz_s > 0 && !spat_codes) || (nnz_f > 0 && !freq_codes)) return fail(FFCZ_E_INVALID, "null code buffer");
+  if (nnz_s < 0 || nnz_f < 0 || nnz_s > L.ncs || nnz_f > L.ncf) return fail(FFCZ_E_INVALID, "code counts out of range");
+  if (xb == y) return fail(FFCZ_E_INVALID, "x_base and y must not alias");
+  if (!std::isfinite(step_s) || !std::isfinite(step_f) || step_s < 0 || step_f < 0)
+    return fail(FFCZ_E_INVALID, "steps must be finite and >= 0");
+  if (((uintptr_t)xb & 15) || ((uintptr_t)y & 15) || ((uintptr_t)spat_flags & 15) || ((uintptr_t)freq_flags & 15) ||
+      ((uintptr_t)spat_codes & 15) || ((uintptr_t)freq_codes & 15))
+    return fail(FFCZ_E_WORKSPACE, "data, flag and code buffers must be 16-byte aligned");
+  if (!ws || ws_bytes < L.bytes) return fail(FFCZ_E_WORKSPACE, "workspace smaller than ffcz_encode_workspace_bytes()");
+  if ((uintptr_t)ws & 255) return fail(FFCZ_E_WORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  return dtype == FFCZ_F32 ? decode_impl<float>(p, L, (char*)ws, xb, spat_flags, spat_codes, nnz_s, freq_flags,
+                                                freq_codes, nnz_f, step_s, step_f, y, s)
+                           : decode_impl<double>(p, L, (char*)ws, xb, spat_flags, spat_codes, nnz_s, freq_flags,
+                                                 freq_codes, nnz_f, step_s, step_f, y, s);
 }
 
 size_t ffcz_batched_workspace_bytes(int32_t dtype, int32_t count, const ffcz_instance* inst, int32_t max_iter) {

@@ -29,6 +29,8 @@ struct DevState {
   const void* px;
   const void* pxb;
   void* py;
+  // the encoder's spatial shrink (its spectral shrink is mu)
+  double mu_s;
 };
 
 enum ColMode : int {
@@ -38,7 +40,10 @@ enum ColMode : int {
   COL_XBACK = 3,   // forward, multiply by recorded f-mask, inverse (adjoint)
   COL_VERIFY = 4,  // forward (FP64), max |Re|,|Im| and violation count; no store
   COL_FWD_NS = 5,  // forward, ignores the done flag (adjoint, verification)
-  COL_INV_NS = 6   // inverse, ignores the done flag (adjoint)
+  COL_INV_NS = 6,  // inverse, ignores the done flag (adjoint, decoder)
+  COL_XEDIT = 7,   // COL_XPASS that also adds each clip displacement to the frequency edits
+  COL_XUNDO = 8    // forward and clip as COL_XPASS, then subtracts the displacement from the
+                   // frequency edits (the check that ended the loop discards its clip); no store
 };
 
 enum RowMode : int {
@@ -49,8 +54,11 @@ enum RowMode : int {
   ROW_BINIT = 4,   // g * s-mask, R2C        (adjoint)
   ROW_BLOOP = 5,   // C2R, 1/N, g * s-mask, R2C (adjoint)
   ROW_BFINAL = 6,  // C2R, 1/N, g * s-mask, store (adjoint)
-  ROW_FINALV = 7   // FP64 fields: ROW_FINAL, then d = y - x from the stored y: max |d|, FP64 R2C (the
+  ROW_FINALV = 7,  // FP64 fields: ROW_FINAL, then d = y - x from the stored y: max |d|, FP64 R2C (the
                    // last-axis pass of the verification, without re-reading x and y)
+  ROW_INITE = 8,   // ROW_INIT that also stores each guard-clip displacement as the first spatial edit
+  ROW_LOOPE = 9,   // ROW_LOOP that also adds each s-clip displacement to the spatial edits
+  ROW_DECODE = 10  // C2R, 1/N, y = x_hat + s + eps summed in FP64 and rounded once (decoder; s in py)
 };
 
 template <typename T>
@@ -72,6 +80,8 @@ struct ColArgs {
   int64_t f_row_bytes; // bytes per half-spectrum row
   int64_t mrow_i;      // mask row = i * mrow_i + outer * mrow_o
   int64_t mrow_o;
+  // frequency edits (COL_XEDIT / COL_XUNDO): same layout as the spectrum the pass transforms
+  cx<T>* fedit;
 };
 
 template <typename T, typename TIO>
@@ -95,6 +105,8 @@ struct RowArgs {
   // only where a pass reads one precision and writes another (ROW_FINALV)
   int64_t spitch;
   int64_t splane;
+  // spatial edits (ROW_INITE / ROW_LOOPE): one value per real point of the instance, C order
+  T* sedit;
 };
 
 // FP64 bound -> working type, rounded toward zero (a tighter bound in FP32).

@@ -27,7 +27,7 @@ col_kernel(ColArgs<T> a) {
   const int64_t bid = blockIdx.x;
   const int64_t o = bid / a.ncb;
   DevState* st = a.st + o / a.outer_per_inst;
-  constexpr bool uses_done = (MODE == COL_FWD || MODE == COL_INV || MODE == COL_XPASS);
+  constexpr bool uses_done = (MODE == COL_FWD || MODE == COL_INV || MODE == COL_XPASS || MODE == COL_XEDIT);
   (void)red_d;
   if (uses_done) {
     if (*(volatile int32_t*)&st->done) return;
@@ -53,11 +53,16 @@ col_kernel(ColArgs<T> a) {
     fft<T, L, E, false, C, 1>(v, lds, tws, c, j);
   } else if constexpr (MODE == COL_INV || MODE == COL_INV_NS) {
     fft<T, L, E, true, C, 1>(v, lds, tws, c, j);
-  } else if constexpr (MODE == COL_XPASS) {
+  } else if constexpr (MODE == COL_XPASS || MODE == COL_XEDIT || MODE == COL_XUNDO) {
+    // COL_XEDIT adds every clip displacement to the frequency edits (Alg. 1 edit bookkeeping);
+    // COL_XUNDO repeats the forward transform and the clip of the check that ended the loop
+    // (same inputs, same arithmetic, so the same displacements) and takes them back out: that
+    // check's clip never reaches the iterate
+    constexpr bool edit = MODE == COL_XEDIT, undo = MODE == COL_XUNDO;
     const int k = *(volatile int32_t*)&st->round;
     const T D = to_t<T>(st->Dc);
     const T Dp = to_t<T>(st->Dp);
-    const bool rec = st->record_masks && (k < st->max_iter);
+    const bool rec = !undo && st->record_masks && (k < st->max_iter);
     fft<T, L, E, false, C, 1>(v, lds, tws, c, j);
     unsigned long long cnt = 0;
     const int lane = t & 63;
@@ -72,6 +77,22 @@ col_kernel(ColArgs<T> a) {
       const bool kim = fabs(z.im) <= Dp;
       z.re = clipv(z.re, Dp);
       z.im = clipv(z.im, Dp);
+      if constexpr (edit || undo) {
+        // displacement delta' - delta, touched only where the clip moved a part
+        const T dre = z.re - v[q].re, dim = z.im - v[q].im;
+        if (valid && (dre != T(0) || dim != T(0))) {
+          cx<T>* f = a.fedit + base + (int64_t)(j + q * P) * a.s;
+          cx<T> acc = *f;
+          if constexpr (edit) {
+            acc.re += dre;
+            acc.im += dim;
+          } else {
+            acc.re -= dre;
+            acc.im -= dim;
+          }
+          *f = acc;
+        }
+      }
       v[q] = z;
       if (rec) {
         const unsigned long long bre = __ballot(valid && kre);
@@ -89,6 +110,7 @@ col_kernel(ColArgs<T> a) {
         }
       }
     }
+    if constexpr (undo) return;
     fft<T, L, E, true, C, 1>(v, lds, tws, c, j);
     // violations of this check: one partial per block, summed by the control kernel
     cnt = wave_sum_u64(cnt);

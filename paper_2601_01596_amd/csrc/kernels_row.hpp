@@ -67,10 +67,14 @@ row_kernel(RowArgs<T, TIO> a) {
   using V2 = typename Vec2<TIO>::type;
   constexpr bool finalv = MODE == ROW_FINALV;  // FP64 fields only
   constexpr bool final_y = (MODE == ROW_FINAL || finalv);  // forms and stores y
-  constexpr bool spec_in = (MODE == ROW_LOOP || final_y || MODE == ROW_BLOOP || MODE == ROW_BFINAL);
-  constexpr bool spec_out = (MODE == ROW_INIT || MODE == ROW_LOOP || MODE == ROW_VERIFY || MODE == ROW_BINIT ||
+  constexpr bool decode = MODE == ROW_DECODE;  // y = x_hat + s + eps (s already in y)
+  constexpr bool m_init = (MODE == ROW_INIT || MODE == ROW_INITE);
+  constexpr bool m_loop = (MODE == ROW_LOOP || MODE == ROW_LOOPE);
+  constexpr bool sedit = (MODE == ROW_INITE || MODE == ROW_LOOPE);  // spatial edit bookkeeping
+  constexpr bool spec_in = (m_loop || final_y || MODE == ROW_BLOOP || MODE == ROW_BFINAL || decode);
+  constexpr bool spec_out = (m_init || m_loop || MODE == ROW_VERIFY || MODE == ROW_BINIT ||
                              MODE == ROW_BLOOP || finalv);
-  constexpr bool rec_s = (MODE == ROW_INIT || MODE == ROW_LOOP);
+  constexpr bool rec_s = (m_init || m_loop);
   constexpr bool use_s = (MODE == ROW_BINIT || MODE == ROW_BLOOP || MODE == ROW_BFINAL);
   // the final passes read the loop's spectrum in the field's precision (TIO), which is
   // the working precision except for an FP64 final of an FP32 field
@@ -93,7 +97,7 @@ row_kernel(RowArgs<T, TIO> a) {
   const int64_t lrow0 = ((int64_t)blockIdx.x - inst * a.bpi) * ROWS;  // row within the instance
   const int64_t row0 = inst * a.rows_per_inst + lrow0;                 // row of the spectrum buffers
   DevState* st = a.st + inst;
-  if constexpr (MODE == ROW_LOOP) {
+  if constexpr (m_loop) {
     if (*(volatile int32_t*)&st->done) return;
   }
   // first entry of spectrum row R (rows are grouped in planes of 2^lg_rpp rows)
@@ -117,7 +121,7 @@ row_kernel(RowArgs<T, TIO> a) {
   int kround = 0;
   bool rec = false;
   if constexpr (rec_s) {
-    if (MODE == ROW_LOOP) kround = *(volatile int32_t*)&st->round;
+    if (m_loop) kround = *(volatile int32_t*)&st->round;
     rec = st->record_masks != 0;
     if (rec)
       for (int i = t; i < ROWS * SW; i += NT) sbits[i] = 0u;
@@ -130,6 +134,8 @@ row_kernel(RowArgs<T, TIO> a) {
     }
   }
   if constexpr (rec_s || use_s) __syncthreads();  // mask words ready before any lane touches them
+  // spatial edits of this instance (real point n of row R at R * 2H + n)
+  T* const sed = sedit ? a.sedit + inst * a.rows_per_inst * (2 * H) : nullptr;
 
   unsigned long long cnt = 0;
   double mx = 0.0;
@@ -211,7 +217,7 @@ row_kernel(RowArgs<T, TIO> a) {
         } else {
           e0 = b0 - xa0;
           e1 = b1 - xa1;
-          if constexpr (MODE == ROW_INIT) {
+          if constexpr (m_init) {
             const bool f0 = isfinite(e0), f1 = isfinite(e1);
             if (!f0 || !f1) {
               atomicAdd(&st->nonfinite, (unsigned long long)((!f0) + (!f1)));
@@ -220,8 +226,16 @@ row_kernel(RowArgs<T, TIO> a) {
             }
             const bool k0 = fabs(e0) <= Ep, k1 = fabs(e1) <= Ep;
             cnt += (!k0) + (!k1);
-            e0 = clipv(e0, Ep);
-            e1 = clipv(e1, Ep);
+            const double c0 = clipv(e0, Ep), c1 = clipv(e1, Ep);
+            if constexpr (sedit) {
+              // the guard clip is the first ProjectOntoSCube displacement (every point written)
+              typename Vec2<T>::type d;
+              d.x = (T)(c0 - e0);
+              d.y = (T)(c1 - e1);
+              *reinterpret_cast<typename Vec2<T>::type*>(sed + (lrow0 + r) * (2 * H) + 2 * m) = d;
+            }
+            e0 = c0;
+            e1 = c1;
             if (rec)
               atomicOr(&sbits[r * SW + (2 * m) / 32], ((uint32_t)k0 | ((uint32_t)k1 << 1)) << ((2 * m) & 31));
           } else {
@@ -314,6 +328,9 @@ row_kernel(RowArgs<T, TIO> a) {
       const T scz = T(1) / T(2 * H);
 #pragma unroll
       for (int q = 0; q < E; ++q) v[q] = scal(v[q], scz);
+    } else if constexpr (decode) {
+#pragma unroll
+      for (int q = 0; q < E; ++q) v[q] = scal(v[q], sc);
     } else if constexpr (MODE == ROW_BLOOP || MODE == ROW_BFINAL) {
 #pragma unroll
       for (int q = 0; q < E; ++q) {
@@ -332,9 +349,16 @@ row_kernel(RowArgs<T, TIO> a) {
         T e0 = v[q].re * sc, e1 = v[q].im * sc;
         const bool k0 = fabs(e0) <= Ep, k1 = fabs(e1) <= Ep;
         if (valid) cnt += (!k0) + (!k1);
-        e0 = clipv(e0, Ep);
-        e1 = clipv(e1, Ep);
-        v[q] = cx<T>{e0, e1};
+        const T c0 = clipv(e0, Ep), c1 = clipv(e1, Ep);
+        if constexpr (sedit) {
+          // spat_edits += eps' - eps at the points the clip moved
+          if (valid && !(k0 && k1)) {
+            T* pe = sed + (lrow0 + rl) * (2 * H) + 2 * k;
+            if (!k0) pe[0] += c0 - e0;
+            if (!k1) pe[1] += c1 - e1;
+          }
+        }
+        v[q] = cx<T>{c0, c1};
         if (rec && valid)
           atomicOr(&sbits[rl * SW + (2 * k) / 32], ((uint32_t)k0 | ((uint32_t)k1 << 1)) << ((2 * k) & 31));
       }
@@ -373,22 +397,29 @@ row_kernel(RowArgs<T, TIO> a) {
       if constexpr (final_y) return closing_clamp<TIO>(round_io<TIO>((double)xv + (double)e), xv, Eb);
       else return (TIO)e;
     };
+    // decoder: x_hat from pxb, the expanded spatial edits already in y
+    auto dec_of = [&](TIO xbv, TIO sv, T e) -> TIO { return round_io<TIO>((double)xbv + (double)sv + (double)e); };
+    constexpr bool ld_x = final_y || decode;
     constexpr int NS = (ROWS * H + NT - 1) / NT;
     if constexpr (io4) {
       // FP32 fields: four reals per 16-byte access
       constexpr int NSQ = (ROWS * HQ + NT - 1) / NT;
       constexpr int BQ = NSQ < 8 ? NSQ : 8;
-      const float4* x4 = reinterpret_cast<const float4*>(st->px);
+      const float4* x4 = reinterpret_cast<const float4*>(decode ? st->pxb : st->px);
       float4* y4 = reinterpret_cast<float4*>(st->py);
 #pragma unroll
       for (int q0 = 0; q0 < NSQ; q0 += BQ) {
         float4 xa[BQ];
-        if constexpr (final_y) {
+        float4 sa[decode ? BQ : 1];
+        if constexpr (ld_x) {
 #pragma unroll
           for (int u = 0; u < BQ; ++u) {
             const int f = t + (q0 + u) * NT;
             const int r = f / HQ, q = f - r * HQ;
-            if (q0 + u < NSQ && f < ROWS * HQ && r < nrow) xa[u] = x4[(lrow0 + r) * HQ + q];
+            if (q0 + u < NSQ && f < ROWS * HQ && r < nrow) {
+              xa[u] = x4[(lrow0 + r) * HQ + q];
+              if constexpr (decode) sa[u] = y4[(lrow0 + r) * HQ + q];
+            }
           }
         }
 #pragma unroll
@@ -401,6 +432,9 @@ row_kernel(RowArgs<T, TIO> a) {
             if constexpr (final_y) {
               o = make_float4(out_of(xa[u].x, e0.re), out_of(xa[u].y, e0.im), out_of(xa[u].z, e1.re),
                               out_of(xa[u].w, e1.im));
+            } else if constexpr (decode) {
+              o = make_float4(dec_of(xa[u].x, sa[u].x, e0.re), dec_of(xa[u].y, sa[u].y, e0.im),
+                              dec_of(xa[u].z, sa[u].z, e1.re), dec_of(xa[u].w, sa[u].w, e1.im));
             } else {
               o = make_float4((float)e0.re, (float)e0.im, (float)e1.re, (float)e1.im);
             }
@@ -409,15 +443,20 @@ row_kernel(RowArgs<T, TIO> a) {
         }
       }
     } else {
+    const V2* xd2 = reinterpret_cast<const V2*>(decode ? st->pxb : st->px);
 #pragma unroll
     for (int b0 = 0; b0 < NS; b0 += BL) {
       V2 xa[BL];
-      if constexpr (final_y) {
+      V2 sa[decode ? BL : 1];
+      if constexpr (ld_x) {
 #pragma unroll
         for (int u = 0; u < BL; ++u) {
           const int f = t + (b0 + u) * NT;
           const int r = f / H, m = f - r * H;
-          if (b0 + u < NS && f < ROWS * H && r < nrow) xa[u] = x2[(lrow0 + r) * H + m];
+          if (b0 + u < NS && f < ROWS * H && r < nrow) {
+            xa[u] = xd2[(lrow0 + r) * H + m];
+            if constexpr (decode) sa[u] = y2[(lrow0 + r) * H + m];
+          }
         }
       }
 #pragma unroll
@@ -430,6 +469,9 @@ row_kernel(RowArgs<T, TIO> a) {
           if constexpr (final_y) {
             out.x = out_of(xa[u].x, e.re);
             out.y = out_of(xa[u].y, e.im);
+          } else if constexpr (decode) {
+            out.x = dec_of(xa[u].x, sa[u].x, e.re);
+            out.y = dec_of(xa[u].y, sa[u].y, e.im);
           } else {
             out.x = (TIO)e.re;
             out.y = (TIO)e.im;
@@ -486,7 +528,7 @@ row_kernel(RowArgs<T, TIO> a) {
   }
 
   // ------------------------------------------------------------------ partials and masks
-  if constexpr (MODE == ROW_INIT || MODE == ROW_LOOP || MODE == ROW_VERIFY || finalv) {
+  if constexpr (m_init || m_loop || MODE == ROW_VERIFY || finalv) {
     cnt = wave_sum_u64(cnt);
     mx = wave_max_f64(mx);
     if ((t & 63) == 0) {

@@ -33,7 +33,8 @@ EXPORTS = ("ffcz_version", "ffcz_last_error", "ffcz_default_options", "ffcz_work
            "ffcz_mask_bytes", "ffcz_suggest_margin", "ffcz_correct", "ffcz_correct_backward",
            "ffcz_batched_workspace_bytes", "ffcz_correct_batched", "ffcz_profile_enable", "ffcz_profile_read",
            "ffcz_profile_select",
-           "ffcz_copy", "ffcz_set_tuning", "ffcz_clear_tuning", "ffcz_correct_noalloc")
+           "ffcz_copy", "ffcz_set_tuning", "ffcz_clear_tuning", "ffcz_correct_noalloc",
+           "ffcz_default_encode_options", "ffcz_encode_workspace_bytes", "ffcz_encode", "ffcz_decode")
 
 PROFILE_KINDS = ("init", "y_fwd", "x_pass", "y_inv", "z_pass", "finalize", "verify_z", "verify_y", "verify_x",
                  "adjoint_z", "adjoint_y", "adjoint_x")
@@ -71,6 +72,33 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class EncodeOptions(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+        ("safety", ctypes.c_double),
+        ("mu_s", ctypes.c_double),
+        ("mu_f", ctypes.c_double),
+        ("y_out", ctypes.c_void_p),
+        ("spat_edits_out", ctypes.c_void_p),
+        ("freq_edits_out", ctypes.c_void_p),
+    ]
+
+
+class EncodeStats(ctypes.Structure):
+    _fields_ = [
+        ("loop", Stats),
+        ("nnz_s", ctypes.c_int64),
+        ("nnz_f", ctypes.c_int64),
+        ("step_s", ctypes.c_double),
+        ("step_f", ctypes.c_double),
+        ("mu_s", ctypes.c_double),
+        ("mu_f", ctypes.c_double),
+        ("m", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+    ]
 
 
 class Instance(ctypes.Structure):
@@ -137,6 +165,21 @@ def lib() -> ctypes.CDLL:
                                            ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                            ctypes.POINTER(Options), ctypes.c_void_p, ctypes.POINTER(Stats)]
         L.ffcz_correct_noalloc.restype = ctypes.c_int32
+        L.ffcz_default_encode_options.argtypes = [ctypes.POINTER(EncodeOptions)]
+        L.ffcz_default_encode_options.restype = None
+        L.ffcz_encode_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, i64p, ctypes.c_int32]
+        L.ffcz_encode_workspace_bytes.restype = ctypes.c_size_t
+        L.ffcz_encode.argtypes = [ctypes.c_int32, ctypes.c_int32, i64p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(Options),
+                                  ctypes.POINTER(EncodeOptions), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                  ctypes.POINTER(EncodeStats)]
+        L.ffcz_encode.restype = ctypes.c_int32
+        L.ffcz_decode.argtypes = [ctypes.c_int32, ctypes.c_int32, i64p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_size_t, ctypes.c_void_p]
+        L.ffcz_decode.restype = ctypes.c_int32
         L.ffcz_correct_backward.argtypes = [ctypes.c_int32, ctypes.c_int32, i64p, ctypes.c_int32, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                             ctypes.c_void_p]
@@ -224,6 +267,40 @@ def ffcz_correct_noalloc(dtype: int, shape, x_ptr: int, xb_ptr: int, y_ptr: int,
                                           ctypes.c_void_p(y_ptr), float(eps_s), float(delta_f), int(max_iter),
                                           ctypes.byref(opts) if opts is not None else None,
                                           ctypes.c_void_p(stream), ctypes.byref(stats) if stats is not None else None))
+
+
+def ffcz_default_encode_options() -> EncodeOptions:
+    o = EncodeOptions()
+    lib().ffcz_default_encode_options(ctypes.byref(o))
+    return o
+
+
+def ffcz_encode_workspace_bytes(dtype: int, shape: Sequence[int], max_iter: int) -> int:
+    nd, arr = _shape(shape)
+    return int(lib().ffcz_encode_workspace_bytes(dtype, nd, arr, max_iter))
+
+
+def ffcz_encode(dtype: int, shape, x_ptr: int, xb_ptr: int, eps_s: float, delta_f: float, max_iter: int,
+                opts: Optional[Options], eopts: Optional[EncodeOptions], sflags_ptr: int, scodes_ptr: int,
+                fflags_ptr: int, fcodes_ptr: int, ws_ptr: int, ws_bytes: int, stream: int,
+                stats: Optional[EncodeStats]) -> int:
+    nd, arr = _shape(shape)
+    return int(lib().ffcz_encode(dtype, nd, arr, ctypes.c_void_p(x_ptr), ctypes.c_void_p(xb_ptr), float(eps_s),
+                                 float(delta_f), int(max_iter), ctypes.byref(opts) if opts is not None else None,
+                                 ctypes.byref(eopts) if eopts is not None else None, ctypes.c_void_p(sflags_ptr),
+                                 ctypes.c_void_p(scodes_ptr), ctypes.c_void_p(fflags_ptr),
+                                 ctypes.c_void_p(fcodes_ptr), ctypes.c_void_p(ws_ptr), ws_bytes,
+                                 ctypes.c_void_p(stream), ctypes.byref(stats) if stats is not None else None))
+
+
+def ffcz_decode(dtype: int, shape, xb_ptr: int, sflags_ptr: int, scodes_ptr: int, nnz_s: int, fflags_ptr: int,
+                fcodes_ptr: int, nnz_f: int, step_s: float, step_f: float, y_ptr: int, ws_ptr: int, ws_bytes: int,
+                stream: int) -> int:
+    nd, arr = _shape(shape)
+    return int(lib().ffcz_decode(dtype, nd, arr, ctypes.c_void_p(xb_ptr), ctypes.c_void_p(sflags_ptr),
+                                 ctypes.c_void_p(scodes_ptr), int(nnz_s), ctypes.c_void_p(fflags_ptr),
+                                 ctypes.c_void_p(fcodes_ptr), int(nnz_f), float(step_s), float(step_f),
+                                 ctypes.c_void_p(y_ptr), ctypes.c_void_p(ws_ptr), ws_bytes, ctypes.c_void_p(stream)))
 
 
 def ffcz_correct_backward(dtype: int, shape, rounds: int, masks_ptr: int, grad_out_ptr: int, grad_base_ptr: int,
@@ -405,6 +482,138 @@ def correct(x, xb, eps_s: float, delta_f: float, max_iter: int, *, margin: float
     if check and st < 0:
         raise FFCzError(st, ffcz_last_error())
     return Result(y=y, status=st, stats=stats.as_dict(), masks=masks, viol=viol)
+
+
+def _squeezed(shape):
+    s = tuple(int(n) for n in shape if int(n) > 1)
+    return s if s else (1,)
+
+
+def edit_coords(shape):
+    """(spatial, frequency) coordinate counts of the edit coding: N and 2 M, with M the
+    half-spectrum entries of the squeezed shape."""
+    sq = _squeezed(shape)
+    n = 1
+    for v in sq:
+        n *= v
+    m = n // sq[-1] * (sq[-1] // 2 + 1)
+    return n, 2 * m
+
+
+@dataclasses.dataclass
+class Encoded:
+    """Output of ``encode``: flags (uint8) and codes (int32, trimmed to their counts) of both
+    edit sets, the steps, the shrinks and the loop statistics."""
+    shape: tuple
+    dtype: int
+    spat_flags: object
+    spat_codes: object
+    freq_flags: object
+    freq_codes: object
+    step_s: float
+    step_f: float
+    mu_s: float
+    mu_f: float
+    m: int
+    status: int
+    stats: dict
+    y: object = None
+    spat_edits: object = None
+    freq_edits: object = None
+
+
+def encode(x, xb, eps_s: float, delta_f: float, max_iter: int, *, m: int = 16, safety: float = 4.0,
+           mus=None, want_y: bool = False, export_edits: bool = False, verify: bool = True, chunk: int = 4,
+           graph: bool = True, ws=None, check: bool = True) -> Encoded:
+    """``ffcz_encode`` on device tensors: the loop with edit bookkeeping, then flags and codes."""
+    torch = _torch()
+    _check_tensor(x, "x")
+    _check_tensor(xb, "xb")
+    if x.shape != xb.shape or x.dtype != xb.dtype or x.device != xb.device:
+        raise FFCzError(E_INVALID, "x and xb must have the same shape, dtype and device")
+    dt = _dtype_code(x)
+    shape = tuple(x.shape)
+    ns, nf = edit_coords(shape)
+    dev = x.device
+    nbytes = ffcz_encode_workspace_bytes(dt, shape, max_iter)
+    if nbytes == 0:
+        raise FFCzError(E_SHAPE, f"unsupported shape {shape}: {ffcz_last_error()}")
+    if ws is None:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    else:
+        _check_bytes(ws, nbytes, dev, "ws")
+    # flag buffers rounded up to 16 bytes (the kernels write whole 8-byte words where they fit)
+    sflags = torch.zeros(((ns + 7) // 8 + 15) // 16 * 16, dtype=torch.uint8, device=dev)
+    fflags = torch.zeros(((nf + 7) // 8 + 15) // 16 * 16, dtype=torch.uint8, device=dev)
+    scodes = torch.empty(max(ns, 1), dtype=torch.int32, device=dev)
+    fcodes = torch.empty(max(nf, 1), dtype=torch.int32, device=dev)
+    eo = ffcz_default_encode_options()
+    eo.m = int(m)
+    eo.safety = float(safety)
+    if mus is not None:
+        eo.mu_s, eo.mu_f = float(mus[0]), float(mus[1])
+    y = se = fe = None
+    if want_y:
+        y = torch.empty_like(x)
+        eo.y_out = y.data_ptr()
+    if export_edits:
+        se = torch.empty(ns, dtype=x.dtype, device=dev)
+        fe = torch.empty(nf, dtype=x.dtype, device=dev)
+        eo.spat_edits_out = se.data_ptr()
+        eo.freq_edits_out = fe.data_ptr()
+    opts = ffcz_default_options()
+    opts.verify_fp64 = 1 if verify else 0
+    opts.graph_chunk = int(chunk)
+    opts.use_graph = 1 if graph else 0
+    st = EncodeStats()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    r = ffcz_encode(dt, shape, x.data_ptr(), xb.data_ptr(), eps_s, delta_f, max_iter, opts, eo, sflags.data_ptr(),
+                    scodes.data_ptr(), fflags.data_ptr(), fcodes.data_ptr(), ws.data_ptr(), ws.numel(), stream, st)
+    if check and r < 0:
+        raise FFCzError(r, ffcz_last_error())
+    nbs, nbf = (ns + 7) // 8, (nf + 7) // 8
+    return Encoded(shape=shape, dtype=dt, spat_flags=sflags[:nbs], spat_codes=scodes[:st.nnz_s],
+                   freq_flags=fflags[:nbf], freq_codes=fcodes[:st.nnz_f], step_s=st.step_s, step_f=st.step_f,
+                   mu_s=st.mu_s, mu_f=st.mu_f, m=st.m, status=r, stats=st.loop.as_dict(), y=y, spat_edits=se,
+                   freq_edits=fe)
+
+
+def decode(xb, enc: Encoded, *, ws=None, out=None):
+    """``ffcz_decode``: ``y = x_hat + s + IFFT(f)`` from an ``Encoded`` (device tensors)."""
+    torch = _torch()
+    _check_tensor(xb, "xb")
+    dt = _dtype_code(xb)
+    shape = tuple(xb.shape)
+    if shape != tuple(enc.shape) or dt != enc.dtype:
+        raise FFCzError(E_INVALID, "x_hat does not match the encoding's shape and dtype")
+    dev = xb.device
+    nbytes = ffcz_encode_workspace_bytes(dt, shape, 0)
+    if ws is None:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    else:
+        _check_bytes(ws, nbytes, dev, "ws")
+    if out is None:
+        y = torch.empty_like(xb)
+    else:
+        _check_like(out, xb, "out")
+        y = out
+
+    def aligned(t):
+        # the C ABI wants 16-byte aligned buffers (the encoder's slices start at their base)
+        t = t.contiguous()
+        if t.data_ptr() % 16:
+            t = t.clone()
+        return t
+
+    sf, ff = aligned(enc.spat_flags), aligned(enc.freq_flags)
+    sc, fc = aligned(enc.spat_codes), aligned(enc.freq_codes)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    r = ffcz_decode(dt, shape, xb.data_ptr(), sf.data_ptr(), sc.data_ptr() if sc.numel() else 0, sc.numel(),
+                    ff.data_ptr(), fc.data_ptr() if fc.numel() else 0, fc.numel(), enc.step_s, enc.step_f,
+                    y.data_ptr(), ws.data_ptr(), ws.numel(), stream)
+    if r < 0:
+        raise FFCzError(r, ffcz_last_error())
+    return y
 
 
 def batched_workspace(members, max_iter: int, device=None):
