@@ -9,8 +9,9 @@ the FP64 re-verification of both bounds.  Inputs are resident in HBM before the
 timed region starts.  ``value`` is the field throughput N * 4 bytes / time.
 
 Also measured (reported under ``extra``): the same field in FP64, the FP32/FP64
-speedup, and forward + backward time of the 50-round differentiable correction
-of a 256^3 FP32 field.  ``roofline`` comes from HIP events around every launch
+speedup, forward + backward time of the 50-round differentiable correction
+of a 256^3 FP32 field, the encoder and decoder of the edits on the FP32 field,
+and the mixed batch.  ``roofline`` comes from HIP events around every launch
 of the dominant pass during the timed steps; ``cpu_baseline`` times the CPU
 oracle on the host cores.
 
@@ -252,6 +253,44 @@ def fwd_bwd(F, torch, W, n, K, steps):
     return (time.perf_counter() - t0) / steps * 1e3
 
 
+def edit_leg(F, torch, prob, steps):
+    """Encoder (the loop with edit bookkeeping, CompactEdits + QuantizeEdits) and decoder
+    (y = x_hat + s + IFFT(f)) on the benchmark field; the decoded output re-verified in FP64
+    outside the timed region."""
+    x = torch.from_numpy(prob.x).cuda()
+    xb = torch.from_numpy(prob.xb).cuda()
+    shape = tuple(prob.x.shape)
+    ws = torch.empty(F.ffcz_encode_workspace_bytes(F.F32, shape, prob.max_iter), dtype=torch.uint8, device="cuda")
+    enc = F.encode(x, xb, prob.E, prob.Delta, prob.max_iter, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        enc = F.encode(x, xb, prob.E, prob.Delta, prob.max_iter, ws=ws)
+    torch.cuda.synchronize()
+    t_enc = (time.perf_counter() - t0) / steps
+    y = torch.empty_like(x)
+    F.decode(xb, enc, ws=ws, out=y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        F.decode(xb, enc, ws=ws, out=y)
+    torch.cuda.synchronize()
+    t_dec = (time.perf_counter() - t0) / steps
+    d = y.double() - x.double()
+    ms = float(d.abs().max())
+    Dk = torch.fft.rfftn(d)
+    mf = float(torch.maximum(Dk.real.abs().max(), Dk.imag.abs().max()))
+    del d, Dk, ws
+    nnz_s, nnz_f = enc.spat_codes.numel(), enc.freq_codes.numel()
+    ns, nf = F.edit_coords(shape)
+    coded = (ns + 7) // 8 + (nf + 7) // 8 + 4 * (nnz_s + nnz_f)
+    return {"encode_ms": t_enc * 1e3, "encode_GBps": prob.x.nbytes / t_enc / 1e9, "decode_ms": t_dec * 1e3,
+            "decode_GBps": prob.x.nbytes / t_dec / 1e9, "encode_rounds": enc.stats["rounds"],
+            "encode_status": enc.status, "edits_nnz_spatial": nnz_s, "edits_nnz_freq": nnz_f,
+            "edits_coded_bytes": coded, "edits_mu_s": enc.mu_s, "edits_mu_f": enc.mu_f,
+            "decoded_max_spatial_err_over_E": ms / prob.E, "decoded_max_spectral_err_over_Delta": mf / prob.Delta}
+
+
 def batch_leg(F, torch, W, steps):
     """512 EEG-like 1D signals (lengths log-uniform in [2^12, 2^18]) and 64 diffraction-like
     2048^2 fields, FP32, corrected in one ffcz_correct_batched call per step."""
@@ -296,6 +335,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-steady", action="store_true")
+    ap.add_argument("--no-edits", action="store_true")
     ap.add_argument("--grad-n", type=int, default=256)
     ap.add_argument("--grad-rounds", type=int, default=50)
     args = ap.parse_args()
@@ -380,6 +420,11 @@ def main():
         extra["fwd_bwd_ms"] = fwd_bwd(F, torch, W, args.grad_n, args.grad_rounds, max(1, args.steps // 2))
         extra["fwd_bwd_config"] = f"{args.grad_n}^3 FP32 GRF k^-2, {args.grad_rounds} fixed rounds + adjoint"
         log(f"[bench] fwd+bwd {extra['fwd_bwd_ms']:.3f} ms")
+
+    if not args.no_edits:
+        log("[bench] edit coding: encoder and decoder on the FP32 field")
+        extra.update(edit_leg(F, torch, p32, args.steps))
+        log(f"[bench] encode {extra['encode_ms']:.3f} ms, decode {extra['decode_ms']:.3f} ms")
 
     if not args.no_batch:
         log("[bench] batched leg: 512 EEG signals + 64 x 2048^2 fields")
