@@ -290,6 +290,108 @@ int32_t ffcz_decode(int32_t dtype, int32_t ndim, const int64_t* shape, const voi
                     const int32_t* freq_codes, int64_t nnz_f, double step_s, double step_f, void* y_out,
                     void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Generalised bounds (the footnote to Eq. 2, Sec. IV-A; Sec. V-B, Observation 4).
+ *
+ * Pointwise bounds replace the scalars point by point and entry by entry:
+ * |eps_n| <= E_n, |Re delta_k| <= D^Re_k and |Im delta_k| <= D^Im_k, or with
+ * disk = 1 |delta_k| <= D_k (the modulus, projected radially; D_k taken from
+ * delta_re).  The loop, margins and verification are those of ffcz_correct,
+ * entry by entry: FP64 output checks D_k and projects onto D_k (1 - mu) and
+ * E_n (1 - mu); FP32 output checks D_k (1 - mu) and projects onto
+ * D_k (1 - 2 mu), with the FP32 margin rule of ffcz_suggest_margin applied to
+ * Delta = min_k D_k (times sqrt 2 for the disk).  Spectral bound arrays must
+ * satisfy D_{-k} = D_k where the half-spectrum holds both entries (the k_z = 0
+ * and Nyquist planes), as the bound of a real field's error does. */
+typedef struct {
+  const void* eps_s;     /* nullable device array: E_n, N values of dtype, C order
+                            (NULL: the scalar eps_s of the call)                    */
+  const void* delta_re;  /* nullable device array: D^Re_k (the disk's D_k), M values
+                            of dtype, half-spectrum in C order (NULL: delta_f)      */
+  const void* delta_im;  /* nullable: D^Im_k (NULL: delta_re, or delta_f)           */
+  int32_t disk;          /* 1: bound the modulus by delta_re (delta_im unused)      */
+  int32_t pad;
+} ffcz_bounds;
+
+/* Workspace bytes of ffcz_correct_bounds and ffcz_power_spectrum_bounds; 0 if unsupported. */
+size_t ffcz_bounds_workspace_bytes(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max_iter);
+
+/* ffcz_correct with pointwise bounds (arrays in bnd, scalars eps_s / delta_f
+ * where an array is NULL).  Shapes that run on the multidimensional passes
+ * (every remaining extent a power of two); no masks (opts->masks_out must be
+ * NULL).  Bound arrays with a negative or non-finite entry return
+ * FFCZ_E_INVALID before the loop.  In the statistics, max_spatial_err is the
+ * largest |y_n - x_n| / E_n and max_spectral_err the largest ratio of a part
+ * (box) or of the modulus (disk) to its bound, both <= 1 on success (0 / 0
+ * counts as 0).  Other arguments and results as ffcz_correct. */
+int32_t ffcz_correct_bounds(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x_orig,
+                            const void* x_base, void* x_out, double eps_s, double delta_f,
+                            const ffcz_bounds* bounds, int32_t max_iter, const ffcz_options* opts,
+                            void* workspace, size_t workspace_bytes, void* stream, ffcz_stats* stats);
+
+/* Relative power-spectrum bound (Sec. V-B, Observation 4): the pointwise
+ * spectral bound D_k (written to delta_out, M values of dtype, half-spectrum
+ * C order) that keeps every shell of the power spectrum within a relative
+ * error rho for any error inside the bounds.  Shell b = rint(|k|) with |k| from
+ * the signed integer frequencies; P_b = sum w_k |X_k|^2 over the shell (w_k = 2
+ * for interior last-axis entries, 1 at k_z = 0 and at the Nyquist plane), with
+ * X the FP64 DFT of x.  With S_b = sum w_k |X_k| and W_b = sum w_k, every entry
+ * of shell b gets the largest D with 2 sqrt2 D S_b + 2 D^2 W_b <= rho P_b (box:
+ * |Re|, |Im| <= D) or 2 D S_b + D^2 W_b <= rho P_b (disk = 1: |delta| <= D),
+ * rounded toward zero in FP32.  The shell sums use atomic additions, so the
+ * last bit of D can differ between calls.  Asynchronous on stream. */
+int32_t ffcz_power_spectrum_bounds(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x_orig,
+                                   double rho, int32_t disk, void* delta_out, void* workspace,
+                                   size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Lossless coding of the edit streams (Alg. 1, LosslesslyCompressEdits;
+ * Sec. IV-B, IV-D): Huffman coding of a stream of symbols -- the flag bytes
+ * (width 1, unsigned) or the int32 codes (width 4) that ffcz_encode writes.
+ * The symbols are counted blockwise into a global frequency table over
+ * [min, max]; the code merges the two lightest nodes, ties going to the node
+ * created first (leaves in symbol order, then merged nodes in turn); codes
+ * longer than 32 bits halve every count ((c + 1) / 2) and rebuild; canonical
+ * codes (by length, then value) are written most significant bit first into
+ * 32-bit words filled from their top bit, with the bit offset of every 1,024th
+ * symbol kept so that decoding runs one lane per 1,024 symbols.  The paper
+ * follows this stage with ZSTD, a third-party compressor not part of this
+ * library.
+ * Stream (device bytes): a 64-byte header (magic "FHUF", width, symbol
+ * count, smallest symbol, alphabet size, bit count, chunk count), the code
+ * lengths (one byte per alphabet entry, padded to 16), the chunk offsets
+ * (uint64), the 32-bit words. */
+typedef struct {
+  int64_t nsym;      /* symbols in the stream                                  */
+  int64_t lo;        /* smallest symbol                                        */
+  int64_t nalpha;    /* alphabet size: largest - smallest + 1 (at most 2^24)   */
+  size_t ws_bytes;   /* workspace of ffcz_huffman_encode / ffcz_huffman_decode */
+  size_t out_bytes;  /* output bytes that always suffice (32 bits a symbol)    */
+} ffcz_huffman_sizes;
+
+/* Workspace bytes for a stream of nsym symbols over an alphabet of nalpha
+ * (ffcz_huffman_plan needs nalpha = 0); 0 if nalpha exceeds 2^24. */
+size_t ffcz_huffman_workspace_bytes(int64_t nsym, int64_t nalpha);
+
+/* The alphabet of a device stream of nsym symbols (min and max on the device)
+ * and the sizes the encoder needs.  Blocks until they are known. */
+int32_t ffcz_huffman_plan(const void* sym, int64_t nsym, int32_t width, void* workspace, size_t workspace_bytes,
+                          void* stream, ffcz_huffman_sizes* plan);
+
+/* Encode the stream into out (device, out_bytes >= the stream's size; the
+ * plan's out_bytes always suffices); *used_bytes receives the size written.
+ * Blocks for the frequency table (the code is built on the host) and the bit
+ * count. */
+int32_t ffcz_huffman_encode(const void* sym, int64_t nsym, int32_t width, const ffcz_huffman_sizes* plan,
+                            void* out, size_t out_bytes, void* workspace, size_t workspace_bytes, void* stream,
+                            size_t* used_bytes);
+
+/* Decode a stream written by ffcz_huffman_encode into sym_out (device,
+ * capacity symbols of the given width); *nsym_out receives the count.
+ * FFCZ_E_INVALID for a corrupt header or a bit pattern that is no code. */
+int32_t ffcz_huffman_decode(const void* in, size_t in_bytes, int32_t width, void* sym_out, int64_t capacity,
+                            void* workspace, size_t workspace_bytes, void* stream, int64_t* nsym_out);
+
 /* One member of a batch: shape (ndim 1..3, unit extents squeezed), device
  * pointers as in ffcz_correct, and its own bounds. */
 typedef struct {

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["capi.hip", "launch_col_f32.hip", "launch_col_f64.hip", "launch_row_f32.hip", "launch_row_f64.hip",
            "launch_sig_f32.hip", "launch_sig_f64.hip", "launch_sigt_f64.hip",
-           "launch_edit_f32.hip", "launch_edit_f64.hip"]
+           "launch_edit_f32.hip", "launch_edit_f64.hip", "launch_bounds_f32.hip", "launch_bounds_f64.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

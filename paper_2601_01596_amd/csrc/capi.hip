@@ -24,6 +24,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <queue>
 #include <thread>
 #include <map>
 #include <string>
@@ -31,7 +32,9 @@
 
 #include "../../include/ffcz.h"
 #include "common.hpp"
+#include "kernels_bounds.hpp"
 #include "kernels_edit.hpp"
+#include "kernels_huff.hpp"
 #include "kernels_sig.hpp"
 #include "launch.hpp"
 #include "sig_dispatch.hpp"
@@ -49,6 +52,10 @@ hipError_t launch_edit_row_f32(int mode, int H, const void* args, int64_t nb, hi
 hipError_t launch_edit_row_f64(int mode, int H, const void* args, int64_t nb, hipStream_t s);
 hipError_t launch_edit_col_f32(int mode, int L, const void* args, int64_t nb, hipStream_t s);
 hipError_t launch_edit_col_f64(int mode, int L, const void* args, int64_t nb, hipStream_t s);
+hipError_t launch_bounds_row_f32(int mode, int H, int vv, const void* args, int64_t nb, hipStream_t s);
+hipError_t launch_bounds_row_f64(int mode, int H, int vv, const void* args, int64_t nb, hipStream_t s);
+hipError_t launch_bounds_col_f32(int mode, int L, const void* args, int64_t nb, hipStream_t s);
+hipError_t launch_bounds_col_f64(int mode, int L, const void* args, int64_t nb, hipStream_t s);
 
 // Which instantiation family runs a mode: the loop in the data type, set-up and
 // verification in FP64 (SigArgs<double>).
@@ -86,6 +93,8 @@ int row_block_rows(int dtype, int H, int v) { return dtype == 0 ? tile_rows<floa
 hipError_t launch_col(int dtype, int mode, int L, int v, const void* args, int64_t nb, hipStream_t s) {
   if (mode == COL_XEDIT || mode == COL_XUNDO)  // edit bookkeeping: default tiles only
     return dtype == 0 ? launch_edit_col_f32(mode, L, args, nb, s) : launch_edit_col_f64(mode, L, args, nb, s);
+  if (mode == COL_XPASSP || mode == COL_VERIFYP)  // pointwise bounds: default tiles only
+    return dtype == 0 ? launch_bounds_col_f32(mode, L, args, nb, s) : launch_bounds_col_f64(mode, L, args, nb, s);
   return dtype == 0 ? launch_col_f32(mode, L, v, args, nb, s) : launch_col_f64(mode, L, v, args, nb, s);
 }
 }  // namespace ffcz
@@ -253,6 +262,9 @@ struct StateInit {
   const void* px;
   const void* pxb;
   void* py;
+  const void* pE;
+  const void* pD;
+  int32_t disk, pad2;
 };
 
 // Check threshold and projection bound of the f-cube.  An FP64 output is
@@ -486,6 +498,12 @@ __global__ void state_init_kernel(DevState* st, int64_t B, const StateInit* arr,
     s.px = p.px;
     s.pxb = p.pxb;
     s.py = p.py;
+    s.pE = p.pE;
+    s.pD = p.pD;
+    s.disk = p.disk;
+    s.fe = 1.0 - p.mu;
+    s.fc = 1.0;
+    s.fp = 1.0 - p.mu;
     st[t] = s;
   }
   for (int64_t i = t; i < nviol; i += (int64_t)gridDim.x * blockDim.x) viol[i] = 0ull;
@@ -671,6 +689,54 @@ __global__ void __launch_bounds__(256) encode_margin_kernel(const double* ulp_pa
   st->Dp = st->Delta * (1.0 - 2.0 * mu_f);
 }
 
+// Margin and threshold factors for pointwise bounds, one block.  FP64 output: mu = 2^-16 (or
+// the caller's), check at D_k, project onto D_k (1 - mu) and E_n (1 - mu).  FP32 output: the
+// FP32 rule of margin_kernel with Delta = the smallest spectral bound (times sqrt 2 for the
+// disk, whose modulus takes the rounding noise of both parts), check at D_k (1 - mu), project
+// onto D_k (1 - 2 mu).
+__global__ void __launch_bounds__(256) bounds_margin_kernel(const double* ulp_part, const unsigned long long* minpart,
+                                                            int nmin, int64_t n, int dt, int disk, double mu_given,
+                                                            DevState* st) {
+  __shared__ double red[4];
+  __shared__ unsigned long long redm[4];
+  const int nslot = ulp_slots(n);
+  double s = 0.0;
+  unsigned long long mb = ~0ull;
+  if (dt == FFCZ_F32)
+    for (int k = threadIdx.x; k < nslot; k += 256) s += ulp_part[k];
+  for (int k = threadIdx.x; k < nmin; k += 256) mb = mb < minpart[k] ? mb : minpart[k];
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off, 64);
+    const unsigned long long o = __shfl_xor(mb, off, 64);
+    mb = mb < o ? mb : o;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = s;
+    redm[threadIdx.x >> 6] = mb;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int w = 1; w < 4; ++w) redm[0] = redm[0] < redm[w] ? redm[0] : redm[w];
+  double mu = mu_given;
+  if (!(mu > 0.0)) {
+    if (dt == FFCZ_F64) {
+      mu = 0x1p-16;
+    } else {
+      const double dmin = redm[0] == ~0ull ? 0.0 : __longlong_as_double((long long)redm[0]);
+      const double sigma = sqrt(((red[0] + red[1]) + (red[2] + red[3])) / (double)n / 12.0);
+      double m = dmin > 0.0 ? 8.0 * sigma * sqrt((double)n / 2.0) / dmin : 0.5;
+      if (disk && dmin > 0.0) m *= sqrt(2.0);
+      mu = fmin(0.5, fmax(0x1p-16, m));
+    }
+  }
+  const double rho = dt == FFCZ_F64 ? 0.0 : mu;
+  st->mu = mu;
+  st->fe = 1.0 - mu;
+  st->fc = 1.0 - rho;
+  st->fp = 1.0 - rho - mu;
+  st->Ep = st->E * (1.0 - mu);
+}
+
 // Per-round control, one block per instance: sum the x-pass partials into
 // v_k, fold the spatial-clip partials of the z-pass that produced the checked
 // iterate into the totals, and decide on the device whether the loop stops
@@ -773,6 +839,8 @@ struct Ctx {
   // edit accumulators (encoder only): spatial, one value per point; frequency, laid out as Z
   void* sacc = nullptr;
   void* facc = nullptr;
+  // pointwise bounds: the (Re, Im) bound pairs laid out as Z (null: the scalar bounds)
+  const void* pD = nullptr;
   DevState* st() const { return (DevState*)(ws + p->off_state); }
   unsigned long long* viol() const { return (unsigned long long*)(ws + p->off_viol); }
   void* twT() const { return ws + p->off_twT; }
@@ -830,7 +898,8 @@ ColGeom geom_x(const Plan& p, int64_t pitch, int64_t plane) {
 template <typename T>
 hipError_t run_col(int dt, int mode, int v, const ColGeom& g, const Plan& p, const void* src, void* dst,
                    const void* tw, DevState* st, unsigned long long* part, uint8_t* fmask,
-                   hipStream_t s, void* fedit = nullptr) {
+                   hipStream_t s, void* fedit = nullptr, const void* bnd = nullptr, int64_t bnd_so = 0,
+                   int64_t bnd_s = 0, int bnd_dbl = 0) {
   ColArgs<T> a;
   memset(&a, 0, sizeof(a));
   const int C = col_block_cols(dt, g.L, v);
@@ -851,6 +920,10 @@ hipError_t run_col(int dt, int mode, int v, const ColGeom& g, const Plan& p, con
   a.mrow_i = g.mrow_i;
   a.mrow_o = g.mrow_o;
   a.fedit = (cx<T>*)fedit;
+  a.bnd = bnd;
+  a.bnd_so = bnd_so;
+  a.bnd_s = bnd_s;
+  a.bnd_dbl = bnd_dbl;
   const int64_t nb = g.outer * a.ncb;
   return launch_col(dt, mode, g.L, v, &a, nb, s);
 }
@@ -881,6 +954,8 @@ hipError_t run_row(int tdt, int iodt, int mode, int v, const Plan& p, int64_t pi
   a.sedit = (T*)sedit;
   if (mode == ROW_INITE || mode == ROW_LOOPE || mode == ROW_DECODE)  // default tiles only
     return tdt == 0 ? launch_edit_row_f32(mode, p.H, &a, nb, s) : launch_edit_row_f64(mode, p.H, &a, nb, s);
+  if (mode >= ROW_INITP && mode <= ROW_VERIFYP)  // pointwise bounds, by the field's dtype
+    return iodt == 0 ? launch_bounds_row_f32(mode, p.H, v, &a, nb, s) : launch_bounds_row_f64(mode, p.H, v, &a, nb, s);
   if (tdt == 1 && iodt == 0) return launch_row_f64_f32io(mode, p.H, v, &a, nb, s);
   return tdt == 0 ? launch_row_f32(mode, p.H, v, &a, nb, s) : launch_row_f64(mode, p.H, v, &a, nb, s);
 }
@@ -888,6 +963,11 @@ hipError_t run_row(int tdt, int iodt, int mode, int v, const Plan& p, int64_t pi
 template <typename T>
 hipError_t row_T(int mode, const Ctx& c, const void* src, void* dst, uint32_t* smask) {
   const Plan& p = *c.p;
+  if (c.pD && (mode == ROW_INIT || mode == ROW_LOOP)) {
+    // pointwise bounds: the staged pass on the default tiles
+    return run_row<T, T>(p.dt, p.dt, mode == ROW_INIT ? ROW_INITP : ROW_LOOPP, 0, p, p.pitch, p.plane, src, dst,
+                         (const char*)c.twT() + sizeof(cx<T>) * p.twz, c.st(), c.part(Ctx::PZ), smask, c.s);
+  }
   if (c.sacc && (mode == ROW_INIT || mode == ROW_LOOP)) {
     // with edit bookkeeping: the staged pass on the default tiles
     return run_row<T, T>(p.dt, p.dt, mode == ROW_INIT ? ROW_INITE : ROW_LOOPE, 0, p, p.pitch, p.plane, src, dst,
@@ -897,6 +977,19 @@ hipError_t row_T(int mode, const Ctx& c, const void* src, void* dst, uint32_t* s
   const int v = mode == ROW_LOOP ? p.vz : init_variant(p);
   const void* tw = (const char*)c.twT() + sizeof(cx<T>) * (v == 2 ? p.twz8 : p.twz);
   return run_row<T, T>(p.dt, p.dt, mode, v, p, p.pitch, p.plane, src, dst, tw, c.st(), c.part(Ctx::PZ), smask, c.s);
+}
+
+// The loop's x-pass: plain, with edit bookkeeping, or against pointwise bounds (the bound
+// pairs share the spectrum's layout).
+template <typename T>
+hipError_t xpass_T(const Ctx& c, const void* src, void* dst, const void* twx, unsigned long long* px, uint8_t* fmask) {
+  const Plan& p = *c.p;
+  const ColGeom g = geom_x(p, p.pitch, p.plane);
+  if (c.pD)
+    return run_col<T>(p.dt, COL_XPASSP, 0, g, p, src, dst, twx, c.st(), px, nullptr, c.s, nullptr, c.pD, g.so, g.s,
+                      p.dt == FFCZ_F64 ? 1 : 0);
+  return run_col<T>(p.dt, c.facc ? COL_XEDIT : COL_XPASS, c.facc ? 0 : p.vx, g, p, src, dst, twx, c.st(), px, fmask,
+                    c.s, c.facc);
 }
 
 template <typename T>
@@ -913,10 +1006,7 @@ hipError_t enqueue_round(const Ctx& c, int r, unsigned long long* viol, int64_t 
       return run_col<T>(p.dt, COL_FWD, p.vy, geom_y(p, p.pitch, p.plane), p, c.Z(), c.A(), twy, c.st(), px, fmask, c.s);
     });
     if (e != hipSuccess) return e;
-    e = timed(PK_XPASS, r, c.s, [&] {
-      return run_col<T>(p.dt, c.facc ? COL_XEDIT : COL_XPASS, c.facc ? 0 : p.vx, geom_x(p, p.pitch, p.plane), p,
-                        c.A(), c.A(), twx, c.st(), px, fmask, c.s, c.facc);
-    });
+    e = timed(PK_XPASS, r, c.s, [&] { return xpass_T<T>(c, c.A(), c.A(), twx, px, fmask); });
     if (e != hipSuccess) return e;
     e = launch_ctl(c, viol, vstride);
     if (e != hipSuccess) return e;
@@ -925,10 +1015,7 @@ hipError_t enqueue_round(const Ctx& c, int r, unsigned long long* viol, int64_t 
     });
     if (e != hipSuccess) return e;
   } else {
-    e = timed(PK_XPASS, r, c.s, [&] {
-      return run_col<T>(p.dt, c.facc ? COL_XEDIT : COL_XPASS, c.facc ? 0 : p.vx, geom_x(p, p.pitch, p.plane), p,
-                        c.Z(), c.A(), twx, c.st(), px, fmask, c.s, c.facc);
-    });
+    e = timed(PK_XPASS, r, c.s, [&] { return xpass_T<T>(c, c.Z(), c.A(), twx, px, fmask); });
     if (e != hipSuccess) return e;
     e = launch_ctl(c, viol, vstride);
     if (e != hipSuccess) return e;
@@ -967,8 +1054,8 @@ hipError_t enqueue_verify(const Ctx& c, bool z_done) {
   hipError_t e = hipSuccess;
   if (!z_done) {
     e = timed(PK_VZ, -1, c.s, [&] {
-      return run_row<double, T>(1, p.dt, ROW_VERIFY, kVerifyRowPlan, p, p.pitch64, p.plane64, nullptr, W,
-                                tb + 16 * (kVerifyRowPlan == 2 ? p.twz8 : p.twz), c.st(),
+      return run_row<double, T>(1, p.dt, c.pD ? ROW_VERIFYP : ROW_VERIFY, kVerifyRowPlan, p, p.pitch64, p.plane64,
+                                nullptr, W, tb + 16 * (kVerifyRowPlan == 2 ? p.twz8 : p.twz), c.st(),
                                 c.part(Ctx::PVZ), nullptr, c.s);
     });
     if (e != hipSuccess) return e;
@@ -981,6 +1068,12 @@ hipError_t enqueue_verify(const Ctx& c, bool z_done) {
     if (e != hipSuccess) return e;
   }
   e = timed(PK_VX, -1, c.s, [&] {
+    if (c.pD) {
+      // bounds at the working-type spectrum's layout, the transform at the FP64 one
+      const ColGeom gb = geom_x(p, p.pitch, p.plane);
+      return run_col<double>(1, COL_VERIFYP, 0, geom_x(p, p.pitch64, p.plane64), p, W, W, tb + 16 * p.twx, c.st(),
+                             c.part(Ctx::PVX), nullptr, c.s, nullptr, c.pD, gb.so, gb.s, p.dt == FFCZ_F64 ? 1 : 0);
+    }
     return run_col<double>(1, COL_VERIFY, 0, geom_x(p, p.pitch64, p.plane64), p, W, W, tb + 16 * p.twx, c.st(),
                            c.part(Ctx::PVX), nullptr, c.s);
   });
@@ -994,6 +1087,14 @@ hipError_t enqueue_verify(const Ctx& c, bool z_done) {
 template <typename T>
 hipError_t enqueue_final(const Ctx& c, bool verify) {
   const Plan& p = *c.p;
+  if (c.pD) {  // pointwise bounds: closing clamp against E_n, then the pointwise verification
+    hipError_t e = timed(PK_FINAL, -1, c.s, [&] {
+      return run_row<T, T>(p.dt, p.dt, ROW_FINALP, 0, p, p.pitch, p.plane, c.Z(), nullptr,
+                           (const char*)c.twT() + sizeof(cx<T>) * p.twz, c.st(), c.part(Ctx::PZ), nullptr, c.s);
+    });
+    if (e != hipSuccess || !verify) return e;
+    return enqueue_verify<T>(c, false);
+  }
   if (!final_fused(p)) {
     hipError_t e = timed(PK_FINAL, -1, c.s, [&] { return row_T<T>(ROW_FINAL, c, c.Z(), nullptr, nullptr); });
     if (e != hipSuccess || !verify) return e;
@@ -1369,6 +1470,53 @@ EditLayout edit_layout(const Plan& p) {
   return L;
 }
 
+// Pointwise bounds of a ffcz_correct_bounds call (null for scalar bounds).
+struct BoundsCfg {
+  const void* pE;               // E_n (caller's device array, field dtype) or null: the scalar E
+  const void* dre;              // D^Re_k (or the disk's D_k), half-spectrum C order, or null
+  const void* dim;              // D^Im_k or null (then D^Re_k, or the scalar)
+  double sre, sim;              // scalar spectral bounds where the arrays are null
+  int disk;
+  void* pD;                     // workspace: the bound pairs laid out as the spectrum
+  unsigned long long* minpart;  // workspace: kMinSlots block minima
+  unsigned long long* bad;      // workspace: invalid-entry counter
+};
+
+// Workspace of ffcz_correct_bounds and ffcz_power_spectrum_bounds beyond the plan's: the bound
+// pairs, block minima and a counter; for the power-spectrum bound a zero field (the verification
+// pass transforms y - x, here x - 0), the per-block shell sums and the shell bounds.
+struct BoundsLayout {
+  size_t off_D = 0, off_min = 0, off_bad = 0, off_zero = 0, off_shell = 0, off_bins = 0, bytes = 0;
+  int nb = 0;   // shells
+  int nsb = 0;  // shell-sum blocks
+};
+
+BoundsLayout bounds_layout(const Plan& p) {
+  BoundsLayout L;
+  const size_t ts = p.dt == FFCZ_F32 ? 4 : 8;
+  double kmax2 = 0.0;
+  for (int i = 0; i < p.nd; ++i) kmax2 += (double)(p.n[i] / 2) * (double)(p.n[i] / 2);
+  L.nb = (int)std::lrint(std::sqrt(kmax2)) + 1;
+  const int64_t M = p.nrows * p.ncols;
+  L.nsb = (int)std::max<int64_t>(1, std::min<int64_t>(256, (M + 4095) / 4096));
+  const int64_t rpp = p.nd == 3 ? p.n[1] : p.nrows;
+  size_t off = align_up(p.bytes, 256);
+  L.off_D = off;
+  off = align_up(off + 2 * ts * (size_t)(p.nrows / rpp) * (size_t)p.plane, 256);
+  L.off_min = off;
+  off = align_up(off + 8 * (size_t)kMinSlots, 256);
+  L.off_bad = off;
+  off = align_up(off + 8, 256);
+  L.off_zero = off;
+  off = align_up(off + ts * (size_t)p.N, 256);
+  L.off_shell = off;
+  off = align_up(off + 8 * 3 * (size_t)L.nsb * (size_t)L.nb, 256);
+  L.off_bins = off;
+  off = align_up(off + 8 * (size_t)L.nb, 256);
+  L.bytes = off;
+  return L;
+}
+
 // One correction over the B instances of a plan.  inst[b] supplies pointers and
 // bounds, mus[b] the margins; mus null (one FP32 instance) derives mu from x on
 // the device, between the state set-up and the first pass.
@@ -1378,7 +1526,8 @@ EditLayout edit_layout(const Plan& p) {
 template <typename T>
 int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* mus, int32_t max_iter,
                       const ffcz_options& o, char* ws, hipStream_t s, ffcz_stats* stats, int32_t* status,
-                      DevState* host_state = nullptr, const EditCfg* ed = nullptr) {
+                      DevState* host_state = nullptr, const EditCfg* ed = nullptr,
+                      const BoundsCfg* bc = nullptr) {
   const bool no_alloc = host_state != nullptr;
   Plan p = p0;
   Ctx c{&p, ws, s};
@@ -1386,6 +1535,7 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
     c.sacc = ed->sacc;
     c.facc = ed->facc;
   }
+  if (bc) c.pD = bc->pD;
   const int64_t vstride = max_iter + 2;
   const bool user_viol = o.viol_per_round && p.B == 1;
   unsigned long long* viol = user_viol ? (unsigned long long*)o.viol_per_round : c.viol();
@@ -1411,6 +1561,11 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
       si.Dc = inst[b].delta_f * (1.0 - ed->mu_f);
       si.Dp = inst[b].delta_f * (1.0 - 2.0 * ed->mu_f);
     }
+    if (bc) {
+      si.pE = bc->pE;
+      si.pD = bc->pD;
+      si.disk = bc->disk;
+    }
     si.max_iter = max_iter;
     si.fixed = o.fixed_iterations ? 1 : 0;
     si.record_masks = rec ? 1 : 0;
@@ -1433,7 +1588,40 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
   hipLaunchKernelGGL(state_init_kernel, dim3((unsigned)std::max<int64_t>(1, (nthr + 255) / 256)), dim3(256), 0, s,
                      c.st(), p.B, arr, one, viol, nviol);
   HIPCHK(hipGetLastError());
-  if (ed && ed->derive) {
+  if (bc) {
+    // the bound pairs into the spectrum layout, their checks and minimum, then mu and the factors
+    if (p.B != 1) return fail(FFCZ_E_INVALID, "pointwise bounds take one instance");
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, bc->bad, (int64_t)1);
+    HIPCHK(hipGetLastError());
+    const int64_t M = p.nrows * p.ncols;
+    const int nmin = (int)std::max<int64_t>(1, std::min<int64_t>(kMinSlots, (M + 255) / 256));
+    const SpecGeom g{p.nrows, (int32_t)p.ncols, p.lg_rpp, p.pitch, p.plane};
+    hipLaunchKernelGGL(bounds_setup_kernel<T>, dim3((unsigned)nmin), dim3(256), 0, s, (const T*)bc->dre,
+                       (const T*)bc->dim, bc->sre, bc->sim, (cx<T>*)bc->pD, M, g, bc->minpart, bc->bad);
+    HIPCHK(hipGetLastError());
+    if (bc->pE) {
+      const int nbe = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (p.N + 255) / 256));
+      hipLaunchKernelGGL(spatial_check_kernel<T>, dim3((unsigned)nbe), dim3(256), 0, s, (const T*)bc->pE, p.N,
+                         bc->bad);
+      HIPCHK(hipGetLastError());
+    }
+    double* slots = (double*)(ws + p.off_ulp);
+    const double mu_given = mus ? mus[0] : 0.0;
+    if (p.dt == FFCZ_F32 && !(mu_given > 0.0)) {
+      const MarginJob one_job{(const float*)inst[0].x_orig, p.N, 0.0};
+      hipLaunchKernelGGL(ulp_part_kernel, dim3((unsigned)ulp_slots(p.N)), dim3(256), 0, s, one_job,
+                         (const MarginJob*)nullptr, slots);
+      HIPCHK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(bounds_margin_kernel, dim3(1), dim3(256), 0, s, (const double*)slots,
+                       (const unsigned long long*)bc->minpart, nmin, p.N, (int)p.dt, bc->disk, mu_given, c.st());
+    HIPCHK(hipGetLastError());
+    unsigned long long nbad = 0;
+    HIPCHK(hipMemcpyAsync(&nbad, bc->bad, sizeof(nbad), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (nbad) return fail(FFCZ_E_INVALID, "bound arrays must hold finite values >= 0 (" + std::to_string(nbad) +
+                                              " entries do not)");
+  } else if (ed && ed->derive) {
     // the encoder's shrinks from x (ulp partials for the FP32 output margin, max |x|)
     if (p.B != 1) return fail(FFCZ_E_INVALID, "the encoder takes one instance");
     const int nsl = ulp_slots(p.N);
@@ -1466,7 +1654,9 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
     HIPCHK(hipGetLastError());
   }
   HIPCHK(write_twiddles(c));
-  if (ed) {
+  if (bc) {
+    set_variants(p, 0, 0, 0);  // the pointwise passes exist for the default tiles only
+  } else if (ed) {
     // edit bookkeeping runs on the default tiles; the frequency accumulators start at zero
     set_variants(p, 0, 0, 0);
     const int64_t nr = edit_layout(p).spec_reals;
@@ -1493,13 +1683,14 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
     if (o.use_graph && !g_prof.on && !no_alloc) {
       GraphKey key{{(int64_t)p.dt, p.nd, p.B, p.n[0], p.n[1], p.n[2], (int64_t)(uintptr_t)ws, (int64_t)(uintptr_t)viol,
                     vstr, (int64_t)(uintptr_t)fmask, (int64_t)(uintptr_t)smask, chunk, max_iter, p.vy, p.vx, p.vz,
-                    (int64_t)(uintptr_t)c.sacc, (int64_t)(uintptr_t)c.facc}};
+                    (int64_t)(uintptr_t)c.sacc, (int64_t)(uintptr_t)c.facc, (int64_t)(uintptr_t)c.pD}};
       gexec = g_graphs.find(key);
       if (!gexec) {
         HIPCHK(g_streams.ready());
         Ctx cc{&p, ws, g_streams.cap};
         cc.sacc = c.sacc;
         cc.facc = c.facc;
+        cc.pD = c.pD;
         HIPCHK(hipStreamBeginCapture(g_streams.cap, hipStreamCaptureModeThreadLocal));
         hipError_t ce = hipSuccess;
         for (int r = 0; r < chunk && ce == hipSuccess; ++r) ce = enqueue_round<T>(cc, r, viol, vstr, fmask, smask);
@@ -1564,7 +1755,8 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
     int32_t r = FFCZ_OK;
     if (h.nonfinite) r = FFCZ_E_NONFINITE;
     else if (!h.converged && !o.fixed_iterations) r = FFCZ_NOT_CONVERGED;
-    else if (o.verify_fp64 && (!(ms <= inst[b].eps_s) || !(mf <= inst[b].delta_f))) r = FFCZ_VERIFY_FAILED;
+    else if (o.verify_fp64 && bc && (!(ms <= 1.0) || !(mf <= 1.0) || h.spectral_viol)) r = FFCZ_VERIFY_FAILED;
+    else if (o.verify_fp64 && !bc && (!(ms <= inst[b].eps_s) || !(mf <= inst[b].delta_f))) r = FFCZ_VERIFY_FAILED;
     status[b] = r;
   }
   return FFCZ_OK;
@@ -2383,6 +2575,193 @@ int32_t decode_impl(const Plan& p, const EditLayout& L, char* ws, const void* xb
   return FFCZ_OK;
 }
 
+// Pointwise spectral bound that keeps every shell of the power spectrum of x within rho:
+// FP64 spectrum of x on the verification passes (their last-axis pass forms y - x; here y = x
+// and x = a zero field), shell sums, shell bounds, then the bound of every entry.
+template <typename T>
+int32_t power_bounds_impl(const Plan& p, const BoundsLayout& L, char* ws, const void* x, double rho, int disk,
+                          void* out, hipStream_t s) {
+  Ctx c{&p, ws, s};
+  StateInit si;
+  memset(&si, 0, sizeof(si));
+  si.inv_n = 1.0 / (double)p.N;
+  si.px = ws + L.off_zero;
+  si.py = const_cast<void*>(x);
+  hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, s, c.st(), (int64_t)1, (const StateInit*)nullptr, si,
+                     c.viol(), (int64_t)1);
+  HIPCHK(hipGetLastError());
+  const int64_t nz = (int64_t)p.N * (p.dt == FFCZ_F32 ? 4 : 8) / 8;
+  hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s,
+                     (unsigned long long*)(ws + L.off_zero), nz);
+  HIPCHK(hipGetLastError());
+  HIPCHK(write_twiddles(c));
+  const char* tb = (const char*)c.tw64();
+  void* W = c.W();
+  const hipError_t ez = run_row<double, T>(1, p.dt, ROW_VERIFY, kVerifyRowPlan, p, p.pitch64, p.plane64, nullptr, W,
+                                           tb + 16 * p.twz8, c.st(), c.part(Ctx::PVZ), nullptr, s);
+  HIPCHK(ez);
+  if (p.nd == 3)
+    HIPCHK(run_col<double>(1, COL_FWD_NS, 0, geom_y(p, p.pitch64, p.plane64), p, W, W, tb + 16 * p.twy, c.st(),
+                           nullptr, nullptr, s));
+  if (p.nd >= 2)
+    HIPCHK(run_col<double>(1, COL_FWD_NS, 0, geom_x(p, p.pitch64, p.plane64), p, W, W, tb + 16 * p.twx, c.st(),
+                           nullptr, nullptr, s));
+  const SpecGeom g64{p.nrows, (int32_t)p.ncols, p.lg_rpp, p.pitch64, p.plane64};
+  const int64_t n0 = p.nd >= 2 ? p.n[0] : 1, n1 = p.nd == 3 ? p.n[1] : 1, nl = p.n[p.nd - 1];
+  double* part = (double*)(ws + L.off_shell);
+  double* bins = (double*)(ws + L.off_bins);
+  hipLaunchKernelGGL(shell_part_kernel, dim3((unsigned)L.nsb), dim3(256), 0, s, (const cx<double>*)W, g64, p.nd, n0,
+                     n1, nl, L.nb, part);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(shell_bound_kernel, dim3((unsigned)((L.nb + 255) / 256)), dim3(256), 0, s,
+                     (const double*)part, L.nsb, L.nb, rho, disk, bins);
+  HIPCHK(hipGetLastError());
+  const int64_t M = p.nrows * p.ncols;
+  hipLaunchKernelGGL(shell_scatter_kernel<T>, dim3((unsigned)std::min<int64_t>(4096, (M + 255) / 256)), dim3(256), 0,
+                     s, (const double*)bins, p.nrows, (int32_t)p.ncols, p.nd, n0, n1, (T*)out);
+  HIPCHK(hipGetLastError());
+  return FFCZ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Huffman code construction (host side of LosslesslyCompressEdits).  The tree merges the two
+// lightest nodes, ties going to the node created first (leaves in symbol order, then merged
+// nodes in turn), so the code lengths depend on the frequency table alone; codes longer than
+// kHuffMaxLen bits make every non-zero count (count + 1) / 2 and the tree is rebuilt.
+
+constexpr int kHuffMaxLen = 32;
+constexpr int64_t kHuffMaxAlpha = int64_t(1) << 24;
+
+std::vector<uint8_t> huff_tree_lengths(const std::vector<unsigned long long>& c) {
+  std::vector<uint8_t> len(c.size(), 0);
+  std::vector<int64_t> present;
+  for (size_t i = 0; i < c.size(); ++i)
+    if (c[i]) present.push_back((int64_t)i);
+  if (present.empty()) return len;
+  if (present.size() == 1) {
+    len[present[0]] = 1;
+    return len;
+  }
+  using Node = std::pair<unsigned long long, int64_t>;  // (weight, id)
+  std::priority_queue<Node, std::vector<Node>, std::greater<Node>> pq;
+  const int64_t nl = (int64_t)present.size();
+  for (int64_t i = 0; i < nl; ++i) pq.push(Node{c[present[i]], i});
+  std::vector<int64_t> parent(2 * nl - 1, -1);
+  int64_t nid = nl;
+  while (pq.size() > 1) {
+    const Node a = pq.top();
+    pq.pop();
+    const Node b = pq.top();
+    pq.pop();
+    parent[a.second] = nid;
+    parent[b.second] = nid;
+    pq.push(Node{a.first + b.first, nid});
+    ++nid;
+  }
+  std::vector<int> depth(nid, 0);
+  for (int64_t node = nid - 2; node >= 0; --node) depth[node] = depth[parent[node]] + 1;  // parents come later
+  for (int64_t i = 0; i < nl; ++i) len[present[i]] = (uint8_t)std::min(depth[i], 255);
+  return len;
+}
+
+std::vector<uint8_t> huff_lengths(std::vector<unsigned long long> c) {
+  for (;;) {
+    std::vector<uint8_t> len = huff_tree_lengths(c);
+    int mx = 0;
+    for (uint8_t l : len) mx = std::max<int>(mx, l);
+    if (mx <= kHuffMaxLen) return len;
+    for (auto& v : c)
+      if (v) v = (v + 1) / 2;
+  }
+}
+
+// Canonical tables: cnt[l] codes of length l, first[l] the first of them, idx[l] the position
+// of the first in `sorted` (symbols ordered by length, then value), code[s] every symbol's code.
+struct HuffTables {
+  uint32_t first[kHuffMaxLen + 1], cnt[kHuffMaxLen + 1], idx[kHuffMaxLen + 1];
+  std::vector<int32_t> sorted;
+  std::vector<uint32_t> code;
+};
+
+HuffTables huff_tables(const std::vector<uint8_t>& len) {
+  HuffTables t;
+  memset(t.first, 0, sizeof(t.first));
+  memset(t.cnt, 0, sizeof(t.cnt));
+  memset(t.idx, 0, sizeof(t.idx));
+  for (uint8_t l : len)
+    if (l) t.cnt[l]++;
+  uint64_t code = 0;
+  uint32_t pos = 0;
+  for (int l = 1; l <= kHuffMaxLen; ++l) {
+    code = (code + (l > 1 ? t.cnt[l - 1] : 0)) << (l > 1 ? 1 : 0);
+    t.first[l] = (uint32_t)code;
+    t.idx[l] = pos;
+    pos += t.cnt[l];
+  }
+  t.sorted.assign(pos, 0);
+  t.code.assign(len.size(), 0);
+  uint32_t fill[kHuffMaxLen + 1];
+  for (int l = 0; l <= kHuffMaxLen; ++l) fill[l] = 0;
+  for (size_t s = 0; s < len.size(); ++s) {
+    const int l = len[s];
+    if (!l) continue;
+    t.sorted[t.idx[l] + fill[l]] = (int32_t)s;
+    t.code[s] = t.first[l] + fill[l];
+    fill[l]++;
+  }
+  return t;
+}
+
+// Stream layout in the caller's output buffer: the header, the code lengths (nalpha bytes,
+// padded to 16), the chunk offsets (uint64), then the 32-bit words.
+struct HuffHeader {
+  uint32_t magic, width;
+  int64_t nsym, lo, nalpha, nbits, nchunks, pad[2];
+};
+constexpr uint32_t kHuffMagic = 0x46554846u;  // "FHUF"
+
+struct HuffLayout {
+  size_t off_len, off_chunks, off_words, bytes;
+};
+HuffLayout huff_layout(int64_t n, int64_t nalpha, int64_t nbits) {
+  HuffLayout L;
+  L.off_len = sizeof(HuffHeader);
+  L.off_chunks = align_up(L.off_len + (size_t)nalpha, 16);
+  const int64_t nch = (n + kHuffChunk - 1) / kHuffChunk;
+  L.off_words = align_up(L.off_chunks + 8 * (size_t)nch, 16);
+  L.bytes = L.off_words + 4 * (size_t)((nbits + 31) / 32);
+  return L;
+}
+
+// Workspace: minmax partials, the frequency table, lengths, codes, block offsets, totals and
+// the decoder's tables.
+struct HuffWs {
+  size_t off_mm, off_counts, off_len, off_code, off_boff, off_tot, off_tab, off_sorted, bytes;
+};
+HuffWs huff_ws(int64_t n, int64_t nalpha) {
+  HuffWs W;
+  size_t off = 0;
+  W.off_mm = off;
+  off = align_up(off + 16 * 1024, 256);
+  W.off_counts = off;
+  off = align_up(off + 8 * (size_t)nalpha, 256);
+  W.off_len = off;
+  off = align_up(off + (size_t)nalpha, 256);
+  W.off_code = off;
+  off = align_up(off + 4 * (size_t)nalpha, 256);
+  const int64_t nblk = (n + kHuffBlockSyms - 1) / kHuffBlockSyms;
+  W.off_boff = off;
+  off = align_up(off + 8 * (size_t)std::max<int64_t>(1, nblk), 256);
+  W.off_tot = off;
+  off = align_up(off + 64, 256);
+  W.off_tab = off;
+  off = align_up(off + 3 * 4 * (kHuffMaxLen + 1), 256);
+  W.off_sorted = off;
+  off = align_up(off + 4 * (size_t)nalpha, 256);
+  W.bytes = off;
+  return W;
+}
+
 // Scratch of ffcz_correct_noalloc (the array is declared at file scope, above): host
 // code never passes the array's name to a kernel (on the host it names a host-side
 // stand-in); it takes the device address hipGetSymbolAddress returns, once per device,
@@ -2604,6 +2983,238 @@ int32_t ffcz_correct_noalloc(int32_t dtype, int32_t ndim, const int64_t* shape, 
   if (r != FFCZ_OK) return r;
   DevState host_state;  // the loop state is read back into this (no pinned staging)
   return single_run(sc, ws, (hipStream_t)stream, stats, &host_state);
+}
+
+size_t ffcz_bounds_workspace_bytes(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max_iter) {
+  if (route_1d(ndim, shape)) return 0;
+  Plan p;
+  std::string keep = g_err;
+  if (make_plan(dtype, ndim, shape, max_iter < 0 ? 0 : max_iter, 1, p) != FFCZ_OK) return 0;
+  g_err = keep;
+  return bounds_layout(p).bytes;
+}
+
+int32_t ffcz_correct_bounds(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x, const void* xb,
+                            void* y, double eps_s, double delta_f, const ffcz_bounds* bnd, int32_t max_iter,
+                            const ffcz_options* opts, void* ws, size_t ws_bytes, void* stream, ffcz_stats* stats) {
+  if (route_1d(ndim, shape))
+    return fail(FFCZ_E_SHAPE, "pointwise bounds take fields that run on the multidimensional passes");
+  SingleCall sc;
+  int32_t r = single_setup(dtype, ndim, shape, x, xb, y, eps_s, delta_f, max_iter, opts, sc);
+  if (r != FFCZ_OK) return r;
+  if (sc.o.masks_out) return fail(FFCZ_E_INVALID, "masks are not recorded with pointwise bounds");
+  ffcz_bounds b;
+  memset(&b, 0, sizeof(b));
+  if (bnd) b = *bnd;
+  if (((uintptr_t)b.eps_s & 15) || ((uintptr_t)b.delta_re & 15) || ((uintptr_t)b.delta_im & 15))
+    return fail(FFCZ_E_WORKSPACE, "bound arrays must be 16-byte aligned");
+  const BoundsLayout L = bounds_layout(sc.p);
+  if (!ws || ws_bytes < L.bytes) return fail(FFCZ_E_WORKSPACE, "workspace smaller than ffcz_bounds_workspace_bytes()");
+  if ((uintptr_t)ws & 255) return fail(FFCZ_E_WORKSPACE, "workspace must be 256-byte aligned");
+  char* w = (char*)ws;
+  BoundsCfg bc;
+  bc.pE = b.eps_s;
+  bc.disk = b.disk ? 1 : 0;
+  bc.dre = b.delta_re;
+  bc.dim = bc.disk ? b.delta_re : b.delta_im;  // the disk bounds the modulus by delta_re
+  bc.sre = delta_f;
+  bc.sim = delta_f;
+  bc.pD = w + L.off_D;
+  bc.minpart = (unsigned long long*)(w + L.off_min);
+  bc.bad = (unsigned long long*)(w + L.off_bad);
+  const double* mus = sc.mu > 0.0 && sc.o.margin_rel > 0.0 ? &sc.mu : nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  int32_t status = FFCZ_OK;
+  r = dtype == FFCZ_F32 ? correct_group<float>(sc.p, &sc.in, mus, max_iter, sc.o, w, s, stats, &status, nullptr,
+                                               nullptr, &bc)
+                        : correct_group<double>(sc.p, &sc.in, mus, max_iter, sc.o, w, s, stats, &status, nullptr,
+                                                nullptr, &bc);
+  if (r != FFCZ_OK) return r;
+  if (stats) stats->status = status;
+  if (status == FFCZ_E_NONFINITE) return fail(FFCZ_E_NONFINITE, "x or x_hat holds NaN or Inf");
+  if (status == FFCZ_VERIFY_FAILED) g_err = "FP64 re-verification against the pointwise bounds failed";
+  return status;
+}
+
+int32_t ffcz_power_spectrum_bounds(int32_t dtype, int32_t ndim, const int64_t* shape, const void* x, double rho,
+                                   int32_t disk, void* delta_out, void* ws, size_t ws_bytes, void* stream) {
+  if (route_1d(ndim, shape))
+    return fail(FFCZ_E_SHAPE, "power-spectrum bounds take fields that run on the multidimensional passes");
+  Plan p;
+  int32_t r = make_plan(dtype, ndim, shape, 0, 1, p);
+  if (r != FFCZ_OK) return r;
+  if (!x || !delta_out) return fail(FFCZ_E_INVALID, "null pointer");
+  if (!std::isfinite(rho) || rho < 0) return fail(FFCZ_E_INVALID, "rho must be finite and >= 0");
+  if (((uintptr_t)x & 15) || ((uintptr_t)delta_out & 15)) return fail(FFCZ_E_WORKSPACE, "data must be 16-byte aligned");
+  const BoundsLayout L = bounds_layout(p);
+  if (L.nb > kMaxShells) return fail(FFCZ_E_SHAPE, "too many shells");
+  if (!ws || ws_bytes < L.bytes) return fail(FFCZ_E_WORKSPACE, "workspace smaller than ffcz_bounds_workspace_bytes()");
+  if ((uintptr_t)ws & 255) return fail(FFCZ_E_WORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  return dtype == FFCZ_F32 ? power_bounds_impl<float>(p, L, (char*)ws, x, rho, disk ? 1 : 0, delta_out, s)
+                           : power_bounds_impl<double>(p, L, (char*)ws, x, rho, disk ? 1 : 0, delta_out, s);
+}
+
+size_t ffcz_huffman_workspace_bytes(int64_t nsym, int64_t nalpha) {
+  if (nsym < 0 || nalpha < 0 || nalpha > kHuffMaxAlpha) return 0;
+  return huff_ws(nsym, nalpha).bytes;
+}
+
+int32_t ffcz_huffman_plan(const void* sym, int64_t nsym, int32_t width, void* ws, size_t ws_bytes, void* stream,
+                          ffcz_huffman_sizes* plan) {
+  if (!plan || (nsym > 0 && !sym)) return fail(FFCZ_E_INVALID, "null pointer");
+  if (width != 1 && width != 4) return fail(FFCZ_E_INVALID, "width must be 1 or 4");
+  if (nsym < 0) return fail(FFCZ_E_INVALID, "nsym must be >= 0");
+  memset(plan, 0, sizeof(*plan));
+  plan->nsym = nsym;
+  if (nsym > 0) {
+    if (!ws || ws_bytes < huff_ws(nsym, 0).bytes || ((uintptr_t)ws & 255))
+      return fail(FFCZ_E_WORKSPACE, "workspace smaller than ffcz_huffman_workspace_bytes(nsym, 0) or misaligned");
+    hipStream_t s = (hipStream_t)stream;
+    const int g = (int)std::min<int64_t>(1024, (nsym + kHuffBlock - 1) / kHuffBlock);
+    long long* mm = (long long*)ws;
+    hipLaunchKernelGGL(huff_minmax_kernel, dim3((unsigned)g), dim3(kHuffBlock), 0, s, sym, (int)width, nsym, mm);
+    HIPCHK(hipGetLastError());
+    std::vector<long long> h(2 * (size_t)g);
+    HIPCHK(hipMemcpyAsync(h.data(), mm, sizeof(long long) * h.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    long long lo = h[0], hi = h[1];
+    for (int b = 1; b < g; ++b) {
+      lo = std::min(lo, h[2 * b]);
+      hi = std::max(hi, h[2 * b + 1]);
+    }
+    plan->lo = lo;
+    plan->nalpha = hi - lo + 1;
+    if (plan->nalpha > kHuffMaxAlpha) return fail(FFCZ_E_INVALID, "alphabet wider than 2^24 symbols");
+  }
+  plan->ws_bytes = huff_ws(nsym, plan->nalpha).bytes;
+  plan->out_bytes = huff_layout(nsym, plan->nalpha, 32 * nsym).bytes;
+  return FFCZ_OK;
+}
+
+int32_t ffcz_huffman_encode(const void* sym, int64_t nsym, int32_t width, const ffcz_huffman_sizes* plan, void* out,
+                            size_t out_bytes, void* ws, size_t ws_bytes, void* stream, size_t* used_bytes) {
+  if (!plan || !out || (nsym > 0 && !sym)) return fail(FFCZ_E_INVALID, "null pointer");
+  if (width != 1 && width != 4) return fail(FFCZ_E_INVALID, "width must be 1 or 4");
+  if (plan->nsym != nsym || plan->nalpha < 0 || plan->nalpha > kHuffMaxAlpha)
+    return fail(FFCZ_E_INVALID, "plan does not match the stream");
+  if ((uintptr_t)out & 15) return fail(FFCZ_E_WORKSPACE, "output must be 16-byte aligned");
+  const int64_t nalpha = plan->nalpha, lo = plan->lo;
+  const HuffWs W = huff_ws(nsym, nalpha);
+  if (!ws || ws_bytes < W.bytes || ((uintptr_t)ws & 255))
+    return fail(FFCZ_E_WORKSPACE, "workspace smaller than the plan's ws_bytes or misaligned");
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  char* o = (char*)out;
+  HuffHeader hd;
+  memset(&hd, 0, sizeof(hd));
+  hd.magic = kHuffMagic;
+  hd.width = (uint32_t)width;
+  hd.nsym = nsym;
+  hd.lo = lo;
+  hd.nalpha = nalpha;
+  hd.nchunks = (nsym + kHuffChunk - 1) / kHuffChunk;
+  std::vector<uint8_t> len;
+  if (nsym > 0) {
+    // the global frequency table, then the code on the host
+    unsigned long long* counts = (unsigned long long*)(w + W.off_counts);
+    hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)((nalpha + 255) / 256)), dim3(256), 0, s, counts, nalpha);
+    HIPCHK(hipGetLastError());
+    const int g = (int)std::min<int64_t>(1024, (nsym + kHuffBlock - 1) / kHuffBlock);
+    hipLaunchKernelGGL(huff_hist_kernel, dim3((unsigned)g), dim3(kHuffBlock), 0, s, sym, (int)width, nsym,
+                       (int64_t)lo, nalpha, counts);
+    HIPCHK(hipGetLastError());
+    std::vector<unsigned long long> hc((size_t)nalpha);
+    HIPCHK(hipMemcpyAsync(hc.data(), counts, 8 * (size_t)nalpha, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    len = huff_lengths(hc);
+    const HuffTables t = huff_tables(len);
+    uint8_t* dlen = (uint8_t*)(w + W.off_len);
+    uint32_t* dcode = (uint32_t*)(w + W.off_code);
+    HIPCHK(hipMemcpyAsync(dlen, len.data(), (size_t)nalpha, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dcode, t.code.data(), 4 * (size_t)nalpha, hipMemcpyHostToDevice, s));
+    // bits per block, block offsets, the total
+    const int64_t nblk = (nsym + kHuffBlockSyms - 1) / kHuffBlockSyms;
+    unsigned long long* boff = (unsigned long long*)(w + W.off_boff);
+    unsigned long long* tot = (unsigned long long*)(w + W.off_tot);
+    hipLaunchKernelGGL(huff_bits_kernel, dim3((unsigned)nblk), dim3(kHuffBlock), 0, s, sym, (int)width, nsym,
+                       (int64_t)lo, (const uint8_t*)dlen, boff);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(edit_scan_kernel, dim3(1), dim3(1024), 0, s, boff, nblk, tot);
+    HIPCHK(hipGetLastError());
+    unsigned long long nbits = 0;
+    HIPCHK(hipMemcpyAsync(&nbits, tot, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    hd.nbits = (int64_t)nbits;
+    const HuffLayout L = huff_layout(nsym, nalpha, hd.nbits);
+    if (out_bytes < L.bytes) return fail(FFCZ_E_WORKSPACE, "output smaller than the stream (" + std::to_string(L.bytes) + " bytes)");
+    const int64_t nwords = (hd.nbits + 31) / 32;
+    hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)(((nwords + 1) / 2 + 255) / 256)), dim3(256), 0, s,
+                       (unsigned long long*)(o + L.off_words), (nwords + 1) / 2);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(huff_encode_kernel, dim3((unsigned)nblk), dim3(kHuffBlock), 0, s, sym, (int)width, nsym,
+                       (int64_t)lo, (const uint8_t*)dlen, (const uint32_t*)dcode, (const unsigned long long*)boff,
+                       (unsigned int*)(o + L.off_words), (unsigned long long*)(o + L.off_chunks));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(o + L.off_len, dlen, (size_t)nalpha, hipMemcpyDeviceToDevice, s));
+  }
+  const HuffLayout L = huff_layout(nsym, nalpha, hd.nbits);
+  if (out_bytes < L.bytes) return fail(FFCZ_E_WORKSPACE, "output smaller than the stream");
+  HIPCHK(hipMemcpyAsync(o, &hd, sizeof(hd), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (used_bytes) *used_bytes = L.bytes;
+  return FFCZ_OK;
+}
+
+int32_t ffcz_huffman_decode(const void* in, size_t in_bytes, int32_t width, void* sym_out, int64_t capacity, void* ws,
+                            size_t ws_bytes, void* stream, int64_t* nsym_out) {
+  if (!in || in_bytes < sizeof(HuffHeader)) return fail(FFCZ_E_INVALID, "input too short");
+  if ((uintptr_t)in & 15) return fail(FFCZ_E_WORKSPACE, "input must be 16-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  HuffHeader hd;
+  HIPCHK(hipMemcpyAsync(&hd, in, sizeof(hd), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hd.magic != kHuffMagic || (hd.width != 1 && hd.width != 4) || hd.nsym < 0 || hd.nalpha < 0 ||
+      hd.nalpha > kHuffMaxAlpha || hd.nbits < 0)
+    return fail(FFCZ_E_INVALID, "not a stream written by ffcz_huffman_encode");
+  if ((int32_t)hd.width != width) return fail(FFCZ_E_INVALID, "symbol width differs from the stream's");
+  const HuffLayout L = huff_layout(hd.nsym, hd.nalpha, hd.nbits);
+  if (in_bytes < L.bytes) return fail(FFCZ_E_INVALID, "input shorter than its stream");
+  if (hd.nsym > capacity || (hd.nsym > 0 && !sym_out)) return fail(FFCZ_E_INVALID, "output holds fewer symbols than the stream");
+  if (nsym_out) *nsym_out = hd.nsym;
+  if (hd.nsym == 0) return FFCZ_OK;
+  const HuffWs W = huff_ws(hd.nsym, hd.nalpha);
+  if (!ws || ws_bytes < W.bytes || ((uintptr_t)ws & 255))
+    return fail(FFCZ_E_WORKSPACE, "workspace smaller than ffcz_huffman_workspace_bytes(nsym, nalpha) or misaligned");
+  std::vector<uint8_t> len((size_t)hd.nalpha);
+  const char* ib = (const char*)in;
+  HIPCHK(hipMemcpyAsync(len.data(), ib + L.off_len, (size_t)hd.nalpha, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (uint8_t l : len)
+    if (l > kHuffMaxLen) return fail(FFCZ_E_INVALID, "code length above 32 in the stream");
+  const HuffTables t = huff_tables(len);
+  char* w = (char*)ws;
+  uint32_t* tab = (uint32_t*)(w + W.off_tab);
+  HIPCHK(hipMemcpyAsync(tab, t.first, sizeof(t.first), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(tab + (kHuffMaxLen + 1), t.cnt, sizeof(t.cnt), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(tab + 2 * (kHuffMaxLen + 1), t.idx, sizeof(t.idx), hipMemcpyHostToDevice, s));
+  if (!t.sorted.empty())
+    HIPCHK(hipMemcpyAsync(w + W.off_sorted, t.sorted.data(), 4 * t.sorted.size(), hipMemcpyHostToDevice, s));
+  unsigned int* bad = (unsigned int*)(w + W.off_tot);
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, (unsigned long long*)bad, (int64_t)1);
+  HIPCHK(hipGetLastError());
+  const int64_t nch = hd.nchunks;
+  hipLaunchKernelGGL(huff_decode_kernel, dim3((unsigned)((nch + kHuffBlock - 1) / kHuffBlock)), dim3(kHuffBlock), 0, s,
+                     (const unsigned int*)(ib + L.off_words), (int64_t)((hd.nbits + 31) / 32),
+                     (const unsigned long long*)(ib + L.off_chunks), hd.nsym, (const uint32_t*)tab,
+                     (const uint32_t*)(tab + (kHuffMaxLen + 1)), (const uint32_t*)(tab + 2 * (kHuffMaxLen + 1)),
+                     (const int32_t*)(w + W.off_sorted), (int64_t)hd.lo, (int)width, sym_out, bad);
+  HIPCHK(hipGetLastError());
+  unsigned int hb = 0;
+  HIPCHK(hipMemcpyAsync(&hb, bad, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hb) return fail(FFCZ_E_INVALID, "the stream holds a bit pattern that is no code");
+  return FFCZ_OK;
 }
 
 size_t ffcz_encode_workspace_bytes(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max_iter) {

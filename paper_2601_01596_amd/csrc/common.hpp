@@ -31,6 +31,14 @@ struct DevState {
   void* py;
   // the encoder's spatial shrink (its spectral shrink is mu)
   double mu_s;
+  // pointwise bounds (ffcz_correct_bounds): E_n in the field's layout and dtype (null: the
+  // scalar E), (D^Re_k, D^Im_k) pairs of the working type laid out as the spectrum; a bound b
+  // gives the shrunk s-bound b fe, the check threshold b fc and the shrunk f-bound b fp
+  const void* pE;
+  const void* pD;
+  double fe, fc, fp;
+  int32_t disk;  // 1: |delta_k| <= D^Re_k (modulus), radial projection
+  int32_t pad3;
 };
 
 enum ColMode : int {
@@ -42,8 +50,10 @@ enum ColMode : int {
   COL_FWD_NS = 5,  // forward, ignores the done flag (adjoint, verification)
   COL_INV_NS = 6,  // inverse, ignores the done flag (adjoint, decoder)
   COL_XEDIT = 7,   // COL_XPASS that also adds each clip displacement to the frequency edits
-  COL_XUNDO = 8    // forward and clip as COL_XPASS, then subtracts the displacement from the
+  COL_XUNDO = 8,   // forward and clip as COL_XPASS, then subtracts the displacement from the
                    // frequency edits (the check that ended the loop discards its clip); no store
+  COL_XPASSP = 9,  // COL_XPASS against pointwise bounds (box on Re and Im, or the disk)
+  COL_VERIFYP = 10 // COL_VERIFY against pointwise bounds: max ratio to the bound, violations
 };
 
 enum RowMode : int {
@@ -58,7 +68,11 @@ enum RowMode : int {
                    // last-axis pass of the verification, without re-reading x and y)
   ROW_INITE = 8,   // ROW_INIT that also stores each guard-clip displacement as the first spatial edit
   ROW_LOOPE = 9,   // ROW_LOOP that also adds each s-clip displacement to the spatial edits
-  ROW_DECODE = 10  // C2R, 1/N, y = x_hat + s + eps summed in FP64 and rounded once (decoder; s in py)
+  ROW_DECODE = 10, // C2R, 1/N, y = x_hat + s + eps summed in FP64 and rounded once (decoder; s in py)
+  ROW_INITP = 11,  // ROW_INIT with a spatial bound per point
+  ROW_LOOPP = 12,  // ROW_LOOP with a spatial bound per point
+  ROW_FINALP = 13, // ROW_FINAL with a spatial bound per point (closing clamp against E_n)
+  ROW_VERIFYP = 14 // ROW_VERIFY keeping max |y_n - x_n| / E_n instead of max |y_n - x_n|
 };
 
 template <typename T>
@@ -82,6 +96,12 @@ struct ColArgs {
   int64_t mrow_o;
   // frequency edits (COL_XEDIT / COL_XUNDO): same layout as the spectrum the pass transforms
   cx<T>* fedit;
+  // pointwise spectral bounds (COL_XPASSP / COL_VERIFYP): (Re, Im) pairs of floats (bnd_dbl 0)
+  // or doubles at bnd_so * outer + column + bnd_s * i, the transformed spectrum's own layout
+  // in the loop, the working-type spectrum's layout in the FP64 verification
+  const void* bnd;
+  int64_t bnd_so, bnd_s;
+  int32_t bnd_dbl, pad4;
 };
 
 template <typename T, typename TIO>

@@ -18,7 +18,7 @@ col_kernel(ColArgs<T> a) {
   constexpr int NW = (NT + 63) / 64;
   // the FP64 verification pass stores nothing, so registers allow four blocks per CU;
   // its exchange goes through LDS one real part at a time to let them fit
-  constexpr bool SPL = (MODE == COL_VERIFY && sizeof(T) == 8);
+  constexpr bool SPL = ((MODE == COL_VERIFY || MODE == COL_VERIFYP) && sizeof(T) == 8);
   __shared__ cx<T> lds[S::nst > 1 ? (SPL ? L * C / 2 : L * C) : 1];
   __shared__ cx<T> tws[TW > 0 ? TW : 1];
   __shared__ unsigned long long red_u[NW];
@@ -27,7 +27,8 @@ col_kernel(ColArgs<T> a) {
   const int64_t bid = blockIdx.x;
   const int64_t o = bid / a.ncb;
   DevState* st = a.st + o / a.outer_per_inst;
-  constexpr bool uses_done = (MODE == COL_FWD || MODE == COL_INV || MODE == COL_XPASS || MODE == COL_XEDIT);
+  constexpr bool uses_done =
+      (MODE == COL_FWD || MODE == COL_INV || MODE == COL_XPASS || MODE == COL_XEDIT || MODE == COL_XPASSP);
   (void)red_d;
   if (uses_done) {
     if (*(volatile int32_t*)&st->done) return;
@@ -53,6 +54,47 @@ col_kernel(ColArgs<T> a) {
     fft<T, L, E, false, C, 1>(v, lds, tws, c, j);
   } else if constexpr (MODE == COL_INV || MODE == COL_INV_NS) {
     fft<T, L, E, true, C, 1>(v, lds, tws, c, j);
+  } else if constexpr (MODE == COL_XPASSP) {
+    // pointwise bounds: entry k is checked against D_k fc and projected onto D_k fp, on Re and
+    // Im separately (box) or on the modulus (disk, radial projection); no masks
+    const T* bp = reinterpret_cast<const T*>(a.bnd);
+    const int64_t bbase = o * a.bnd_so + col;
+    const double fc = st->fc, fp = st->fp;
+    const bool disk = st->disk != 0;
+    fft<T, L, E, false, C, 1>(v, lds, tws, c, j);
+    unsigned long long cnt = 0;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      cx<T> z = v[q];
+      const int64_t bi = valid ? 2 * (bbase + (int64_t)(j + q * P) * a.bnd_s) : 0;
+      const T br = valid ? bp[bi] : T(0), bim = valid ? bp[bi + 1] : T(0);
+      if (disk) {
+        const T m = hypot(z.re, z.im);
+        const T dc = to_t<T>((double)br * fc), dp = to_t<T>((double)br * fp);
+        cnt += (valid && m > dc) ? 1 : 0;
+        if (m > dp) {
+          const T sc = dp / m;
+          z.re *= sc;
+          z.im *= sc;
+        }
+      } else {
+        const T dcr = to_t<T>((double)br * fc), dpr = to_t<T>((double)br * fp);
+        const T dci = to_t<T>((double)bim * fc), dpi = to_t<T>((double)bim * fp);
+        cnt += (valid && (fabs(z.re) > dcr || fabs(z.im) > dci)) ? 1 : 0;
+        z.re = clipv(z.re, dpr);
+        z.im = clipv(z.im, dpi);
+      }
+      v[q] = z;
+    }
+    fft<T, L, E, true, C, 1>(v, lds, tws, c, j);
+    cnt = wave_sum_u64(cnt);
+    if ((t & 63) == 0) red_u[t >> 6] = cnt;
+    __syncthreads();
+    if (t == 0) {
+      unsigned long long s = 0;
+      for (int w = 0; w < NW; ++w) s += red_u[w];
+      a.part[bid] = s;
+    }
   } else if constexpr (MODE == COL_XPASS || MODE == COL_XEDIT || MODE == COL_XUNDO) {
     // COL_XEDIT adds every clip displacement to the frequency edits (Alg. 1 edit bookkeeping);
     // COL_XUNDO repeats the forward transform and the clip of the check that ended the loop
@@ -136,17 +178,41 @@ col_kernel(ColArgs<T> a) {
       v[q].im = ki ? v[q].im : T(0);
     }
     fft<T, L, E, true, C, 1>(v, lds, tws, c, j);
-  } else if constexpr (MODE == COL_VERIFY) {
+  } else if constexpr (MODE == COL_VERIFY || MODE == COL_VERIFYP) {
     fft<T, L, E, false, C, 1, 0, SPL>(v, lds, tws, c, j);
     const double D = st->Delta;
     unsigned long long cnt = 0;
     double mx = 0.0;
+    if constexpr (MODE == COL_VERIFY) {
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-      if (valid) {
-        const double m = fmax(fabs((double)v[q].re), fabs((double)v[q].im));
-        mx = fmax(mx, m);
-        cnt += (m > D) ? 1 : 0;
+      for (int q = 0; q < E; ++q) {
+        if (valid) {
+          const double m = fmax(fabs((double)v[q].re), fabs((double)v[q].im));
+          mx = fmax(mx, m);
+          cnt += (m > D) ? 1 : 0;
+        }
+      }
+    } else {
+      // the largest ratio to the bound (0 / 0 counts as 0) and the entries above their bound
+      const bool disk = st->disk != 0;
+      const int64_t bbase = o * a.bnd_so + col;
+      auto ratio = [](double x, double b) -> double { return x == 0.0 ? 0.0 : x / b; };
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        if (valid) {
+          const int64_t bi = 2 * (bbase + (int64_t)(j + q * P) * a.bnd_s);
+          const double br = a.bnd_dbl ? ((const double*)a.bnd)[bi] : (double)((const float*)a.bnd)[bi];
+          const double bim = a.bnd_dbl ? ((const double*)a.bnd)[bi + 1] : (double)((const float*)a.bnd)[bi + 1];
+          const double re = fabs((double)v[q].re), im = fabs((double)v[q].im);
+          if (disk) {
+            const double m = hypot(re, im);
+            mx = fmax(mx, ratio(m, br));
+            cnt += (m > br) ? 1 : 0;
+          } else {
+            mx = fmax(mx, fmax(ratio(re, br), ratio(im, bim)));
+            cnt += (re > br || im > bim) ? 1 : 0;
+          }
+        }
       }
     }
     cnt = wave_sum_u64(cnt);

@@ -66,13 +66,16 @@ row_kernel(RowArgs<T, TIO> a) {
   constexpr int SW = 2 * (H >= 32 ? H / 32 : 1);  // uint32 words per s-mask row (64-bit padded)
   using V2 = typename Vec2<TIO>::type;
   constexpr bool finalv = MODE == ROW_FINALV;  // FP64 fields only
-  constexpr bool final_y = (MODE == ROW_FINAL || finalv);  // forms and stores y
+  constexpr bool final_y = (MODE == ROW_FINAL || finalv || MODE == ROW_FINALP);  // forms and stores y
   constexpr bool decode = MODE == ROW_DECODE;  // y = x_hat + s + eps (s already in y)
-  constexpr bool m_init = (MODE == ROW_INIT || MODE == ROW_INITE);
-  constexpr bool m_loop = (MODE == ROW_LOOP || MODE == ROW_LOOPE);
+  constexpr bool m_init = (MODE == ROW_INIT || MODE == ROW_INITE || MODE == ROW_INITP);
+  constexpr bool m_loop = (MODE == ROW_LOOP || MODE == ROW_LOOPE || MODE == ROW_LOOPP);
+  constexpr bool m_verify = (MODE == ROW_VERIFY || MODE == ROW_VERIFYP);
   constexpr bool sedit = (MODE == ROW_INITE || MODE == ROW_LOOPE);  // spatial edit bookkeeping
+  // a spatial bound per point (E_n from st->pE, or the scalar when that is null)
+  constexpr bool pwE = (MODE == ROW_INITP || MODE == ROW_LOOPP || MODE == ROW_FINALP || MODE == ROW_VERIFYP);
   constexpr bool spec_in = (m_loop || final_y || MODE == ROW_BLOOP || MODE == ROW_BFINAL || decode);
-  constexpr bool spec_out = (m_init || m_loop || MODE == ROW_VERIFY || MODE == ROW_BINIT ||
+  constexpr bool spec_out = (m_init || m_loop || m_verify || MODE == ROW_BINIT ||
                              MODE == ROW_BLOOP || finalv);
   constexpr bool rec_s = (m_init || m_loop);
   constexpr bool use_s = (MODE == ROW_BINIT || MODE == ROW_BLOOP || MODE == ROW_BFINAL);
@@ -141,7 +144,9 @@ row_kernel(RowArgs<T, TIO> a) {
   double mx = 0.0;
   // INIT: (x, x_hat); VERIFY: (x, y); BINIT: dL/dy in pxb; FINAL: x, writes y; BFINAL writes py
   const V2* x2 = reinterpret_cast<const V2*>(st->px);
-  const V2* b2 = reinterpret_cast<const V2*>(MODE == ROW_VERIFY ? (const void*)st->py : st->pxb);
+  const V2* b2 = reinterpret_cast<const V2*>(m_verify ? (const void*)st->py : st->pxb);
+  // pointwise spatial bounds, same layout and dtype as the fields
+  const TIO* const pE = pwE ? reinterpret_cast<const TIO*>(st->pE) : nullptr;
 
   // ------------------------------------------------------------------ load
   // Unrolled in batches of BL so each lane keeps BL global loads in flight.
@@ -204,9 +209,13 @@ row_kernel(RowArgs<T, TIO> a) {
     }
   } else {
     // real rows -> packed pairs; INIT also forms eps0 = x_hat - x in FP64 and clips it
-    const double Ep = st->Ep;
-    // packed entry m of row r from (x, second field) reals 2m, 2m+1
-    auto pack = [&](int r, int m, double xa0, double xa1, double b0, double b1) -> cx<T> {
+    // spatial bound of INIT (the shrunk one) and VERIFY (the bound itself) when no array is given
+    const double Ep = m_verify ? st->E : st->Ep;
+    const double fe = st->fe;
+    // packed entry m of row r from (x, second field) reals 2m, 2m+1; ep0, ep1: their spatial
+    // bounds (INIT: shrunk; VERIFY: as given)
+    auto pack = [&](int r, int m, double xa0, double xa1, double b0, double b1, double ep0,
+                    double ep1) -> cx<T> {
       double e0 = 0.0, e1 = 0.0;
       if (r < nrow) {
         if constexpr (MODE == ROW_BINIT) {
@@ -224,9 +233,9 @@ row_kernel(RowArgs<T, TIO> a) {
               e0 = f0 ? e0 : 0.0;
               e1 = f1 ? e1 : 0.0;
             }
-            const bool k0 = fabs(e0) <= Ep, k1 = fabs(e1) <= Ep;
+            const bool k0 = fabs(e0) <= ep0, k1 = fabs(e1) <= ep1;
             cnt += (!k0) + (!k1);
-            const double c0 = clipv(e0, Ep), c1 = clipv(e1, Ep);
+            const double c0 = clipv(e0, ep0), c1 = clipv(e1, ep1);
             if constexpr (sedit) {
               // the guard clip is the first ProjectOntoSCube displacement (every point written)
               typename Vec2<T>::type d;
@@ -238,6 +247,10 @@ row_kernel(RowArgs<T, TIO> a) {
             e1 = c1;
             if (rec)
               atomicOr(&sbits[r * SW + (2 * m) / 32], ((uint32_t)k0 | ((uint32_t)k1 << 1)) << ((2 * m) & 31));
+          } else if constexpr (MODE == ROW_VERIFYP) {
+            // the largest ratio to the bound (0 / 0 counts as 0)
+            const double r0 = e0 == 0.0 ? 0.0 : fabs(e0) / ep0, r1 = e1 == 0.0 ? 0.0 : fabs(e1) / ep1;
+            mx = fmax(mx, fmax(r0, r1));
           } else {
             mx = fmax(mx, fmax(fabs(e0), fabs(e1)));
           }
@@ -245,16 +258,20 @@ row_kernel(RowArgs<T, TIO> a) {
       }
       return cx<T>{(T)e0, (T)e1};  // rounded once to the working type
     };
+    // the spatial bounds of reals 2m, 2m+1 from a loaded pair of E_n (INIT shrinks them)
+    auto bnd = [&](double E0) -> double { return MODE == ROW_INITP ? E0 * fe : E0; };
     if constexpr (io4) {
       // FP32 fields: four reals (two packed entries) per 16-byte load, BQ loads of each field per
       // lane in flight (more spills: the FP64 difference, clip and mask work needs the registers)
       constexpr int NLQ = (ROWS * HQ + NT - 1) / NT;
       constexpr int BQ = NLQ < 4 ? NLQ : 4;
       const float4* x4 = reinterpret_cast<const float4*>(st->px);
-      const float4* b4 = reinterpret_cast<const float4*>(MODE == ROW_VERIFY ? (const void*)st->py : st->pxb);
+      const float4* b4 = reinterpret_cast<const float4*>(m_verify ? (const void*)st->py : st->pxb);
+      const float4* e4 = reinterpret_cast<const float4*>(pE);
 #pragma unroll
       for (int q0 = 0; q0 < NLQ; q0 += BQ) {
         float4 xa[BQ], xbv[BQ];
+        float4 ea[pwE ? BQ : 1];
 #pragma unroll
         for (int u = 0; u < BQ; ++u) {
           const int f = t + (q0 + u) * NT;
@@ -267,14 +284,28 @@ row_kernel(RowArgs<T, TIO> a) {
             if (ok) xa[u] = x4[gi];
           }
           if (ok) xbv[u] = b4[gi];
+          if constexpr (pwE) {
+            ea[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (ok && e4) ea[u] = e4[gi];
+          }
         }
 #pragma unroll
         for (int u = 0; u < BQ; ++u) {
           const int f = t + (q0 + u) * NT;
           if (!(q0 + u < NLQ && f < ROWS * HQ)) continue;
           const int r = f / HQ, q = f - r * HQ;
-          lds[r * LP + lds_skew<SKW>(2 * q)] = pack(r, 2 * q, xa[u].x, xa[u].y, xbv[u].x, xbv[u].y);
-          lds[r * LP + lds_skew<SKW>(2 * q + 1)] = pack(r, 2 * q + 1, xa[u].z, xa[u].w, xbv[u].z, xbv[u].w);
+          double p0 = Ep, p1 = Ep, p2 = Ep, p3 = Ep;
+          if constexpr (pwE) {
+            if (e4) {
+              p0 = bnd(ea[u].x);
+              p1 = bnd(ea[u].y);
+              p2 = bnd(ea[u].z);
+              p3 = bnd(ea[u].w);
+            }
+          }
+          lds[r * LP + lds_skew<SKW>(2 * q)] = pack(r, 2 * q, xa[u].x, xa[u].y, xbv[u].x, xbv[u].y, p0, p1);
+          lds[r * LP + lds_skew<SKW>(2 * q + 1)] =
+              pack(r, 2 * q + 1, xa[u].z, xa[u].w, xbv[u].z, xbv[u].w, p2, p3);
         }
       }
     } else {
@@ -282,6 +313,8 @@ row_kernel(RowArgs<T, TIO> a) {
 #pragma unroll
       for (int b0 = 0; b0 < NL; b0 += BL) {
         V2 xa[BL], xbv[BL];
+        V2 ea[pwE ? BL : 1];
+        const V2* e2 = reinterpret_cast<const V2*>(pE);
 #pragma unroll
         for (int u = 0; u < BL; ++u) {
           const int f = t + (b0 + u) * NT;
@@ -292,13 +325,24 @@ row_kernel(RowArgs<T, TIO> a) {
             if (ok) xa[u] = x2[gi];
           }
           if (ok) xbv[u] = b2[gi];
+          if constexpr (pwE) {
+            if (ok && e2) ea[u] = e2[gi];
+          }
         }
 #pragma unroll
         for (int u = 0; u < BL; ++u) {
           const int f = t + (b0 + u) * NT;
           if (!(b0 + u < NL && f < ROWS * H)) continue;
           const int r = f / H, m = f - r * H;
-          lds[r * LP + lds_skew<SKW>(m)] = pack(r, m, (double)xa[u].x, (double)xa[u].y, (double)xbv[u].x, (double)xbv[u].y);
+          double p0 = Ep, p1 = Ep;
+          if constexpr (pwE) {
+            if (e2 && r < nrow) {
+              p0 = bnd((double)ea[u].x);
+              p1 = bnd((double)ea[u].y);
+            }
+          }
+          lds[r * LP + lds_skew<SKW>(m)] =
+              pack(r, m, (double)xa[u].x, (double)xa[u].y, (double)xbv[u].x, (double)xbv[u].y, p0, p1);
         }
       }
     }
@@ -343,13 +387,24 @@ row_kernel(RowArgs<T, TIO> a) {
     } else {  // ROW_LOOP: ProjectOntoSCube
       const T Ep = to_t<T>(st->Ep);
       const bool valid = rl < nrow;
+      const V2* e2 = reinterpret_cast<const V2*>(pE);
+      const double fe = st->fe;
 #pragma unroll
       for (int q = 0; q < E; ++q) {
         const int k = j + q * P;
         T e0 = v[q].re * sc, e1 = v[q].im * sc;
-        const bool k0 = fabs(e0) <= Ep, k1 = fabs(e1) <= Ep;
+        T Ep0 = Ep, Ep1 = Ep;
+        if constexpr (pwE) {
+          // the bounds of reals 2k, 2k+1 of this row, shrunk (rounded toward zero in FP32)
+          if (e2 && valid) {
+            const V2 ev = e2[(lrow0 + rl) * H + k];
+            Ep0 = to_t<T>((double)ev.x * fe);
+            Ep1 = to_t<T>((double)ev.y * fe);
+          }
+        }
+        const bool k0 = fabs(e0) <= Ep0, k1 = fabs(e1) <= Ep1;
         if (valid) cnt += (!k0) + (!k1);
-        const T c0 = clipv(e0, Ep), c1 = clipv(e1, Ep);
+        const T c0 = clipv(e0, Ep0), c1 = clipv(e1, Ep1);
         if constexpr (sedit) {
           // spat_edits += eps' - eps at the points the clip moved
           if (valid && !(k0 && k1)) {
@@ -393,8 +448,8 @@ row_kernel(RowArgs<T, TIO> a) {
     // entries and keeps max |d|.
     V2* y2 = reinterpret_cast<V2*>(st->py);
     const double Eb = st->E;
-    auto out_of = [&](TIO xv, T e) -> TIO {
-      if constexpr (final_y) return closing_clamp<TIO>(round_io<TIO>((double)xv + (double)e), xv, Eb);
+    auto out_of = [&](TIO xv, T e, double Ebound) -> TIO {
+      if constexpr (final_y) return closing_clamp<TIO>(round_io<TIO>((double)xv + (double)e), xv, Ebound);
       else return (TIO)e;
     };
     // decoder: x_hat from pxb, the expanded spatial edits already in y
@@ -407,10 +462,12 @@ row_kernel(RowArgs<T, TIO> a) {
       constexpr int BQ = NSQ < 8 ? NSQ : 8;
       const float4* x4 = reinterpret_cast<const float4*>(decode ? st->pxb : st->px);
       float4* y4 = reinterpret_cast<float4*>(st->py);
+      const float4* e4 = reinterpret_cast<const float4*>(pE);
 #pragma unroll
       for (int q0 = 0; q0 < NSQ; q0 += BQ) {
         float4 xa[BQ];
         float4 sa[decode ? BQ : 1];
+        float4 ea[pwE ? BQ : 1];
         if constexpr (ld_x) {
 #pragma unroll
           for (int u = 0; u < BQ; ++u) {
@@ -419,6 +476,10 @@ row_kernel(RowArgs<T, TIO> a) {
             if (q0 + u < NSQ && f < ROWS * HQ && r < nrow) {
               xa[u] = x4[(lrow0 + r) * HQ + q];
               if constexpr (decode) sa[u] = y4[(lrow0 + r) * HQ + q];
+              if constexpr (pwE) {
+                const float Es = (float)Eb;  // unused when e4 is null
+                ea[u] = e4 ? e4[(lrow0 + r) * HQ + q] : make_float4(Es, Es, Es, Es);
+              }
             }
           }
         }
@@ -429,9 +490,15 @@ row_kernel(RowArgs<T, TIO> a) {
           if (q0 + u < NSQ && f < ROWS * HQ && r < nrow) {
             const cx<T> e0 = lds[r * LP + lds_skew<SKW>(2 * q)], e1 = lds[r * LP + lds_skew<SKW>(2 * q + 1)];
             float4 o;
-            if constexpr (final_y) {
-              o = make_float4(out_of(xa[u].x, e0.re), out_of(xa[u].y, e0.im), out_of(xa[u].z, e1.re),
-                              out_of(xa[u].w, e1.im));
+            if constexpr (pwE) {
+              const bool ga = e4 != nullptr;
+              o = make_float4(out_of(xa[u].x, e0.re, ga ? (double)ea[u].x : Eb),
+                              out_of(xa[u].y, e0.im, ga ? (double)ea[u].y : Eb),
+                              out_of(xa[u].z, e1.re, ga ? (double)ea[u].z : Eb),
+                              out_of(xa[u].w, e1.im, ga ? (double)ea[u].w : Eb));
+            } else if constexpr (final_y) {
+              o = make_float4(out_of(xa[u].x, e0.re, Eb), out_of(xa[u].y, e0.im, Eb), out_of(xa[u].z, e1.re, Eb),
+                              out_of(xa[u].w, e1.im, Eb));
             } else if constexpr (decode) {
               o = make_float4(dec_of(xa[u].x, sa[u].x, e0.re), dec_of(xa[u].y, sa[u].y, e0.im),
                               dec_of(xa[u].z, sa[u].z, e1.re), dec_of(xa[u].w, sa[u].w, e1.im));
@@ -444,10 +511,12 @@ row_kernel(RowArgs<T, TIO> a) {
       }
     } else {
     const V2* xd2 = reinterpret_cast<const V2*>(decode ? st->pxb : st->px);
+    const V2* ed2 = reinterpret_cast<const V2*>(pE);
 #pragma unroll
     for (int b0 = 0; b0 < NS; b0 += BL) {
       V2 xa[BL];
       V2 sa[decode ? BL : 1];
+      double eb0[pwE ? BL : 1], eb1[pwE ? BL : 1];
       if constexpr (ld_x) {
 #pragma unroll
         for (int u = 0; u < BL; ++u) {
@@ -456,6 +525,14 @@ row_kernel(RowArgs<T, TIO> a) {
           if (b0 + u < NS && f < ROWS * H && r < nrow) {
             xa[u] = xd2[(lrow0 + r) * H + m];
             if constexpr (decode) sa[u] = y2[(lrow0 + r) * H + m];
+            if constexpr (pwE) {
+              eb0[u] = eb1[u] = Eb;
+              if (ed2) {
+                const V2 ev = ed2[(lrow0 + r) * H + m];
+                eb0[u] = (double)ev.x;
+                eb1[u] = (double)ev.y;
+              }
+            }
           }
         }
       }
@@ -466,9 +543,12 @@ row_kernel(RowArgs<T, TIO> a) {
         if (b0 + u < NS && f < ROWS * H && r < nrow) {
           const cx<T> e = lds[r * LP + lds_skew<SKW>(m)];
           V2 out;
-          if constexpr (final_y) {
-            out.x = out_of(xa[u].x, e.re);
-            out.y = out_of(xa[u].y, e.im);
+          if constexpr (pwE) {
+            out.x = out_of(xa[u].x, e.re, eb0[u]);
+            out.y = out_of(xa[u].y, e.im, eb1[u]);
+          } else if constexpr (final_y) {
+            out.x = out_of(xa[u].x, e.re, Eb);
+            out.y = out_of(xa[u].y, e.im, Eb);
           } else if constexpr (decode) {
             out.x = dec_of(xa[u].x, sa[u].x, e.re);
             out.y = dec_of(xa[u].y, sa[u].y, e.im);
@@ -528,7 +608,7 @@ row_kernel(RowArgs<T, TIO> a) {
   }
 
   // ------------------------------------------------------------------ partials and masks
-  if constexpr (m_init || m_loop || MODE == ROW_VERIFY || finalv) {
+  if constexpr (m_init || m_loop || m_verify || finalv) {
     cnt = wave_sum_u64(cnt);
     mx = wave_max_f64(mx);
     if ((t & 63) == 0) {
@@ -544,7 +624,7 @@ row_kernel(RowArgs<T, TIO> a) {
         m = fmax(m, red_d[w]);
       }
       // one partial per block, reduced by the control / statistics kernels
-      if constexpr (MODE == ROW_VERIFY || finalv) a.part[blockIdx.x] = (unsigned long long)__double_as_longlong(m);
+      if constexpr (m_verify || finalv) a.part[blockIdx.x] = (unsigned long long)__double_as_longlong(m);
       else a.part[blockIdx.x] = s;
     }
     if constexpr (rec_s) {

@@ -34,7 +34,9 @@ EXPORTS = ("ffcz_version", "ffcz_last_error", "ffcz_default_options", "ffcz_work
            "ffcz_batched_workspace_bytes", "ffcz_correct_batched", "ffcz_profile_enable", "ffcz_profile_read",
            "ffcz_profile_select",
            "ffcz_copy", "ffcz_set_tuning", "ffcz_clear_tuning", "ffcz_correct_noalloc",
-           "ffcz_default_encode_options", "ffcz_encode_workspace_bytes", "ffcz_encode", "ffcz_decode")
+           "ffcz_default_encode_options", "ffcz_encode_workspace_bytes", "ffcz_encode", "ffcz_decode",
+           "ffcz_bounds_workspace_bytes", "ffcz_correct_bounds", "ffcz_power_spectrum_bounds",
+           "ffcz_huffman_workspace_bytes", "ffcz_huffman_plan", "ffcz_huffman_encode", "ffcz_huffman_decode")
 
 PROFILE_KINDS = ("init", "y_fwd", "x_pass", "y_inv", "z_pass", "finalize", "verify_z", "verify_y", "verify_x",
                  "adjoint_z", "adjoint_y", "adjoint_x")
@@ -72,6 +74,26 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class HuffmanSizes(ctypes.Structure):
+    _fields_ = [
+        ("nsym", ctypes.c_int64),
+        ("lo", ctypes.c_int64),
+        ("nalpha", ctypes.c_int64),
+        ("ws_bytes", ctypes.c_size_t),
+        ("out_bytes", ctypes.c_size_t),
+    ]
+
+
+class Bounds(ctypes.Structure):
+    _fields_ = [
+        ("eps_s", ctypes.c_void_p),
+        ("delta_re", ctypes.c_void_p),
+        ("delta_im", ctypes.c_void_p),
+        ("disk", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+    ]
 
 
 class EncodeOptions(ctypes.Structure):
@@ -180,6 +202,31 @@ def lib() -> ctypes.CDLL:
                                   ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_size_t, ctypes.c_void_p]
         L.ffcz_decode.restype = ctypes.c_int32
+        L.ffcz_bounds_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, i64p, ctypes.c_int32]
+        L.ffcz_bounds_workspace_bytes.restype = ctypes.c_size_t
+        L.ffcz_correct_bounds.argtypes = [ctypes.c_int32, ctypes.c_int32, i64p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.POINTER(Bounds),
+                                          ctypes.c_int32, ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_size_t,
+                                          ctypes.c_void_p, ctypes.POINTER(Stats)]
+        L.ffcz_correct_bounds.restype = ctypes.c_int32
+        L.ffcz_power_spectrum_bounds.argtypes = [ctypes.c_int32, ctypes.c_int32, i64p, ctypes.c_void_p,
+                                                 ctypes.c_double, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_size_t, ctypes.c_void_p]
+        L.ffcz_power_spectrum_bounds.restype = ctypes.c_int32
+        L.ffcz_huffman_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64]
+        L.ffcz_huffman_workspace_bytes.restype = ctypes.c_size_t
+        L.ffcz_huffman_plan.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(HuffmanSizes)]
+        L.ffcz_huffman_plan.restype = ctypes.c_int32
+        L.ffcz_huffman_encode.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.POINTER(HuffmanSizes), ctypes.c_void_p, ctypes.c_size_t,
+                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_size_t)]
+        L.ffcz_huffman_encode.restype = ctypes.c_int32
+        L.ffcz_huffman_decode.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_int64)]
+        L.ffcz_huffman_decode.restype = ctypes.c_int32
         L.ffcz_correct_backward.argtypes = [ctypes.c_int32, ctypes.c_int32, i64p, ctypes.c_int32, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                             ctypes.c_void_p]
@@ -267,6 +314,59 @@ def ffcz_correct_noalloc(dtype: int, shape, x_ptr: int, xb_ptr: int, y_ptr: int,
                                           ctypes.c_void_p(y_ptr), float(eps_s), float(delta_f), int(max_iter),
                                           ctypes.byref(opts) if opts is not None else None,
                                           ctypes.c_void_p(stream), ctypes.byref(stats) if stats is not None else None))
+
+
+def ffcz_bounds_workspace_bytes(dtype: int, shape: Sequence[int], max_iter: int) -> int:
+    nd, arr = _shape(shape)
+    return int(lib().ffcz_bounds_workspace_bytes(dtype, nd, arr, max_iter))
+
+
+def ffcz_correct_bounds(dtype: int, shape, x_ptr: int, xb_ptr: int, y_ptr: int, eps_s: float, delta_f: float,
+                        bounds: Optional[Bounds], max_iter: int, opts: Optional[Options], ws_ptr: int, ws_bytes: int,
+                        stream: int, stats: Optional[Stats]) -> int:
+    nd, arr = _shape(shape)
+    return int(lib().ffcz_correct_bounds(dtype, nd, arr, ctypes.c_void_p(x_ptr), ctypes.c_void_p(xb_ptr),
+                                         ctypes.c_void_p(y_ptr), float(eps_s), float(delta_f),
+                                         ctypes.byref(bounds) if bounds is not None else None, int(max_iter),
+                                         ctypes.byref(opts) if opts is not None else None, ctypes.c_void_p(ws_ptr),
+                                         ws_bytes, ctypes.c_void_p(stream),
+                                         ctypes.byref(stats) if stats is not None else None))
+
+
+def ffcz_power_spectrum_bounds(dtype: int, shape, x_ptr: int, rho: float, disk: int, out_ptr: int, ws_ptr: int,
+                               ws_bytes: int, stream: int) -> int:
+    nd, arr = _shape(shape)
+    return int(lib().ffcz_power_spectrum_bounds(dtype, nd, arr, ctypes.c_void_p(x_ptr), float(rho), int(disk),
+                                                ctypes.c_void_p(out_ptr), ctypes.c_void_p(ws_ptr), ws_bytes,
+                                                ctypes.c_void_p(stream)))
+
+
+def ffcz_huffman_workspace_bytes(nsym: int, nalpha: int) -> int:
+    return int(lib().ffcz_huffman_workspace_bytes(int(nsym), int(nalpha)))
+
+
+def ffcz_huffman_plan(sym_ptr: int, nsym: int, width: int, ws_ptr: int, ws_bytes: int, stream: int,
+                      sizes: HuffmanSizes) -> int:
+    return int(lib().ffcz_huffman_plan(ctypes.c_void_p(sym_ptr), int(nsym), int(width), ctypes.c_void_p(ws_ptr),
+                                       ws_bytes, ctypes.c_void_p(stream), ctypes.byref(sizes)))
+
+
+def ffcz_huffman_encode(sym_ptr: int, nsym: int, width: int, sizes: HuffmanSizes, out_ptr: int, out_bytes: int,
+                        ws_ptr: int, ws_bytes: int, stream: int):
+    used = ctypes.c_size_t(0)
+    st = int(lib().ffcz_huffman_encode(ctypes.c_void_p(sym_ptr), int(nsym), int(width), ctypes.byref(sizes),
+                                       ctypes.c_void_p(out_ptr), out_bytes, ctypes.c_void_p(ws_ptr), ws_bytes,
+                                       ctypes.c_void_p(stream), ctypes.byref(used)))
+    return st, int(used.value)
+
+
+def ffcz_huffman_decode(in_ptr: int, in_bytes: int, width: int, out_ptr: int, capacity: int, ws_ptr: int,
+                        ws_bytes: int, stream: int):
+    n = ctypes.c_int64(0)
+    st = int(lib().ffcz_huffman_decode(ctypes.c_void_p(in_ptr), in_bytes, int(width), ctypes.c_void_p(out_ptr),
+                                       int(capacity), ctypes.c_void_p(ws_ptr), ws_bytes, ctypes.c_void_p(stream),
+                                       ctypes.byref(n)))
+    return st, int(n.value)
 
 
 def ffcz_default_encode_options() -> EncodeOptions:
@@ -614,6 +714,122 @@ def decode(xb, enc: Encoded, *, ws=None, out=None):
     if r < 0:
         raise FFCzError(r, ffcz_last_error())
     return y
+
+
+def half_shape(shape):
+    """Half-spectrum shape of a field (last axis n -> n // 2 + 1)."""
+    shape = tuple(int(n) for n in shape)
+    return shape[:-1] + (shape[-1] // 2 + 1,)
+
+
+def correct_bounds(x, xb, max_iter: int, *, eps_s: float = 0.0, delta_f: float = 0.0, E=None, D_re=None,
+                   D_im=None, disk: bool = False, margin: float = 0.0, fixed: bool = False, verify: bool = True,
+                   chunk: int = 4, graph: bool = True, out=None, ws=None, check: bool = True) -> Result:
+    """``ffcz_correct_bounds`` on device tensors: pointwise bound tensors ``E`` (shape of x),
+    ``D_re`` / ``D_im`` (half-spectrum shape), or the scalars where a tensor is None."""
+    torch = _torch()
+    _check_tensor(x, "x")
+    _check_tensor(xb, "xb")
+    if x.shape != xb.shape or x.dtype != xb.dtype or x.device != xb.device:
+        raise FFCzError(E_INVALID, "x and xb must have the same shape, dtype and device")
+    dt = _dtype_code(x)
+    shape = tuple(x.shape)
+    b = Bounds()
+    b.disk = 1 if disk else 0
+    keep = []
+    for name, t, shp in (("eps_s", E, shape), ("delta_re", D_re, half_shape(shape)),
+                         ("delta_im", D_im, half_shape(shape))):
+        if t is None:
+            continue
+        if tuple(t.shape) != tuple(shp) or t.dtype != x.dtype or t.device != x.device or not t.is_contiguous():
+            raise FFCzError(E_INVALID, f"{name} must be a contiguous {x.dtype} tensor of shape {shp} on {x.device}")
+        keep.append(t)
+        setattr(b, name, t.data_ptr())
+    y = torch.empty_like(x) if out is None else out
+    if out is not None:
+        _check_like(out, x, "out")
+    nbytes = ffcz_bounds_workspace_bytes(dt, shape, max_iter)
+    if nbytes == 0:
+        raise FFCzError(E_SHAPE, f"unsupported shape {shape}: {ffcz_last_error()}")
+    if ws is None:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    else:
+        _check_bytes(ws, nbytes, x.device, "ws")
+    opts = ffcz_default_options()
+    opts.margin_rel = float(margin)
+    opts.fixed_iterations = 1 if fixed else 0
+    opts.verify_fp64 = 1 if verify else 0
+    opts.graph_chunk = int(chunk)
+    opts.use_graph = 1 if graph else 0
+    stats = Stats()
+    stream = torch.cuda.current_stream(x.device).cuda_stream
+    st = ffcz_correct_bounds(dt, shape, x.data_ptr(), xb.data_ptr(), y.data_ptr(), eps_s, delta_f, b, max_iter, opts,
+                             ws.data_ptr(), ws.numel(), stream, stats)
+    if check and st < 0:
+        raise FFCzError(st, ffcz_last_error())
+    return Result(y=y, status=st, stats=stats.as_dict())
+
+
+def power_spectrum_bounds(x, rho: float, *, disk: bool = False, ws=None):
+    """``ffcz_power_spectrum_bounds``: the half-spectrum bound tensor that keeps every shell of
+    the power spectrum of ``x`` within ``rho`` relative error."""
+    torch = _torch()
+    _check_tensor(x, "x")
+    dt = _dtype_code(x)
+    shape = tuple(x.shape)
+    nbytes = ffcz_bounds_workspace_bytes(dt, shape, 0)
+    if nbytes == 0:
+        raise FFCzError(E_SHAPE, f"unsupported shape {shape}: {ffcz_last_error()}")
+    if ws is None:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    else:
+        _check_bytes(ws, nbytes, x.device, "ws")
+    out = torch.empty(half_shape(shape), dtype=x.dtype, device=x.device)
+    st = ffcz_power_spectrum_bounds(dt, shape, x.data_ptr(), rho, 1 if disk else 0, out.data_ptr(), ws.data_ptr(),
+                                    ws.numel(), torch.cuda.current_stream(x.device).cuda_stream)
+    if st < 0:
+        raise FFCzError(st, ffcz_last_error())
+    return out
+
+
+def huffman_compress(sym):
+    """Huffman-code a device tensor of symbols (uint8: width 1; int32: width 4).  Returns
+    ``(stream uint8 tensor, HuffmanSizes)``."""
+    torch = _torch()
+    _check_tensor(sym, "sym")
+    if sym.dtype == torch.uint8:
+        width = 1
+    elif sym.dtype == torch.int32:
+        width = 4
+    else:
+        raise FFCzError(E_INVALID, "symbols must be uint8 or int32")
+    n = sym.numel()
+    stream = torch.cuda.current_stream(sym.device).cuda_stream
+    ws = torch.empty(max(ffcz_huffman_workspace_bytes(n, 0), 256), dtype=torch.uint8, device=sym.device)
+    sizes = HuffmanSizes()
+    st = ffcz_huffman_plan(sym.data_ptr(), n, width, ws.data_ptr(), ws.numel(), stream, sizes)
+    if st < 0:
+        raise FFCzError(st, ffcz_last_error())
+    ws = torch.empty(max(int(sizes.ws_bytes), 256), dtype=torch.uint8, device=sym.device)
+    out = torch.empty(int(sizes.out_bytes), dtype=torch.uint8, device=sym.device)
+    st, used = ffcz_huffman_encode(sym.data_ptr(), n, width, sizes, out.data_ptr(), out.numel(), ws.data_ptr(),
+                                   ws.numel(), stream)
+    if st < 0:
+        raise FFCzError(st, ffcz_last_error())
+    return out[:used], sizes
+
+
+def huffman_decompress(stream_t, n: int, dtype, nalpha: int):
+    """Decode a stream of ``n`` symbols (``dtype`` uint8 or int32) from ``huffman_compress``."""
+    torch = _torch()
+    width = 1 if dtype == torch.uint8 else 4
+    ws = torch.empty(max(ffcz_huffman_workspace_bytes(n, nalpha), 256), dtype=torch.uint8, device=stream_t.device)
+    out = torch.empty(max(n, 1), dtype=dtype, device=stream_t.device)
+    st, m = ffcz_huffman_decode(stream_t.data_ptr(), stream_t.numel(), width, out.data_ptr(), out.numel(),
+                                ws.data_ptr(), ws.numel(), torch.cuda.current_stream(stream_t.device).cuda_stream)
+    if st < 0:
+        raise FFCzError(st, ffcz_last_error())
+    return out[:m]
 
 
 def batched_workspace(members, max_iter: int, device=None):

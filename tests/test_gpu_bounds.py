@@ -1,0 +1,196 @@
+"""Generalised bounds on the GPU against the oracle (footnote to Eq. 2, Sec. IV-A; Sec. V-B,
+Observation 4), through the C ABI.
+
+- ffcz_power_spectrum_bounds: the per-shell bound against the oracle's (FP64 within 1e-12,
+  FP32 at most the oracle's value and within 1e-6).
+- ffcz_correct_bounds: pointwise E_n and D_k (box with separate Re / Im arrays, and the disk),
+  against the oracle loop fed the same bound arrays and the GPU's margin: FP64 equal rounds and
+  per-check counts, outputs within 1e-12; FP32 within 1e-5 (rounds within one).  The library's
+  FP64 ratios equal the oracle's re-verification of the same output, and the power spectrum of
+  the corrected field stays within rho on every shell.
+- Invalid bound arrays are refused before the loop; constant arrays give the plain correction.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import bounds as B
+from oracle import ffcz as O
+from paper_2601_01596_amd import ffcz as F
+from paper_2601_01596_amd import workloads as W
+from tests.gpu_util import rel_err
+from tests.progress import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _sym_random(shape, seed, lo, hi):
+    g = np.random.default_rng(seed)
+    full = g.uniform(lo, hi, shape)
+    idx = np.indices(shape)
+    neg = tuple((-idx[i]) % shape[i] for i in range(len(shape)))
+    return (0.5 * (full + full[neg]))[..., : shape[-1] // 2 + 1]
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (64, 128), (512,), (16, 8, 64)])
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("disk", [False, True])
+def test_power_spectrum_bounds_match_the_oracle(shape, dt, disk):
+    x = (W.lognormal(shape, 2.5, 11) if len(shape) == 3 else W.grf(shape, 2.0, 12) + 0.5).astype(dt)
+    d = F.power_spectrum_bounds(_dev(x), 1e-3, disk=disk).cpu().numpy()
+    ref = B.power_spectrum_bounds(x.astype(np.float64), 1e-3, disk=disk)
+    assert d.shape == ref.shape and d.dtype == np.dtype(dt)
+    r = np.abs(d.astype(np.float64) - ref) / ref
+    if dt == np.float64:
+        assert float(r.max()) <= 1e-12
+    else:
+        assert float(r.max()) <= 1e-6
+        assert np.all(d.astype(np.float64) <= ref * (1 + 1e-12))  # rounded toward zero
+
+
+def _case(kind, dt):
+    """(x, x_hat, scalar E, scalar D, E array or None, D_re, D_im or None, disk, rho or None)."""
+    if kind in ("ps_box", "ps_disk"):
+        x = W.lognormal((32, 32, 32), 2.5, 61).astype(dt)
+        E = W.spatial_bound(x, 3e-5)
+        xb = W.quantize(x, E).astype(dt)
+        disk = kind == "ps_disk"
+        D = B.power_spectrum_bounds(x.astype(np.float64), 1e-3, disk=disk).astype(dt)
+        return x, xb, E, 0.0, None, D, None, disk, 1e-3
+    g = np.random.default_rng(3)
+    x = W.grf((16, 32, 64), 2.0, 9).astype(dt)
+    E = W.spatial_bound(x, 2e-2)
+    En = (E * g.uniform(0.5, 1.0, x.shape)).astype(dt)
+    xb = W.quantize(x, E)
+    xb = (np.clip(xb - x, -En, En) + x).astype(dt)
+    D = W.spectral_bound(x, xb, 80.0)
+    if kind == "en_scalar_d":
+        return x, xb, E, D, En, None, None, False, None
+    if kind == "en_disk":
+        return x, xb, E, D, En, None, None, True, None
+    if kind == "en_re_im":
+        hs = B.half_shape(x.shape)
+        Dre = (D * _sym_random(x.shape, 21, 0.7, 1.3)).astype(dt)
+        Dim = (D * _sym_random(x.shape, 22, 0.7, 1.3)).astype(dt)
+        return x, xb, E, D, En, Dre, Dim, False, None
+    if kind == "scalar_e_d_arr":
+        Dre = (D * _sym_random(x.shape, 23, 0.6, 1.0)).astype(dt)
+        return x, xb, E, D, None, Dre, None, False, None
+    raise KeyError(kind)
+
+
+KINDS = ["ps_box", "ps_disk", "en_scalar_d", "en_disk", "en_re_im", "scalar_e_d_arr"]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_pointwise_correction_matches_the_oracle(kind, dt):
+    x, xb, E, D, En, Dre, Dim, disk, rho = _case(kind, dt)
+    t = lambda a: None if a is None else _dev(a)
+    r = F.correct_bounds(_dev(x), _dev(xb), 300, eps_s=E, delta_f=D, E=t(En), D_re=t(Dre), D_im=t(Dim), disk=disk)
+    assert r.status == F.OK, (r.status, F.ffcz_last_error())
+    y = r.y.cpu().numpy()
+    mu = r.stats["margin_used"]
+    Eo = E if En is None else En.astype(np.float64)
+    if Dre is None and dt == np.float32:
+        # an FP32 field's scalar spectral bound is rounded toward zero to FP32 (never grows)
+        d32 = np.float32(D)
+        D = float(np.nextafter(d32, np.float32(0)) if float(d32) > D else d32)
+    Dro = D if Dre is None else Dre.astype(np.float64)
+    Dio = None if Dim is None else Dim.astype(np.float64)
+    orc = B.correct(x, xb, Eo, Dro, 300, D_im=Dio, disk=disk, mu=mu)
+    k = r.stats["rounds"]
+    if dt == np.float64:
+        assert k == orc.rounds
+        assert r.stats["f_viol_initial"] == orc.viol[0] and r.stats["s_guard"] == orc.s_clipped[0]
+        assert rel_err(y, orc.y) <= 1e-12
+    else:
+        if k != orc.rounds:
+            assert abs(k - orc.rounds) <= 1
+            orc = B.correct(x, xb, Eo, Dro, k, D_im=Dio, disk=disk, mu=mu, fixed=True)
+        assert rel_err(y, orc.y) <= 1e-5
+    rs, rf, nv, ok = B.verify(x, y, Eo, Dro, Dio, disk=disk)
+    say(f"[bounds] {kind} {np.dtype(dt).name}: rounds {k}, mu {mu:.3e}, ratios {rs:.6f} / {rf:.6f}")
+    assert ok and nv == 0
+    assert r.stats["max_spatial_err"] == pytest.approx(rs, rel=1e-12)
+    assert r.stats["max_spectral_err"] == pytest.approx(rf, rel=1e-9)
+    if dt == np.float32 and En is None and Dre is not None:
+        Dmin = float(min(Dro.min(), Dio.min() if Dio is not None else Dro.min()))
+        assert mu == pytest.approx(B.suggest_margin(x, Dmin, disk), rel=1e-9)
+    if rho is not None:
+        b, w = B.shells(x.shape)
+        P = B.shell_power(O.fft(x.astype(np.float64)), b, w)
+        Py = B.shell_power(O.fft(y.astype(np.float64)), b, w)
+        assert float(np.max(np.abs(Py - P) / P)) <= rho
+
+
+def test_constant_arrays_give_the_plain_correction():
+    p = W.config_lognormal(32, np.float64)
+    x, xb = _dev(p.x), _dev(p.xb)
+    plain = F.correct(x, xb, p.E, p.Delta, p.max_iter)
+    hs = F.half_shape(p.x.shape)
+    import torch
+    r = F.correct_bounds(x, xb, p.max_iter, E=torch.full_like(x, p.E),
+                         D_re=torch.full(hs, p.Delta, dtype=torch.float64, device="cuda"))
+    assert r.status == F.OK and r.stats["rounds"] == plain.stats["rounds"]
+    assert rel_err(r.y.cpu().numpy(), plain.y.cpu().numpy()) <= 1e-12
+
+
+def test_invalid_bound_arrays_are_refused():
+    import torch
+    p = W.config_lognormal(32, np.float32)
+    x, xb = _dev(p.x), _dev(p.xb)
+    En = torch.full_like(x, p.E)
+    En[3, 4, 5] = -1.0
+    with pytest.raises(F.FFCzError) as ei:
+        F.correct_bounds(x, xb, 50, delta_f=p.Delta, E=En)
+    assert ei.value.status == F.E_INVALID
+    D = torch.full(F.half_shape(p.x.shape), p.Delta, dtype=torch.float32, device="cuda")
+    D[0, 1, 2] = float("nan")
+    with pytest.raises(F.FFCzError) as ei:
+        F.correct_bounds(x, xb, 50, eps_s=p.E, D_re=D)
+    assert ei.value.status == F.E_INVALID
+
+
+@pytest.mark.timeout(600)
+def test_lognormal512_power_spectrum_bound_full_size():
+    import torch
+    O.set_workers(max(1, min(16, O.default_workers())))
+    say("[bounds] lognormal 512^3 FP32: generating")
+    p = W.config_lognormal(512, np.float32)
+    x, xb = _dev(p.x), _dev(p.xb)
+    rho = 1e-3
+    D = F.power_spectrum_bounds(x, rho)
+    say("[bounds] shell bound against the oracle")
+    ref = B.power_spectrum_bounds(p.x.astype(np.float64), rho)
+    Dh = D.cpu().numpy().astype(np.float64)
+    assert float(np.max(np.abs(Dh - ref) / ref)) <= 1e-6 and np.all(Dh <= ref * (1 + 1e-12))
+    del ref
+    say("[bounds] correction on the GPU")
+    r = F.correct_bounds(x, xb, 500, eps_s=p.E, D_re=D)
+    assert r.status == F.OK, (r.status, F.ffcz_last_error())
+    say(f"[bounds] rounds {r.stats['rounds']}, ratios {r.stats['max_spatial_err']:.6f} / "
+        f"{r.stats['max_spectral_err']:.6f}; power spectrum in FP64")
+    # every shell of the power spectrum within rho (FP64, on the device)
+    n = 512
+    b, w = B.shells((n, n, n))
+    bt = torch.from_numpy(b.reshape(-1)).cuda()
+    wt = torch.from_numpy(np.ascontiguousarray(w).reshape(-1)).cuda()
+    del b, w
+
+    def shells(f):
+        X = torch.fft.rfftn(f.double()).reshape(-1)
+        pw = wt * (X.real ** 2 + X.imag ** 2)
+        return torch.zeros(int(bt.max()) + 1, dtype=torch.float64, device="cuda").index_add_(0, bt, pw)
+
+    P, Py, Pb = shells(x), shells(r.y), shells(xb)
+    rel = float(((Py - P).abs() / P).max())
+    relb = float(((Pb - P).abs() / P).max())
+    say(f"[bounds] power spectrum: corrected {rel:.3e}, base {relb:.3e} (rho {rho})")
+    assert rel <= rho and relb > rho
+    assert float((r.y.double() - x.double()).abs().max()) <= p.E
