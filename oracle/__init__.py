@@ -14,6 +14,11 @@ Modules
               from Eq. 1 / Eq. 3, used to pin ``ffcz`` on tiny grids.
 ``spectrum``  the shell-binned power spectrum of Sec. III and the
               log-spectrum loss used to exercise the adjoint.
+``edits``     edit bookkeeping, CompactEdits, QuantizeEdits and the decoder
+              (Alg. 1; Sec. IV-B, IV-D).
+``bounds``    pointwise bounds, the disk variant and relative power-spectrum
+              bounds (the footnote to Eq. 2; Sec. V-B).
+``huffman``   the Huffman coding of the edit streams (LosslesslyCompressEdits).
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test
 (brute-force DFT, Parseval, projection identities, regime closed forms,

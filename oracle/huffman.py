@@ -25,7 +25,7 @@ Readings taken where the paper is silent
   32-bit words, each word filled from its most significant bit down; the last
   word is padded with zeros.
 * Chunk offsets: the bit position where symbol ``j * chunk`` starts, for every
-  chunk (``chunk = 1024``), so that a decoder can start at any chunk.
+  chunk (``chunk = 256``), so that a decoder can start at any chunk.
 """
 
 from __future__ import annotations
@@ -36,7 +36,7 @@ import heapq
 import numpy as np
 
 MAX_LEN = 32
-CHUNK = 1024
+CHUNK = 256
 
 
 def histogram(sym: np.ndarray):
