@@ -284,11 +284,87 @@ def edit_leg(F, torch, prob, steps):
     nnz_s, nnz_f = enc.spat_codes.numel(), enc.freq_codes.numel()
     ns, nf = F.edit_coords(shape)
     coded = (ns + 7) // 8 + (nf + 7) // 8 + 4 * (nnz_s + nnz_f)
-    return {"encode_ms": t_enc * 1e3, "encode_GBps": prob.x.nbytes / t_enc / 1e9, "decode_ms": t_dec * 1e3,
+    huff = huffman_leg(F, torch, enc, steps)
+    return {**huff, "encode_ms": t_enc * 1e3, "encode_GBps": prob.x.nbytes / t_enc / 1e9, "decode_ms": t_dec * 1e3,
             "decode_GBps": prob.x.nbytes / t_dec / 1e9, "encode_rounds": enc.stats["rounds"],
             "encode_status": enc.status, "edits_nnz_spatial": nnz_s, "edits_nnz_freq": nnz_f,
             "edits_coded_bytes": coded, "edits_mu_s": enc.mu_s, "edits_mu_f": enc.mu_f,
             "decoded_max_spatial_err_over_E": ms / prob.E, "decoded_max_spectral_err_over_Delta": mf / prob.Delta}
+
+
+def huffman_leg(F, torch, enc, steps):
+    """Huffman coding of the four edit streams of an encoding (flags and codes of both sets):
+    time of plan + encode per stream set, sizes, and the decoders' time."""
+    streams = [enc.spat_flags, enc.spat_codes, enc.freq_flags, enc.freq_codes]
+    out = [F.huffman_compress(t) for t in streams]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = [F.huffman_compress(t) for t in streams]
+    torch.cuda.synchronize()
+    t_enc = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        back = [F.huffman_decompress(o[0], t.numel(), t.dtype, int(o[1].nalpha)) for o, t in zip(out, streams)]
+    torch.cuda.synchronize()
+    t_dec = (time.perf_counter() - t0) / steps
+    for b, t in zip(back, streams):
+        assert torch.equal(b[: t.numel()], t), "Huffman round trip failed"
+    raw = sum(t.numel() * t.element_size() for t in streams)
+    coded = sum(int(o[0].numel()) for o in out)
+    return {"huffman_encode_ms": t_enc * 1e3, "huffman_decode_ms": t_dec * 1e3, "edits_raw_bytes": raw,
+            "edits_huffman_bytes": coded, "edits_bits_per_point": 8.0 * coded / F.edit_coords(enc.shape)[0]}
+
+
+def bounds_leg(F, torch, prob, steps, rho=1e-3):
+    """Relative power-spectrum bound (rho = 1e-3 on every shell) on the benchmark field: the
+    shell bound, then the correction against it; every shell re-checked in FP64 afterwards."""
+    import numpy as np
+    x = torch.from_numpy(prob.x).cuda()
+    xb = torch.from_numpy(prob.xb).cuda()
+    shape = tuple(prob.x.shape)
+    ws = torch.empty(F.ffcz_bounds_workspace_bytes(F.F32, shape, prob.max_iter), dtype=torch.uint8, device="cuda")
+    D = F.power_spectrum_bounds(x, rho, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        D = F.power_spectrum_bounds(x, rho, ws=ws)
+    torch.cuda.synchronize()
+    t_ps = (time.perf_counter() - t0) / steps
+    y = torch.empty_like(x)
+    r = F.correct_bounds(x, xb, prob.max_iter, eps_s=prob.E, D_re=D, ws=ws, out=y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = F.correct_bounds(x, xb, prob.max_iter, eps_s=prob.E, D_re=D, ws=ws, out=y)
+    torch.cuda.synchronize()
+    t_cb = (time.perf_counter() - t0) / steps
+    del ws
+    # the harness's own check, outside the timing: shell rint(|k|) and full-spectrum weight of
+    # every half-spectrum entry, then every shell's power in FP64
+    freqs = [np.fft.fftfreq(n) * n for n in shape[:-1]] + [np.arange(shape[-1] // 2 + 1, dtype=np.float64)]
+    grids = np.meshgrid(*freqs, indexing="ij")
+    b = np.rint(np.sqrt(sum(g * g for g in grids))).astype(np.int64)
+    del grids
+    kz = np.arange(shape[-1] // 2 + 1)
+    w = np.broadcast_to(np.where((kz == 0) | (kz == shape[-1] // 2), 1.0, 2.0), b.shape)
+    b = b.reshape(-1)
+    w = np.ascontiguousarray(w).reshape(-1)
+
+    def shells(f):
+        # weighted |X_k|^2 on the device, binned on the host (device atomics on a few hundred
+        # FP64 bins serialise)
+        X = torch.fft.rfftn(f.double()).reshape(-1)
+        pw = (X.real ** 2 + X.imag ** 2).cpu().numpy()
+        return torch.from_numpy(np.bincount(b, weights=w * pw))
+
+    P, Py, Pb = shells(x), shells(y), shells(xb)
+    return {"ps_bound_ms": t_ps * 1e3, "bounds_correct_ms": t_cb * 1e3, "bounds_rounds": r.stats["rounds"],
+            "bounds_status": r.status, "bounds_rho": rho,
+            "bounds_ps_rel_err_corrected": float(((Py - P).abs() / P).max()),
+            "bounds_ps_rel_err_base": float(((Pb - P).abs() / P).max()),
+            "bounds_max_spatial_ratio": r.stats["max_spatial_err"],
+            "bounds_max_spectral_ratio": r.stats["max_spectral_err"]}
 
 
 def batch_leg(F, torch, W, steps):
@@ -315,8 +391,24 @@ def batch_leg(F, torch, W, steps):
     t2d, _ = timed(mem[512:])
     r1 = [s["rounds"] for s in stats[:512]]
     r2 = [s["rounds"] for s in stats[512:]]
+
+    def model_bytes(ps, ss):
+        # fused model per member: x and x_hat read and y written (3 N s), the first last-axis
+        # transform written and the closing pass's read (2 M c), and per check two passes that
+        # each read and write the half spectrum, one fewer after the last check ((2 R + 1) 2 M c)
+        tot = 0
+        for p, s in zip(ps, ss):
+            shape = p.x.shape
+            n = p.x.size
+            m = n // shape[-1] * (shape[-1] // 2 + 1)
+            tot += 3 * n * 4 + 2 * m * 8 + (2 * s["rounds"] + 1) * 2 * m * 8
+        return tot
+
+    mb, mb1, mb2 = model_bytes(probs, stats), model_bytes(probs[:512], stats[:512]), model_bytes(probs[512:], stats[512:])
     return {"batch_ms": t * 1e3, "batch_GBps": nbytes / t / 1e9, "batch_status": st, "batch_bytes": nbytes,
             "batch_1d_only_ms": t1d * 1e3, "batch_2d_only_ms": t2d * 1e3,
+            "batch_model_GB": mb / 1e9, "batch_model_GBps": mb / t / 1e9, "batch_frac_of_peak": mb / t / 8e12,
+            "batch_1d_model_frac_of_peak": mb1 / t1d / 8e12, "batch_2d_model_frac_of_peak": mb2 / t2d / 8e12,
             "batch_rounds_1d_mean": float(sum(r1)) / len(r1), "batch_rounds_1d_max": max(r1),
             "batch_rounds_2d_mean": float(sum(r2)) / len(r2), "batch_rounds_2d_max": max(r2),
             "batch_config": "512 EEG-like FP32 signals (L log-uniform in [2^12, 2^18], seeds 40000+i) + "
@@ -336,6 +428,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-steady", action="store_true")
     ap.add_argument("--no-edits", action="store_true")
+    ap.add_argument("--no-bounds", action="store_true")
     ap.add_argument("--grad-n", type=int, default=256)
     ap.add_argument("--grad-rounds", type=int, default=50)
     args = ap.parse_args()
@@ -419,12 +512,26 @@ def main():
         log(f"[bench] fwd+bwd {args.grad_n}^3, {args.grad_rounds} rounds")
         extra["fwd_bwd_ms"] = fwd_bwd(F, torch, W, args.grad_n, args.grad_rounds, max(1, args.steps // 2))
         extra["fwd_bwd_config"] = f"{args.grad_n}^3 FP32 GRF k^-2, {args.grad_rounds} fixed rounds + adjoint"
+        # pass model: forward and adjoint rounds each move 8 M c through the four passes, plus the
+        # masks (1 bit per point, 2 bits per half-spectrum entry per round) written then read; the
+        # init / closing passes 2 N s + M c each way
+        gn, K = args.grad_n, args.grad_rounds
+        gN, gM = gn ** 3, gn * gn * (gn // 2 + 1)
+        model = 2 * K * 8 * gM * 8 + 2 * K * (gN // 8 + gM // 4) + 2 * (2 * gN * 4 + gM * 8)
+        extra["fwd_bwd_model_GB"] = model / 1e9
+        extra["fwd_bwd_model_GBps"] = model / (extra["fwd_bwd_ms"] * 1e-3) / 1e9
+        extra["fwd_bwd_frac_of_peak"] = extra["fwd_bwd_model_GBps"] / HBM_PEAK_GBS
         log(f"[bench] fwd+bwd {extra['fwd_bwd_ms']:.3f} ms")
 
     if not args.no_edits:
         log("[bench] edit coding: encoder and decoder on the FP32 field")
         extra.update(edit_leg(F, torch, p32, args.steps))
         log(f"[bench] encode {extra['encode_ms']:.3f} ms, decode {extra['decode_ms']:.3f} ms")
+
+    if not args.no_bounds:
+        log("[bench] power-spectrum bound (rho 1e-3) and the correction against it")
+        extra.update(bounds_leg(F, torch, p32, args.steps))
+        log(f"[bench] shell bound {extra['ps_bound_ms']:.3f} ms, correction {extra['bounds_correct_ms']:.3f} ms")
 
     if not args.no_batch:
         log("[bench] batched leg: 512 EEG signals + 64 x 2048^2 fields")

@@ -90,9 +90,19 @@ typedef struct {
    * power-of-two L >= 4, else the Bluestein length >= 2L - 1) is at least
    * 2^tiled_1d_lg run as tiled passes, many blocks per signal, with the rounds
    * driven by the host; shorter ones run one block per signal for the whole
-   * correction.  0 selects the default 15; values below 12 count as 12; above 20
-   * keeps every 1D member on one block.  Both give bit-identical results. */
+   * correction.  Values below 12 count as 12; above 20 keep every 1D member on
+   * one block.  0 (default): work lengths below 2^12 run one block per signal,
+   * above 2^16 tiled, and each length class between takes the plan tuner's
+   * decision (ffcz_set_tuning): on its first use on a device architecture (per
+   * data type and power-of-two bucket of the class's signal count) both forms
+   * run three fixed rounds on the call's own members, before the correction,
+   * and the faster is kept; with tuning off, classes from 2^15 run tiled.
+   * Both forms give bit-identical results. */
   int32_t tiled_1d_lg;
+  /* 1 (default): a 1D member that runs on one block keeps its work buffer in
+   * that block's LDS when it fits (FP32 work length up to 2^14, FP64 up to
+   * 2^13); 0: in the workspace.  Both give bit-identical results. */
+  int32_t resident_1d;
 } ffcz_options;
 
 typedef struct {               /* host struct filled on return */
@@ -353,8 +363,8 @@ int32_t ffcz_power_spectrum_bounds(int32_t dtype, int32_t ndim, const int64_t* s
  * created first (leaves in symbol order, then merged nodes in turn); codes
  * longer than 32 bits halve every count ((c + 1) / 2) and rebuild; canonical
  * codes (by length, then value) are written most significant bit first into
- * 32-bit words filled from their top bit, with the bit offset of every 1,024th
- * symbol kept so that decoding runs one lane per 1,024 symbols.  The paper
+ * 32-bit words filled from their top bit, with the bit offset of every 256th
+ * symbol kept so that decoding runs one lane per 256 symbols.  The paper
  * follows this stage with ZSTD, a third-party compressor not part of this
  * library.
  * Stream (device bytes): a 64-byte header (magic "FHUF", width, symbol

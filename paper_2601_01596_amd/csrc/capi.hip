@@ -24,9 +24,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
-#include <queue>
-#include <thread>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -60,7 +59,7 @@ hipError_t launch_bounds_col_f64(int mode, int L, const void* args, int64_t nb, 
 // Which instantiation family runs a mode: the loop in the data type, set-up and
 // verification in FP64 (SigArgs<double>).
 bool sig_mode_fp64(int mode, int iodt) {
-  const bool loop = mode == SIG_RUN || mode == SIGT_EPS0 || mode == SIGT_CIN || mode == SIGT_RMUL ||
+  const bool loop = mode == SIG_RUN || mode == SIG_RUNL || mode == SIGT_EPS0 || mode == SIGT_CIN || mode == SIGT_RMUL ||
                     mode == SIGT_RCHECK || mode == SIGT_CCHECK || mode == SIGT_CSPAT || mode == SIGT_Y;
   return !loop || iodt == 1;
 }
@@ -1136,20 +1135,23 @@ thread_local HostBuf g_host_sig, g_host_sigstate;
 // Private streams (default priority): one to capture graphs on, one for the
 // 1D members of a batch, which run beside the grouped members.
 struct Streams {
-  hipStream_t cap = nullptr, side = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  // cap, cap2: capture (the second for a graph's parallel branch); side: the 1D members of a
+  // mixed batch; side2: the 1D members that run one block each
+  hipStream_t cap = nullptr, cap2 = nullptr, side = nullptr, side2 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, fork2 = nullptr, join2 = nullptr, ready1d = nullptr, looped = nullptr,
+             cfork = nullptr, cjoin = nullptr;
   ~Streams() {
-    if (cap) (void)hipStreamDestroy(cap);
-    if (side) (void)hipStreamDestroy(side);
-    if (fork) (void)hipEventDestroy(fork);
-    if (join) (void)hipEventDestroy(join);
+    for (hipStream_t q : {cap, cap2, side, side2})
+      if (q) (void)hipStreamDestroy(q);
+    for (hipEvent_t ev : {fork, join, fork2, join2, ready1d, looped, cfork, cjoin})
+      if (ev) (void)hipEventDestroy(ev);
   }
   hipError_t ready() {
     hipError_t e = hipSuccess;
-    if (!cap) e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-    if (e == hipSuccess && !side) e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
-    if (e == hipSuccess && !fork) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-    if (e == hipSuccess && !join) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    for (hipStream_t* q : {&cap, &cap2, &side, &side2})
+      if (e == hipSuccess && !*q) e = hipStreamCreateWithFlags(q, hipStreamNonBlocking);
+    for (hipEvent_t* ev : {&fork, &join, &fork2, &join2, &ready1d, &looped, &cfork, &cjoin})
+      if (e == hipSuccess && !*ev) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
     return e;
   }
 };
@@ -1185,6 +1187,14 @@ struct GraphCache {
   }
 };
 thread_local GraphCache g_graphs;
+// Graphs of the tiled 1D rounds: process-wide (the thread that drives the 1D members of a
+// mixed batch is started per call), behind a mutex.  Never destroyed at exit: the HIP runtime
+// may already be gone when static destructors run.
+std::mutex g_sig_graphs_m;
+GraphCache& sig_graphs() {
+  static GraphCache* c = new GraphCache();
+  return *c;
+}
 
 double bits_to_double(unsigned long long b) {
   double d;
@@ -1523,191 +1533,247 @@ BoundsLayout bounds_layout(const Plan& p) {
 // host_state: when given (one entry per instance, ordinary host memory), the call
 // allocates nothing: the loop state is read back into it, the rounds run as plain
 // launches (no graph) and the tile plans come from the table or the defaults.
+// One group's correction (a plan over B same-shape instances) in phases: begin (set-up through
+// the first last-axis transform, on the call's stream), the rounds in chunks (run here, or
+// captured with other work by the mixed-batch loop), end (closing pass, verification,
+// statistics).  Holds a Ctx that points at its own Plan: neither copied nor moved.
 template <typename T>
-int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* mus, int32_t max_iter,
-                      const ffcz_options& o, char* ws, hipStream_t s, ffcz_stats* stats, int32_t* status,
-                      DevState* host_state = nullptr, const EditCfg* ed = nullptr,
-                      const BoundsCfg* bc = nullptr) {
-  const bool no_alloc = host_state != nullptr;
-  Plan p = p0;
-  Ctx c{&p, ws, s};
-  if (ed) {
-    c.sacc = ed->sacc;
-    c.facc = ed->facc;
-  }
-  if (bc) c.pD = bc->pD;
-  const int64_t vstride = max_iter + 2;
-  const bool user_viol = o.viol_per_round && p.B == 1;
-  unsigned long long* viol = user_viol ? (unsigned long long*)o.viol_per_round : c.viol();
-  const int64_t vstr = user_viol ? 0 : vstride;
-  const bool rec = o.masks_out != nullptr && p.B == 1;
-  uint32_t* smask = rec ? (uint32_t*)o.masks_out : nullptr;
-  uint8_t* fmask = rec ? (uint8_t*)o.masks_out + (size_t)(max_iter + 1) * p.s_plane_bytes : nullptr;
+struct GroupRun {
+  Plan p;
+  Ctx c{nullptr, nullptr, nullptr};
+  const ffcz_instance* inst = nullptr;
+  const double* mus = nullptr;
+  int32_t max_iter = 0;
+  ffcz_options o{};
+  DevState* host_state = nullptr;  // the no-allocation form's host copy of the state (else null)
+  const EditCfg* ed = nullptr;
+  const BoundsCfg* bc = nullptr;
+  bool no_alloc = false, rec = false;
+  unsigned long long* viol = nullptr;
+  int64_t vstr = 0;
+  uint32_t* smask = nullptr;
+  uint8_t* fmask = nullptr;
+  int chunk = 4;
 
-  auto fill = [&](int64_t b) {
-    StateInit si;
-    memset(&si, 0, sizeof(si));
-    si.E = inst[b].eps_s;
-    const double mu = mus ? mus[b] : 0.0;  // without mus, margin_kernel rewrites the mu-dependent fields
-    si.Ep = inst[b].eps_s * (1.0 - mu);
-    si.Delta = inst[b].delta_f;
-    spectral_thresholds(p.dt, inst[b].delta_f, mu, &si.Dc, &si.Dp);
-    si.inv_n = 1.0 / (double)p.N;
-    si.mu = mu;
-    if (ed && !ed->derive) {  // the encoder's given shrinks
-      si.mu = ed->mu_f;
-      si.mu_s = ed->mu_s;
-      si.Ep = inst[b].eps_s * (1.0 - ed->mu_s);
-      si.Dc = inst[b].delta_f * (1.0 - ed->mu_f);
-      si.Dp = inst[b].delta_f * (1.0 - 2.0 * ed->mu_f);
+  GroupRun() = default;
+  GroupRun(const GroupRun&) = delete;
+  GroupRun& operator=(const GroupRun&) = delete;
+
+  int32_t begin(const Plan& p0, const ffcz_instance* inst_, const double* mus_, int32_t max_iter_,
+                const ffcz_options& o_, char* ws, hipStream_t s, DevState* host_state_, const EditCfg* ed_,
+                const BoundsCfg* bc_) {
+    inst = inst_;
+    mus = mus_;
+    max_iter = max_iter_;
+    o = o_;
+    host_state = host_state_;
+    ed = ed_;
+    bc = bc_;
+    no_alloc = host_state != nullptr;
+    p = p0;
+    c = Ctx{&p, ws, s};
+    if (ed) {
+      c.sacc = ed->sacc;
+      c.facc = ed->facc;
     }
+    if (bc) c.pD = bc->pD;
+    const int64_t vstride = max_iter + 2;
+    const bool user_viol = o.viol_per_round && p.B == 1;
+    viol = user_viol ? (unsigned long long*)o.viol_per_round : c.viol();
+    vstr = user_viol ? 0 : vstride;
+    rec = o.masks_out != nullptr && p.B == 1;
+    smask = rec ? (uint32_t*)o.masks_out : nullptr;
+    fmask = rec ? (uint8_t*)o.masks_out + (size_t)(max_iter + 1) * p.s_plane_bytes : nullptr;
+    chunk = o.graph_chunk > 0 ? o.graph_chunk : 4;
+
+    auto fill = [&](int64_t b) {
+      StateInit si;
+      memset(&si, 0, sizeof(si));
+      si.E = inst[b].eps_s;
+      const double mu = mus ? mus[b] : 0.0;  // without mus, margin_kernel rewrites the mu-dependent fields
+      si.Ep = inst[b].eps_s * (1.0 - mu);
+      si.Delta = inst[b].delta_f;
+      spectral_thresholds(p.dt, inst[b].delta_f, mu, &si.Dc, &si.Dp);
+      si.inv_n = 1.0 / (double)p.N;
+      si.mu = mu;
+      if (ed && !ed->derive) {  // the encoder's given shrinks
+        si.mu = ed->mu_f;
+        si.mu_s = ed->mu_s;
+        si.Ep = inst[b].eps_s * (1.0 - ed->mu_s);
+        si.Dc = inst[b].delta_f * (1.0 - ed->mu_f);
+        si.Dp = inst[b].delta_f * (1.0 - 2.0 * ed->mu_f);
+      }
+      if (bc) {
+        si.pE = bc->pE;
+        si.pD = bc->pD;
+        si.disk = bc->disk;
+      }
+      si.max_iter = max_iter;
+      si.fixed = o.fixed_iterations ? 1 : 0;
+      si.record_masks = rec ? 1 : 0;
+      si.px = inst[b].x_orig;
+      si.pxb = inst[b].x_base;
+      si.py = inst[b].x_out;
+      return si;
+    };
+    const StateInit* arr = nullptr;
+    StateInit one = fill(0);
+    if (p.B > 1) {
+      HIPCHK(g_host_init.reserve(sizeof(StateInit) * p.B));
+      StateInit* h = (StateInit*)g_host_init.p;
+      for (int64_t b = 0; b < p.B; ++b) h[b] = fill(b);
+      arr = (const StateInit*)(ws + p.off_init);
+      HIPCHK(hipMemcpyAsync((void*)arr, h, sizeof(StateInit) * p.B, hipMemcpyHostToDevice, s));
+    }
+    const int64_t nviol = user_viol ? (int64_t)max_iter + 1 : vstride * p.B;
+    const int64_t nthr = std::max<int64_t>(p.B, nviol);
+    hipLaunchKernelGGL(state_init_kernel, dim3((unsigned)std::max<int64_t>(1, (nthr + 255) / 256)), dim3(256), 0, s,
+                       c.st(), p.B, arr, one, viol, nviol);
+    HIPCHK(hipGetLastError());
     if (bc) {
-      si.pE = bc->pE;
-      si.pD = bc->pD;
-      si.disk = bc->disk;
-    }
-    si.max_iter = max_iter;
-    si.fixed = o.fixed_iterations ? 1 : 0;
-    si.record_masks = rec ? 1 : 0;
-    si.px = inst[b].x_orig;
-    si.pxb = inst[b].x_base;
-    si.py = inst[b].x_out;
-    return si;
-  };
-  const StateInit* arr = nullptr;
-  StateInit one = fill(0);
-  if (p.B > 1) {
-    HIPCHK(g_host_init.reserve(sizeof(StateInit) * p.B));
-    StateInit* h = (StateInit*)g_host_init.p;
-    for (int64_t b = 0; b < p.B; ++b) h[b] = fill(b);
-    arr = (const StateInit*)(ws + p.off_init);
-    HIPCHK(hipMemcpyAsync((void*)arr, h, sizeof(StateInit) * p.B, hipMemcpyHostToDevice, s));
-  }
-  const int64_t nviol = user_viol ? (int64_t)max_iter + 1 : vstride * p.B;
-  const int64_t nthr = std::max<int64_t>(p.B, nviol);
-  hipLaunchKernelGGL(state_init_kernel, dim3((unsigned)std::max<int64_t>(1, (nthr + 255) / 256)), dim3(256), 0, s,
-                     c.st(), p.B, arr, one, viol, nviol);
-  HIPCHK(hipGetLastError());
-  if (bc) {
-    // the bound pairs into the spectrum layout, their checks and minimum, then mu and the factors
-    if (p.B != 1) return fail(FFCZ_E_INVALID, "pointwise bounds take one instance");
-    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, bc->bad, (int64_t)1);
-    HIPCHK(hipGetLastError());
-    const int64_t M = p.nrows * p.ncols;
-    const int nmin = (int)std::max<int64_t>(1, std::min<int64_t>(kMinSlots, (M + 255) / 256));
-    const SpecGeom g{p.nrows, (int32_t)p.ncols, p.lg_rpp, p.pitch, p.plane};
-    hipLaunchKernelGGL(bounds_setup_kernel<T>, dim3((unsigned)nmin), dim3(256), 0, s, (const T*)bc->dre,
-                       (const T*)bc->dim, bc->sre, bc->sim, (cx<T>*)bc->pD, M, g, bc->minpart, bc->bad);
-    HIPCHK(hipGetLastError());
-    if (bc->pE) {
-      const int nbe = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (p.N + 255) / 256));
-      hipLaunchKernelGGL(spatial_check_kernel<T>, dim3((unsigned)nbe), dim3(256), 0, s, (const T*)bc->pE, p.N,
-                         bc->bad);
+      // the bound pairs into the spectrum layout, their checks and minimum, then mu and the factors
+      if (p.B != 1) return fail(FFCZ_E_INVALID, "pointwise bounds take one instance");
+      hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, bc->bad, (int64_t)1);
       HIPCHK(hipGetLastError());
-    }
-    double* slots = (double*)(ws + p.off_ulp);
-    const double mu_given = mus ? mus[0] : 0.0;
-    if (p.dt == FFCZ_F32 && !(mu_given > 0.0)) {
-      const MarginJob one_job{(const float*)inst[0].x_orig, p.N, 0.0};
-      hipLaunchKernelGGL(ulp_part_kernel, dim3((unsigned)ulp_slots(p.N)), dim3(256), 0, s, one_job,
-                         (const MarginJob*)nullptr, slots);
+      const int64_t M = p.nrows * p.ncols;
+      const int nmin = (int)std::max<int64_t>(1, std::min<int64_t>(kMinSlots, (M + 255) / 256));
+      const SpecGeom g{p.nrows, (int32_t)p.ncols, p.lg_rpp, p.pitch, p.plane};
+      hipLaunchKernelGGL(bounds_setup_kernel<T>, dim3((unsigned)nmin), dim3(256), 0, s, (const T*)bc->dre,
+                         (const T*)bc->dim, bc->sre, bc->sim, (cx<T>*)bc->pD, M, g, bc->minpart, bc->bad);
       HIPCHK(hipGetLastError());
-    }
-    hipLaunchKernelGGL(bounds_margin_kernel, dim3(1), dim3(256), 0, s, (const double*)slots,
-                       (const unsigned long long*)bc->minpart, nmin, p.N, (int)p.dt, bc->disk, mu_given, c.st());
-    HIPCHK(hipGetLastError());
-    unsigned long long nbad = 0;
-    HIPCHK(hipMemcpyAsync(&nbad, bc->bad, sizeof(nbad), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (nbad) return fail(FFCZ_E_INVALID, "bound arrays must hold finite values >= 0 (" + std::to_string(nbad) +
-                                              " entries do not)");
-  } else if (ed && ed->derive) {
-    // the encoder's shrinks from x (ulp partials for the FP32 output margin, max |x|)
-    if (p.B != 1) return fail(FFCZ_E_INVALID, "the encoder takes one instance");
-    const int nsl = ulp_slots(p.N);
-    double* slots = (double*)(ws + p.off_ulp);
-    if (p.dt == FFCZ_F32) {
+      if (bc->pE) {
+        const int nbe = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (p.N + 255) / 256));
+        hipLaunchKernelGGL(spatial_check_kernel<T>, dim3((unsigned)nbe), dim3(256), 0, s, (const T*)bc->pE, p.N,
+                           bc->bad);
+        HIPCHK(hipGetLastError());
+      }
+      double* slots = (double*)(ws + p.off_ulp);
+      const double mu_given = mus ? mus[0] : 0.0;
+      if (p.dt == FFCZ_F32 && !(mu_given > 0.0)) {
+        const MarginJob one_job{(const float*)inst[0].x_orig, p.N, 0.0};
+        hipLaunchKernelGGL(ulp_part_kernel, dim3((unsigned)ulp_slots(p.N)), dim3(256), 0, s, one_job,
+                           (const MarginJob*)nullptr, slots);
+        HIPCHK(hipGetLastError());
+      }
+      hipLaunchKernelGGL(bounds_margin_kernel, dim3(1), dim3(256), 0, s, (const double*)slots,
+                         (const unsigned long long*)bc->minpart, nmin, p.N, (int)p.dt, bc->disk, mu_given, c.st());
+      HIPCHK(hipGetLastError());
+      unsigned long long nbad = 0;
+      HIPCHK(hipMemcpyAsync(&nbad, bc->bad, sizeof(nbad), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (nbad) return fail(FFCZ_E_INVALID, "bound arrays must hold finite values >= 0 (" + std::to_string(nbad) +
+                                                " entries do not)");
+    } else if (ed && ed->derive) {
+      // the encoder's shrinks from x (ulp partials for the FP32 output margin, max |x|)
+      if (p.B != 1) return fail(FFCZ_E_INVALID, "the encoder takes one instance");
+      const int nsl = ulp_slots(p.N);
+      double* slots = (double*)(ws + p.off_ulp);
+      if (p.dt == FFCZ_F32) {
+        const MarginJob one_job{(const float*)inst[0].x_orig, p.N, inst[0].delta_f};
+        hipLaunchKernelGGL(ulp_part_kernel, dim3((unsigned)nsl), dim3(256), 0, s, one_job, (const MarginJob*)nullptr,
+                           slots);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(absmax_part_kernel<float>, dim3((unsigned)nsl), dim3(256), 0, s,
+                           (const float*)inst[0].x_orig, p.N, ed->amax);
+      } else {
+        hipLaunchKernelGGL(absmax_part_kernel<double>, dim3((unsigned)nsl), dim3(256), 0, s,
+                           (const double*)inst[0].x_orig, p.N, ed->amax);
+      }
+      HIPCHK(hipGetLastError());
+      hipLaunchKernelGGL(encode_margin_kernel, dim3(1), dim3(256), 0, s, (const double*)slots,
+                         (const unsigned long long*)ed->amax, p.N, (int)p.dt, ed->q, c.st());
+      HIPCHK(hipGetLastError());
+    } else if (!mus) {
+      if (p.B != 1 || p.dt != FFCZ_F32) return fail(FFCZ_E_INVALID, "device margin needs one FP32 instance");
+      const int nsl = ulp_slots(p.N);
+      double* slots = (double*)(ws + p.off_ulp);
       const MarginJob one_job{(const float*)inst[0].x_orig, p.N, inst[0].delta_f};
       hipLaunchKernelGGL(ulp_part_kernel, dim3((unsigned)nsl), dim3(256), 0, s, one_job, (const MarginJob*)nullptr,
                          slots);
       HIPCHK(hipGetLastError());
-      hipLaunchKernelGGL(absmax_part_kernel<float>, dim3((unsigned)nsl), dim3(256), 0, s,
-                         (const float*)inst[0].x_orig, p.N, ed->amax);
-    } else {
-      hipLaunchKernelGGL(absmax_part_kernel<double>, dim3((unsigned)nsl), dim3(256), 0, s,
-                         (const double*)inst[0].x_orig, p.N, ed->amax);
+      hipLaunchKernelGGL(margin_kernel, dim3(1), dim3(256), 0, s, (const double*)slots, one_job,
+                         (const MarginJob*)nullptr, (int)p.dt, (double*)nullptr, c.st());
+      HIPCHK(hipGetLastError());
     }
-    HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(encode_margin_kernel, dim3(1), dim3(256), 0, s, (const double*)slots,
-                       (const unsigned long long*)ed->amax, p.N, (int)p.dt, ed->q, c.st());
-    HIPCHK(hipGetLastError());
-  } else if (!mus) {
-    if (p.B != 1 || p.dt != FFCZ_F32) return fail(FFCZ_E_INVALID, "device margin needs one FP32 instance");
-    const int nsl = ulp_slots(p.N);
-    double* slots = (double*)(ws + p.off_ulp);
-    const MarginJob one_job{(const float*)inst[0].x_orig, p.N, inst[0].delta_f};
-    hipLaunchKernelGGL(ulp_part_kernel, dim3((unsigned)nsl), dim3(256), 0, s, one_job, (const MarginJob*)nullptr,
-                       slots);
-    HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(margin_kernel, dim3(1), dim3(256), 0, s, (const double*)slots, one_job,
-                       (const MarginJob*)nullptr, (int)p.dt, (double*)nullptr, c.st());
-    HIPCHK(hipGetLastError());
+    HIPCHK(write_twiddles(c));
+    if (bc) {
+      set_variants(p, 0, 0, 0);  // the pointwise passes exist for the default tiles only
+    } else if (ed) {
+      // edit bookkeeping runs on the default tiles; the frequency accumulators start at zero
+      set_variants(p, 0, 0, 0);
+      const int64_t nr = edit_layout(p).spec_reals;
+      hipLaunchKernelGGL(zero_fill_kernel<T>, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, (T*)ed->facc, nr);
+      HIPCHK(hipGetLastError());
+    } else {
+      const int32_t tr = tune_plan<T>(p, ws, s, rec, no_alloc);
+      if (tr != FFCZ_OK) return tr;
+    }
+    HIPCHK(timed(PK_INIT, -1, s, [&] { return row_T<T>(ROW_INIT, c, nullptr, c.Z(), smask); }));
+    return FFCZ_OK;
   }
-  HIPCHK(write_twiddles(c));
-  if (bc) {
-    set_variants(p, 0, 0, 0);  // the pointwise passes exist for the default tiles only
-  } else if (ed) {
-    // edit bookkeeping runs on the default tiles; the frequency accumulators start at zero
-    set_variants(p, 0, 0, 0);
-    const int64_t nr = edit_layout(p).spec_reals;
-    hipLaunchKernelGGL(zero_fill_kernel<T>, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, (T*)ed->facc, nr);
-    HIPCHK(hipGetLastError());
-  } else {
-    const int32_t tr = tune_plan<T>(p, ws, s, rec, no_alloc);
-    if (tr != FFCZ_OK) return tr;
-  }
-  HIPCHK(timed(PK_INIT, -1, s, [&] { return row_T<T>(ROW_INIT, c, nullptr, c.Z(), smask); }));
 
-  const int chunk = o.graph_chunk > 0 ? o.graph_chunk : 4;
-  if (!no_alloc) HIPCHK(g_host_state.reserve(sizeof(DevState) * p.B));
-  DevState* hs = no_alloc ? host_state : (DevState*)g_host_state.p;
-  int enq = 0;
-  // asynchronous only when nothing is reported: fixed rounds, no statistics, no verification
-  const bool sync_needed = !(o.fixed_iterations && stats == nullptr && !o.verify_fp64);
-  if (o.fixed_iterations) {
-    // exactly max_iter blocks plus the final check: no polling needed
-    for (int r = 0; r <= max_iter; ++r) HIPCHK(enqueue_round<T>(c, r, viol, vstr, fmask, smask));
-  } else {
-    // a chunk of rounds, captured once in a hipGraph (unless per-launch timing is on)
+  // One chunk of rounds on st (the round passes return at entry once the instance is done).
+  hipError_t enqueue_chunk(hipStream_t st) const {
+    Ctx cc{&p, c.ws, st};
+    cc.sacc = c.sacc;
+    cc.facc = c.facc;
+    cc.pD = c.pD;
+    for (int r = 0; r < chunk; ++r) {
+      const hipError_t e = enqueue_round<T>(cc, r, viol, vstr, fmask, smask);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+
+  // Everything a captured chunk bakes in.
+  GraphKey graph_key() const {
+    return GraphKey{{(int64_t)p.dt, p.nd, p.B, p.n[0], p.n[1], p.n[2], (int64_t)(uintptr_t)c.ws,
+                     (int64_t)(uintptr_t)viol, vstr, (int64_t)(uintptr_t)fmask, (int64_t)(uintptr_t)smask, chunk,
+                     max_iter, p.vy, p.vx, p.vz, (int64_t)(uintptr_t)c.sacc, (int64_t)(uintptr_t)c.facc,
+                     (int64_t)(uintptr_t)c.pD}};
+  }
+
+  // The host copy of the instances' states (the no-allocation form brings its own).
+  int32_t host_states(DevState** hs) {
+    if (!no_alloc) HIPCHK(g_host_state.reserve(sizeof(DevState) * p.B));
+    *hs = no_alloc ? host_state : (DevState*)g_host_state.p;
+    return FFCZ_OK;
+  }
+
+  // The rounds, driven from here: fixed rounds enqueued at once, else chunks (captured once in
+  // a hipGraph unless per-launch timing is on) with one poll of the done-flags per chunk.
+  int32_t loop() {
+    const hipStream_t s = c.s;
+    DevState* hs = nullptr;
+    int32_t hr = host_states(&hs);
+    if (hr != FFCZ_OK) return hr;
+    if (o.fixed_iterations) {
+      // exactly max_iter blocks plus the final check: no polling needed
+      for (int r = 0; r <= max_iter; ++r) HIPCHK(enqueue_round<T>(c, r, viol, vstr, fmask, smask));
+      return FFCZ_OK;
+    }
     hipGraphExec_t gexec = nullptr;
     if (o.use_graph && !g_prof.on && !no_alloc) {
-      GraphKey key{{(int64_t)p.dt, p.nd, p.B, p.n[0], p.n[1], p.n[2], (int64_t)(uintptr_t)ws, (int64_t)(uintptr_t)viol,
-                    vstr, (int64_t)(uintptr_t)fmask, (int64_t)(uintptr_t)smask, chunk, max_iter, p.vy, p.vx, p.vz,
-                    (int64_t)(uintptr_t)c.sacc, (int64_t)(uintptr_t)c.facc, (int64_t)(uintptr_t)c.pD}};
+      const GraphKey key = graph_key();
       gexec = g_graphs.find(key);
       if (!gexec) {
         HIPCHK(g_streams.ready());
-        Ctx cc{&p, ws, g_streams.cap};
-        cc.sacc = c.sacc;
-        cc.facc = c.facc;
-        cc.pD = c.pD;
         HIPCHK(hipStreamBeginCapture(g_streams.cap, hipStreamCaptureModeThreadLocal));
-        hipError_t ce = hipSuccess;
-        for (int r = 0; r < chunk && ce == hipSuccess; ++r) ce = enqueue_round<T>(cc, r, viol, vstr, fmask, smask);
+        const hipError_t ce = enqueue_chunk(g_streams.cap);
         hipGraph_t graph = nullptr;
-        hipError_t ee = hipStreamEndCapture(g_streams.cap, &graph);
+        const hipError_t ee = hipStreamEndCapture(g_streams.cap, &graph);
         if (ce != hipSuccess) {
           if (graph) (void)hipGraphDestroy(graph);
           return fail(FFCZ_E_HIP, std::string("capture: ") + hipGetErrorString(ce));
         }
         HIPCHK(ee);
-        hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+        const hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         HIPCHK(ie);
         g_graphs.put(key, gexec);
       }
     }
-    for (;;) {
+    for (int enq = 0;;) {
       if (gexec) HIPCHK(hipGraphLaunch(gexec, s));
       else
         for (int r = 0; r < chunk; ++r) HIPCHK(enqueue_round<T>(c, enq + r, viol, vstr, fmask, smask));
@@ -1720,46 +1786,70 @@ int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* m
       if (enq > max_iter + 2 * chunk + 2)
         return fail(FFCZ_E_HIP, "loop did not report completion (device state inconsistent)");
     }
-  }
-  if (ed) HIPCHK(enqueue_undo<T>(c));
-  if (!ed || ed->want_y) HIPCHK(enqueue_final<T>(c, o.verify_fp64 != 0));
-  if (!sync_needed) {
-    prof_settle(max_iter);
-    for (int64_t b = 0; b < p.B; ++b) status[b] = FFCZ_OK;
     return FFCZ_OK;
   }
-  HIPCHK(hipMemcpyAsync(hs, c.st(), sizeof(DevState) * p.B, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  int maxr = 0;
-  for (int64_t b = 0; b < p.B; ++b) maxr = std::max(maxr, hs[b].round);
-  prof_settle(maxr);
-  if (ed && ed->mu_s_out) *ed->mu_s_out = hs[0].mu_s;
-  for (int64_t b = 0; b < p.B; ++b) {
-    const DevState& h = hs[b];
-    const double ms = bits_to_double(h.max_spatial_bits), mf = bits_to_double(h.max_spectral_bits);
-    if (stats) {
-      ffcz_stats& st = stats[b];
-      memset(&st, 0, sizeof(st));
-      st.rounds = h.round;
-      st.converged = h.converged;
-      st.f_viol_initial = (int64_t)h.v_first;
-      st.f_viol_final = (int64_t)h.v_last;
-      st.s_clipped_total = (int64_t)h.s_clipped_total;
-      st.s_guard = (int64_t)h.s_guard;
-      st.nonfinite = (int64_t)h.nonfinite;
-      st.max_spatial_err = o.verify_fp64 ? ms : NAN;
-      st.max_spectral_err = o.verify_fp64 ? mf : NAN;
-      st.spectral_viol = (int64_t)h.spectral_viol;
-      st.margin_used = h.mu;
+
+  // After the rounds: the closing pass and verification, then (unless nothing is reported)
+  // the instances' statistics and statuses.
+  int32_t end(ffcz_stats* stats, int32_t* status) {
+    DevState* hs = nullptr;
+    int32_t hr = host_states(&hs);
+    if (hr != FFCZ_OK) return hr;
+    // asynchronous only when nothing is reported: fixed rounds, no statistics, no verification
+    const bool sync_needed = !(o.fixed_iterations && stats == nullptr && !o.verify_fp64);
+    if (ed) HIPCHK(enqueue_undo<T>(c));
+    if (!ed || ed->want_y) HIPCHK(enqueue_final<T>(c, o.verify_fp64 != 0));
+    if (!sync_needed) {
+      prof_settle(max_iter);
+      for (int64_t b = 0; b < p.B; ++b) status[b] = FFCZ_OK;
+      return FFCZ_OK;
     }
-    int32_t r = FFCZ_OK;
-    if (h.nonfinite) r = FFCZ_E_NONFINITE;
-    else if (!h.converged && !o.fixed_iterations) r = FFCZ_NOT_CONVERGED;
-    else if (o.verify_fp64 && bc && (!(ms <= 1.0) || !(mf <= 1.0) || h.spectral_viol)) r = FFCZ_VERIFY_FAILED;
-    else if (o.verify_fp64 && !bc && (!(ms <= inst[b].eps_s) || !(mf <= inst[b].delta_f))) r = FFCZ_VERIFY_FAILED;
-    status[b] = r;
+    HIPCHK(hipMemcpyAsync(hs, c.st(), sizeof(DevState) * p.B, hipMemcpyDeviceToHost, c.s));
+    HIPCHK(hipStreamSynchronize(c.s));
+    int maxr = 0;
+    for (int64_t b = 0; b < p.B; ++b) maxr = std::max(maxr, hs[b].round);
+    prof_settle(maxr);
+    if (ed && ed->mu_s_out) *ed->mu_s_out = hs[0].mu_s;
+    for (int64_t b = 0; b < p.B; ++b) {
+      const DevState& h = hs[b];
+      const double ms = bits_to_double(h.max_spatial_bits), mf = bits_to_double(h.max_spectral_bits);
+      if (stats) {
+        ffcz_stats& st = stats[b];
+        memset(&st, 0, sizeof(st));
+        st.rounds = h.round;
+        st.converged = h.converged;
+        st.f_viol_initial = (int64_t)h.v_first;
+        st.f_viol_final = (int64_t)h.v_last;
+        st.s_clipped_total = (int64_t)h.s_clipped_total;
+        st.s_guard = (int64_t)h.s_guard;
+        st.nonfinite = (int64_t)h.nonfinite;
+        st.max_spatial_err = o.verify_fp64 ? ms : NAN;
+        st.max_spectral_err = o.verify_fp64 ? mf : NAN;
+        st.spectral_viol = (int64_t)h.spectral_viol;
+        st.margin_used = h.mu;
+      }
+      int32_t r = FFCZ_OK;
+      if (h.nonfinite) r = FFCZ_E_NONFINITE;
+      else if (!h.converged && !o.fixed_iterations) r = FFCZ_NOT_CONVERGED;
+      else if (o.verify_fp64 && bc && (!(ms <= 1.0) || !(mf <= 1.0) || h.spectral_viol)) r = FFCZ_VERIFY_FAILED;
+      else if (o.verify_fp64 && !bc && (!(ms <= inst[b].eps_s) || !(mf <= inst[b].delta_f))) r = FFCZ_VERIFY_FAILED;
+      status[b] = r;
+    }
+    return FFCZ_OK;
   }
-  return FFCZ_OK;
+};
+
+template <typename T>
+int32_t correct_group(const Plan& p0, const ffcz_instance* inst, const double* mus, int32_t max_iter,
+                      const ffcz_options& o, char* ws, hipStream_t s, ffcz_stats* stats, int32_t* status,
+                      DevState* host_state = nullptr, const EditCfg* ed = nullptr,
+                      const BoundsCfg* bc = nullptr) {
+  GroupRun<T> g;
+  int32_t r = g.begin(p0, inst, mus, max_iter, o, ws, s, host_state, ed, bc);
+  if (r != FFCZ_OK) return r;
+  r = g.loop();
+  if (r != FFCZ_OK) return r;
+  return g.end(stats, status);
 }
 
 template <typename T>
@@ -1932,11 +2022,6 @@ hipError_t write_mc_tabs(int dt, int lgMc, char* base, const McTabs& t, hipStrea
 }
 
 // Layout of the batched workspace
-// Length classes from 2^this (work length Mc) up run as tiled passes, many blocks per
-// signal; shorter ones run one block per signal.
-int sig_tiled_from_lg(const ffcz_options& o) {
-  return o.tiled_1d_lg > 0 ? std::max(kSigTiledMinLg, (int)o.tiled_1d_lg) : 15;
-}
 
 struct BatchPlan {
   int dt = 0;
@@ -2170,10 +2255,11 @@ hipError_t sig_launch(int dt, int mode, int lgMc, const BatchPlan& bp, char* ws,
   return launch_sig(dt, mode, lgMc, &a, nsig, s);
 }
 
-int32_t run_sigs(const BatchPlan& bp, const ffcz_instance* inst, const double* mus, int32_t max_iter,
-                 const ffcz_options& o, char* ws, hipStream_t s, HostBuf& hsig, HostBuf& hstate) {
+// Descriptors (bounds, thresholds, buffer addresses) and block order of the 1D members, and
+// the four-step tables of every length class; first[lg] is the class's first slot in the order.
+int32_t sig_prepare(const BatchPlan& bp, const ffcz_instance* inst, const double* mus, char* ws, hipStream_t s,
+                    HostBuf& hsig, std::map<int, int>& first) {
   const int ns = (int)bp.sig_ids.size();
-  if (ns == 0) return FFCZ_OK;
   // own staging buffer: the grouped members reuse g_host_init while these copies may be in flight
   HIPCHK(hsig.reserve(sizeof(SigDesc) * ns + sizeof(int32_t) * ns));
   SigDesc* hd = (SigDesc*)hsig.p;
@@ -2206,7 +2292,7 @@ int32_t run_sigs(const BatchPlan& bp, const ffcz_instance* inst, const double* m
   }
   // block order per convolution length: larger signals first
   int pos = 0;
-  std::map<int, int> first;
+  first.clear();
   for (auto& kv : bp.by_mc) {
     std::vector<int> ids = kv.second;
     std::sort(ids.begin(), ids.end(), [&](int a, int b) { return bp.sigs[a].L > bp.sigs[b].L; });
@@ -2217,92 +2303,340 @@ int32_t run_sigs(const BatchPlan& bp, const ffcz_instance* inst, const double* m
   HIPCHK(hipMemcpyAsync(ws + bp.off_order, ho, sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
   for (auto& kv : bp.by_mc)
     HIPCHK(write_mc_tabs(bp.dt, kv.first, ws + bp.mc_off.at(kv.first), bp.mc_tab.at(kv.first), s));
-  const int32_t* order = (const int32_t*)(ws + bp.off_order);
+  return FFCZ_OK;
+}
+
+// One-block or tiled for a length class.  A threshold given in the options decides alone;
+// otherwise classes below 2^kSigTiledMinLg run one block per signal, classes above 2^16 run
+// tiled, and the ones between take the tuner's decision for (architecture, data type, work
+// length, power-of-two bucket of the class's signal count, kinds of length): variant 0 is the
+// default rule (tiled from 2^15), variant 1 the other form.
+constexpr int kSigTuneMaxLg = 16;
+std::string sig_tune_key(const BatchPlan& bp, int lg) {
+  const std::vector<int>& ids = bp.by_mc.at(lg);
+  int n = 1;
+  while (n < (int)ids.size()) n <<= 1;
+  bool blue = false, p2 = false;
+  for (int k : ids) (bp.sigs[k].blue ? blue : p2) = true;
+  char buf[160];
+  snprintf(buf, sizeof(buf), "%s %s sig lg=%d n<=%d kinds=%s%s", device_arch().c_str(),
+           bp.dt == FFCZ_F32 ? "f32" : "f64", lg, n, blue ? "b" : "", p2 ? "p" : "");
+  return buf;
+}
+bool sig_default_tiled(int lg) { return lg >= 15; }
+
+// The decision for class lg without timing (the table's entry, else the default rule).
+int32_t sig_class_tiled(const BatchPlan& bp, const ffcz_options& o, int lg, hipStream_t s, bool* tiled) {
+  if (o.tiled_1d_lg > 0) {
+    *tiled = lg >= std::max(kSigTiledMinLg, (int)o.tiled_1d_lg);
+    return FFCZ_OK;
+  }
+  if (lg < kSigTiledMinLg || lg > kSigTuneMaxLg) {
+    *tiled = lg >= kSigTiledMinLg;
+    return FFCZ_OK;
+  }
+  int v = 0;
+  int32_t r = tune_pass(sig_tune_key(bp, lg), s, false, 0.9f, 2, [](int) { return hipSuccess; }, &v);
+  if (r != FFCZ_OK) return r;
+  *tiled = sig_default_tiled(lg) != (v == 1);
+  return FFCZ_OK;
+}
+
+// A class's correction with a fixed number of rounds and no verification, one-block or tiled:
+// the timing run of the tuner (writes the members' outputs, which the real run rewrites).
+template <typename T>
+hipError_t sig_trial(const BatchPlan& bp, char* ws, const int32_t* ord, int lg, bool tiled, bool resident,
+                     int rounds, hipStream_t s) {
+  const int nb = (int)bp.by_mc.at(lg).size();
+  const int ns = (int)bp.sig_ids.size();
+  auto go = [&](int mode) -> hipError_t {
+    if (sig_mode_fp64(mode, bp.dt)) return sig_launch<double>(bp.dt, mode, lg, bp, ws, ord, nb, rounds, 1, s);
+    return sig_launch<T>(bp.dt, mode, lg, bp, ws, ord, nb, rounds, 1, s);
+  };
   hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)((ns * sizeof(SigStats) / 8 + 255) / 256)), dim3(256), 0, s,
                      (unsigned long long*)(ws + bp.off_sstats), (int64_t)(ns * sizeof(SigStats) / 8));
-  HIPCHK(hipGetLastError());
-  const int fixed = o.fixed_iterations ? 1 : 0;
-  // a launch of one mode over every signal of class lg, in the mode's arithmetic
-  auto go = [&](int mode, int lg) -> hipError_t {
-    const int nb = (int)bp.by_mc.at(lg).size();
-    const int32_t* ord = order + first[lg];
-    if (sig_mode_fp64(mode, bp.dt)) return sig_launch<double>(bp.dt, mode, lg, bp, ws, ord, nb, max_iter, fixed, s);
-    return sig_launch<float>(bp.dt, mode, lg, bp, ws, ord, nb, max_iter, fixed, s);
-  };
-  std::vector<int> tiled;
-  std::map<int, std::pair<bool, bool>> kinds;  // class -> (has Bluestein lengths, has power-of-two lengths)
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (!tiled) {
+    if ((e = go(SIG_SETUP)) != hipSuccess) return e;
+    return go(resident && sig_res_fits(bp.dt, lg) ? SIG_RUNL : SIG_RUN);
+  }
+  bool blue = false, p2 = false;
+  for (int k : bp.by_mc.at(lg)) (bp.sigs[k].blue ? blue : p2) = true;
+  if (blue)
+    for (int m : {(int)SIGT_CHIRP, (int)SIGT_BCOL, (int)SIGT_BROW})
+      if ((e = go(m)) != hipSuccess) return e;
+  if ((e = go(SIGT_EPS0)) != hipSuccess) return e;
+  if ((e = go(SIGT_CIN)) != hipSuccess) return e;
+  int nct = 0, nrt = 0;
+  sig_tiles(lg, &nct, &nrt);
+  for (int r = 0; r <= rounds; ++r) {  // fixed rounds: the control stops the loop at the last check
+    if (blue && (e = go(SIGT_RMUL)) != hipSuccess) return e;
+    if (p2 && (e = go(SIGT_RCHECK)) != hipSuccess) return e;
+    if (blue && (e = go(SIGT_CCHECK)) != hipSuccess) return e;
+    hipLaunchKernelGGL(sig_ctl_kernel, dim3((unsigned)nb), dim3(256), 0, s, (const SigDesc*)(ws + bp.off_desc),
+                       (SigStats*)(ws + bp.off_sstats), ord, (const unsigned long long*)(ws + bp.tpart_off.at(lg)),
+                       (int32_t)nb, (int32_t)bp.tpart_tiles.at(lg), (int32_t)nct, (int32_t)nrt, (int32_t)rounds,
+                       (int32_t)1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (blue && (e = go(SIGT_RMUL)) != hipSuccess) return e;
+    if ((e = go(SIGT_CSPAT)) != hipSuccess) return e;
+  }
+  return go(SIGT_Y);
+}
+
+// Time both forms of every class the tuner decides and has no entry for, on the call's own
+// members (three fixed rounds each, before the real run; nothing else runs meanwhile).
+int32_t pretune_sigs(const BatchPlan& bp, const ffcz_instance* inst, const double* mus, const ffcz_options& o,
+                     char* ws, hipStream_t s, HostBuf& hsig) {
+  if (bp.sig_ids.empty() || o.tiled_1d_lg > 0) return FFCZ_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIPCHK(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone) return FFCZ_OK;  // nothing is timed under capture
+  std::map<int, int> first;
+  bool prepared = false;
   for (auto& kv : bp.by_mc) {
     const int lg = kv.first;
-    if (lg >= sig_tiled_from_lg(o)) {
-      tiled.push_back(lg);
-      bool b = false, p2 = false;
-      for (int k : kv.second) (bp.sigs[k].blue ? b : p2) = true;
-      kinds[lg] = {b, p2};
-      continue;
+    if (lg < kSigTiledMinLg || lg > kSigTuneMaxLg) continue;
+    if (!prepared) {
+      int32_t r = sig_prepare(bp, inst, mus, ws, s, hsig, first);
+      if (r != FFCZ_OK) return r;
+      prepared = true;
     }
-    HIPCHK(go(SIG_SETUP, lg));
-    HIPCHK(go(SIG_RUN, lg));
-    if (o.verify_fp64) HIPCHK(go(SIG_VERIFY, lg));
-  }
-  if (tiled.empty()) return FFCZ_OK;
-
-  // tiled classes: set-up, eps0 and the first forward column pass
-  for (int lg : tiled) {
-    if (kinds[lg].first) {
-      HIPCHK(go(SIGT_CHIRP, lg));
-      HIPCHK(go(SIGT_BCOL, lg));
-      HIPCHK(go(SIGT_BROW, lg));
-    }
-    HIPCHK(go(SIGT_EPS0, lg));
-    HIPCHK(go(SIGT_CIN, lg));
-  }
-  // rounds in chunks; every round pass returns at entry once its signal's loop has ended
-  const int chunk = o.graph_chunk > 0 ? o.graph_chunk : 4;
-  HIPCHK(hstate.reserve(sizeof(SigStats) * ns));
-  SigStats* hs = (SigStats*)hstate.p;
-  for (int enq = 0;; enq += chunk) {
-    for (int r = 0; r < chunk; ++r) {
-      for (int lg : tiled) {
-        const bool b = kinds[lg].first, p2 = kinds[lg].second;
-        if (b) HIPCHK(go(SIGT_RMUL, lg));
-        if (p2) HIPCHK(go(SIGT_RCHECK, lg));
-        if (b) HIPCHK(go(SIGT_CCHECK, lg));
-        int nct = 0, nrt = 0;
-        sig_tiles(lg, &nct, &nrt);
-        const int nb = (int)bp.by_mc.at(lg).size();
-        hipLaunchKernelGGL(sig_ctl_kernel, dim3((unsigned)nb), dim3(256), 0, s, (const SigDesc*)(ws + bp.off_desc),
-                           (SigStats*)(ws + bp.off_sstats), order + first[lg],
-                           (const unsigned long long*)(ws + bp.tpart_off.at(lg)), (int32_t)nb,
-                           (int32_t)bp.tpart_tiles.at(lg), (int32_t)nct, (int32_t)nrt, max_iter, (int32_t)fixed);
-        HIPCHK(hipGetLastError());
-        if (b) HIPCHK(go(SIGT_RMUL, lg));
-        HIPCHK(go(SIGT_CSPAT, lg));
-      }
-    }
-    HIPCHK(hipMemcpyAsync(hs, ws + bp.off_sstats, sizeof(SigStats) * ns, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    bool all = true;
-    for (int lg : tiled)
-      for (int k : bp.by_mc.at(lg)) all = all && hs[k].done;
-    if (all) break;
-    if (enq > max_iter + 2 * chunk + 2) return fail(FFCZ_E_HIP, "tiled signals did not report completion");
-  }
-  for (int lg : tiled) {
-    HIPCHK(go(SIGT_Y, lg));
-    if (!o.verify_fp64) continue;
-    HIPCHK(go(SIGT_VCOL, lg));
-    HIPCHK(go(SIGT_VROW, lg));
-    if (kinds[lg].first) HIPCHK(go(SIGT_VCOL2, lg));
-    int nct = 0, nrt = 0;
-    sig_tiles(lg, &nct, &nrt);
-    const int nb = (int)bp.by_mc.at(lg).size();
-    hipLaunchKernelGGL(sig_vstats_kernel, dim3((unsigned)nb), dim3(256), 0, s, (const SigDesc*)(ws + bp.off_desc),
-                       (SigStats*)(ws + bp.off_sstats), order + first[lg],
-                       (const unsigned long long*)(ws + bp.tpart_off.at(lg)), (int32_t)nb,
-                       (int32_t)bp.tpart_tiles.at(lg), (int32_t)nct, (int32_t)nrt);
-    HIPCHK(hipGetLastError());
+    const int32_t* ord = (const int32_t*)(ws + bp.off_order) + first[lg];
+    const bool dflt = sig_default_tiled(lg);
+    int v = 0;
+    int32_t r = tune_pass(sig_tune_key(bp, lg), s, true, 0.9f, 2, [&](int var) {
+      const bool tiled = dflt != (var == 1);
+      return bp.dt == FFCZ_F32 ? sig_trial<float>(bp, ws, ord, lg, tiled, o.resident_1d != 0, 3, s)
+                               : sig_trial<double>(bp, ws, ord, lg, tiled, o.resident_1d != 0, 3, s);
+    }, &v);
+    if (r != FFCZ_OK) return r;
   }
   return FFCZ_OK;
+}
+
+// The 1D members of a batch in phases: begin (descriptors and tables, the one-block classes on
+// their own stream, the tiled classes' set-up), the tiled rounds in chunks (run here, or
+// captured with the groups' rounds by the mixed-batch loop), end (the tiled classes' outputs and
+// verification, then the one-block stream joined).  Every tiled round pass returns at entry once
+// its signal's loop has ended.
+struct SigRun {
+  const BatchPlan* bp = nullptr;
+  const ffcz_instance* inst = nullptr;
+  const double* mus = nullptr;
+  int32_t max_iter = 0;
+  ffcz_options o{};
+  char* ws = nullptr;
+  hipStream_t s = nullptr;       // set-up, tiled passes, end
+  hipStream_t side = nullptr;    // one-block classes (joined into s at the end)
+  hipEvent_t fork = nullptr, join = nullptr;
+  std::map<int, int> first;      // class -> first slot in the block order
+  std::vector<int> tiled;
+  std::map<int, std::pair<bool, bool>> kinds;  // class -> (has Bluestein lengths, has power-of-two lengths)
+  int fixed = 0, chunk = 4;
+  bool side_used = false;
+
+  const int32_t* order() const { return (const int32_t*)(ws + bp->off_order); }
+  int nsig() const { return (int)bp->sig_ids.size(); }
+
+  // a launch of one mode over every signal of class lg, in the mode's arithmetic, on st
+  hipError_t go(int mode, int lg, hipStream_t st) const {
+    const int nb = (int)bp->by_mc.at(lg).size();
+    const int32_t* ord = order() + first.at(lg);
+    if (sig_mode_fp64(mode, bp->dt)) return sig_launch<double>(bp->dt, mode, lg, *bp, ws, ord, nb, max_iter, fixed, st);
+    return sig_launch<float>(bp->dt, mode, lg, *bp, ws, ord, nb, max_iter, fixed, st);
+  }
+
+  int32_t begin(const BatchPlan& bp_, const ffcz_instance* inst_, const double* mus_, int32_t max_iter_,
+                const ffcz_options& o_, char* ws_, hipStream_t s_, hipStream_t side_, hipEvent_t fork_,
+                hipEvent_t join_, HostBuf& hsig) {
+    bp = &bp_;
+    inst = inst_;
+    mus = mus_;
+    max_iter = max_iter_;
+    o = o_;
+    ws = ws_;
+    s = s_;
+    side = side_;
+    fork = fork_;
+    join = join_;
+    fixed = o.fixed_iterations ? 1 : 0;
+    chunk = o.graph_chunk > 0 ? o.graph_chunk : 4;
+    const int ns = nsig();
+    if (ns == 0) return FFCZ_OK;
+    int32_t pr = sig_prepare(*bp, inst, mus, ws, s, hsig, first);
+    if (pr != FFCZ_OK) return pr;
+    hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)((ns * sizeof(SigStats) / 8 + 255) / 256)), dim3(256), 0, s,
+                       (unsigned long long*)(ws + bp->off_sstats), (int64_t)(ns * sizeof(SigStats) / 8));
+    HIPCHK(hipGetLastError());
+    std::vector<int> oneblock;
+    for (auto& kv : bp->by_mc) {
+      const int lg = kv.first;
+      bool is_tiled = false;
+      int32_t tr = sig_class_tiled(*bp, o, lg, s, &is_tiled);
+      if (tr != FFCZ_OK) return tr;
+      if (!is_tiled) {
+        oneblock.push_back(lg);
+        continue;
+      }
+      tiled.push_back(lg);
+      bool b = false, p2 = false;
+      for (int k : kv.second) (bp->sigs[k].blue ? b : p2) = true;
+      kinds[lg] = {b, p2};
+    }
+    // the one-block classes run their whole correction beside the tiled rounds
+    hipStream_t sb = s;
+    if (!oneblock.empty() && !tiled.empty() && side) {
+      HIPCHK(hipEventRecord(fork, s));
+      HIPCHK(hipStreamWaitEvent(side, fork, 0));
+      sb = side;
+      side_used = true;
+    }
+    for (int lg : oneblock) {
+      HIPCHK(go(SIG_SETUP, lg, sb));
+      HIPCHK(go(o.resident_1d && sig_res_fits(bp->dt, lg) ? SIG_RUNL : SIG_RUN, lg, sb));
+      if (o.verify_fp64) HIPCHK(go(SIG_VERIFY, lg, sb));
+    }
+    // tiled classes: set-up, eps0 and the first forward column pass
+    for (int lg : tiled) {
+      if (kinds[lg].first) {
+        HIPCHK(go(SIGT_CHIRP, lg, s));
+        HIPCHK(go(SIGT_BCOL, lg, s));
+        HIPCHK(go(SIGT_BROW, lg, s));
+      }
+      HIPCHK(go(SIGT_EPS0, lg, s));
+      HIPCHK(go(SIGT_CIN, lg, s));
+    }
+    return FFCZ_OK;
+  }
+
+  // one chunk of rounds of every tiled class, on st
+  hipError_t enqueue_chunk(hipStream_t st) const {
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < chunk && e == hipSuccess; ++r) {
+      for (int lg : tiled) {
+        const bool b = kinds.at(lg).first, p2 = kinds.at(lg).second;
+        if (b && (e = go(SIGT_RMUL, lg, st)) != hipSuccess) return e;
+        if (p2 && (e = go(SIGT_RCHECK, lg, st)) != hipSuccess) return e;
+        if (b && (e = go(SIGT_CCHECK, lg, st)) != hipSuccess) return e;
+        int nct = 0, nrt = 0;
+        sig_tiles(lg, &nct, &nrt);
+        const int nb = (int)bp->by_mc.at(lg).size();
+        hipLaunchKernelGGL(sig_ctl_kernel, dim3((unsigned)nb), dim3(256), 0, st, (const SigDesc*)(ws + bp->off_desc),
+                           (SigStats*)(ws + bp->off_sstats), order() + first.at(lg),
+                           (const unsigned long long*)(ws + bp->tpart_off.at(lg)), (int32_t)nb,
+                           (int32_t)bp->tpart_tiles.at(lg), (int32_t)nct, (int32_t)nrt, max_iter, (int32_t)fixed);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (b && (e = go(SIGT_RMUL, lg, st)) != hipSuccess) return e;
+        if ((e = go(SIGT_CSPAT, lg, st)) != hipSuccess) return e;
+      }
+    }
+    return e;
+  }
+
+  // everything a captured chunk bakes in: the workspace, the members' layout, the cap, the chunk
+  void key_into(GraphKey& key) const {
+    key.k.insert(key.k.end(), {-1, (int64_t)bp->dt, (int64_t)(uintptr_t)ws, (int64_t)max_iter, (int64_t)fixed,
+                               (int64_t)chunk, (int64_t)nsig()});
+    for (int k = 0; k < nsig(); ++k) {
+      key.k.push_back(bp->sigs[k].L);
+      key.k.push_back(bp->sigs[k].blue);
+      key.k.push_back((int64_t)bp->sig_off[k]);
+    }
+    for (int lg : tiled) key.k.push_back(lg);
+  }
+
+  // whether every tiled signal's loop has ended, from a host copy of the signal states
+  bool all_done(const SigStats* hs) const {
+    for (int lg : tiled)
+      for (int k : bp->by_mc.at(lg))
+        if (!hs[k].done) return false;
+    return true;
+  }
+
+  // the tiled rounds driven from here: chunks captured once in a hipGraph (process-wide cache)
+  // and replayed, one poll of the done-flags per chunk
+  int32_t loop(HostBuf& hstate) {
+    if (tiled.empty()) return FFCZ_OK;
+    const int ns = nsig();
+    HIPCHK(hstate.reserve(sizeof(SigStats) * ns));
+    SigStats* hs = (SigStats*)hstate.p;
+    hipGraphExec_t gexec = nullptr;
+    if (o.use_graph && !g_prof.on) {
+      GraphKey key;
+      key_into(key);
+      std::lock_guard<std::mutex> lk(g_sig_graphs_m);
+      gexec = sig_graphs().find(key);
+      if (!gexec) {
+        HIPCHK(g_streams.ready());
+        HIPCHK(hipStreamBeginCapture(g_streams.cap, hipStreamCaptureModeThreadLocal));
+        const hipError_t ce = enqueue_chunk(g_streams.cap);
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(g_streams.cap, &graph);
+        if (ce != hipSuccess) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return fail(FFCZ_E_HIP, std::string("capture of the 1D rounds: ") + hipGetErrorString(ce));
+        }
+        HIPCHK(ee);
+        const hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(ie);
+        sig_graphs().put(key, gexec);
+      }
+    }
+    for (int enq = 0;; enq += chunk) {
+      if (gexec) HIPCHK(hipGraphLaunch(gexec, s));
+      else HIPCHK(enqueue_chunk(s));
+      HIPCHK(hipMemcpyAsync(hs, ws + bp->off_sstats, sizeof(SigStats) * ns, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (all_done(hs)) break;
+      if (enq > max_iter + 2 * chunk + 2) return fail(FFCZ_E_HIP, "tiled signals did not report completion");
+    }
+    return FFCZ_OK;
+  }
+
+  // the tiled classes' outputs and verification on s, then s waits for the one-block classes
+  int32_t end() {
+    for (int lg : tiled) {
+      HIPCHK(go(SIGT_Y, lg, s));
+      if (!o.verify_fp64) continue;
+      HIPCHK(go(SIGT_VCOL, lg, s));
+      HIPCHK(go(SIGT_VROW, lg, s));
+      if (kinds[lg].first) HIPCHK(go(SIGT_VCOL2, lg, s));
+      int nct = 0, nrt = 0;
+      sig_tiles(lg, &nct, &nrt);
+      const int nb = (int)bp->by_mc.at(lg).size();
+      hipLaunchKernelGGL(sig_vstats_kernel, dim3((unsigned)nb), dim3(256), 0, s, (const SigDesc*)(ws + bp->off_desc),
+                         (SigStats*)(ws + bp->off_sstats), order() + first.at(lg),
+                         (const unsigned long long*)(ws + bp->tpart_off.at(lg)), (int32_t)nb,
+                         (int32_t)bp->tpart_tiles.at(lg), (int32_t)nct, (int32_t)nrt);
+      HIPCHK(hipGetLastError());
+    }
+    return rejoin();
+  }
+
+  // s waits for the one-block stream (also on early exits, so no launch outlives the call)
+  int32_t rejoin() {
+    if (!side_used) return FFCZ_OK;
+    side_used = false;
+    HIPCHK(hipEventRecord(join, side));
+    HIPCHK(hipStreamWaitEvent(s, join, 0));
+    return FFCZ_OK;
+  }
+  ~SigRun() { (void)rejoin(); }
+};
+
+int32_t run_sigs(const BatchPlan& bp, const ffcz_instance* inst, const double* mus, int32_t max_iter,
+                 const ffcz_options& o, char* ws, hipStream_t s, HostBuf& hsig, HostBuf& hstate) {
+  if (bp.sig_ids.empty()) return FFCZ_OK;
+  HIPCHK(g_streams.ready());
+  SigRun sr;
+  int32_t r = sr.begin(bp, inst, mus, max_iter, o, ws, s, g_streams.side2, g_streams.fork2, g_streams.join2, hsig);
+  if (r != FFCZ_OK) return r;
+  r = sr.loop(hstate);
+  if (r != FFCZ_OK) return r;
+  return sr.end();
 }
 
 int32_t collect_sigs(const BatchPlan& bp, const ffcz_instance* inst, const double* mus, const ffcz_options& o,
@@ -2366,16 +2700,130 @@ struct SideJoin {
   }
 };
 
-// The thread that drives the 1D members of a mixed batch; joined on every exit path.
-struct SigWorker {
-  std::thread th;
-  int32_t rc = FFCZ_OK;
-  std::string err;
-  void join() {
-    if (th.joinable()) th.join();
+
+// A batch of 1D and grouped members, driven from the calling thread.  Everything is tuned
+// first, with nothing else running.  Then the 1D set-up runs on a side stream (its one-block
+// classes on a second one, beside everything else) while the groups' set-up runs on the caller's
+// stream; every chunk of rounds is one hipGraph holding each group's chunk and every tiled 1D
+// class's chunk as two parallel branches, replayed with one poll of all done-flags per chunk;
+// last, the groups' closing passes on the caller's stream and the tiled classes' outputs and
+// verification on the side stream, joined before return.
+template <typename T>
+int32_t mixed_batch(const BatchPlan& bp, const ffcz_instance* inst, const std::vector<double>& mus,
+                    int32_t max_iter, const ffcz_options& o, char* w, hipStream_t s, ffcz_stats* stats,
+                    std::vector<int32_t>& status) {
+  for (size_t g = 0; g < bp.groups.size(); ++g) {
+    int32_t r = pretune_group<T>(bp.gplans[g], w + bp.goff[g], s);
+    if (r != FFCZ_OK) return r;
   }
-  ~SigWorker() { join(); }
-};
+  int32_t r = pretune_sigs(bp, inst, mus.data(), o, w, s, g_host_sig);
+  if (r != FFCZ_OK) return r;
+  HIPCHK(g_streams.ready());
+  const hipStream_t s1 = g_streams.side;
+  HIPCHK(hipEventRecord(g_streams.fork, s));
+  HIPCHK(hipStreamWaitEvent(s1, g_streams.fork, 0));
+  SideJoin side;  // s waits for s1 on every exit from here
+  side.s = s;
+  side.s1 = s1;
+  SigRun sr;      // declared after the join: its own stream joins s1 first
+  r = sr.begin(bp, inst, mus.data(), max_iter, o, w, s1, g_streams.side2, g_streams.fork2, g_streams.join2, g_host_sig);
+  if (r != FFCZ_OK) return r;
+  HIPCHK(hipEventRecord(g_streams.ready1d, s1));
+  // the groups' set-up on s; their instance and margin arrays live as long as the runs
+  const size_t ng = bp.groups.size();
+  std::vector<std::vector<ffcz_instance>> gis(ng);
+  std::vector<std::vector<double>> gms(ng);
+  std::vector<std::unique_ptr<GroupRun<T>>> gr;
+  for (size_t g = 0; g < ng; ++g) {
+    for (int id : bp.groups[g]) {
+      gis[g].push_back(inst[id]);
+      gms[g].push_back(mus[id]);
+    }
+    gr.emplace_back(new GroupRun<T>());
+    r = gr.back()->begin(bp.gplans[g], gis[g].data(), gms[g].data(), max_iter, o, w + bp.goff[g], s, nullptr,
+                         nullptr, nullptr);
+    if (r != FFCZ_OK) return r;
+  }
+  HIPCHK(hipStreamWaitEvent(s, g_streams.ready1d, 0));
+  // one chunk of everything: the groups on a, the tiled 1D classes on b, forked from and joined into a
+  auto enqueue_all = [&](hipStream_t a, hipStream_t b) -> hipError_t {
+    hipError_t e = hipEventRecord(g_streams.cfork, a);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b, g_streams.cfork, 0);
+    for (size_t g = 0; g < ng && e == hipSuccess; ++g) e = gr[g]->enqueue_chunk(a);
+    if (e == hipSuccess) e = sr.enqueue_chunk(b);
+    if (e == hipSuccess) e = hipEventRecord(g_streams.cjoin, b);
+    if (e == hipSuccess) e = hipStreamWaitEvent(a, g_streams.cjoin, 0);
+    return e;
+  };
+  hipGraphExec_t gexec = nullptr;
+  if (o.use_graph && !g_prof.on) {
+    GraphKey key{{-2}};
+    for (size_t g = 0; g < ng; ++g) {
+      const GraphKey gk = gr[g]->graph_key();
+      key.k.insert(key.k.end(), gk.k.begin(), gk.k.end());
+    }
+    sr.key_into(key);
+    std::lock_guard<std::mutex> lk(g_sig_graphs_m);
+    gexec = sig_graphs().find(key);
+    if (!gexec) {
+      HIPCHK(hipStreamBeginCapture(g_streams.cap, hipStreamCaptureModeThreadLocal));
+      const hipError_t ce = enqueue_all(g_streams.cap, g_streams.cap2);
+      hipGraph_t graph = nullptr;
+      const hipError_t ee = hipStreamEndCapture(g_streams.cap, &graph);
+      if (ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(FFCZ_E_HIP, std::string("capture of the batch rounds: ") + hipGetErrorString(ce));
+      }
+      HIPCHK(ee);
+      const hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIPCHK(ie);
+      sig_graphs().put(key, gexec);
+    }
+  }
+  // host copies of every group's states and of the signal states, polled once per chunk
+  size_t hbytes = sizeof(SigStats) * bp.sig_ids.size();
+  std::vector<size_t> hoff(ng);
+  for (size_t g = 0; g < ng; ++g) {
+    hoff[g] = hbytes;
+    hbytes += sizeof(DevState) * (size_t)bp.gplans[g].B;
+  }
+  HIPCHK(g_host_sigstate.reserve(hbytes));
+  char* hb = (char*)g_host_sigstate.p;
+  const int chunk = o.graph_chunk > 0 ? o.graph_chunk : 4;
+  for (int enq = 0;; enq += chunk) {
+    if (gexec) HIPCHK(hipGraphLaunch(gexec, s));
+    else HIPCHK(enqueue_all(s, s1));
+    HIPCHK(hipMemcpyAsync(hb, w + bp.off_sstats, sizeof(SigStats) * bp.sig_ids.size(), hipMemcpyDeviceToHost, s));
+    for (size_t g = 0; g < ng; ++g)
+      HIPCHK(hipMemcpyAsync(hb + hoff[g], gr[g]->c.st(), sizeof(DevState) * (size_t)bp.gplans[g].B,
+                            hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    bool all = sr.all_done((const SigStats*)hb);
+    for (size_t g = 0; g < ng && all; ++g) {
+      const DevState* hs = (const DevState*)(hb + hoff[g]);
+      for (int64_t b = 0; b < bp.gplans[g].B; ++b) all = all && hs[b].done;
+    }
+    if (all) break;
+    if (enq > max_iter + 2 * chunk + 2) return fail(FFCZ_E_HIP, "batch did not report completion");
+  }
+  // the tiled classes' end on s1 (after the loop), the groups' ends on s
+  HIPCHK(hipEventRecord(g_streams.looped, s));
+  HIPCHK(hipStreamWaitEvent(s1, g_streams.looped, 0));
+  r = sr.end();
+  if (r != FFCZ_OK) return r;
+  for (size_t g = 0; g < ng; ++g) {
+    std::vector<int32_t> gs(gis[g].size(), FFCZ_OK);
+    std::vector<ffcz_stats> gst(gis[g].size());
+    r = gr[g]->end(gst.data(), gs.data());
+    if (r != FFCZ_OK) return r;
+    for (size_t k = 0; k < gis[g].size(); ++k) {
+      status[bp.groups[g][k]] = gs[k];
+      if (stats) stats[bp.groups[g][k]] = gst[k];
+    }
+  }
+  return FFCZ_OK;
+}
 
 int32_t worst(const std::vector<int32_t>& st) {
   int32_t w = FFCZ_OK;
@@ -2632,32 +3080,59 @@ int32_t power_bounds_impl(const Plan& p, const BoundsLayout& L, char* ws, const 
 constexpr int kHuffMaxLen = 32;
 constexpr int64_t kHuffMaxAlpha = int64_t(1) << 24;
 
+// The merges in O(n) after a sort: leaves sorted by (count, symbol), merged nodes appended to a
+// second queue in creation order.  Merged weights never decrease, so both queues stay ordered
+// by (weight, id) and the lighter front is the node a heap ordered by (weight, id) would pop
+// (on equal weights the leaf, whose id is the smaller).
 std::vector<uint8_t> huff_tree_lengths(const std::vector<unsigned long long>& c) {
   std::vector<uint8_t> len(c.size(), 0);
   std::vector<int64_t> present;
+  std::vector<unsigned long long> w;  // leaf weights, leaf id = position in present
   for (size_t i = 0; i < c.size(); ++i)
-    if (c[i]) present.push_back((int64_t)i);
-  if (present.empty()) return len;
-  if (present.size() == 1) {
+    if (c[i]) {
+      present.push_back((int64_t)i);
+      w.push_back(c[i]);
+    }
+  const int64_t nl = (int64_t)present.size();
+  if (nl == 0) return len;
+  if (nl == 1) {
     len[present[0]] = 1;
     return len;
   }
-  using Node = std::pair<unsigned long long, int64_t>;  // (weight, id)
-  std::priority_queue<Node, std::vector<Node>, std::greater<Node>> pq;
-  const int64_t nl = (int64_t)present.size();
-  for (int64_t i = 0; i < nl; ++i) pq.push(Node{c[present[i]], i});
-  std::vector<int64_t> parent(2 * nl - 1, -1);
-  int64_t nid = nl;
-  while (pq.size() > 1) {
-    const Node a = pq.top();
-    pq.pop();
-    const Node b = pq.top();
-    pq.pop();
-    parent[a.second] = nid;
-    parent[b.second] = nid;
-    pq.push(Node{a.first + b.first, nid});
-    ++nid;
+  // sort the leaf ids by (weight, id): least significant digit radix sort on 11-bit digits
+  // (stable, so equal weights keep id order)
+  std::vector<int64_t> leaf(nl), tmp(nl);
+  for (int64_t i = 0; i < nl; ++i) leaf[i] = i;
+  unsigned long long wmax = 0;
+  for (int64_t i = 0; i < nl; ++i) wmax = std::max(wmax, w[i]);
+  for (int sh = 0; sh < 64 && (wmax >> sh) != 0; sh += 11) {
+    std::vector<int64_t> bucket(2049, 0);
+    for (int64_t i = 0; i < nl; ++i) bucket[((w[leaf[i]] >> sh) & 2047) + 1]++;
+    for (int d = 0; d < 2048; ++d) bucket[d + 1] += bucket[d];
+    for (int64_t i = 0; i < nl; ++i) tmp[bucket[(w[leaf[i]] >> sh) & 2047]++] = leaf[i];
+    leaf.swap(tmp);
   }
+  std::vector<unsigned long long> mw;  // merged weights, node id nl + k
+  mw.reserve(nl - 1);
+  std::vector<int64_t> parent(2 * nl - 1, -1);
+  int64_t li = 0, mi = 0;
+  auto pop = [&]() -> std::pair<unsigned long long, int64_t> {
+    const bool take_leaf = li < nl && (mi >= (int64_t)mw.size() || w[leaf[li]] <= mw[mi]);
+    if (take_leaf) {
+      const int64_t id = leaf[li++];
+      return {w[id], id};
+    }
+    const int64_t id = nl + mi;
+    return {mw[mi++], id};
+  };
+  for (int64_t k = 0; k < nl - 1; ++k) {
+    const auto a = pop();
+    const auto b = pop();
+    parent[a.second] = nl + k;
+    parent[b.second] = nl + k;
+    mw.push_back(a.first + b.first);
+  }
+  const int64_t nid = 2 * nl - 1;
   std::vector<int> depth(nid, 0);
   for (int64_t node = nid - 2; node >= 0; --node) depth[node] = depth[parent[node]] + 1;  // parents come later
   for (int64_t i = 0; i < nl; ++i) len[present[i]] = (uint8_t)std::min(depth[i], 255);
@@ -2877,7 +3352,8 @@ void ffcz_default_options(ffcz_options* o) {
   o->verify_fp64 = 1;
   o->graph_chunk = 4;
   o->use_graph = 1;
-  o->tiled_1d_lg = 15;
+  o->resident_1d = 1;
+  o->tiled_1d_lg = 0;
 }
 
 size_t ffcz_workspace_bytes(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max_iter) {
@@ -3124,15 +3600,22 @@ int32_t ffcz_huffman_encode(const void* sym, int64_t nsym, int32_t width, const 
     hipLaunchKernelGGL(huff_hist_kernel, dim3((unsigned)g), dim3(kHuffBlock), 0, s, sym, (int)width, nsym,
                        (int64_t)lo, nalpha, counts);
     HIPCHK(hipGetLastError());
-    std::vector<unsigned long long> hc((size_t)nalpha);
-    HIPCHK(hipMemcpyAsync(hc.data(), counts, 8 * (size_t)nalpha, hipMemcpyDeviceToHost, s));
+    // through pinned staging: the table out, the lengths and codes back (the copies in are
+    // complete at the synchronisation that reads the bit count, before the buffer is reused)
+    HIPCHK(g_host_misc.reserve(8 * (size_t)nalpha));
+    unsigned long long* hcp = (unsigned long long*)g_host_misc.p;
+    HIPCHK(hipMemcpyAsync(hcp, counts, 8 * (size_t)nalpha, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    len = huff_lengths(hc);
+    len = huff_lengths(std::vector<unsigned long long>(hcp, hcp + nalpha));
     const HuffTables t = huff_tables(len);
     uint8_t* dlen = (uint8_t*)(w + W.off_len);
     uint32_t* dcode = (uint32_t*)(w + W.off_code);
-    HIPCHK(hipMemcpyAsync(dlen, len.data(), (size_t)nalpha, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(dcode, t.code.data(), 4 * (size_t)nalpha, hipMemcpyHostToDevice, s));
+    uint32_t* hcode = (uint32_t*)g_host_misc.p;
+    uint8_t* hlen = (uint8_t*)(hcode + nalpha);
+    memcpy(hcode, t.code.data(), 4 * (size_t)nalpha);
+    memcpy(hlen, len.data(), (size_t)nalpha);
+    HIPCHK(hipMemcpyAsync(dlen, hlen, (size_t)nalpha, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dcode, hcode, 4 * (size_t)nalpha, hipMemcpyHostToDevice, s));
     // bits per block, block offsets, the total
     const int64_t nblk = (nsym + kHuffBlockSyms - 1) / kHuffBlockSyms;
     unsigned long long* boff = (unsigned long long*)(w + W.off_boff);
@@ -3178,6 +3661,8 @@ int32_t ffcz_huffman_decode(const void* in, size_t in_bytes, int32_t width, void
       hd.nalpha > kHuffMaxAlpha || hd.nbits < 0)
     return fail(FFCZ_E_INVALID, "not a stream written by ffcz_huffman_encode");
   if ((int32_t)hd.width != width) return fail(FFCZ_E_INVALID, "symbol width differs from the stream's");
+  if (hd.nchunks != (hd.nsym + kHuffChunk - 1) / kHuffChunk)
+    return fail(FFCZ_E_INVALID, "chunk count does not match the symbol count");
   const HuffLayout L = huff_layout(hd.nsym, hd.nalpha, hd.nbits);
   if (in_bytes < L.bytes) return fail(FFCZ_E_INVALID, "input shorter than its stream");
   if (hd.nsym > capacity || (hd.nsym > 0 && !sym_out)) return fail(FFCZ_E_INVALID, "output holds fewer symbols than the stream");
@@ -3186,25 +3671,38 @@ int32_t ffcz_huffman_decode(const void* in, size_t in_bytes, int32_t width, void
   const HuffWs W = huff_ws(hd.nsym, hd.nalpha);
   if (!ws || ws_bytes < W.bytes || ((uintptr_t)ws & 255))
     return fail(FFCZ_E_WORKSPACE, "workspace smaller than ffcz_huffman_workspace_bytes(nsym, nalpha) or misaligned");
-  std::vector<uint8_t> len((size_t)hd.nalpha);
+  // through pinned staging: the lengths out, the decoder's tables back
+  const size_t tab_bytes = 3 * sizeof(uint32_t) * (kHuffMaxLen + 1);
+  HIPCHK(g_host_misc.reserve(std::max<size_t>((size_t)hd.nalpha, tab_bytes + 4 * (size_t)hd.nalpha)));
   const char* ib = (const char*)in;
-  HIPCHK(hipMemcpyAsync(len.data(), ib + L.off_len, (size_t)hd.nalpha, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(g_host_misc.p, ib + L.off_len, (size_t)hd.nalpha, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  std::vector<uint8_t> len((const uint8_t*)g_host_misc.p, (const uint8_t*)g_host_misc.p + hd.nalpha);
   for (uint8_t l : len)
     if (l > kHuffMaxLen) return fail(FFCZ_E_INVALID, "code length above 32 in the stream");
   const HuffTables t = huff_tables(len);
+  // a prefix code: at most 2^l codes of length l after the shorter ones (Kraft), so every
+  // window the decoder meets maps into the table or is reported
+  uint64_t kraft = 0;  // sum of 2^(32 - l) over the codes, at most 2^32
+  for (int l = 1; l <= kHuffMaxLen; ++l) kraft += (uint64_t)t.cnt[l] << (kHuffMaxLen - l);
+  if (kraft > (1ull << kHuffMaxLen)) return fail(FFCZ_E_INVALID, "code lengths break the Kraft inequality");
   char* w = (char*)ws;
   uint32_t* tab = (uint32_t*)(w + W.off_tab);
-  HIPCHK(hipMemcpyAsync(tab, t.first, sizeof(t.first), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(tab + (kHuffMaxLen + 1), t.cnt, sizeof(t.cnt), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(tab + 2 * (kHuffMaxLen + 1), t.idx, sizeof(t.idx), hipMemcpyHostToDevice, s));
-  if (!t.sorted.empty())
-    HIPCHK(hipMemcpyAsync(w + W.off_sorted, t.sorted.data(), 4 * t.sorted.size(), hipMemcpyHostToDevice, s));
+  uint32_t* htab = (uint32_t*)g_host_misc.p;  // first, cnt, idx, then the sorted symbols
+  memcpy(htab, t.first, sizeof(t.first));
+  memcpy(htab + (kHuffMaxLen + 1), t.cnt, sizeof(t.cnt));
+  memcpy(htab + 2 * (kHuffMaxLen + 1), t.idx, sizeof(t.idx));
+  HIPCHK(hipMemcpyAsync(tab, htab, tab_bytes, hipMemcpyHostToDevice, s));
+  if (!t.sorted.empty()) {
+    memcpy((char*)htab + tab_bytes, t.sorted.data(), 4 * t.sorted.size());
+    HIPCHK(hipMemcpyAsync(w + W.off_sorted, (char*)htab + tab_bytes, 4 * t.sorted.size(), hipMemcpyHostToDevice, s));
+  }
   unsigned int* bad = (unsigned int*)(w + W.off_tot);
   hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, (unsigned long long*)bad, (int64_t)1);
   HIPCHK(hipGetLastError());
   const int64_t nch = hd.nchunks;
-  hipLaunchKernelGGL(huff_decode_kernel, dim3((unsigned)((nch + kHuffBlock - 1) / kHuffBlock)), dim3(kHuffBlock), 0, s,
+  hipLaunchKernelGGL(huff_decode_kernel, dim3((unsigned)((nch + kHuffDecBlock - 1) / kHuffDecBlock)),
+                     dim3(kHuffDecBlock), 0, s,
                      (const unsigned int*)(ib + L.off_words), (int64_t)((hd.nbits + 31) / 32),
                      (const unsigned long long*)(ib + L.off_chunks), hd.nsym, (const uint32_t*)tab,
                      (const uint32_t*)(tab + (kHuffMaxLen + 1)), (const uint32_t*)(tab + 2 * (kHuffMaxLen + 1)),
@@ -3410,64 +3908,34 @@ int32_t ffcz_correct_batched(int32_t dtype, int32_t count, const ffcz_instance* 
     }
   }
   std::vector<int32_t> status(count, FFCZ_OK);
-  // 1D members on a side stream forked from the caller's, driven by a worker thread (the tiled
-  // classes poll their done-flags), so they run beside the grouped members' rounds
-  hipStream_t s1 = s;
-  SideJoin side;  // declared before the worker: on an early return the worker is joined first
-  SigWorker worker;
   if (!bp.sig_ids.empty() && !bp.groups.empty()) {
-    for (size_t g = 0; g < bp.groups.size(); ++g) {
-      r = dtype == FFCZ_F32 ? pretune_group<float>(bp.gplans[g], w + bp.goff[g], s)
-                            : pretune_group<double>(bp.gplans[g], w + bp.goff[g], s);
-      if (r != FFCZ_OK) return r;
-    }
-    HIPCHK(g_streams.ready());
-    s1 = g_streams.side;
-    HIPCHK(hipEventRecord(g_streams.fork, s));
-    HIPCHK(hipStreamWaitEvent(s1, g_streams.fork, 0));
-    side.s = s;
-    side.s1 = s1;
-    int dev = 0;
-    HIPCHK(hipGetDevice(&dev));
-    HostBuf& hsig = g_host_sig;  // this thread's buffers, lent to the worker
-    HostBuf& hstate = g_host_sigstate;
-    worker.th = std::thread([&, dev, s1] {
-      if (hipSetDevice(dev) != hipSuccess) {
-        worker.rc = fail(FFCZ_E_HIP, "hipSetDevice failed on the 1D worker");
-      } else {
-        worker.rc = run_sigs(bp, inst, mus.data(), max_iter, o, w, s1, hsig, hstate);
-      }
-      if (worker.rc != FFCZ_OK) worker.err = g_err;
-    });
+    r = dtype == FFCZ_F32 ? mixed_batch<float>(bp, inst, mus, max_iter, o, w, s, stats, status)
+                          : mixed_batch<double>(bp, inst, mus, max_iter, o, w, s, stats, status);
+    if (r != FFCZ_OK) return r;
   } else {
-    r = run_sigs(bp, inst, mus.data(), max_iter, o, w, s1, g_host_sig, g_host_sigstate);
+    r = pretune_sigs(bp, inst, mus.data(), o, w, s, g_host_sig);
     if (r != FFCZ_OK) return r;
-  }
-  for (size_t g = 0; g < bp.groups.size(); ++g) {
-    const Plan& p = bp.gplans[g];
-    std::vector<ffcz_instance> gi;
-    std::vector<double> gm;
-    for (int id : bp.groups[g]) {
-      gi.push_back(inst[id]);
-      gm.push_back(mus[id]);
-    }
-    std::vector<int32_t> gs(gi.size(), FFCZ_OK);
-    std::vector<ffcz_stats> gst(gi.size());
-    r = dtype == FFCZ_F32
-            ? correct_group<float>(p, gi.data(), gm.data(), max_iter, o, w + bp.goff[g], s, gst.data(), gs.data())
-            : correct_group<double>(p, gi.data(), gm.data(), max_iter, o, w + bp.goff[g], s, gst.data(), gs.data());
+    r = run_sigs(bp, inst, mus.data(), max_iter, o, w, s, g_host_sig, g_host_sigstate);
     if (r != FFCZ_OK) return r;
-    for (size_t k = 0; k < gi.size(); ++k) {
-      status[bp.groups[g][k]] = gs[k];
-      if (stats) stats[bp.groups[g][k]] = gst[k];
+    for (size_t g = 0; g < bp.groups.size(); ++g) {
+      const Plan& p = bp.gplans[g];
+      std::vector<ffcz_instance> gi;
+      std::vector<double> gm;
+      for (int id : bp.groups[g]) {
+        gi.push_back(inst[id]);
+        gm.push_back(mus[id]);
+      }
+      std::vector<int32_t> gs(gi.size(), FFCZ_OK);
+      std::vector<ffcz_stats> gst(gi.size());
+      r = dtype == FFCZ_F32
+              ? correct_group<float>(p, gi.data(), gm.data(), max_iter, o, w + bp.goff[g], s, gst.data(), gs.data())
+              : correct_group<double>(p, gi.data(), gm.data(), max_iter, o, w + bp.goff[g], s, gst.data(), gs.data());
+      if (r != FFCZ_OK) return r;
+      for (size_t k = 0; k < gi.size(); ++k) {
+        status[bp.groups[g][k]] = gs[k];
+        if (stats) stats[bp.groups[g][k]] = gst[k];
+      }
     }
-  }
-  if (s1 != s) {
-    worker.join();
-    side.s1 = nullptr;  // joined here, with its errors reported
-    HIPCHK(hipEventRecord(g_streams.join, s1));
-    HIPCHK(hipStreamWaitEvent(s, g_streams.join, 0));
-    if (worker.rc != FFCZ_OK) return fail(worker.rc, worker.err);
   }
   r = collect_sigs(bp, inst, mus.data(), o, w, s, stats, status.data());
   if (r != FFCZ_OK) return r;

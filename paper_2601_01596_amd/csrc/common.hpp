@@ -137,9 +137,12 @@ __device__ __forceinline__ float to_t<float>(double v) { return __double2float_r
 template <>
 __device__ __forceinline__ double to_t<double>(double v) { return v; }
 
-// Clip to [-b, b].
+// Clip to [-b, b] (b >= 0, v finite).  FP32: one v_med3_f32, the median of (v, -b, b), which
+// returns one of its inputs, so an unclipped value comes back unchanged.
 template <typename T>
 __device__ __forceinline__ T clipv(T v, T b) { return v > b ? b : (v < -b ? -b : v); }
+template <>
+__device__ __forceinline__ float clipv<float>(float v, float b) { return __builtin_amdgcn_fmed3f(v, -b, b); }
 
 // Columns per block: 128-byte rows, halved until the tile fits in 128 KiB of LDS.
 template <typename T>

@@ -14,11 +14,13 @@
 
 namespace ffcz {
 
-constexpr int kHuffChunk = 1024;      // symbols per decoder chunk
+constexpr int kHuffChunk = 256;       // symbols per decoder chunk
 constexpr int kHuffBlock = 256;       // lanes per block
 constexpr int kHuffPerLane = 8;       // symbols per lane in the offset passes
 constexpr int64_t kHuffBlockSyms = (int64_t)kHuffBlock * kHuffPerLane;
 constexpr int kHuffLdsBins = 8192;    // alphabets up to this size count in LDS
+constexpr int kHuffDecBlock = 64;     // decoder lanes per block (one chunk each): small blocks
+                                      // spread the few chunks of a stream over more CUs
 
 // symbol i of a stream of 1-byte (width 1) or 4-byte signed (width 4) symbols
 __device__ __forceinline__ int64_t huff_sym(const void* s, int width, int64_t i) {
@@ -65,10 +67,26 @@ __global__ void __launch_bounds__(kHuffBlock) huff_hist_kernel(const void* s, in
   if (local)
     for (int i = threadIdx.x; i < nalpha; i += kHuffBlock) h[i] = 0u;
   __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * kHuffBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kHuffBlock) {
-    const int64_t b = huff_sym(s, width, i) - lo;
-    if (local) atomicAdd(&h[b], 1u);
-    else atomicAdd(&counts[b], 1ull);
+  // Edit streams are dominated by one symbol (zero flag bytes, zero codes): the lanes of a
+  // wave holding the same symbol as the wave's first active lane add once, by their number.
+  const int64_t stride = (int64_t)gridDim.x * kHuffBlock;
+  const int64_t start = (int64_t)blockIdx.x * kHuffBlock + threadIdx.x;
+  const int64_t span = (n + kHuffBlock - 1) / kHuffBlock * kHuffBlock;  // whole waves stay in the loop
+  for (int64_t i = start; i < span; i += stride) {
+    const bool in = i < n;
+    const int64_t b = in ? huff_sym(s, width, i) - lo : -1;
+    const int64_t b0 = __builtin_amdgcn_readfirstlane((int)b);
+    const unsigned long long same = __ballot(in && b == b0);
+    const unsigned long long below = __builtin_amdgcn_mbcnt_hi((unsigned)(same >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((unsigned)same, 0u));
+    if (!in) continue;
+    unsigned int add = 1u;
+    if (b == b0) {
+      if (below != 0) continue;  // not the first lane of the group
+      add = (unsigned int)__popcll(same);
+    }
+    if (local) atomicAdd(&h[b], add);
+    else atomicAdd(&counts[b], (unsigned long long)add);
   }
   __syncthreads();
   if (local)
@@ -138,39 +156,56 @@ __global__ void __launch_bounds__(kHuffBlock) huff_encode_kernel(const void* s, 
   }
 }
 
-// Decode: one lane per chunk walks its symbols from the chunk's first bit with the canonical
-// tables: first[l] = first code of length l, cnt[l] = codes of that length, idx[l] = position
-// of the first of them in sorted (symbols by length, then value).
-__global__ void __launch_bounds__(kHuffBlock) huff_decode_kernel(const unsigned int* words, int64_t nwords,
+// Decode: one lane per chunk walks its symbols from the chunk's first bit.  The lane keeps a
+// 64-bit window of the stream (refilled a word at a time) and decodes against left-justified
+// canonical limits: with v the window's top 32 bits, the code length is the smallest l with
+// v < lim[l] = (first[l] + cnt[l]) << (32 - l), and the symbol is
+// sorted[idx[l] + (v >> (32 - l)) - first[l]] (symbols ordered by length, then value).  The
+// tables sit in LDS.
+__global__ void __launch_bounds__(kHuffDecBlock) huff_decode_kernel(const unsigned int* words, int64_t nwords,
                                                                  const unsigned long long* chunk_bits, int64_t n,
                                                                  const uint32_t* first, const uint32_t* cnt,
                                                                  const uint32_t* idx, const int32_t* sorted,
                                                                  int64_t lo, int width, void* out,
                                                                  unsigned int* bad) {
-  const int64_t ch = (int64_t)blockIdx.x * kHuffBlock + threadIdx.x;
+  __shared__ unsigned long long lim[33];
+  __shared__ uint32_t fst[33], ix[33];
+  if (threadIdx.x < 33) {
+    const int l = threadIdx.x;
+    fst[l] = first[l];
+    ix[l] = idx[l];
+    // lengths without codes get a limit no window reaches past the previous length's
+    lim[l] = l == 0 ? 0ull : ((unsigned long long)first[l] + cnt[l]) << (32 - l);
+  }
+  __syncthreads();
+  const int64_t ch = (int64_t)blockIdx.x * kHuffDecBlock + threadIdx.x;
   const int64_t i0 = ch * kHuffChunk;
   if (i0 >= n) return;
   const int64_t i1 = i0 + kHuffChunk < n ? i0 + kHuffChunk : n;
-  unsigned long long pos = chunk_bits[ch];
+  const unsigned long long p0 = chunk_bits[ch];
+  // window: the stream's bits from position pos on, left-justified, nb of them valid
+  int64_t w = (int64_t)(p0 >> 5);
+  auto word = [&](int64_t k) -> unsigned long long { return k < nwords ? (unsigned long long)words[k] : 0ull; };
+  unsigned long long buf = ((word(w) << 32) | word(w + 1)) << (p0 & 31);
+  int nb = 64 - (int)(p0 & 31);
+  w += 2;
   for (int64_t i = i0; i < i1; ++i) {
-    uint32_t c = 0;
-    int l = 0;
-    int64_t sym = -1;
-    while (l < 32) {
-      const int64_t w = (int64_t)(pos >> 5);
-      const unsigned int word = w < nwords ? words[w] : 0u;
-      c = (c << 1) | ((word >> (31 - (int)(pos & 31))) & 1u);
-      ++pos;
-      ++l;
-      if (cnt[l] && c - first[l] < cnt[l]) {
-        sym = sorted[idx[l] + (c - first[l])];
-        break;
-      }
+    if (nb <= 32) {  // refill one word below the valid bits
+      buf |= word(w) << (32 - nb);
+      nb += 32;
+      ++w;
     }
-    if (sym < 0) {
+    const unsigned long long v = buf >> 32;
+    int l = 1;
+    while (l <= 32 && v >= lim[l]) ++l;
+    if (l > 32) {
       atomicOr(bad, 1u);
       return;
     }
+    const uint32_t c = (uint32_t)(v >> (32 - l));
+    const int64_t sym = sorted[ix[l] + (c - fst[l])];
+    buf <<= l;
+    nb -= l;
     if (width == 1) ((uint8_t*)out)[i] = (uint8_t)(sym + lo);
     else ((int32_t*)out)[i] = (int32_t)(sym + lo);
   }

@@ -22,6 +22,11 @@
 // next forward DFT]; a power-of-two L needs only [row: forward, count, clip,
 // inverse] [column: inverse, clip, forward].
 //
+// Signals whose work buffer fits in LDS (FP32 up to Mc = 2^14, FP64 up to 2^13) keep it
+// there for the whole loop (SIG_RUNL): the buffer is stored with a row pitch of MA + 1 and
+// every pass exchanges its FFT stages in place inside the tile it owns, so only the tables,
+// the iterate and the input and output touch memory.
+//
 // Long signals run the same passes tiled: each SIGT_* launch does one pass,
 // one block per (signal, column tile) or (signal, row tile), and writes one
 // partial count per block; sig_ctl_kernel sums them per signal and sets the
@@ -98,6 +103,9 @@ struct SigGeom {
   static constexpr int LDS = imax2(CC * MB, RR * LPA);
   static constexpr int NCT = MA / CC;  // column tiles (also the element chunks of the tiled passes)
   static constexpr int NRT = MB / RR;  // row tiles
+  // the whole work buffer at a row pitch of LPA in one block's LDS (160 KiB per CU, some
+  // left for the reductions)
+  static constexpr bool RES_FITS = (int64_t)MB * LPA * (int64_t)sizeof(cx<T>) <= 158 * 1024;
   // row-pass table layout: entry (k2, k1) at ((k2 / RR) * MA + k1) * RR + k2 % RR
   __host__ __device__ static constexpr int64_t rpos(int k2, int k1) {
     return ((int64_t)(k2 / RR) * MA + k1) * RR + (k2 % RR);
@@ -122,10 +130,11 @@ enum SigMode : int {
   SIGT_Y = 12,      // y = x + eps (FP64, clamp); max |y - x| partial
   SIGT_VCOL = 13,   // verification: column pass of d = y - x (FP64)
   SIGT_VROW = 14,   // verification: row pass (Bluestein: x spectrum of b; else maxima partials)
-  SIGT_VCOL2 = 15   // verification: final column pass, maxima partials         [Bluestein]
+  SIGT_VCOL2 = 15,  // verification: final column pass, maxima partials         [Bluestein]
+  SIG_RUNL = 16     // as SIG_RUN with the work buffer resident in LDS
 };
 
-__host__ __device__ constexpr bool sig_tiled(int m) { return m >= SIGT_CHIRP; }
+__host__ __device__ constexpr bool sig_tiled(int m) { return m >= SIGT_CHIRP && m <= SIGT_VCOL2; }
 // tiled passes laid out over row tiles; all others over column tiles / element chunks
 __host__ __device__ constexpr bool sig_row_tiled(int m) {
   return m == SIGT_BROW || m == SIGT_RMUL || m == SIGT_RCHECK || m == SIGT_VROW;
@@ -139,7 +148,8 @@ __host__ __device__ constexpr bool sig_elem_tiled(int m) {
 // lets more blocks share a compute unit
 template <typename G, int MODE>
 __host__ __device__ constexpr int sig_lds_entries() {
-  if constexpr (!sig_tiled(MODE)) return G::LDS;
+  if constexpr (MODE == SIG_RUNL) return G::MB_ * G::LPA;
+  else if constexpr (!sig_tiled(MODE)) return G::LDS;
   else if constexpr (sig_row_tiled(MODE)) return G::RR * G::LPA;
   else if constexpr (sig_elem_tiled(MODE)) return 1;
   else return G::CC * G::MB_;
@@ -195,9 +205,13 @@ sig_kernel(SigArgs<T> a) {
   const int t = threadIdx.x;
   // the loop (SIG_RUN and the round passes) works in T = the data type; set-up and
   // verification in FP64 on the FP64 buffers
-  constexpr bool loopT = (MODE == SIG_RUN || MODE == SIGT_EPS0 || MODE == SIGT_CIN || MODE == SIGT_RMUL ||
+  constexpr bool loopT = (MODE == SIG_RUN || MODE == SIG_RUNL || MODE == SIGT_EPS0 || MODE == SIGT_CIN || MODE == SIGT_RMUL ||
                           MODE == SIGT_RCHECK || MODE == SIGT_CCHECK || MODE == SIGT_CSPAT || MODE == SIGT_Y);
-  cx<T>* conv = (cx<T>*)(loopT ? sd.conv : sd.conv64);
+  // the work buffer: in memory at a row pitch of MA, or (SIG_RUNL) in LDS at a pitch of LPA,
+  // where each pass's FFT exchanges run in place inside the tile the pass owns
+  constexpr bool RES = MODE == SIG_RUNL;
+  constexpr int CP = RES ? LPA : MA;
+  cx<T>* conv = RES ? lds : (cx<T>*)(loopT ? sd.conv : sd.conv64);
   const cx<T>* chirp = (const cx<T>*)(loopT ? sd.chirp : sd.chirp64);
   const cx<T>* btab = (const cx<T>*)(loopT ? sd.btab : sd.btab64);
   // tiled partial slot of this block
@@ -241,8 +255,9 @@ sig_kernel(SigArgs<T> a) {
       cx<T> v[EB];
       if constexpr (INV1) {
 #pragma unroll
-        for (int q = 0; q < EB; ++q) v[q] = conv[(int64_t)(j + q * PB) * MA + n1];
-        fft<T, MB, EB, true, CC, 1>(v, lds, tb.twb, c, j);
+        for (int q = 0; q < EB; ++q) v[q] = conv[(int64_t)(j + q * PB) * CP + n1];
+        if constexpr (RES) fft<T, MB, EB, true, CP, 1>(v, conv + c0, tb.twb, c, j);
+        else fft<T, MB, EB, true, CC, 1>(v, lds, tb.twb, c, j);
       } else {
 #pragma unroll
         for (int q = 0; q < EB; ++q) v[q] = in(n1, j + q * PB);
@@ -250,11 +265,16 @@ sig_kernel(SigArgs<T> a) {
 #pragma unroll
       for (int q = 0; q < EB; ++q) v[q] = op(n1, j + q * PB, v[q]);
       if constexpr (FWD2) {
-        fft<T, MB, EB, false, CC, 1>(v, lds, tb.twb, c, j);
+        if constexpr (RES) {
+          fft<T, MB, EB, false, CP, 1>(v, conv + c0, tb.twb, c, j);
+          __syncthreads();  // the last exchange's reads are done before the tile is overwritten
+        } else {
+          fft<T, MB, EB, false, CC, 1>(v, lds, tb.twb, c, j);
+        }
 #pragma unroll
         for (int q = 0; q < EB; ++q) {
           const int64_t p = (int64_t)(j + q * PB) * MA + n1;
-          conv[p] = cmul(v[q], tb.tw4[p]);
+          conv[(int64_t)(j + q * PB) * CP + n1] = cmul(v[q], tb.tw4[p]);
         }
       }
     }
@@ -266,8 +286,29 @@ sig_kernel(SigArgs<T> a) {
   auto row_pass = [&](auto INVc, auto op) {
     constexpr bool INV = decltype(INVc)::value;
     const int rl = t % RR, j = t / RR;
-    cx<T>* lrow = lds + rl * LPA;
     for (int r0 = rtlo * RR; r0 < rthi * RR; r0 += RR) {
+      const int k2 = r0 + rl;
+      cx<T> v[EA];
+      if constexpr (RES) {
+        // the rows are already in LDS at pitch LPA: transform them in place
+        cx<T>* rows = conv + (int64_t)r0 * CP;
+#pragma unroll
+        for (int q = 0; q < EA; ++q) v[q] = rows[rl * CP + j + q * PA];
+        fft<T, MA, EA, false, 1, CP>(v, rows, tb.twa, rl, j);
+#pragma unroll
+        for (int q = 0; q < EA; ++q) v[q] = op(k2, j + q * PA, v[q]);
+        if constexpr (INV) {
+          fft<T, MA, EA, true, 1, CP>(v, rows, tb.twa, rl, j);
+#pragma unroll
+          for (int q = 0; q < EA; ++q) v[q] = cmulc(v[q], tb.tw4r[G::rpos(k2, j + q * PA)]);
+          __syncthreads();  // the last exchange's reads are done before the rows are overwritten
+#pragma unroll
+          for (int q = 0; q < EA; ++q) rows[rl * CP + j + q * PA] = v[q];
+        }
+        __syncthreads();
+        continue;
+      }
+      cx<T>* lrow = lds + rl * LPA;
       constexpr int NL = (RR * MA + NT - 1) / NT;
       // FP64 staging defines every entry on every path (zero where a ragged tile ends),
       // or the batch lands in scratch memory, and a tile of whole block-wide steps
@@ -294,11 +335,9 @@ sig_kernel(SigArgs<T> a) {
         }
       }
       __syncthreads();
-      cx<T> v[EA];
 #pragma unroll
       for (int q = 0; q < EA; ++q) v[q] = lrow[j + q * PA];
       fft<T, MA, EA, false, 1, LPA>(v, lds, tb.twa, rl, j);
-      const int k2 = r0 + rl;
 #pragma unroll
       for (int q = 0; q < EA; ++q) v[q] = op(k2, j + q * PA, v[q]);
       if constexpr (INV) {
@@ -503,7 +542,7 @@ sig_kernel(SigArgs<T> a) {
   };
   const double Eb = sd.E;
 
-  if constexpr (MODE == SIGT_EPS0 || MODE == SIG_RUN) {
+  if constexpr (MODE == SIGT_EPS0 || MODE == SIG_RUN || MODE == SIG_RUNL) {
     // eps0 = x_hat - x in FP64, guard clip
     unsigned long long guard = 0, nonfin = 0;
     for (int64_t n = n_lo + t; n < n_hi; n += NT) {
@@ -520,7 +559,7 @@ sig_kernel(SigArgs<T> a) {
       put_sum(SP_NONFIN, nonfin);
       return;
     }
-    if constexpr (MODE == SIG_RUN) {
+    if constexpr (MODE == SIG_RUN || MODE == SIG_RUNL) {
       guard = block_sum<NT>(guard, red_u);
       nonfin = block_sum<NT>(nonfin, red_u);
       if (nonfin) {

@@ -9,6 +9,7 @@ hipError_t launch_sig_f32(int mode, int lgMc, const void* args, int nsig, hipStr
   const SigArgs<float>& a = *static_cast<const SigArgs<float>*>(args);
   switch (mode) {
     case SIG_RUN: return sig_go<float, float, SIG_RUN>(lgMc, a, nsig, s);
+    case SIG_RUNL: return sig_go<float, float, SIG_RUNL>(lgMc, a, nsig, s);
     case SIG_VERIFY:
       return sig_go<double, float, SIG_VERIFY>(lgMc, *static_cast<const SigArgs<double>*>(args), nsig, s);
     case SIGT_EPS0: return sig_go<float, float, SIGT_EPS0>(lgMc, a, nsig, s);

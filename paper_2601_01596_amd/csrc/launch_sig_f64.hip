@@ -10,6 +10,7 @@ hipError_t launch_sig_f64(int mode, int lgMc, const void* args, int nsig, hipStr
   switch (mode) {
     case SIG_SETUP: return sig_go<double, double, SIG_SETUP>(lgMc, a, nsig, s);
     case SIG_RUN: return sig_go<double, double, SIG_RUN>(lgMc, a, nsig, s);
+    case SIG_RUNL: return sig_go<double, double, SIG_RUNL>(lgMc, a, nsig, s);
     case SIG_VERIFY: return sig_go<double, double, SIG_VERIFY>(lgMc, a, nsig, s);
     case SIGT_CHIRP: return sig_go<double, double, SIGT_CHIRP>(lgMc, a, nsig, s);
     case SIGT_BCOL: return sig_go<double, double, SIGT_BCOL>(lgMc, a, nsig, s);

@@ -24,7 +24,8 @@ hipError_t sig_go(int lgMc, const SigArgs<T>& a, int nsig, hipStream_t s) {
   switch (lgMc) {
 #define FFCZ_CASE(LG, MA, MB) \
   case LG:                    \
-    if constexpr (!sig_tiled(MODE) || LG >= kSigTiledMinLg) return sig_launch_one<T, TIO, MODE, MA, MB>(a, nsig, s); \
+    if constexpr ((!sig_tiled(MODE) || LG >= kSigTiledMinLg) && (MODE != SIG_RUNL || SigGeom<T, MA, MB>::RES_FITS)) \
+      return sig_launch_one<T, TIO, MODE, MA, MB>(a, nsig, s);                                                        \
     break;
     FFCZ_CASE(2, 2, 2) FFCZ_CASE(3, 4, 2) FFCZ_CASE(4, 4, 4) FFCZ_CASE(5, 8, 4) FFCZ_CASE(6, 8, 8)
     FFCZ_CASE(7, 16, 8) FFCZ_CASE(8, 16, 16) FFCZ_CASE(9, 32, 16) FFCZ_CASE(10, 32, 32)
@@ -35,6 +36,12 @@ hipError_t sig_go(int lgMc, const SigArgs<T>& a, int nsig, hipStream_t s) {
     default: break;
   }
   return hipErrorInvalidValue;
+}
+
+// Whether a class's work buffer fits in one block's LDS (SIG_RUNL), mirror of SigGeom::RES_FITS.
+inline bool sig_res_fits(int dt, int lgMc) {
+  const int64_t MA = (int64_t)1 << ((lgMc + 1) / 2), MB = ((int64_t)1 << lgMc) / MA;
+  return MB * (MA + 1) * (dt == 0 ? 8 : 16) <= 158 * 1024;
 }
 
 // Tiles per signal of a tiled mode (grid = signals x tiles), for the host's partial buffers.

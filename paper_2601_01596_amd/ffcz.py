@@ -52,6 +52,7 @@ class Options(ctypes.Structure):
         ("graph_chunk", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
         ("tiled_1d_lg", ctypes.c_int32),
+        ("resident_1d", ctypes.c_int32),
     ]
 
 
@@ -851,8 +852,8 @@ def batched_workspace(members, max_iter: int, device=None):
 
 
 def correct_batched(members, max_iter: int, *, margin: float = 0.0, fixed: bool = False, verify: bool = True,
-                    chunk: int = 4, graph: bool = True, tiled_1d_lg: int = 0, ws=None, check: bool = True,
-                    outs=None):
+                    chunk: int = 4, graph: bool = True, tiled_1d_lg: int = 0, resident_1d: bool = True, ws=None,
+                    check: bool = True, outs=None):
     """``ffcz_correct_batched`` over ``members = [(x, xb, eps_s, delta_f), ...]`` (device tensors).
 
     ``outs``: optional output tensors, one per member (same shape and dtype as its x);
@@ -902,6 +903,7 @@ def correct_batched(members, max_iter: int, *, margin: float = 0.0, fixed: bool 
     opts.use_graph = 1 if graph else 0
     if tiled_1d_lg:
         opts.tiled_1d_lg = int(tiled_1d_lg)
+    opts.resident_1d = 1 if resident_1d else 0
     stats = (Stats * len(insts))()
     stream = torch.cuda.current_stream(dev).cuda_stream
     st = ffcz_correct_batched(dt, insts, max_iter, opts, ws.data_ptr(), ws.numel(), stream, stats)

@@ -100,6 +100,22 @@ def test_tiled_1d_passes_match_one_block_bitwise(dt):
 
 
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_lds_resident_1d_matches_memory_bitwise(dt):
+    # one block per signal with the work buffer in LDS (FP32 work lengths up to 2^14, FP64 up to
+    # 2^13; longer ones keep it in memory) or in the workspace: identical bits, counts and maxima
+    lengths = [2, 3, 5, 8, 64, 100, 1000, 1024, 2049, 4096, 4097, 6000, 8192]
+    probs = [_member((L,), 700 + i, dt) for i, L in enumerate(lengths)]
+    ys_l, st_l, stats_l = _run(probs, resident_1d=True)
+    ys_m, st_m, stats_m = _run(probs, resident_1d=False)
+    assert st_l == F.OK and st_m == F.OK, (st_l, st_m, F.ffcz_last_error())
+    for p, a, b, sa, sb in zip(probs, ys_l, ys_m, stats_l, stats_m):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), p.x.shape
+        assert sa == sb, (p.x.shape, sa, sb)
+    for p, y, s in zip(probs, ys_l, stats_l):
+        _check(p, y, s, dt)
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
 def test_batched_matches_single_calls_bitwise(dt):
     # a group of same-shape members and single calls run the same passes (FP64 fields: the
     # closing pass fused with the verification's first pass, over 3 instances or 1)
