@@ -443,9 +443,11 @@ def main():
     from paper_2601_01596_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    # tile decisions of this process, written to a scratch file and reported under extra.tuning
+    # tile decisions of this process, written to a scratch file (or to FFCZ_PLAN_CACHE, so that
+    # several runs, such as the counter passes of one profile, share them) and reported under
+    # extra.tuning
     import tempfile
-    tune_path = os.path.join(tempfile.mkdtemp(prefix="ffcz_bench_"), "plans.json")
+    tune_path = os.environ.get("FFCZ_PLAN_CACHE") or os.path.join(tempfile.mkdtemp(prefix="ffcz_bench_"), "plans.json")
     F.ffcz_set_tuning(1, tune_path)
     n = args.n
     log(f"[bench] generating {n}^3 lognormal field (seed 2)")

@@ -421,14 +421,21 @@ size_t ffcz_batched_workspace_bytes(int32_t dtype, int32_t count, const ffcz_ins
 /* Alg. 1 on many fields of uneven size in one call (the paper treats 1D, 2D
  * and 3D data alike, Sec. IV-C).  Members of the same 2D shape share every
  * launch (their spectra are stacked; each keeps its own bounds, counts and
- * done-flag); 1D members take any length 1..2^19, with a length-L DFT by
- * four-step FFTs and, for lengths that are not powers of two, Bluestein's
- * chirp-z convolution: those whose work length is below 2^tiled_1d_lg run one
- * block per signal with the whole loop inside one launch, longer ones run as
- * tiled passes (many blocks per signal) whose rounds the host enqueues in
- * chunks, polling the signals' done-flags; 3D members run one after another.  Options as in ffcz_correct except that masks
- * and per-round counts are not recorded.  stats: NULL or a host array[count].
- * Returns the worst member status (negative if any member failed). */
+ * done-flag); 3D members run one after another.  1D members take any length
+ * 1..2^19, with a length-L DFT by four-step FFTs and, for lengths that are not
+ * powers of two, Bluestein's chirp-z convolution.  A 1D length class runs
+ * either one block per signal with the whole loop inside one launch (its work
+ * buffer in LDS when it fits, see resident_1d), beside everything else, or as
+ * tiled passes (many blocks per signal); tiled_1d_lg describes the choice.
+ * The rounds of the grouped members and of the tiled 1D classes are enqueued
+ * in chunks, each chunk one hipGraph replay (both kinds as parallel branches
+ * of one graph when the batch has both), with one host poll of the done-flags
+ * per chunk; the call returns when every member is finished and verified.
+ * The first call with a new shape or length class may time tile variants and
+ * the 1D forms on the call's own data (see ffcz_set_tuning).  Options as in
+ * ffcz_correct except that masks and per-round counts are not recorded.
+ * stats: NULL or a host array[count].  Returns the worst member status
+ * (negative if any member failed). */
 int32_t ffcz_correct_batched(int32_t dtype, int32_t count, const ffcz_instance* inst, int32_t max_iter,
                              const ffcz_options* opts, void* workspace, size_t workspace_bytes, void* stream,
                              ffcz_stats* stats);

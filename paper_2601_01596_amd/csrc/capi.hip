@@ -303,19 +303,38 @@ int init_variant(const Plan& p) {
   return (p.vz == 3 && p.dt == FFCZ_F32 && (p.H == 128 || p.H == 256)) ? 3 : 0;
 }
 
+// Neighbouring column tiles that read parts of the same 128-byte lines (1 when a tile row fills
+// a line), and the tiles per outer index, padded to a multiple of that so that each group of
+// neighbours runs on one XCD (xcd_tile; padding tiles hold no column).  FFCZ_XCD_ORDER=0 keeps
+// the plain order (for measurement); both orders give identical bits.
+bool xcd_order_on() {
+  static const bool on = [] {
+    const char* e = getenv("FFCZ_XCD_ORDER");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+int col_line_share(int dt, int L, int v) {
+  const int row_bytes = col_block_cols(dt, L, v) * (dt == FFCZ_F32 ? 8 : 16);
+  return (xcd_order_on() && row_bytes < 128) ? 128 / row_bytes : 1;
+}
+int64_t col_tiles(int dt, int L, int v, int64_t ncols) {
+  const int C = col_block_cols(dt, L, v), k = col_line_share(dt, L, v);
+  return ((ncols + C - 1) / C + k - 1) / k * k;
+}
+
 void set_variants(Plan& p, int vy, int vx, int vz) {
   p.vy = vy;
   p.vx = vx;
   p.vz = vz;
   const int64_t outer_x = p.nd == 3 ? p.n[1] : 1;
-  const int Cx = col_block_cols(p.dt, p.Lx, vx), Cx64 = col_block_cols(1, p.Lx, 0);
   const int Rz = row_block_rows(p.dt, p.H, vz), Rz64 = row_block_rows(1, p.H, kVerifyRowPlan);
   p.zbpi = (p.nrows + Rz - 1) / Rz;
   const int Ri = row_block_rows(p.dt, p.H, init_variant(p));
   p.ibpi = (p.nrows + Ri - 1) / Ri;
   p.vzbpi = (p.nrows + Rz64 - 1) / Rz64;
-  p.xbpi = outer_x * ((p.ncols + Cx - 1) / Cx);
-  p.vxbpi = outer_x * ((p.ncols + Cx64 - 1) / Cx64);
+  p.xbpi = outer_x * col_tiles(p.dt, p.Lx, vx, p.ncols);
+  p.vxbpi = outer_x * col_tiles(FFCZ_F64, p.Lx, 0, p.ncols);
 }
 
 int32_t make_plan(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max_iter, int64_t B, Plan& p) {
@@ -365,10 +384,11 @@ int32_t make_plan(int32_t dtype, int32_t ndim, const int64_t* shape, int32_t max
   {
     // partial slots for the narrowest tiles any variant uses
     const int64_t outer_x = nd == 3 ? p.n[1] : 1;
-    const int Cmin = col_block_cols(dtype, p.Lx, kColVariants - 1);
+    int64_t xtiles = 0;
+    for (int v = 0; v < kColVariants; ++v) xtiles = std::max(xtiles, col_tiles(dtype, p.Lx, v, p.ncols));
     int Rmin = row_block_rows(dtype, p.H, 0);
     for (int v = 1; v < kRowVariants; ++v) Rmin = std::min(Rmin, row_block_rows(dtype, p.H, v));
-    const int64_t zmax = (p.nrows + Rmin - 1) / Rmin, xmax = outer_x * ((p.ncols + Cmin - 1) / Cmin);
+    const int64_t zmax = (p.nrows + Rmin - 1) / Rmin, xmax = outer_x * xtiles;
     p.pmax = B * std::max(std::max(zmax, p.vzbpi), std::max(xmax, p.vxbpi));
   }
   size_t off = 0;
@@ -901,13 +921,13 @@ hipError_t run_col(int dt, int mode, int v, const ColGeom& g, const Plan& p, con
                    int64_t bnd_s = 0, int bnd_dbl = 0) {
   ColArgs<T> a;
   memset(&a, 0, sizeof(a));
-  const int C = col_block_cols(dt, g.L, v);
   a.src = (const cx<T>*)src;
   a.dst = (cx<T>*)dst;
   a.so = g.so;
   a.s = g.s;
   a.ncols = (int32_t)p.ncols;
-  a.ncb = (int32_t)((p.ncols + C - 1) / C);
+  a.ncb = (int32_t)col_tiles(dt, g.L, v, p.ncols);
+  a.xcd_k = col_line_share(dt, g.L, v);
   a.outer_per_inst = g.outer_per_inst;
   a.tw = (const cx<T>*)tw;
   a.st = st;

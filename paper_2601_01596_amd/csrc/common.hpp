@@ -101,8 +101,25 @@ struct ColArgs {
   // in the loop, the working-type spectrum's layout in the FP64 verification
   const void* bnd;
   int64_t bnd_so, bnd_s;
-  int32_t bnd_dbl, pad4;
+  int32_t bnd_dbl;
+  // neighbouring tiles that share 128-byte lines (1: none); the grid holds a multiple of it per
+  // outer index and the kernel runs each such group on one XCD (xcd_tile)
+  int32_t xcd_k;
 };
+
+// Logical tile of physical block p.  Blocks are dealt round-robin to the 8 XCDs, each with its
+// own L2.  When a tile is narrower than a 128-byte line, k neighbouring tiles read parts of the
+// same lines; the k tiles of an aligned run go to physical blocks x, x + 8, ..., x + 8 (k - 1)
+// of a group of 8 k, which land on one XCD at about the same time, so each line is fetched into
+// that L2 once.  A ragged last group keeps the plain order.  A permutation: every tile runs once.
+__device__ __forceinline__ int64_t xcd_tile(int64_t p, int64_t n, int k) {
+  if (k <= 1) return p;
+  const int64_t G = 8 * (int64_t)k;
+  const int64_t g = p / G;
+  if ((g + 1) * G > n) return p;
+  const int64_t r = p - g * G;
+  return g * G + (int64_t)k * (r & 7) + (r >> 3);
+}
 
 template <typename T, typename TIO>
 struct RowArgs {

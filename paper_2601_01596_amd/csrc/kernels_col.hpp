@@ -24,7 +24,7 @@ col_kernel(ColArgs<T> a) {
   __shared__ unsigned long long red_u[NW];
   __shared__ double red_d[NW];
 
-  const int64_t bid = blockIdx.x;
+  const int64_t bid = xcd_tile(blockIdx.x, gridDim.x, a.xcd_k);
   const int64_t o = bid / a.ncb;
   DevState* st = a.st + o / a.outer_per_inst;
   constexpr bool uses_done =
@@ -139,7 +139,7 @@ col_kernel(ColArgs<T> a) {
       if (rec) {
         const unsigned long long bre = __ballot(valid && kre);
         const unsigned long long bim = __ballot(valid && kim);
-        if (c == 0) {
+        if (c == 0 && cb * C < a.ncols) {  // a padding tile holds no column
           const int64_t row = (int64_t)(j + q * P) * a.mrow_i + o * a.mrow_o;
           const int64_t off = row * a.f_row_bytes + (cb * C) / 8;
           if constexpr (C == 16) {

@@ -116,6 +116,37 @@ def test_lds_resident_1d_matches_memory_bitwise(dt):
 
 
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_mixed_batch_graph_and_plain_launches_bitwise(dt):
+    # a mixed batch (two 2D groups, tiled and one-block 1D classes): its chunks replayed as one
+    # graph with two branches, or launched plainly on two streams, and in chunks of 1 or 4
+    # rounds, give identical bits, counts and maxima
+    probs = [_member((64, 128), 800 + i, dt) for i in range(3)] + [_member((32, 32), 810, dt)]
+    probs += [_member((L,), 820 + i, dt) for i, L in enumerate([3000, 5000, 40000, 70000, 131072])]
+    runs = [_run(probs, tiled_1d_lg=14, graph=g, chunk=c) for g, c in ((True, 4), (False, 4), (True, 1))]
+    for ys, st, stats in runs:
+        assert st == F.OK, (st, F.ffcz_last_error())
+    ys0, _, st0 = runs[0]
+    for ys, _, stats in runs[1:]:
+        for p, a, b, sa, sb in zip(probs, ys0, ys, st0, stats):
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), p.x.shape
+            assert sa == sb, (p.x.shape, sa, sb)
+    for p, y, s in zip(probs, ys0, st0):
+        _check(p, y, s, dt)
+
+
+def test_mixed_batch_fixed_rounds():
+    # fixed rounds in a mixed batch: every member runs exactly max_iter projection blocks
+    probs = [_member((64, 64), 830 + i, np.float32) for i in range(2)]
+    probs += [_member((L,), 840 + i, np.float32) for i, L in enumerate([1000, 9000, 70000])]
+    ys, st, stats = _run(probs, max_iter=7, fixed=True, tiled_1d_lg=14)
+    assert st == F.OK, (st, F.ffcz_last_error())
+    assert [s["rounds"] for s in stats] == [7] * len(probs)
+    for p, y, s in zip(probs, ys, stats):
+        orc = O.correct(p.x, p.xb, p.E, p.Delta, 7, mu=s["margin_used"], fixed=True)
+        assert rel_err(y, orc.y) <= 1e-5
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
 def test_batched_matches_single_calls_bitwise(dt):
     # a group of same-shape members and single calls run the same passes (FP64 fields: the
     # closing pass fused with the verification's first pass, over 3 instances or 1)

@@ -104,3 +104,44 @@ def test_edit_streams_of_an_encoded_field():
         say(f"[huffman] {name}: {t.numel()} symbols, {t.numel() * t.element_size()} -> {nb} bytes")
     say(f"[huffman] edits of the 64^3 field: {total_in} -> {total_out} bytes")
     assert total_out < total_in
+
+
+def test_corrupt_streams_are_refused():
+    # the decoder checks the header (magic, width, chunk count) and the stored code lengths
+    # (at most 32 bits, Kraft sum at most 1) before it launches; a corrupt stream is refused
+    import torch
+    g = np.random.default_rng(5)
+    sym = np.rint(g.standard_normal(5000) * 40).astype(np.int32)
+    stream, sizes = F.huffman_compress(torch.from_numpy(sym).cuda())
+    n, na = sym.size, int(sizes.nalpha)
+    good = F.huffman_decompress(stream, n, torch.int32, na)
+    np.testing.assert_array_equal(good.cpu().numpy()[:n], sym)
+
+    def refused(mutate):
+        b = stream.clone()
+        mutate(b)
+        with pytest.raises(F.FFCzError) as ei:
+            F.huffman_decompress(b, n, torch.int32, na)
+        assert ei.value.status == F.E_INVALID
+
+    def bad_magic(b):
+        b[0] ^= 0xFF
+
+    def bad_chunks(b):  # header word 5 (int64): the chunk count
+        h = b[:HDR].cpu().numpy().view(np.int64).copy()
+        h[5] += 1
+        b[:HDR] = torch.from_numpy(h.view(np.uint8)).cuda()
+
+    def over_kraft(b):  # every present symbol gets a 1-bit code
+        lens = b[HDR:HDR + na]
+        b[HDR:HDR + na] = torch.where(lens > 0, torch.ones_like(lens), lens)
+
+    def too_long(b):
+        i = int(np.argmax(b[HDR:HDR + na].cpu().numpy()))
+        b[HDR + i] = 33
+
+    for m in (bad_magic, bad_chunks, over_kraft, too_long):
+        refused(m)
+    with pytest.raises(F.FFCzError):  # wrong symbol width
+        F.huffman_decompress(stream, n, torch.uint8, na)
+
