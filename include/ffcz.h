@@ -87,7 +87,7 @@ typedef struct {
    * the caller's stream; 0: plain launches.  Ignored while profiling. */
   int32_t use_graph;
   /* Batched 1D members whose power-of-two work length Mc (Mc = L for a
-   * power-of-two L >= 4, else the Bluestein length >= 2L - 1) is at least
+   * power-of-two L >= 4, else the Bluestein length >= L + floor(L/2)) is at least
    * 2^tiled_1d_lg run as tiled passes, many blocks per signal, with the rounds
    * driven by the host; shorter ones run one block per signal for the whole
    * correction.  Values below 12 count as 12; above 20 keep every 1D member on

@@ -60,6 +60,7 @@ hipError_t launch_bounds_col_f64(int mode, int L, const void* args, int64_t nb, 
 // verification in FP64 (SigArgs<double>).
 bool sig_mode_fp64(int mode, int iodt) {
   const bool loop = mode == SIG_RUN || mode == SIG_RUNL || mode == SIGT_EPS0 || mode == SIGT_CIN || mode == SIGT_RMUL ||
+                    mode == SIGT_RMULI ||
                     mode == SIGT_RCHECK || mode == SIGT_CCHECK || mode == SIGT_CSPAT || mode == SIGT_Y;
   return !loop || iodt == 1;
 }
@@ -1928,7 +1929,7 @@ struct SigPlan {
   int64_t L = 0;
   int blue = 0;
   int lgMc = 0;
-  size_t conv64 = 0, btab = 0, btab64 = 0, chirp = 0, chirp64 = 0, eps = 0, bytes = 0;  // offsets in the signal block
+  size_t conv64 = 0, btab = 0, btab64 = 0, btabi = 0, chirp = 0, chirp64 = 0, eps = 0, bytes = 0;  // offsets in the signal block
 };
 
 SigPlan sig_plan(int dt, int64_t L) {
@@ -1936,7 +1937,8 @@ SigPlan sig_plan(int dt, int64_t L) {
   s.dt = dt;
   s.L = L;
   s.blue = (is_pow2(L) && L >= 4) ? 0 : 1;  // direct four-step needs Mc = L >= 4
-  s.lgMc = s.blue ? ceil_lg(2 * L - 1) : ceil_lg(L);
+  // Bluestein over the half spectrum: Mc >= L + K - 1 with K = floor(L/2) + 1
+  s.lgMc = s.blue ? ceil_lg(L + L / 2) : ceil_lg(L);
   if (s.lgMc < 2) s.lgMc = 2;
   const size_t Mc = (size_t)1 << s.lgMc;
   size_t off = 0;
@@ -1956,6 +1958,8 @@ SigPlan sig_plan(int dt, int64_t L) {
       s.btab = s.btab64;
       s.chirp = s.chirp64;
     }
+    s.btabi = off;  // the reflected table, in the loop's working type
+    off = align_up(off + (dt == FFCZ_F32 ? 8 : 16) * Mc, 256);
   }
   s.eps = off;
   off = align_up(off + (dt == FFCZ_F32 ? 4 : 8) * (size_t)L, 256);
@@ -2304,6 +2308,7 @@ int32_t sig_prepare(const BatchPlan& bp, const ffcz_instance* inst, const double
     if (sp.blue) {
       d.btab = b + sp.btab;
       d.btab64 = b + sp.btab64;
+      d.btabi = b + sp.btabi;
       d.chirp = b + sp.chirp;
       d.chirp64 = b + sp.chirp64;
     }
@@ -2399,7 +2404,7 @@ hipError_t sig_trial(const BatchPlan& bp, char* ws, const int32_t* ord, int lg, 
                        (int32_t)nb, (int32_t)bp.tpart_tiles.at(lg), (int32_t)nct, (int32_t)nrt, (int32_t)rounds,
                        (int32_t)1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (blue && (e = go(SIGT_RMUL)) != hipSuccess) return e;
+    if (blue && (e = go(SIGT_RMULI)) != hipSuccess) return e;
     if ((e = go(SIGT_CSPAT)) != hipSuccess) return e;
   }
   return go(SIGT_Y);
@@ -2548,7 +2553,7 @@ struct SigRun {
                            (const unsigned long long*)(ws + bp->tpart_off.at(lg)), (int32_t)nb,
                            (int32_t)bp->tpart_tiles.at(lg), (int32_t)nct, (int32_t)nrt, max_iter, (int32_t)fixed);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (b && (e = go(SIGT_RMUL, lg, st)) != hipSuccess) return e;
+        if (b && (e = go(SIGT_RMULI, lg, st)) != hipSuccess) return e;
         if ((e = go(SIGT_CSPAT, lg, st)) != hipSuccess) return e;
       }
     }

@@ -10,11 +10,19 @@
 //   four-step inverse: row pass (MA-point inverse, times W_Mc^{-n1 k2}),
 //     column pass (MB-point inverse) back to natural order.
 // L a power of two: Mc = L and the DFT is the four-step itself.  Otherwise
-// Bluestein (chirp z): with w[n] = exp(-i pi n^2 / L),
-//   X[k] = w[k] (a conv b)[k],  a[n] = v[n] w[n],  b[m] = conj(w[m]) (m in (-L, L)),
+// Bluestein (chirp z): with w[n] = exp(-i pi n^2 / L) (even in n),
+//   X[k] = w[k] (a conv b)[k],  a[n] = v[n] w[n],  b[m] = conj(w[m]),
 // the circular convolution done as forward four-step, product with the
-// precomputed spectrum of b (times 1/Mc), inverse four-step, with
-// Mc >= 2L - 1.  The inverse DFT is conj(DFT(conj X)).
+// precomputed spectrum of b (times 1/Mc), inverse four-step.  The data are
+// real, so only X[k] for k < K = floor(L/2) + 1 is needed, and b only over
+// m in [-(L-1), K-1]; the inverse takes only those K coefficients: with
+// g[0] = 1, g[L/2] = 1 (L even) and g[k] = 2 otherwise,
+//   L eps[n] = Re(U[n]),  U[n] = sum_{k<K} g[k] X'[k] exp(+2 pi i n k / L),
+// and conj(U[n]) = w[n] (a2 conv b)[n] with a2[k] = conj(g[k] X'[k]) w[k],
+// now over m = n - k in [-(K-1), L-1]: the reflection of the forward range, so
+// its spectrum is the forward one at index -k (a second table).  Neither
+// range wraps onto itself for Mc >= L + K - 1 (about 1.5 L, against 2L - 1
+// for the whole spectrum), which halves Mc for L up to 4/3 of a power of two.
 //
 // Per round (Alg. 1) the block runs: [row] [column: finish the forward DFT,
 // count violations over k <= L/2, clip Re/Im, start the inverse DFT] [row]
@@ -49,8 +57,9 @@ struct SigDesc {
   double E, Delta, Ep, Dc, Dp;  // bounds, shrunk s-bound, check threshold, shrunk f-bound
   void* conv;         // Mc complex of the working type (aliases conv64)
   void* conv64;       // Mc complex FP64 (set-up and verification)
-  void* btab;         // Mc complex, working type, row-pass layout (Bluestein)
+  void* btab;         // Mc complex, working type, row-pass layout (Bluestein): spectrum of b / Mc
   void* btab64;       // Mc complex FP64, row-pass layout (Bluestein)
+  void* btabi;        // Mc complex, working type, row-pass layout: entry k holds entry -k of btab
   void* chirp;        // L complex, working type (Bluestein)
   void* chirp64;      // L complex FP64 (Bluestein)
   void* eps;          // L reals, working type (the iterate)
@@ -131,13 +140,14 @@ enum SigMode : int {
   SIGT_VCOL = 13,   // verification: column pass of d = y - x (FP64)
   SIGT_VROW = 14,   // verification: row pass (Bluestein: x spectrum of b; else maxima partials)
   SIGT_VCOL2 = 15,  // verification: final column pass, maxima partials         [Bluestein]
-  SIG_RUNL = 16     // as SIG_RUN with the work buffer resident in LDS
+  SIG_RUNL = 16,    // as SIG_RUN with the work buffer resident in LDS
+  SIGT_RMULI = 17   // row pass of the inverse DFT: forward, x reflected spectrum, inverse [Bluestein]
 };
 
-__host__ __device__ constexpr bool sig_tiled(int m) { return m >= SIGT_CHIRP && m <= SIGT_VCOL2; }
+__host__ __device__ constexpr bool sig_tiled(int m) { return (m >= SIGT_CHIRP && m <= SIGT_VCOL2) || m == SIGT_RMULI; }
 // tiled passes laid out over row tiles; all others over column tiles / element chunks
 __host__ __device__ constexpr bool sig_row_tiled(int m) {
-  return m == SIGT_BROW || m == SIGT_RMUL || m == SIGT_RCHECK || m == SIGT_VROW;
+  return m == SIGT_BROW || m == SIGT_RMUL || m == SIGT_RMULI || m == SIGT_RCHECK || m == SIGT_VROW;
 }
 // tiled passes that work on element chunks only (no transform, no LDS)
 __host__ __device__ constexpr bool sig_elem_tiled(int m) {
@@ -205,7 +215,8 @@ sig_kernel(SigArgs<T> a) {
   const int t = threadIdx.x;
   // the loop (SIG_RUN and the round passes) works in T = the data type; set-up and
   // verification in FP64 on the FP64 buffers
-  constexpr bool loopT = (MODE == SIG_RUN || MODE == SIG_RUNL || MODE == SIGT_EPS0 || MODE == SIGT_CIN || MODE == SIGT_RMUL ||
+  constexpr bool loopT = (MODE == SIG_RUN || MODE == SIG_RUNL || MODE == SIGT_EPS0 || MODE == SIGT_CIN ||
+                          MODE == SIGT_RMUL || MODE == SIGT_RMULI ||
                           MODE == SIGT_RCHECK || MODE == SIGT_CCHECK || MODE == SIGT_CSPAT || MODE == SIGT_Y);
   // the work buffer: in memory at a row pitch of MA, or (SIG_RUNL) in LDS at a pitch of LPA,
   // where each pass's FFT exchanges run in place inside the tile the pass owns
@@ -214,17 +225,19 @@ sig_kernel(SigArgs<T> a) {
   cx<T>* conv = RES ? lds : (cx<T>*)(loopT ? sd.conv : sd.conv64);
   const cx<T>* chirp = (const cx<T>*)(loopT ? sd.chirp : sd.chirp64);
   const cx<T>* btab = (const cx<T>*)(loopT ? sd.btab : sd.btab64);
+  const cx<T>* btabi = (const cx<T>*)sd.btabi;  // the loop's inverse row passes only
   // tiled partial slot of this block
   auto pslot = [&](int kind) -> unsigned long long& {
     return a.part[((int64_t)kind * a.nsig + slot) * a.ptiles + tile];
   };
   // the tiled round passes stop once the signal's loop has ended
-  if constexpr (MODE == SIGT_RMUL || MODE == SIGT_RCHECK || MODE == SIGT_CCHECK || MODE == SIGT_CSPAT) {
+  if constexpr (MODE == SIGT_RMUL || MODE == SIGT_RMULI || MODE == SIGT_RCHECK || MODE == SIGT_CCHECK ||
+                MODE == SIGT_CSPAT) {
     if (*(volatile int32_t*)&so->done) return;
   }
   // passes that exist only for one kind of length
   if constexpr (MODE == SIGT_CHIRP || MODE == SIGT_BCOL || MODE == SIGT_BROW || MODE == SIGT_RMUL ||
-                MODE == SIGT_CCHECK || MODE == SIGT_VCOL2) {
+                MODE == SIGT_RMULI || MODE == SIGT_CCHECK || MODE == SIGT_VCOL2) {
     if (!blue) return;
   }
   if constexpr (MODE == SIGT_RCHECK) {
@@ -393,11 +406,12 @@ sig_kernel(SigArgs<T> a) {
       __syncthreads();
     }
     if constexpr (MODE == SIG_SETUP || MODE == SIGT_BCOL) {
+      const int64_t K = L / 2 + 1;
       auto bin = [&](int n1, int i) -> cx<T> {
         const int64_t n = n1 + (int64_t)MA * i;
         int64_t m = -1;
-        if (n < L) m = n;
-        else if (n > Mc - L) m = Mc - n;
+        if (n < K) m = n;                   // b[m], m in [0, K-1]
+        else if (n > Mc - L) m = Mc - n;    // b[-m], m in [1, L-1]
         if (m < 0) return zero;
         const cx<double> w = ch64[m];
         return cx<T>{(T)w.re, (T)(-w.im)};
@@ -406,16 +420,20 @@ sig_kernel(SigArgs<T> a) {
       col_pass(FF{}, TT{}, bin, ident);
       if constexpr (MODE == SIGT_BCOL) return;
     }
-    // row FFT; store (1/Mc) * spectrum in the row-pass layout of both precisions
+    // row FFT; store (1/Mc) * spectrum in the row-pass layout of both precisions, and the loop's
+    // reflected table: entry k of the spectrum also at index -k (the loop's working type)
     cx<float>* bt32 = (sd.btab != sd.btab64) ? (cx<float>*)sd.btab : nullptr;
     cx<double>* bt64 = (cx<double>*)sd.btab64;
     const double inv = 1.0 / (double)Mc;
     auto store_b = [&](int k2, int k1, cx<T> v) {
-      bt64[G::rpos(k2, k1)] = cx<double>{(double)v.re * inv, (double)v.im * inv};
-      if (bt32) {
-        using G32 = SigGeom<float, MA, MB>;
-        bt32[G32::rpos(k2, k1)] = cx<float>{__double2float_rn((double)v.re * inv), __double2float_rn((double)v.im * inv)};
-      }
+      const cx<double> b64{(double)v.re * inv, (double)v.im * inv};
+      const cx<float> b32{__double2float_rn(b64.re), __double2float_rn(b64.im)};
+      bt64[G::rpos(k2, k1)] = b64;
+      if (bt32) bt32[G::rpos(k2, k1)] = b32;  // the row layout does not depend on the type
+      const int64_t kr = ((int64_t)Mc - (k2 + (int64_t)MB * k1)) & (Mc - 1);
+      const int64_t ri = G::rpos((int)(kr % MB), (int)(kr / MB));
+      if (bt32) ((cx<float>*)sd.btabi)[ri] = b32;
+      else ((cx<double>*)sd.btabi)[ri] = b64;
       return v;
     };
     row_pass(FF{}, store_b);
@@ -507,6 +525,8 @@ sig_kernel(SigArgs<T> a) {
   };
   auto ident = [&](int, int, cx<T> v) { return v; };
   auto mulb = [&](int k2, int k1, cx<T> v) { return cmul(v, btab[(int64_t)G::rpos(k2, k1)]); };
+  auto mulbi = [&](int k2, int k1, cx<T> v) { return cmul(v, btabi[(int64_t)G::rpos(k2, k1)]); };
+  const int64_t Kh = L / 2 + 1;  // half-spectrum entries
   unsigned long long cnt = 0, sc = 0;
   // row: the forward DFT completes here -> count + clip -> inverse row FFT (power of two)
   auto rop = [&](int k2, int k1, cx<T> X) {
@@ -514,14 +534,16 @@ sig_kernel(SigArgs<T> a) {
     if (kk <= L / 2 && (fabs(X.re) > D || fabs(X.im) > D)) ++cnt;
     return cx<T>{clipv(X.re, Dp), clipv(X.im, Dp)};
   };
-  // column: X = w c -> count + clip -> start the inverse DFT with conj(X') w (Bluestein)
+  // column: X = w c for k < K -> count + clip -> start the inverse DFT with conj(g X') w
+  // (Bluestein; the entries k >= K are not needed and start the inverse as zero)
   auto fop = [&](int n1, int i, cx<T> c) -> cx<T> {
     const int64_t n = n1 + (int64_t)MA * i;
-    if (n >= L) return zero;
+    if (n >= Kh) return zero;
     const cx<T> w = chirp[n];
     const cx<T> X = cmul(w, c);
-    if (n <= L / 2 && (fabs(X.re) > D || fabs(X.im) > D)) ++cnt;
-    const cx<T> Xc{clipv(X.re, Dp), -clipv(X.im, Dp)};
+    if (fabs(X.re) > D || fabs(X.im) > D) ++cnt;
+    const T g = (n == 0 || 2 * n == L) ? T(1) : T(2);
+    const cx<T> Xc{g * clipv(X.re, Dp), -(g * clipv(X.im, Dp))};
     return cmul(Xc, w);
   };
   // column: finish the inverse DFT, spatial clip, start the next forward DFT
@@ -587,7 +609,7 @@ sig_kernel(SigArgs<T> a) {
         if (k == 0) v0 = cnt;
         vk = cnt;
         if ((!a.fixed && cnt == 0) || k >= a.max_iter) break;
-        if (blue) row_pass(TT{}, mulb);
+        if (blue) row_pass(TT{}, mulbi);
         sc = 0;
         col_pass(TT{}, TT{}, [&](int, int) { return zero; }, sop);
         sclip += block_sum<NT>(sc, red_u);
@@ -616,6 +638,10 @@ sig_kernel(SigArgs<T> a) {
   }
   if constexpr (MODE == SIGT_RMUL) {
     row_pass(TT{}, mulb);
+    return;
+  }
+  if constexpr (MODE == SIGT_RMULI) {
+    row_pass(TT{}, mulbi);
     return;
   }
   if constexpr (MODE == SIGT_RCHECK) {

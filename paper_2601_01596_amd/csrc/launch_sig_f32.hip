@@ -15,6 +15,7 @@ hipError_t launch_sig_f32(int mode, int lgMc, const void* args, int nsig, hipStr
     case SIGT_EPS0: return sig_go<float, float, SIGT_EPS0>(lgMc, a, nsig, s);
     case SIGT_CIN: return sig_go<float, float, SIGT_CIN>(lgMc, a, nsig, s);
     case SIGT_RMUL: return sig_go<float, float, SIGT_RMUL>(lgMc, a, nsig, s);
+    case SIGT_RMULI: return sig_go<float, float, SIGT_RMULI>(lgMc, a, nsig, s);
     case SIGT_RCHECK: return sig_go<float, float, SIGT_RCHECK>(lgMc, a, nsig, s);
     case SIGT_CCHECK: return sig_go<float, float, SIGT_CCHECK>(lgMc, a, nsig, s);
     case SIGT_CSPAT: return sig_go<float, float, SIGT_CSPAT>(lgMc, a, nsig, s);

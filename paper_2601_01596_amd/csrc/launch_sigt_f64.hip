@@ -19,6 +19,7 @@ hipError_t launch_sigt_f64(int mode, int iodt, int lgMc, const void* args, int n
     case SIGT_EPS0: return sig_go<double, double, SIGT_EPS0>(lgMc, a, nsig, s);
     case SIGT_CIN: return sig_go<double, double, SIGT_CIN>(lgMc, a, nsig, s);
     case SIGT_RMUL: return sig_go<double, double, SIGT_RMUL>(lgMc, a, nsig, s);
+    case SIGT_RMULI: return sig_go<double, double, SIGT_RMULI>(lgMc, a, nsig, s);
     case SIGT_RCHECK: return sig_go<double, double, SIGT_RCHECK>(lgMc, a, nsig, s);
     case SIGT_CCHECK: return sig_go<double, double, SIGT_CCHECK>(lgMc, a, nsig, s);
     case SIGT_CSPAT: return sig_go<double, double, SIGT_CSPAT>(lgMc, a, nsig, s);
