@@ -343,14 +343,16 @@ def test_output_independent_of_verification(dt, shape):
 
 @pytest.mark.parametrize("mode,dt,shape", [(3, np.float32, (32, 64, 256)), (3, np.float64, (16, 32, 512)),
                                            (3, np.float32, (128, 1024)), (3, np.float64, (64, 128)),
+                                           (3, np.float32, (1024, 64)), (3, np.float32, (2048, 32)),
+                                           (3, np.float32, (8, 1024, 16)), (3, np.float64, (1024, 32)),
                                            (4, np.float32, (16, 32, 512)), (4, np.float32, (2, 4, 512)),
                                            (4, np.float32, (256, 512)), (4, np.float64, (16, 32, 512)),
                                            (4, np.float32, (16, 32, 256)), (4, np.float32, (4, 8, 256)),
                                            (4, np.float32, (64, 256))])
 def test_rounding_plans_match_oracle(mode, dt, shape):
-    # the radix-8 last-axis plan (mode 3) and the direct last-axis loop pass (mode 4, FP32 rows
-    # of 256 entries; FP64 runs the narrow tiles) round differently from the default plan but
-    # meet the same bars
+    # the radix-8 last-axis plan (mode 3; long columns included) and the direct last-axis loop
+    # pass (mode 4, FP32 rows of 256 entries; FP64 runs the narrow tiles) round differently
+    # from the default plan but meet the same bars
     p = _problem(shape, 77, dt)
     try:
         F.ffcz_set_tuning(mode)
