@@ -544,6 +544,12 @@ def main():
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
         cpu = cpu_baseline(p32, r32.stats["rounds"])
+    # every plan decision of the run (the later legs' shapes and 1D length classes included)
+    try:
+        with open(tune_path) as fh:
+            extra["tuning"] = {k: v for k, v in json.load(fh)["entries"].items()}
+    except (OSError, ValueError, KeyError):
+        pass
 
     out = {
         "metric": METRIC,

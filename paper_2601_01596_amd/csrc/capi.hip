@@ -2510,9 +2510,11 @@ struct SigRun {
       for (int k : kv.second) (bp->sigs[k].blue ? b : p2) = true;
       kinds[lg] = {b, p2};
     }
-    // the one-block classes run their whole correction beside the tiled rounds
+    // the one-block classes run their whole correction on their own stream, beside the tiled
+    // rounds (and, in a mixed batch, beside the grouped members: the set-up's end on s does
+    // not wait for them)
     hipStream_t sb = s;
-    if (!oneblock.empty() && !tiled.empty() && side) {
+    if (!oneblock.empty() && side) {
       HIPCHK(hipEventRecord(fork, s));
       HIPCHK(hipStreamWaitEvent(side, fork, 0));
       sb = side;
