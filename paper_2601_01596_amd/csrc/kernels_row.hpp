@@ -659,6 +659,13 @@ template <int P>
 __device__ __forceinline__ cx<float> group_partner(cx<float> z) {
   return cx<float>{group_partner<P>(z.re), group_partner<P>(z.im)};
 }
+// The value z of lane (P - j) mod P of the lane's group (j = lane mod P), through the
+// LDS crossbar (ds_bpermute: no LDS storage, no barrier); baddr = 4 x that lane's index
+// in the wave.  Lane 0 of a group reads its own z.
+__device__ __forceinline__ cx<float> lane_read(cx<float> z, int baddr) {
+  return cx<float>{__int_as_float(__builtin_amdgcn_ds_bpermute(baddr, __float_as_int(z.re))),
+                   __int_as_float(__builtin_amdgcn_ds_bpermute(baddr, __float_as_int(z.im)))};
+}
 
 // Row pitch (entries) of the direct passes: H entries skewed as i + (i >> log2 P),
 // rounded up to = P mod 32 8-byte slots, so the 64 / P rows of a wave fill every
@@ -726,11 +733,18 @@ __global__ void __launch_bounds__(ROWS * (H / 16), 4) row_direct_kernel(RowArgs<
   const int j = t & (P - 1);
   const int rl = t / P;
   const int nrow = (int)((a.rows_per_inst - lrow0) < ROWS ? (a.rows_per_inst - lrow0) : ROWS);
+  // Lanes past the block's last row (only in an instance's last block) repeat that row:
+  // same loads, same arithmetic, so their stores write the same bytes to the same
+  // addresses, and loads and stores need no per-lane guard; they count nothing and
+  // record no mask bits.  They keep their own LDS row for the exchange.
   const bool valid = rl < nrow;
+  const int rr = valid ? rl : nrow - 1;
   const cx<T>* rtw = tws + TW;
-  const int64_t g0 = (lrow0 + rl) * H;  // first real pair of the row in the fields
+  // ds_bpermute address of lane (P - j) mod P of this lane's group, the C2R / R2C partner
+  const int paddr = 4 * (((t & 63) & ~(P - 1)) | ((P - j) & (P - 1)));
+  const int64_t g0 = (lrow0 + rr) * H;  // first real pair of the row in the fields
   // s-mask bits 2m, 2m+1 of this row (real pair m)
-  auto sbit = [&](int m, int b) -> bool { return (sbits[rl * SW + (2 * m) / 32] >> (((2 * m) & 31) + b)) & 1u; };
+  auto sbit = [&](int m, int b) -> bool { return (sbits[rr * SW + (2 * m) / 32] >> (((2 * m) & 31) + b)) & 1u; };
 
   for (int i = t; i < TW + H; i += NT) tws[i] = a.tw[i];
   int kround = 0;
@@ -748,9 +762,14 @@ __global__ void __launch_bounds__(ROWS * (H / 16), 4) row_direct_kernel(RowArgs<
       sbits[i] = (r < nrow && w < a.s_row_w32) ? a.smask[(row0 + r) * a.s_row_w32 + w] : 0u;
     }
   }
-  unsigned long long cnt = 0;
+  uint32_t cnt = 0;   // per lane, at most 2 E
+  uint32_t wcnt = 0;  // per wave (the same in every lane)
   cx<T> v[E];
-  const int64_t rbase = valid ? rowaddr(row0 + rl) : 0;
+  const int64_t rbase = rowaddr(row0 + rr);
+  // scale of the R2C's output: 1/2, times 1/N in the loop passes (N a product of
+  // power-of-two extents, so moving 1/N past the clip and the transform changes no bit
+  // beyond the transform's own rounding)
+  T hsc = T(0.5);
 
   if constexpr (MODE == ROW_INIT) {
     // eps0 = x_hat - x in FP64 for the real pairs m = j + P q, guard clip (+ s-mask)
@@ -767,33 +786,25 @@ __global__ void __launch_bounds__(ROWS * (H / 16), 4) row_direct_kernel(RowArgs<
       if (q % BQ == 0) {
 #pragma unroll
         for (int u = 0; u < BQ; ++u) {
-          xa[u] = make_float2(0.f, 0.f);
-          xb[u] = make_float2(0.f, 0.f);
-          if (valid) {
-            xa[u] = x2[g0 + j + (q + u) * P];
-            xb[u] = b2[g0 + j + (q + u) * P];
-          }
+          xa[u] = x2[g0 + j + (q + u) * P];
+          xb[u] = b2[g0 + j + (q + u) * P];
         }
       }
       const int m = j + q * P;
       const int u = q % BQ;
       double e0 = (double)xb[u].x - (double)xa[u].x, e1 = (double)xb[u].y - (double)xa[u].y;
-      if (valid) {
-        const bool f0 = isfinite(e0), f1 = isfinite(e1);
-        if (!f0 || !f1) {
-          atomicAdd(&st->nonfinite, (unsigned long long)((!f0) + (!f1)));
-          e0 = f0 ? e0 : 0.0;
-          e1 = f1 ? e1 : 0.0;
-        }
-        const bool k0 = fabs(e0) <= Ep, k1 = fabs(e1) <= Ep;
-        cnt += (!k0) + (!k1);
-        e0 = clipv(e0, Ep);
-        e1 = clipv(e1, Ep);
-        if (rec) atomicOr(&sbits[rl * SW + (2 * m) / 32], ((uint32_t)k0 | ((uint32_t)k1 << 1)) << ((2 * m) & 31));
-      } else {
-        e0 = 0.0;
-        e1 = 0.0;
+      const bool f0 = isfinite(e0), f1 = isfinite(e1);
+      if (!f0 || !f1) {
+        if (valid) atomicAdd(&st->nonfinite, (unsigned long long)((!f0) + (!f1)));
+        e0 = f0 ? e0 : 0.0;
+        e1 = f1 ? e1 : 0.0;
       }
+      const bool k0 = fabs(e0) <= Ep, k1 = fabs(e1) <= Ep;
+      cnt += (uint32_t)(!k0) + (uint32_t)(!k1);
+      e0 = clipv(e0, Ep);
+      e1 = clipv(e1, Ep);
+      if (rec && valid)
+        atomicOr(&sbits[rl * SW + (2 * m) / 32], ((uint32_t)k0 | ((uint32_t)k1 << 1)) << ((2 * m) & 31));
       v[q] = cx<T>{(T)e0, (T)e1};
     }
   } else if constexpr (MODE == ROW_BINIT) {
@@ -801,12 +812,12 @@ __global__ void __launch_bounds__(ROWS * (H / 16), 4) row_direct_kernel(RowArgs<
     const float2* g2 = reinterpret_cast<const float2*>(st->pxb);
     float2 gv[E];
 #pragma unroll
-    for (int q = 0; q < E; ++q) gv[q] = valid ? g2[g0 + j + q * P] : make_float2(0.f, 0.f);
+    for (int q = 0; q < E; ++q) gv[q] = g2[g0 + j + q * P];
     __syncthreads();  // mask words visible
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const int m = j + q * P;
-      v[q] = valid ? cx<T>{sbit(m, 0) ? gv[q].x : T(0), sbit(m, 1) ? gv[q].y : T(0)} : cx<T>{T(0), T(0)};
+      v[q] = cx<T>{sbit(m, 0) ? gv[q].x : T(0), sbit(m, 1) ? gv[q].y : T(0)};
     }
   } else {
     static_assert(spec_in, "");
@@ -814,41 +825,54 @@ __global__ void __launch_bounds__(ROWS * (H / 16), 4) row_direct_kernel(RowArgs<
     cx<T> x[E];
     cx<T> nyq{T(0), T(0)};
 #pragma unroll
-    for (int q = 0; q < E; ++q) x[q] = valid ? a.src[rbase + j + q * P] : cx<T>{T(0), T(0)};
-    if (valid && j == 0) nyq = a.src[rbase + H];
+    for (int q = 0; q < E; ++q) x[q] = a.src[rbase + j + q * P];
+    if (j == 0) nyq = a.src[rbase + H];
     __syncthreads();  // twiddles (and mask words) visible
-    // C2R: Z'[k] = (X[k] + X[H-k]*) + i W^-k (X[k] - X[H-k]*)
+    // C2R: Z'[k] = (X[k] + X[H-k]*) + i W^-k (X[k] - X[H-k]*), with d = X[k] - X[H-k]*:
+    // Re Z' = Re s - Im d Re W + Re d Im W, Im Z' = Im s + Re d Re W + Im d Im W
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const int k = j + q * P;
       cx<T> A = x[q];
-      const cx<T> Bp = group_partner<P>(x[E - 1 - q]);
+      // X[H - k] is entry E-1-q of lane P-j; for j = 0 it is this lane's entry
+      // (E-q) mod E (the Nyquist entry for q = 0), which lane 0 sends to itself
       const cx<T> own = (q == 0) ? nyq : x[(E - q) & (E - 1)];
-      cx<T> B = (j == 0) ? own : Bp;
+      cx<T> B = lane_read((j == 0) ? own : x[E - 1 - q], paddr);
       if (k == 0) {
         A.im = T(0);
         B.im = T(0);
       }
-      const cx<T> sm = A + conjg(B);
-      const cx<T> df = cmulc(A - conjg(B), rtw[k]);
-      v[q] = cx<T>{sm.re - df.im, sm.im + df.re};
+      const cx<T> w = rtw[k];
+      const T sre = A.re + B.re, sim = A.im - B.im;
+      const T dre = A.re - B.re, dim = A.im + B.im;
+      v[q] = cx<T>{__builtin_fmaf(dre, w.im, __builtin_fmaf(-dim, w.re, sre)),
+                   __builtin_fmaf(dim, w.im, __builtin_fmaf(dre, w.re, sim))};
     }
     fft<T, H, E, true, 1, LP, SKW>(v, lds, tws, rl, j);
     if constexpr (MODE == ROW_LOOP) {
-      // 1/N, ProjectOntoSCube (+ s-mask)
+      // ProjectOntoSCube (+ s-mask) on N eps: the bound scaled by N, and 1/N applied by
+      // the R2C below
       const T sc = (T)st->inv_n;
-      const T Ep = to_t<T>(st->Ep);
+      const T Ep = to_t<T>(st->Ep) / sc;
+      hsc = T(0.5) * sc;
+      if (rec) {
+        if (valid) {
+#pragma unroll
+          for (int q = 0; q < E; ++q) {
+            const int k = j + q * P;
+            const bool k0 = fabs(v[q].re) <= Ep, k1 = fabs(v[q].im) <= Ep;
+            atomicOr(&sbits[rl * SW + (2 * k) / 32], ((uint32_t)k0 | ((uint32_t)k1 << 1)) << ((2 * k) & 31));
+          }
+        }
+      }
+      // the count per wave: a ballot per value and a scalar popcount (the lanes of rows
+      // past the block's end masked off)
+      const unsigned long long vm = __builtin_amdgcn_ballot_w64(valid);
 #pragma unroll
       for (int q = 0; q < E; ++q) {
-        const int k = j + q * P;
-        T e0 = v[q].re * sc, e1 = v[q].im * sc;
-        const bool k0 = fabs(e0) <= Ep, k1 = fabs(e1) <= Ep;
-        if (valid) cnt += (!k0) + (!k1);
-        e0 = clipv(e0, Ep);
-        e1 = clipv(e1, Ep);
-        v[q] = cx<T>{e0, e1};
-        if (rec && valid)
-          atomicOr(&sbits[rl * SW + (2 * k) / 32], ((uint32_t)k0 | ((uint32_t)k1 << 1)) << ((2 * k) & 31));
+        wcnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(!(fabs(v[q].re) <= Ep)) & vm);
+        wcnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(!(fabs(v[q].im) <= Ep)) & vm);
+        v[q] = cx<T>{clipv(v[q].re, Ep), clipv(v[q].im, Ep)};
       }
     } else if constexpr (MODE == ROW_FINAL) {
       // the source holds only the last-axis R2C of eps, so the C2R scale is 1/n_last
@@ -856,13 +880,15 @@ __global__ void __launch_bounds__(ROWS * (H / 16), 4) row_direct_kernel(RowArgs<
 #pragma unroll
       for (int q = 0; q < E; ++q) v[q] = scal(v[q], scz);
     } else {
-      // adjoint: 1/N, g * s-mask
+      // adjoint: g * s-mask and 1/N (in the loop pass, 1/N is applied by the R2C below)
       const T sc = (T)st->inv_n;
+      if constexpr (MODE == ROW_BLOOP) hsc = T(0.5) * sc;
+      const T sv = MODE == ROW_BLOOP ? T(1) : sc;
 #pragma unroll
       for (int q = 0; q < E; ++q) {
         const int k = j + q * P;
-        v[q].re = sbit(k, 0) ? v[q].re * sc : T(0);
-        v[q].im = sbit(k, 1) ? v[q].im * sc : T(0);
+        v[q].re = sbit(k, 0) ? v[q].re * sv : T(0);
+        v[q].im = sbit(k, 1) ? v[q].im * sv : T(0);
       }
     }
   }
@@ -881,7 +907,7 @@ __global__ void __launch_bounds__(ROWS * (H / 16), 4) row_direct_kernel(RowArgs<
 #pragma unroll
       for (int q0 = 0; q0 < E; q0 += BQ) {
 #pragma unroll
-        for (int u = 0; u < BQ; ++u) xv[u] = valid ? x2[g0 + j + (q0 + u) * P] : make_float2(0.f, 0.f);
+        for (int u = 0; u < BQ; ++u) xv[u] = x2[g0 + j + (q0 + u) * P];
 #pragma unroll
         for (int u = 0; u < BQ; ++u) {
           const int q = q0 + u;
@@ -893,35 +919,36 @@ __global__ void __launch_bounds__(ROWS * (H / 16), 4) row_direct_kernel(RowArgs<
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < E; ++q)
-        if (valid) y2[g0 + j + q * P] = make_float2(v[q].re, v[q].im);
+      for (int q = 0; q < E; ++q) y2[g0 + j + q * P] = make_float2(v[q].re, v[q].im);
     }
   } else {
     static_assert(spec_out, "");
     fft<T, H, E, false, 1, LP, SKW>(v, lds, tws, rl, j);
-    // R2C: X[k] = (Z[k] + Z[H-k]*)/2 - i W^k (Z[k] - Z[H-k]*)/2, X[H] = Re Z0 - Im Z0
+    // R2C: X[k] = (Z[k] + Z[H-k]*)/2 - i W^k (Z[k] - Z[H-k]*)/2, X[H] = Re Z0 - Im Z0,
+    // times the pass's scale c (hsc = c/2); with s = Z[k] + Z[H-k]*, d = Z[k] - Z[H-k]*:
+    // Re X = c/2 (Re s + Re W Im d + Im W Re d), Im X = c/2 (Im s - Re W Re d + Im W Im d)
     cx<T>* dst = a.dst + rbase;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const int k = j + q * P;
       const cx<T> Zk = v[q];
-      const cx<T> Zp = group_partner<P>(v[E - 1 - q]);
       const cx<T> own = v[(E - q) & (E - 1)];  // lane 0: Z[H - P q], Z[0] for q = 0
-      const cx<T> Zm = (j == 0) ? own : Zp;
-      const cx<T> ev = scal(Zk + conjg(Zm), T(0.5));
-      const cx<T> d = Zk - conjg(Zm);
-      const cx<T> od = cx<T>{d.im * T(0.5), -d.re * T(0.5)};
-      const cx<T> X = ev + cmul(rtw[k], od);
-      if (valid) dst[k] = X;
+      const cx<T> Zm = lane_read((j == 0) ? own : v[E - 1 - q], paddr);
+      const cx<T> w = rtw[k];
+      const T sre = Zk.re + Zm.re, sim = Zk.im - Zm.im;
+      const T dre = Zk.re - Zm.re, dim = Zk.im + Zm.im;
+      dst[k] = cx<T>{hsc * __builtin_fmaf(w.im, dre, __builtin_fmaf(w.re, dim, sre)),
+                     hsc * __builtin_fmaf(w.im, dim, __builtin_fmaf(-w.re, dre, sim))};
     }
     // entry H and the row's first padding entry (zero) as one 16-byte store
-    if (valid && j == 0) *reinterpret_cast<float4*>(dst + H) = make_float4(v[0].re - v[0].im, 0.f, 0.f, 0.f);
+    if (j == 0) *reinterpret_cast<float4*>(dst + H) = make_float4((hsc + hsc) * (v[0].re - v[0].im), 0.f, 0.f, 0.f);
   }
 
   if constexpr (rec_s) {
     // one partial per block (guard-clip or s-clip count), reduced by the control kernel
-    cnt = wave_sum_u64(cnt);
-    if ((t & 63) == 0) red_u[t >> 6] = cnt;
+    unsigned long long wc = wcnt;
+    if constexpr (MODE == ROW_INIT) wc = wave_sum_u64(valid ? (unsigned long long)cnt : 0ull);
+    if ((t & 63) == 0) red_u[t >> 6] = wc;
     __syncthreads();
     if (t == 0) {
       unsigned long long s2 = 0;

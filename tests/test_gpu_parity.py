@@ -188,22 +188,33 @@ def test_fixed_rounds_masks_match_oracle(dt, shape, mode):
     orc = O.correct(p.x, p.xb, p.E, p.Delta, K, mu=mu, fixed=True, record_masks=True)
     assert rel_err(y, orc.y) <= (1e-12 if dt == np.float64 else 1e-5)
     gm = unpack_masks(res.masks.cpu().numpy(), p.x.shape, K)
+    _masks_differ_only_at_bounds(p, dt, mu, K, gm, orc.masks)
+
+
+def _masks_differ_only_at_bounds(p, dt, mu, K, gm, om):
+    """The GPU's keep-masks gm equal the oracle's om; in FP32 a bit may differ only where the
+    oracle's pre-clip value lies within FP32 noise (1e-5 relative) of its bound (the clip
+    decision of Eq. 2's projections at the bound is a rounding question).  Returns the number
+    of differing bits."""
     Ep = p.E * (1 - mu)
     Dp = O.spectral_thresholds(p.Delta, mu, dt)[1]
-    np.testing.assert_array_equal(gm.s[0], orc.masks.s[0])  # guard clip runs in FP64
+    np.testing.assert_array_equal(gm.s[0], om.s[0])  # guard clip runs in FP64
+    nbad = 0
     for k in range(1, K + 1):
         prev = O.correct(p.x, p.xb, p.E, p.Delta, k - 1, mu=mu, fixed=True, verify_output=False).eps
         d = O.fft(prev)                                   # pre-clip spectrum of block k
         pre_s = O.ifft(O.project_f(d, Dp)[0], p.x.shape)  # pre-clip spatial error of block k
-        pairs = ((gm.s[k], orc.masks.s[k], pre_s, Ep), (gm.f_re[k], orc.masks.f_re[k], d.real, Dp),
-                 (gm.f_im[k], orc.masks.f_im[k], d.imag, Dp))
+        pairs = ((gm.s[k], om.s[k], pre_s, Ep), (gm.f_re[k], om.f_re[k], d.real, Dp),
+                 (gm.f_im[k], om.f_im[k], d.imag, Dp))
         for a, b, pre, thr in pairs:
             bad = a != b
+            nbad += int(bad.sum())
             if dt == np.float64:
                 assert not bad.any(), (k, int(bad.sum()))
             else:
                 gap = np.abs(np.abs(pre[bad]) - thr)
                 assert np.all(gap <= 1e-5 * thr), (k, int(bad.sum()), float(gap.max(initial=0)) / thr)
+    return nbad
 
 
 @pytest.mark.parametrize("dt,shape", [(np.float64, (16, 16, 64)), (np.float32, (16, 16, 64)),
@@ -223,10 +234,15 @@ def test_backward_matches_oracle_adjoint(dt, shape, mode=1):
     ref = O.adjoint(gm, g.astype(np.float64))          # oracle fed the GPU's own masks
     tol = 1e-12 if dt == np.float64 else 1e-5
     assert rel_err(gb, ref) <= tol
-    orc = O.correct(p.x, p.xb, p.E, p.Delta, K, mu=res.stats["margin_used"], fixed=True, record_masks=True)
-    ref2 = O.adjoint(orc.masks, g.astype(np.float64))  # oracle's own trajectory
-    rel_l2 = np.linalg.norm(gb - ref2) / np.linalg.norm(ref2)
-    assert rel_l2 <= (1e-12 if dt == np.float64 else 1e-4)
+    mu = res.stats["margin_used"]
+    orc = O.correct(p.x, p.xb, p.E, p.Delta, K, mu=mu, fixed=True, record_masks=True)
+    # the oracle's own trajectory: its masks equal the GPU's but for FP32 clip decisions at a
+    # bound, and where they all agree its adjoint is the GPU's
+    nbad = _masks_differ_only_at_bounds(p, dt, mu, K, gm, orc.masks)
+    if nbad == 0:
+        ref2 = O.adjoint(orc.masks, g.astype(np.float64))
+        rel_l2 = np.linalg.norm(gb - ref2) / np.linalg.norm(ref2)
+        assert rel_l2 <= (1e-12 if dt == np.float64 else 1e-4)
 
 
 @pytest.mark.parametrize("shape", [(16, 16, 256), (8, 16, 512), (32, 256)])
