@@ -40,14 +40,31 @@ col_kernel(ColArgs<T> a) {
   const int col = cb * C + c;
   const bool valid = col < a.ncols;
   const int64_t base = o * a.so + col;
+  // The x-direction passes (VALU-bound: two transforms per pass) address an entry as a
+  // block-uniform part (outer index and row q P) plus a 32-bit lane part (column and row j;
+  // the host keeps it below 2^31 bytes), one 64-bit add per access instead of a 64-bit
+  // multiply-add, and lanes past the last column read that column (no per-lane guard on
+  // loads; they store nothing and count nothing).  The other passes, with VALU to spare,
+  // keep 64-bit indices and guarded loads, which timed faster for them.
+  constexpr bool lean = (MODE == COL_XPASS || MODE == COL_XEDIT || MODE == COL_XUNDO ||
+                         MODE == COL_XBACK || MODE == COL_XPASSP);
+  const int col_in = valid ? col : a.ncols - 1;
+  const uint32_t lob = (uint32_t)(((int64_t)col_in + (int64_t)j * a.s) * (int64_t)sizeof(cx<T>));
+  const int64_t ob = o * a.so;
+  auto src_at = [&](int q) -> const cx<T>* {
+    return reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(a.src + ob + (int64_t)(q * P) * a.s) + lob);
+  };
+  auto dst_at = [&](int q) -> cx<T>* {
+    return reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(a.dst + ob + (int64_t)(q * P) * a.s) + lob);
+  };
 
   for (int i = t; i < TW; i += NT) tws[i] = a.tw[i];
 
   cx<T> v[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) {
-    const int64_t idx = base + (int64_t)(j + q * P) * a.s;
-    v[q] = valid ? a.src[idx] : cx<T>{T(0), T(0)};
+    if constexpr (lean) v[q] = *src_at(q);
+    else v[q] = valid ? a.src[base + (int64_t)(j + q * P) * a.s] : cx<T>{T(0), T(0)};
   }
 
   if constexpr (MODE == COL_FWD || MODE == COL_FWD_NS) {
@@ -106,7 +123,7 @@ col_kernel(ColArgs<T> a) {
     const T Dp = to_t<T>(st->Dp);
     const bool rec = !undo && st->record_masks && (k < st->max_iter);
     fft<T, L, E, false, C, 1>(v, lds, tws, c, j);
-    unsigned long long cnt = 0;
+    uint32_t wcnt = 0;  // violations of the wave (a ballot per entry, a scalar popcount)
     const int lane = t & 63;
     uint8_t* mre = a.fmask + (int64_t)k * 2 * a.f_plane;
     uint8_t* mim = mre + a.f_plane;
@@ -114,7 +131,7 @@ col_kernel(ColArgs<T> a) {
     for (int q = 0; q < E; ++q) {
       cx<T> z = v[q];
       const bool bad = valid && (fabs(z.re) > D || fabs(z.im) > D);
-      cnt += bad ? 1 : 0;
+      wcnt += (uint32_t)__popcll(__ballot(bad));
       const bool kre = fabs(z.re) <= Dp;
       const bool kim = fabs(z.im) <= Dp;
       z.re = clipv(z.re, Dp);
@@ -155,8 +172,7 @@ col_kernel(ColArgs<T> a) {
     if constexpr (undo) return;
     fft<T, L, E, true, C, 1>(v, lds, tws, c, j);
     // violations of this check: one partial per block, summed by the control kernel
-    cnt = wave_sum_u64(cnt);
-    if ((t & 63) == 0) red_u[t >> 6] = cnt;
+    if ((t & 63) == 0) red_u[t >> 6] = wcnt;
     __syncthreads();
     if (t == 0) {
       unsigned long long s = 0;
@@ -164,18 +180,52 @@ col_kernel(ColArgs<T> a) {
       a.part[bid] = s;
     }
   } else if constexpr (MODE == COL_XBACK) {
-    fft<T, L, E, false, C, 1>(v, lds, tws, c, j);
-    const uint8_t* mre = a.fmask;
-    const uint8_t* mim = a.fmask + a.f_plane;
+    // The tile's f-mask bits of row j + q P are one C-bit word per plane (bit c: column
+    // cb C + c).  Lane c of the C lanes of row group j loads the (Re, Im) words of the rows
+    // with q = c (mod C), and the group reads them from that lane through the LDS crossbar
+    // (ds_bpermute), in place of a byte load per entry and plane.
+    // (Tiles of fewer than 8 columns read a byte per entry.)
+    constexpr int WB = C >= 8 ? C / 8 : 1;  // mask bytes per tile row
+    static_assert(C < 8 || WB == 1 || WB == 2, "tiles of 8 or 16 columns");
+    constexpr int NWD = C >= 8 ? (E + C - 1) / C : 1;
+    uint32_t wd[NWD];
+    const bool tile_ok = cb * C < a.ncols;  // a padding tile has no mask bytes
+    if constexpr (C >= 8) {
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-      const int64_t row = (int64_t)(j + q * P) * a.mrow_i + o * a.mrow_o;
-      const int64_t off = row * a.f_row_bytes + col / 8;
-      const int bit = col & 7;
-      const int kr = valid ? (mre[off] >> bit) & 1 : 0;
-      const int ki = valid ? (mim[off] >> bit) & 1 : 0;
-      v[q].re = kr ? v[q].re : T(0);
-      v[q].im = ki ? v[q].im : T(0);
+      for (int m = 0; m < NWD; ++m) {
+        const int q = c + m * C;
+        wd[m] = 0u;
+        if (tile_ok && q < E) {
+          const int64_t off = ((int64_t)(j + q * P) * a.mrow_i + o * a.mrow_o) * a.f_row_bytes + (cb * C) / 8;
+          if constexpr (WB == 2)
+            wd[m] = (uint32_t)*reinterpret_cast<const uint16_t*>(a.fmask + off) |
+                    ((uint32_t)*reinterpret_cast<const uint16_t*>(a.fmask + a.f_plane + off) << 16);
+          else
+            wd[m] = (uint32_t)a.fmask[off] | ((uint32_t)a.fmask[a.f_plane + off] << 8);
+        }
+      }
+    }
+    fft<T, L, E, false, C, 1>(v, lds, tws, c, j);
+    if constexpr (C >= 8) {
+      const int gbase = (t & 63) & ~(C - 1);  // first lane of this row group in the wave
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const uint32_t w = (uint32_t)__builtin_amdgcn_ds_bpermute(4 * (gbase | (q % C)), (int)wd[q / C]);
+        v[q].re = ((w >> c) & 1u) ? v[q].re : T(0);
+        v[q].im = ((w >> (c + 8 * WB)) & 1u) ? v[q].im : T(0);
+      }
+    } else {
+      const uint8_t* mre = a.fmask;
+      const uint8_t* mim = a.fmask + a.f_plane;
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int64_t off = ((int64_t)(j + q * P) * a.mrow_i + o * a.mrow_o) * a.f_row_bytes + col / 8;
+        const int bit = col & 7;
+        const int kr = valid ? (mre[off] >> bit) & 1 : 0;
+        const int ki = valid ? (mim[off] >> bit) & 1 : 0;
+        v[q].re = kr ? v[q].re : T(0);
+        v[q].im = ki ? v[q].im : T(0);
+      }
     }
     fft<T, L, E, true, C, 1>(v, lds, tws, c, j);
   } else if constexpr (MODE == COL_VERIFY || MODE == COL_VERIFYP) {
@@ -235,9 +285,16 @@ col_kernel(ColArgs<T> a) {
     return;
   }
 
+  if constexpr (lean) {
+    if (valid) {
 #pragma unroll
-  for (int q = 0; q < E; ++q) {
-    if (valid) a.dst[base + (int64_t)(j + q * P) * a.s] = v[q];
+      for (int q = 0; q < E; ++q) *dst_at(q) = v[q];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      if (valid) a.dst[base + (int64_t)(j + q * P) * a.s] = v[q];
+    }
   }
 }
 
