@@ -757,6 +757,27 @@ __global__ void __launch_bounds__(256) bounds_margin_kernel(const double* ulp_pa
   st->Ep = st->E * (1.0 - mu);
 }
 
+// Partials p[0..n) read by the nt lanes of a block, U independent loads in flight per lane
+// (a plain strided loop waits for each load in turn: with thousands of partials that was
+// most of a control kernel's time).  fold is a sum or a max of non-negative values.
+template <int U, typename F>
+__device__ __forceinline__ unsigned long long fold_strided(const unsigned long long* p, int64_t n, int t, int nt,
+                                                           unsigned long long acc, F fold) {
+  for (int64_t i0 = t; i0 < n; i0 += (int64_t)U * nt) {
+    unsigned long long v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + (int64_t)u * nt;
+      v[u] = i < n ? p[i] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = fold(acc, v[u]);
+  }
+  return acc;
+}
+__device__ __forceinline__ unsigned long long add_u64(unsigned long long a, unsigned long long b) { return a + b; }
+__device__ __forceinline__ unsigned long long max_u64(unsigned long long a, unsigned long long b) { return a > b ? a : b; }
+
 // Per-round control, one block per instance: sum the x-pass partials into
 // v_k, fold the spatial-clip partials of the z-pass that produced the checked
 // iterate into the totals, and decide on the device whether the loop stops
@@ -771,11 +792,10 @@ __global__ void __launch_bounds__(1024) ctl_kernel(DevState* st0, unsigned long 
   DevState* st = st0 + b;
   if (*(volatile int32_t*)&st->done) return;
   const int t = threadIdx.x;
-  unsigned long long sx = 0, sz = 0;
-  for (int64_t i = t; i < xbpi; i += blockDim.x) sx += xpart[b * xbpi + i];
   // the checked iterate came from the init pass (round 0) or from a z-pass, whose tiles may differ
   const int64_t nz = st->round == 0 ? ibpi : zbpi;
-  for (int64_t i = t; i < nz; i += blockDim.x) sz += zpart[b * nz + i];
+  unsigned long long sx = fold_strided<8>(xpart + b * xbpi, xbpi, t, (int)blockDim.x, 0ull, add_u64);
+  unsigned long long sz = fold_strided<8>(zpart + b * nz, nz, t, (int)blockDim.x, 0ull, add_u64);
   sx = wave_sum_u64(sx);
   sz = wave_sum_u64(sz);
   if ((t & 63) == 0) {
@@ -819,12 +839,10 @@ __global__ void __launch_bounds__(1024) stats_kernel(DevState* st0, const unsign
   __shared__ unsigned long long ra[16], rb[16], rc[16];
   const int64_t inst = blockIdx.x;
   const int t = threadIdx.x;
-  unsigned long long a = 0, b = 0, c = 0;  // max bits of non-negative doubles order as integers
-  for (int64_t i = t; i < vzbpi; i += blockDim.x) a = a > vz[inst * vzbpi + i] ? a : vz[inst * vzbpi + i];
-  for (int64_t i = t; i < vxbpi; i += blockDim.x) {
-    c += vxc[inst * vxbpi + i];
-    b = b > vxm[inst * vxbpi + i] ? b : vxm[inst * vxbpi + i];
-  }
+  // max bits of non-negative doubles order as integers
+  unsigned long long a = fold_strided<8>(vz + inst * vzbpi, vzbpi, t, (int)blockDim.x, 0ull, max_u64);
+  unsigned long long b = fold_strided<8>(vxm + inst * vxbpi, vxbpi, t, (int)blockDim.x, 0ull, max_u64);
+  unsigned long long c = fold_strided<8>(vxc + inst * vxbpi, vxbpi, t, (int)blockDim.x, 0ull, add_u64);
   for (int off = 32; off > 0; off >>= 1) {
     const unsigned long long oa = __shfl_xor(a, off, 64), ob = __shfl_xor(b, off, 64);
     a = a > oa ? a : oa;

@@ -245,10 +245,11 @@ def test_backward_matches_oracle_adjoint(dt, shape, mode=1):
         assert rel_l2 <= (1e-12 if dt == np.float64 else 1e-4)
 
 
-@pytest.mark.parametrize("shape", [(16, 16, 256), (8, 16, 512), (32, 256)])
+@pytest.mark.parametrize("shape", [(16, 16, 256), (8, 16, 512), (32, 256), (2, 4, 256), (2, 4, 512)])
 def test_direct_last_axis_backward_matches_oracle_adjoint(shape):
     # mode 4: the forward and the adjoint run the direct last-axis passes (rows of 128 and
-    # 256 entries)
+    # 256 entries); the last two shapes have fewer rows than one block (8 of 32 and of 16), so
+    # lanes past the last row repeat it, mask bits included
     test_backward_matches_oracle_adjoint(np.float32, shape, mode=4)
 
 
