@@ -644,21 +644,6 @@ row_kernel(RowArgs<T, TIO> a) {
 
 namespace ffcz {
 
-// Lane (P - j) mod P of the lane's group of P = 16 or 8 lanes (j = lane mod P,
-// j >= 1): DPP row_mirror (lane i <- 15 - i within a row of 16) or row_half_mirror
-// (lane i <- 7 - i within each half-row of 8), then row_shr:1 (lane i <- i - 1).
-// Lane 0 of each group receives another group's value or 0; callers take its
-// partner from its own registers.
-template <int P>
-__device__ __forceinline__ float group_partner(float x) {
-  static_assert(P == 16 || P == 8, "a row or half-row of DPP lanes");
-  const int m = __builtin_amdgcn_mov_dpp(__float_as_int(x), P == 16 ? 0x140 : 0x141, 0xF, 0xF, false);
-  return __int_as_float(__builtin_amdgcn_mov_dpp(m, 0x111, 0xF, 0xF, true));
-}
-template <int P>
-__device__ __forceinline__ cx<float> group_partner(cx<float> z) {
-  return cx<float>{group_partner<P>(z.re), group_partner<P>(z.im)};
-}
 // The value z of lane (P - j) mod P of the lane's group (j = lane mod P), through the
 // LDS crossbar (ds_bpermute: no LDS storage, no barrier); baddr = 4 x that lane's index
 // in the wave.  Lane 0 of a group reads its own z.
@@ -680,11 +665,11 @@ __host__ __device__ constexpr int direct_lds_pitch(int H) {
 }
 
 // Last-axis passes for FP32 rows of H = 128 or 256 entries with lanes
-// index-fastest: the P = H / 16 lanes of a row are one DPP group, lane j keeps
-// entries j + P q (q < 16).  Spectrum entries (and the real pairs r[2m], r[2m+1]
-// of the fields) move straight between HBM and registers (P lanes cover 8 P
+// index-fastest: the P = H / 16 lanes of a row are one group of a wave, lane j
+// keeps entries j + P q (q < 16).  Spectrum entries (and the real pairs r[2m],
+// r[2m+1] of the fields) move straight between HBM and registers (P lanes cover 8 P
 // contiguous bytes of a row per access), the C2R and R2C partners k <-> H - k come
-// from lane (P - j) mod P by DPP, and LDS carries only the transform's own
+// from lane (P - j) mod P through ds_bpermute, and LDS carries only the transform's own
 // exchange, with entry i at i + (i >> log2 P) and rows direct_lds_pitch(H) apart
 // (every 8-byte slot taken exactly twice per wave access).  row_kernel stages the
 // whole tile through LDS on the way in and out; the loop pass moves about 40 % less
