@@ -696,7 +696,11 @@ __global__ void __launch_bounds__(ROWS * (H / 16), 4) row_direct_kernel(RowArgs<
   static_assert(MODE != ROW_VERIFY, "the verification runs in FP64");
   static_assert(S::nst == 2, "one exchange per transform");
 
-  __shared__ cx<T> lds[ROWS * LP];
+  // Rows of 128 entries exchange the real parts, then the imaginary parts, through one real
+  // per entry: half the LDS, so more blocks share a CU (the full-width exchange held these
+  // blocks to 12 waves per CU)
+  constexpr bool SPX = (H == 128);
+  __shared__ cx<T> lds[SPX ? (ROWS * LP + 1) / 2 : ROWS * LP];
   __shared__ cx<T> tws[TW + H];
   __shared__ unsigned long long red_u[NW];
   __shared__ uint32_t sbits[(rec_s || use_s) ? ROWS * SW : 1];
@@ -833,7 +837,7 @@ __global__ void __launch_bounds__(ROWS * (H / 16), 4) row_direct_kernel(RowArgs<
       v[q] = cx<T>{__builtin_fmaf(dre, w.im, __builtin_fmaf(-dim, w.re, sre)),
                    __builtin_fmaf(dim, w.im, __builtin_fmaf(dre, w.re, sim))};
     }
-    fft<T, H, E, true, 1, LP, SKW>(v, lds, tws, rl, j);
+    fft<T, H, E, true, 1, LP, SKW, SPX>(v, lds, tws, rl, j);
     if constexpr (MODE == ROW_LOOP) {
       // ProjectOntoSCube (+ s-mask) on N eps: the bound scaled by N, and 1/N applied by
       // the R2C below
@@ -908,7 +912,7 @@ __global__ void __launch_bounds__(ROWS * (H / 16), 4) row_direct_kernel(RowArgs<
     }
   } else {
     static_assert(spec_out, "");
-    fft<T, H, E, false, 1, LP, SKW>(v, lds, tws, rl, j);
+    fft<T, H, E, false, 1, LP, SKW, SPX>(v, lds, tws, rl, j);
     // R2C: X[k] = (Z[k] + Z[H-k]*)/2 - i W^k (Z[k] - Z[H-k]*)/2, X[H] = Re Z0 - Im Z0,
     // times the pass's scale c (hsc = c/2); with s = Z[k] + Z[H-k]*, d = Z[k] - Z[H-k]*:
     // Re X = c/2 (Re s + Re W Im d + Im W Re d), Im X = c/2 (Im s - Re W Re d + Im W Im d)
