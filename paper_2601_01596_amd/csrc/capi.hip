@@ -962,10 +962,6 @@ hipError_t run_col(int dt, int mode, int v, const ColGeom& g, const Plan& p, con
   a.bnd_so = bnd_so;
   a.bnd_s = bnd_s;
   a.bnd_dbl = bnd_dbl;
-  // the kernel addresses a lane's entries as a block-uniform base plus a 32-bit byte offset
-  // (its column and its first row along the axis): the largest must stay below 2^31
-  const int64_t P = g.L / pick_E(g.L);
-  if ((p.ncols - 1 + (P - 1) * g.s) * (int64_t)sizeof(cx<T>) >= (int64_t(1) << 31)) return hipErrorInvalidValue;
   const int64_t nb = g.outer * a.ncb;
   return launch_col(dt, mode, g.L, v, &a, nb, s);
 }

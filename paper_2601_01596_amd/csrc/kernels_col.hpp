@@ -41,15 +41,15 @@ col_kernel(ColArgs<T> a) {
   const bool valid = col < a.ncols;
   const int64_t base = o * a.so + col;
   // The x-direction passes (VALU-bound: two transforms per pass) address an entry as a
-  // block-uniform part (outer index and row q P) plus a 32-bit lane part (column and row j;
-  // the host keeps it below 2^31 bytes), one 64-bit add per access instead of a 64-bit
-  // multiply-add, and lanes past the last column read that column (no per-lane guard on
-  // loads; they store nothing and count nothing).  The other passes, with VALU to spare,
+  // block-uniform part (outer index and row q P) plus a lane part (column and row j, in
+  // bytes), one 64-bit add per access instead of a 64-bit multiply-add, and lanes past the
+  // last column read that column (no per-lane guard on loads; they store nothing and count
+  // nothing).  The other passes, with VALU to spare,
   // keep 64-bit indices and guarded loads, which timed faster for them.
   constexpr bool lean = (MODE == COL_XPASS || MODE == COL_XEDIT || MODE == COL_XUNDO ||
                          MODE == COL_XBACK || MODE == COL_XPASSP);
   const int col_in = valid ? col : a.ncols - 1;
-  const uint32_t lob = (uint32_t)(((int64_t)col_in + (int64_t)j * a.s) * (int64_t)sizeof(cx<T>));
+  const int64_t lob = ((int64_t)col_in + (int64_t)j * a.s) * (int64_t)sizeof(cx<T>);
   const int64_t ob = o * a.so;
   auto src_at = [&](int q) -> const cx<T>* {
     return reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(a.src + ob + (int64_t)(q * P) * a.s) + lob);
