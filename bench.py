@@ -183,6 +183,30 @@ def copy_ceiling(F, torch, nbytes, reps):
     return 2 * nbytes / (a.elapsed_time(b) / reps * 1e-3) / 1e9
 
 
+def pattern_ceilings(F, torch, n, reps):
+    """Rates of copies with the x-pass and y-pass access patterns over the layout of an n^3 FP32
+    half spectrum (rows of n/2 + 1 complex entries, rounded up to 16 bytes, at the 128-byte padded
+    pitch; x-planes padded by one 128-byte line): bytes read + written per second."""
+    H = n // 2
+    row_bytes = ((H + 1) * 8 + 15) // 16 * 16
+    pitch = ((H + 1 + 15) // 16) * 16 * 8
+    plane = n * pitch + 128
+    src = torch.empty(n * plane, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    out = {}
+    for name, args in (("x", (n, plane, n, pitch)), ("y", (n, pitch, n, plane))):
+        F.copy_columns_(dst, src, *args, row_bytes)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            F.copy_columns_(dst, src, *args, row_bytes)
+        b.record()
+        torch.cuda.synchronize()
+        out[name] = 2 * n * n * row_bytes / (a.elapsed_time(b) / reps * 1e-3) / 1e9
+    del src, dst
+    return out
+
+
 def cpu_baseline(prob, rounds_gpu):
     """Oracle on the host cores; rounds capped at 3, time scaled by checks run.  The
     correction is repeated until about 10 s of host work (at most 3 runs); the mean counts."""
@@ -496,6 +520,10 @@ def main():
     log("[bench] copy ceiling (1 GiB streaming copy)")
     cp = copy_ceiling(F, torch, 1 << 30, 10)
     extra["copy_kernel_GBps"] = cp
+    # the ceilings of the strided passes' own access patterns on this field's spectrum layout
+    pc = pattern_ceilings(F, torch, n, 10)
+    extra["xpattern_copy_GBps"] = pc["x"]
+    extra["ypattern_copy_GBps"] = pc["y"]
     if not args.no_steady:
         log("[bench] steady-state rounds (50 fixed rounds vs 0)")
         t_round, t_fixed0 = steady_rounds(F, torch, p32, 50, 3)

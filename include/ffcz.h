@@ -510,6 +510,23 @@ void ffcz_clear_tuning(void);
  * fails. */
 int32_t ffcz_copy(void* dst, const void* src, size_t bytes, void* stream);
 
+/* Strided copy with the access pattern of the strided-axis passes (x- and
+ * y-direction), the ceiling those passes are compared with.  For every
+ * f < n_fixed and i < n_axis it copies row_bytes bytes at byte offset
+ * f * fixed_stride + i * axis_stride from src to dst; one 256-lane block per
+ * (f, 128-byte tile of the row) walks i, 16 bytes per lane.  The x-pass
+ * pattern of a 3D spectrum is axis = x-planes (axis_stride = plane bytes),
+ * fixed = rows (fixed_stride = row pitch); the y-pass pattern swaps them.  A
+ * measurement helper, like ffcz_copy.  src and dst are device pointers the
+ * caller owns, not overlapping, each holding (n_fixed - 1) * fixed_stride +
+ * (n_axis - 1) * axis_stride + row_bytes bytes; the rows must not overlap one
+ * another.  Asynchronous on `stream`.  Returns FFCZ_E_INVALID for negative
+ * arguments, null pointers, pointers, strides or row_bytes that are not
+ * multiples of 16 bytes, or more than 2^31 - 1 blocks; FFCZ_E_HIP if the
+ * launch fails.  Zero counts or row_bytes copy nothing. */
+int32_t ffcz_copy_columns(void* dst, const void* src, int64_t n_axis, int64_t axis_stride, int64_t n_fixed,
+                          int64_t fixed_stride, int64_t row_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2733,6 +2733,25 @@ __global__ void copy_tail_kernel(unsigned char* __restrict__ dst, const unsigned
   if ((int)threadIdx.x < n) dst[threadIdx.x] = src[threadIdx.x];
 }
 
+// Copy with the access pattern of the strided-axis passes: block (f, tile) moves the
+// 128-byte tile of the rows (f, i) for every i along the axis, 16 bytes per lane, 8 lanes
+// per tile row and 32 rows per step.  Row (f, i) starts at f fixed_stride + i axis_stride.
+__global__ void __launch_bounds__(256) copy_columns_kernel(char* __restrict__ dst, const char* __restrict__ src,
+                                                           int64_t n_axis, int64_t axis_stride, int64_t fixed_stride,
+                                                           int64_t row_bytes, int32_t tiles) {
+  const int64_t b = blockIdx.x;
+  const int64_t f = b / tiles;
+  const int tile = (int)(b - f * tiles);
+  const int64_t off = (int64_t)tile * 128 + (threadIdx.x & 7) * 16;
+  if (off >= row_bytes) return;  // row_bytes is a multiple of 16; no barrier follows
+  const int64_t base = f * fixed_stride + off;
+#pragma unroll 4
+  for (int64_t i = threadIdx.x >> 3; i < n_axis; i += 32) {
+    const int64_t a = base + i * axis_stride;
+    *reinterpret_cast<uint4*>(dst + a) = *reinterpret_cast<const uint4*>(src + a);
+  }
+}
+
 // Makes the caller's stream wait for the side stream on every exit after the fork, so no
 // 1D launch still writes the caller's buffers once the call has returned.
 struct SideJoin {
@@ -3352,6 +3371,22 @@ int32_t ffcz_copy(void* dst, const void* src, size_t bytes, void* stream) {
                        (const unsigned char*)src + n16 * 16, tail);
     HIPCHK(hipGetLastError());
   }
+  return FFCZ_OK;
+}
+
+int32_t ffcz_copy_columns(void* dst, const void* src, int64_t n_axis, int64_t axis_stride, int64_t n_fixed,
+                          int64_t fixed_stride, int64_t row_bytes, void* stream) {
+  if (n_axis < 0 || n_fixed < 0 || row_bytes < 0 || axis_stride < 0 || fixed_stride < 0)
+    return fail(FFCZ_E_INVALID, "negative count, stride or row size");
+  if (n_axis == 0 || n_fixed == 0 || row_bytes == 0) return FFCZ_OK;
+  if (!dst || !src) return fail(FFCZ_E_INVALID, "null pointer");
+  if ((((uintptr_t)dst | (uintptr_t)src) & 15) || ((axis_stride | fixed_stride | row_bytes) & 15))
+    return fail(FFCZ_E_INVALID, "pointers, strides and the row size must be multiples of 16 bytes");
+  const int64_t tiles = (row_bytes + 127) / 128;
+  if (tiles > INT32_MAX || n_fixed > INT32_MAX / tiles) return fail(FFCZ_E_INVALID, "too many tiles for one launch");
+  hipLaunchKernelGGL(copy_columns_kernel, dim3((unsigned)(n_fixed * tiles)), dim3(256), 0, (hipStream_t)stream,
+                     (char*)dst, (const char*)src, n_axis, axis_stride, fixed_stride, row_bytes, (int32_t)tiles);
+  HIPCHK(hipGetLastError());
   return FFCZ_OK;
 }
 

@@ -33,7 +33,7 @@ EXPORTS = ("ffcz_version", "ffcz_last_error", "ffcz_default_options", "ffcz_work
            "ffcz_mask_bytes", "ffcz_suggest_margin", "ffcz_correct", "ffcz_correct_backward",
            "ffcz_batched_workspace_bytes", "ffcz_correct_batched", "ffcz_profile_enable", "ffcz_profile_read",
            "ffcz_profile_select",
-           "ffcz_copy", "ffcz_set_tuning", "ffcz_clear_tuning", "ffcz_correct_noalloc",
+           "ffcz_copy", "ffcz_copy_columns", "ffcz_set_tuning", "ffcz_clear_tuning", "ffcz_correct_noalloc",
            "ffcz_default_encode_options", "ffcz_encode_workspace_bytes", "ffcz_encode", "ffcz_decode",
            "ffcz_bounds_workspace_bytes", "ffcz_correct_bounds", "ffcz_power_spectrum_bounds",
            "ffcz_huffman_workspace_bytes", "ffcz_huffman_plan", "ffcz_huffman_encode", "ffcz_huffman_decode")
@@ -247,6 +247,8 @@ def lib() -> ctypes.CDLL:
         L.ffcz_profile_select.restype = None
         L.ffcz_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L.ffcz_copy.restype = ctypes.c_int32
+        L.ffcz_copy_columns.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int64] * 5 + [ctypes.c_void_p]
+        L.ffcz_copy_columns.restype = ctypes.c_int32
         L.ffcz_set_tuning.argtypes = [ctypes.c_int32, ctypes.c_char_p]
         L.ffcz_set_tuning.restype = ctypes.c_int32
         L.ffcz_clear_tuning.argtypes = []
@@ -514,6 +516,34 @@ def copy_(dst, src):
         raise ValueError("copy_: tensors must be contiguous")
     st = ffcz_copy(dst.data_ptr(), src.data_ptr(), src.numel() * src.element_size(),
                    torch.cuda.current_stream(src.device).cuda_stream)
+    if st < 0:
+        raise FFCzError(st, ffcz_last_error())
+    return dst
+
+
+def ffcz_copy_columns(dst_ptr: int, src_ptr: int, n_axis: int, axis_stride: int, n_fixed: int,
+                      fixed_stride: int, row_bytes: int, stream: int) -> int:
+    return int(lib().ffcz_copy_columns(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr), int(n_axis),
+                                       int(axis_stride), int(n_fixed), int(fixed_stride), int(row_bytes),
+                                       ctypes.c_void_p(stream)))
+
+
+def copy_columns_(dst, src, n_axis: int, axis_stride: int, n_fixed: int, fixed_stride: int, row_bytes: int):
+    """Rows (f, i) of row_bytes bytes at f * fixed_stride + i * axis_stride copied from src to dst
+    (contiguous device tensors, viewed as bytes) with the strided passes' access pattern, on the
+    current stream."""
+    torch = _torch()
+    if not (dst.is_contiguous() and src.is_contiguous()) or dst.device != src.device or not src.is_cuda:
+        raise ValueError("copy_columns_: contiguous device tensors on one device")
+    if min(n_axis, n_fixed, row_bytes, axis_stride, fixed_stride) < 0:
+        raise ValueError("copy_columns_: negative argument")
+    if n_axis and n_fixed and row_bytes:
+        need = (n_fixed - 1) * fixed_stride + (n_axis - 1) * axis_stride + row_bytes
+        for t, name in ((dst, "dst"), (src, "src")):
+            if t.numel() * t.element_size() < need:
+                raise ValueError(f"copy_columns_: {name} holds fewer than the {need} bytes the rows reach")
+    st = ffcz_copy_columns(dst.data_ptr(), src.data_ptr(), n_axis, axis_stride, n_fixed, fixed_stride, row_bytes,
+                           torch.cuda.current_stream(src.device).cuda_stream)
     if st < 0:
         raise FFCzError(st, ffcz_last_error())
     return dst

@@ -114,6 +114,18 @@ def test_one_dimensional_fields_of_any_length_have_a_workspace():
     assert ffcz.ffcz_mask_bytes((4096,), 3) > 0  # powers of two up to 4096 keep the field passes
 
 
+def test_strided_copy_argument_checks():
+    # refused on the host before any launch, so no GPU is needed
+    from paper_2601_01596_amd import ffcz
+    E = ffcz.E_INVALID
+    assert ffcz.ffcz_copy_columns(0, 0, 4, 4096, 4, 256, 128, 0) == E     # null pointers
+    assert ffcz.ffcz_copy_columns(16, 32, -1, 4096, 4, 256, 128, 0) == E  # negative count
+    assert ffcz.ffcz_copy_columns(8, 32, 4, 4096, 4, 256, 128, 0) == E    # misaligned pointer
+    assert ffcz.ffcz_copy_columns(16, 32, 4, 4100, 4, 256, 128, 0) == E   # misaligned stride
+    assert ffcz.ffcz_copy_columns(16, 32, 4, 4096, 4, 256, 120, 0) == E   # row size not 16-byte
+    assert ffcz.ffcz_copy_columns(16, 32, 0, 4096, 4, 256, 128, 0) == ffcz.OK  # nothing to copy
+
+
 def test_profile_select_names():
     from paper_2601_01596_amd import ffcz
     ffcz.ffcz_profile_select(["x_pass", "z_pass"])

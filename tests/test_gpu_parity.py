@@ -311,6 +311,29 @@ def test_copy_kernel_bit_exact(nbytes):
     assert torch.equal(dst, src)
 
 
+@pytest.mark.parametrize("pattern", ["x", "y"])
+def test_strided_copy_bit_exact(pattern):
+    # rows of 2064 bytes (the last 128-byte tile holds 16 of them) at a pitch of 2176 bytes,
+    # 9 rows per plane, 37 planes padded by 128 bytes: the x-pass pattern walks the planes,
+    # the y-pass pattern the rows; every other byte stays untouched
+    import torch
+    nrow, pitch, nplane, row_bytes = 9, 2176, 37, 2064
+    plane = nrow * pitch + 128
+    args = (nplane, plane, nrow, pitch) if pattern == "x" else (nrow, pitch, nplane, plane)
+    size = nplane * plane
+    src = torch.randint(0, 256, (size,), dtype=torch.uint8, generator=torch.Generator().manual_seed(91))
+    exp = np.zeros(size, dtype=np.uint8)
+    s_np = src.numpy()
+    for pl in range(nplane):
+        for r in range(nrow):
+            o = pl * plane + r * pitch
+            exp[o:o + row_bytes] = s_np[o:o + row_bytes]
+    dst = torch.zeros(size, dtype=torch.uint8).cuda()
+    F.copy_columns_(dst, src.cuda(), *args, row_bytes)
+    torch.cuda.synchronize()
+    assert np.array_equal(dst.cpu().numpy(), exp)
+
+
 @pytest.mark.parametrize("dt,shape", [(np.float32, (32, 64, 128)), (np.float64, (64, 32, 256)),
                                       (np.float32, (256, 512)), (np.float32, (2048, 128)),
                                       (np.float32, (2, 4, 512)), (np.float32, (4, 8, 1024)),
