@@ -921,16 +921,17 @@ struct ColGeom {
   int64_t outer, so, s;
   int64_t mrow_i, mrow_o;
   int64_t outer_per_inst;
+  int64_t pitch;  // complex entries per row of the buffer (the padded row)
 };
 
 // pitch / plane: complex entries per spectrum row / per x-plane of the buffer addressed
 ColGeom geom_y(const Plan& p, int64_t pitch, int64_t plane) {  // 3D only (B = 1)
-  return ColGeom{p.Ly, p.n[0], plane, pitch, 0, 0, p.n[0]};
+  return ColGeom{p.Ly, p.n[0], plane, pitch, 0, 0, p.n[0], pitch};
 }
 ColGeom geom_x(const Plan& p, int64_t pitch, int64_t plane) {
-  if (p.nd == 3) return ColGeom{p.Lx, p.n[1], pitch, plane, p.n[1], 1, p.n[1]};
+  if (p.nd == 3) return ColGeom{p.Lx, p.n[1], pitch, plane, p.n[1], 1, p.n[1], pitch};
   // 2D (and 1D, Lx = 1): one outer index per instance (a whole instance is one plane)
-  return ColGeom{p.Lx, p.B, plane, pitch, 1, 0, 1};
+  return ColGeom{p.Lx, p.B, plane, pitch, 1, 0, 1, pitch};
 }
 
 template <typename T>
@@ -945,6 +946,7 @@ hipError_t run_col(int dt, int mode, int v, const ColGeom& g, const Plan& p, con
   a.so = g.so;
   a.s = g.s;
   a.ncols = (int32_t)p.ncols;
+  a.ncols_pad = (int32_t)g.pitch;
   a.ncb = (int32_t)col_tiles(dt, g.L, v, p.ncols);
   a.xcd_k = col_line_share(dt, g.L, v);
   a.outer_per_inst = g.outer_per_inst;

@@ -82,6 +82,7 @@ struct ColArgs {
   int64_t so;      // stride between outer indices (complex entries)
   int64_t s;       // stride along the transformed axis
   int32_t ncols;   // valid contiguous columns
+  int32_t ncols_pad;  // columns of the padded row: those past ncols are stored as zeros
   int32_t ncb;     // column blocks per outer index
   int64_t outer_per_inst;  // outer indices per instance (instance = outer / outer_per_inst)
   const cx<T>* tw; // stage twiddles of this length

@@ -39,6 +39,11 @@ col_kernel(ColArgs<T> a) {
   const int cb = (int)(bid - o * a.ncb);
   const int col = cb * C + c;
   const bool valid = col < a.ncols;
+  // A padding column of the row (past the last column, inside the padded row) is stored as
+  // zero: every line a pass writes is then whole (a store of part of a line cost about as
+  // much as the whole line, 12 % of a strided pass for the row-end line).  Padding never
+  // carries data.
+  const bool padcol = !valid && col < a.ncols_pad;
   const int64_t base = o * a.so + col;
   // The x-direction passes (VALU-bound: two transforms per pass) address an entry as a
   // block-uniform part (outer index and row q P) plus a lane part (column and row j, in
@@ -54,8 +59,9 @@ col_kernel(ColArgs<T> a) {
   auto src_at = [&](int q) -> const cx<T>* {
     return reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(a.src + ob + (int64_t)(q * P) * a.s) + lob);
   };
+  const int64_t pad_b = (int64_t)(col - col_in) * (int64_t)sizeof(cx<T>);  // the lane's own column, for its stores
   auto dst_at = [&](int q) -> cx<T>* {
-    return reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(a.dst + ob + (int64_t)(q * P) * a.s) + lob);
+    return reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(a.dst + ob + (int64_t)(q * P) * a.s) + lob + pad_b);
   };
 
   for (int i = t; i < TW; i += NT) tws[i] = a.tw[i];
@@ -286,14 +292,14 @@ col_kernel(ColArgs<T> a) {
   }
 
   if constexpr (lean) {
-    if (valid) {
+    if (valid || padcol) {
 #pragma unroll
-      for (int q = 0; q < E; ++q) *dst_at(q) = v[q];
+      for (int q = 0; q < E; ++q) *dst_at(q) = valid ? v[q] : cx<T>{T(0), T(0)};
     }
   } else {
 #pragma unroll
     for (int q = 0; q < E; ++q) {
-      if (valid) a.dst[base + (int64_t)(j + q * P) * a.s] = v[q];
+      if (valid || padcol) a.dst[base + (int64_t)(j + q * P) * a.s] = valid ? v[q] : cx<T>{T(0), T(0)};
     }
   }
 }
